@@ -1,0 +1,25 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) and the built HIP library")
+    config.addinivalue_line("markers", "slow: CPU test that takes more than ~20 s")
+
+
+@pytest.fixture(scope="session")
+def cfg1():
+    from paper_1309_5796_amd import meshgen
+    return meshgen.config1()
+
+
+@pytest.fixture(scope="session")
+def cfg1_system(cfg1):
+    import oracle
+    return oracle.System(cfg1["mesh"])

@@ -1,0 +1,180 @@
+"""Pins of the oracle's minimizer: the curvilinear step (Method section,
+eq. (7)), the gradient identities (eq. (2)-(5)), the step rule's invariants,
+and the physics it must reproduce (Stoner-Wohlfarth switching, including the
+paper's own 45-degree pin, and the Bloch wall).  No GPU."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.fem import ANIS, EXCH, MU0, ZEEM
+from oracle.minimize import Options, bisect_switch, cayley, minimize
+from paper_1309_5796_amd import meshgen
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _unit(rng, n):
+    v = rng.normal(size=(n, 3))
+    return v / np.linalg.norm(v, axis=1, keepdims=True)
+
+
+def test_lagrange_formula_gives_projected_gradient():
+    """a x (b x c) = (a.c) b - (a.b) c, so m x (-m x G) = G - (m.G) m for |m| = 1."""
+    rng = np.random.default_rng(0)
+    a, b, c = rng.normal(size=(3, 50, 3))
+    lhs = np.cross(a, np.cross(b, c))
+    rhs = np.sum(a * c, 1)[:, None] * b - np.sum(a * b, 1)[:, None] * c
+    assert np.abs(lhs - rhs).max() < 1e-13
+    m = _unit(rng, 50)
+    G = rng.normal(size=(50, 3))
+    assert np.abs(np.cross(m, -np.cross(m, G)) - (G - np.sum(m * G, 1)[:, None] * m)).max() < 1e-13
+
+
+@pytest.mark.parametrize("tau", [1e-6, 0.1, 1.0, 37.0])
+def test_cayley_step_solves_implicit_equation_and_keeps_norm(tau):
+    rng = np.random.default_rng(1)
+    m = _unit(rng, 200)
+    h = rng.normal(size=(200, 3)) * 3
+    mp = cayley(m, h, tau)
+    H = np.cross(m, h)
+    resid = mp - m + tau * np.cross(0.5 * (m + mp), H)
+    assert np.abs(resid).max() < 1e-13 * max(1.0, tau * np.abs(H).max())
+    assert np.abs(np.linalg.norm(mp, axis=1) - 1).max() < 2e-15
+
+
+def test_cayley_first_order_limit_is_projected_steepest_descent():
+    """m+ = m - tau m x H + O(tau^2) = m + tau (h - (m.h) m) + O(tau^2), eq. (6)."""
+    rng = np.random.default_rng(2)
+    m = _unit(rng, 100)
+    h = rng.normal(size=(100, 3))
+    errs = []
+    for tau in (1e-2, 1e-3):
+        lin = m + tau * (h - np.sum(m * h, 1)[:, None] * m)
+        errs.append(np.abs(cayley(m, h, tau) - lin).max())
+    assert errs[1] < errs[0] / 50
+
+
+def test_energy_slope_along_the_curve_is_minus_weighted_torque_squared(cfg1, cfg1_system):
+    """de/dtau at tau = 0 equals -sum_i V_i |m_i x h_i|^2 (reduced units)."""
+    s = cfg1_system
+    rng = np.random.default_rng(3)
+    m = cfg1["m0"] + 0.2 * rng.normal(size=cfg1["m0"].shape)
+    m /= np.linalg.norm(m, axis=1, keepdims=True)
+    b = cfg1["b_ext"]
+    ev = s.evaluate(m, b)
+    H = np.cross(m, ev["h"])
+    slope = -float(np.sum(s.V * np.sum(H * H, 1)))
+    d = 1e-4 / np.abs(H).max()
+    fd = (s.evaluate(cayley(m, ev["h"], d), b)["e"] - s.evaluate(cayley(m, ev["h"], -d), b)["e"]) / (2 * d)
+    assert abs(fd - slope) < 1e-6 * abs(slope)
+
+
+def test_minimize_config1_invariants(cfg1, cfg1_system):
+    """Converges below the torque tolerance; |m_i| = 1 after every step; no
+    accepted energy exceeds the maximum of the 20 before it."""
+    r = minimize(cfg1_system, cfg1["m0"], cfg1["b_ext"], Options(record=True))
+    assert r.status == 0 and r.max_torque < 1e-6
+    assert r.norm_drift < 1e-12
+    E = r.energies
+    for k in range(1, len(E)):
+        assert E[k] <= max(E[max(0, k - 20):k])
+    assert E[-1] < E[0]
+    assert r.evals >= r.iterations + 1
+
+
+def _sw_system(psi_deg):
+    mesh = meshgen.kuhn_box((1e-9,) * 3, (2, 2, 2), air=False)
+    return oracle.System(mesh)
+
+
+def sw_field(psi):
+    """Stoner-Wohlfarth astroid: h_sw = (cos^(2/3) psi + sin^(2/3) psi)^(-3/2) in units of 2 K1 / Ms."""
+    return (math.cos(psi) ** (2 / 3) + math.sin(psi) ** (2 / 3)) ** (-1.5)
+
+
+@pytest.mark.parametrize("psi_deg,tol", [(45.0, 2e-4), (1.0, 2e-4)])
+def test_stoner_wohlfarth_switching_field(psi_deg, tol):
+    """Small cube, stray field off: uniform rotation, so the switching field is
+    the astroid's.  At 45 degrees it is half the anisotropy field, the paper's
+    own check of its demagnetization curve (Results, comparison section)."""
+    s = _sw_system(psi_deg)
+    psi = math.radians(psi_deg)
+    u = np.array([math.sin(psi), 0.0, math.cos(psi)])
+    mu0HK = 2 * meshgen.K1_JM3 / (meshgen.JS_T / MU0)
+    o = Options(terms=EXCH | ANIS | ZEEM, tol=1e-9, max_evals=200000)
+    m = np.tile([0.0, 0.0, 1.0], (s.N, 1))
+    exact = sw_field(psi) * mu0HK
+    # start below the switching field, step past it, then bisect
+    B_lo, B_hi = -0.97 * exact * u, -1.03 * exact * u
+    r = minimize(s, m, B_lo, o)
+    assert s.mean_m(r.m) @ u > 0
+    r2 = minimize(s, r.m, B_hi, o)
+    assert s.mean_m(r2.m) @ u < 0
+    b_sw = -bisect_switch(s, r.m, B_lo, B_hi, u, 1e-4 * mu0HK, o)
+    assert abs(b_sw - exact) < tol * exact
+
+
+def test_paper_pin_45deg_coercive_field_is_half_anisotropy_field():
+    with open(os.path.join(GOLDEN, "paper_pins.json")) as f:
+        pins = json.load(f)
+    assert abs(sw_field(math.radians(45.0)) - pins["coercive_field_over_anisotropy_field_at_45deg"]) < 1e-15
+
+
+def test_sw_loop_matches_brute_force_single_spin():
+    """Hysteresis continuation of the uniform cube vs a brute-force
+    continuation of e(theta) = K1 sin^2(theta) - Ms B cos(theta - psi)."""
+    s = _sw_system(1.0)
+    psi = math.radians(1.0)
+    u = meshgen.U_H_1DEG
+    Ms = meshgen.JS_T / MU0
+    Bs = np.concatenate([np.arange(8.0, -8.01, -0.5), np.arange(-7.5, 8.01, 0.5)])
+    recs, _ = oracle.hysteresis(s, np.tile([0.0, 0.0, 1.0], (s.N, 1)), Bs[:, None] * u[None, :],
+                                Options(terms=EXCH | ANIS | ZEEM, tol=1e-9))
+    theta = 0.0
+    grid = np.linspace(-1e-3, 1e-3, 2001)
+    for B, rec in zip(Bs, recs):
+        # follow the local minimum in theta by steepest descent
+        for _ in range(200000):
+            g = 2 * meshgen.K1_JM3 * math.sin(theta) * math.cos(theta) + Ms * B * math.sin(theta - psi)
+            step = -g / (2 * meshgen.K1_JM3 + 2 * Ms * abs(B)) * 0.5
+            theta += step
+            if abs(step) < 1e-13:
+                break
+        e = meshgen.K1_JM3 * np.sin(theta + grid) ** 2 - Ms * B * np.cos(theta + grid - psi)
+        assert np.argmin(e) == 1000                   # a true local minimum
+        m1 = math.cos(theta - psi)
+        assert abs(float(rec.m_avg @ u) - m1) < 1e-6, (B, float(rec.m_avg @ u), m1)
+
+
+def _bloch(cells_per_nm):
+    n = 64 * cells_per_nm
+    mesh = meshgen.kuhn_box((32e-9, 0.5e-9, 0.5e-9), (n, cells_per_nm, cells_per_nm), air=False)
+    s = oracle.System(mesh)
+    x = mesh.xyz[s.nodes, 0]
+    d0 = math.sqrt(meshgen.A_JM / meshgen.K1_JM3)
+    th = 2 * np.arctan(np.exp(x / d0))
+    m = np.stack([np.zeros_like(th), np.sin(th), np.cos(th)], axis=1)
+    r = minimize(s, m, np.zeros(3), Options(terms=EXCH | ANIS, tol=1e-8))
+    assert r.status == 0
+    sigma = r.E / 1e-18
+    # for theta = 2 atan(exp(x/d0)), integral of sin^2(theta) dx = 2 d0, so the
+    # wall width pi d0 is pi/2 times that integral per unit cross-section
+    width = 0.5 * math.pi * float(np.sum(s.V * (1.0 - r.m[:, 2] ** 2))) / 1e-18
+    return sigma, width
+
+
+def test_bloch_wall_energy_and_width_converge_second_order():
+    sig_exact = 4 * math.sqrt(meshgen.A_JM * meshgen.K1_JM3)
+    w_exact = math.pi * math.sqrt(meshgen.A_JM / meshgen.K1_JM3)
+    s1, w1 = _bloch(1)
+    s2, w2 = _bloch(2)
+    e1, e2 = (s1 - sig_exact) / sig_exact, (s2 - sig_exact) / sig_exact
+    assert abs(e1) < 0.04 and abs(e2) < 0.01
+    assert 3.0 < e1 / e2 < 6.0                        # O(h^2)
+    f1, f2 = (w1 - w_exact) / w_exact, (w2 - w_exact) / w_exact
+    assert abs(f1) < 0.10 and abs(f2) < 0.025
+    assert 3.0 < f1 / f2 < 6.0                        # O(h^2)
