@@ -1,0 +1,242 @@
+/*
+ * mmsd.h -- C ABI of the MI355X (gfx950) curvilinear steepest-descent
+ * micromagnetic energy minimizer.
+ *
+ * Method: Exl, Bance, Reichel, Schrefl, Stimming, Mauser, "LaBonte's method
+ * revisited: an effective steepest descent method for micromagnetic energy
+ * minimization" (arXiv:1309.5796).  The library minimizes the total Gibbs
+ * free energy (stray field + exchange + anisotropy + Zeeman) of a P1
+ * tetrahedral mesh under |m_i| = 1 (Method section, eq. (1)) by the
+ * curvilinear search on the sphere (eq. (7)) with Barzilai-Borwein step
+ * lengths (eq. (9)) selected by the adaptive rule the paper adopts, a
+ * 20-energy nonmonotone line search, and the stopping test on the torque.
+ * The stray field comes from a magnetic scalar potential with an open
+ * boundary handled by a space transformation (Results, comparison section);
+ * the potential is solved by Jacobi-preconditioned CG on the device.
+ *
+ * Conventions
+ *  - Every function returns int: 0 = OK, > 0 = warning (result valid),
+ *    < 0 = error (the object is left as it was).  mmsd_last_error() gives a
+ *    thread-local message for the last error on the calling thread.
+ *  - Host arrays passed in are copied during the call; the caller keeps
+ *    ownership and may free them on return.  Host output arrays are written
+ *    during the call and are owned by the caller.
+ *  - Device memory is owned by the library (allocated through the context's
+ *    allocator, default hipMalloc) and released by the matching destroy call.
+ *  - SI units at the boundary: metres, tesla (mu0 H and Js), J/m^3, J/m, J.
+ *    Fields h returned by mmsd_get_field are in units of Ms (dimensionless).
+ *  - A problem handle is used by one host thread at a time.  A server handle
+ *    is internally synchronized.
+ *  - All work of a context is issued on the context's stream.
+ */
+#ifndef MMSD_H
+#define MMSD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define MMSD_OK 0
+#define MMSD_W_MAXEVALS 1     /* evaluation budget reached before the stopping test */
+#define MMSD_W_FLOOR 2        /* backtracking step fell below the floor; torque reported */
+#define MMSD_E_INVALID (-1)   /* bad argument */
+#define MMSD_E_MESH (-2)      /* degenerate/inverted tetrahedron, bad index, bad Dirichlet set */
+#define MMSD_E_NOMEM (-3)     /* device or host allocation failed */
+#define MMSD_E_HIP (-4)       /* HIP runtime error (the context should be recreated) */
+#define MMSD_E_NONFINITE (-5) /* non-finite energy or torque */
+#define MMSD_E_BUSY (-6)      /* server: result not ready yet */
+#define MMSD_E_CANCELLED (-7) /* server: request was cancelled */
+
+/* precision of a problem */
+#define MMSD_FP64 0           /* all storage and arithmetic in FP64 */
+#define MMSD_MIXED 1          /* FP32 matrices/vectors/SpMV/updates; FP64 reductions,
+                                 energy, step logic and PCG scalars */
+
+/* energy terms (bit mask) */
+#define MMSD_EXCH 1
+#define MMSD_ANIS 2
+#define MMSD_ZEEM 4
+#define MMSD_DEMAG 8
+#define MMSD_ALL 15
+
+/* step-length rules (eq. (9)); ADAPTIVE is the rule the paper uses */
+#define MMSD_STEP_ADAPTIVE 0  /* adaptive tau1/tau2 switching with a min-window */
+#define MMSD_STEP_ALTERNATE 1 /* plain alternation of tau1 and tau2 */
+#define MMSD_STEP_BB1 2
+#define MMSD_STEP_BB2 3
+
+typedef struct mmsd_ctx_s* mmsd_ctx;
+typedef struct mmsd_problem_s* mmsd_problem;
+typedef struct mmsd_server_s* mmsd_server;
+
+/* Device allocator hooks; both NULL selects hipMalloc/hipFree.  alloc returns
+ * NULL on failure.  Called only from the thread that calls into the library. */
+typedef void* (*mmsd_alloc_fn)(size_t bytes, void* user);
+typedef void (*mmsd_free_fn)(void* ptr, void* user);
+
+/* Create a context on HIP device `device`.  hip_stream: a hipStream_t to
+ * issue all work on (e.g. torch.cuda.current_stream().cuda_stream), or NULL
+ * for a stream the library creates.  The stream must outlive the context. */
+int mmsd_ctx_create(int device, void* hip_stream, mmsd_alloc_fn alloc, mmsd_free_fn free_fn,
+                    void* user, mmsd_ctx* out);
+int mmsd_ctx_destroy(mmsd_ctx ctx);
+
+/* ---- mesh and materials ------------------------------------------------ */
+/* A full potential mesh: magnet + air + transformation shell, P1 tetrahedra
+ * (Abstract: standard linear tetrahedral elements). */
+typedef struct {
+  int64_t n_nodes;
+  const double* xyz;          /* [n_nodes*3] node coordinates, metres, AoS */
+  int64_t n_tets;
+  const int32_t* tets;        /* [n_tets*4] 0-based node ids, either orientation */
+  const int32_t* tet_region;  /* [n_tets] >= 1 magnetic region id, 0 = non-magnetic */
+  const uint8_t* dirichlet;   /* [n_nodes] 1 = potential fixed to 0 (outer box); may be
+                                 NULL when the stray field is never requested */
+  const double* shell;        /* [9] open-boundary space transformation: centre c[3],
+                                 inner half-extent a[3] (identity for |x_k - c_k| <= a_k),
+                                 outer half-extent b[3] (mapped to infinity); NULL = none */
+} mmsd_mesh;
+
+typedef struct {
+  int32_t region;   /* region id >= 1 */
+  double Js_T;      /* saturation polarization mu0 Ms (must be equal for all regions) */
+  double K1_Jm3;    /* uniaxial anisotropy constant */
+  double A_Jm;      /* exchange constant */
+  double easy_axis[3];
+} mmsd_material;
+
+/* Bytes of device memory a problem on this mesh will hold (admission). */
+int mmsd_footprint(const mmsd_mesh* mesh, int precision, size_t* bytes_out);
+
+/* Validate the mesh, assemble the FE operators on the host and upload them.
+ * Magnetic nodes are the nodes of region >= 1 tetrahedra, in ascending input
+ * order; every magnetic region needs a material.  Errors: MMSD_E_MESH for an
+ * index out of range, a degenerate tetrahedron, no magnetic tetrahedra or a
+ * magnetic node on the Dirichlet set; MMSD_E_INVALID for a missing material or
+ * unequal Js; MMSD_E_NOMEM / MMSD_E_HIP for device failures.  The initial
+ * state is m = +z, b_ext = 0, potential 0. */
+int mmsd_problem_create(mmsd_ctx ctx, const mmsd_mesh* mesh, const mmsd_material* mats,
+                        int n_mats, int precision, mmsd_problem* out);
+int mmsd_problem_destroy(mmsd_problem p);
+
+int mmsd_n_magnetic(mmsd_problem p, int64_t* n);   /* N: magnetic nodes */
+int mmsd_n_potential(mmsd_problem p, int64_t* n);  /* free (non-Dirichlet) nodes, 0 if none */
+
+/* Replace the material of one region (re-assembles exchange and anisotropy). */
+int mmsd_set_material(mmsd_problem p, const mmsd_material* mat);
+/* Applied field b = mu0 H_ext (T), uniform. */
+int mmsd_set_field(mmsd_problem p, const double b_ext_T[3]);
+/* m: [N*3] AoS, magnetic-node order; each vector is normalized on entry; a
+ * zero or non-finite vector gives MMSD_E_INVALID. */
+int mmsd_set_m(mmsd_problem p, const double* m);
+int mmsd_get_m(mmsd_problem p, double* m_out);
+
+/* ---- minimization ------------------------------------------------------ */
+typedef struct {
+  double tol_torque;    /* stop when max_i |m_i x h_i| < tol (h in units of Ms); default 1e-6 */
+  int64_t max_evals;    /* energy-gradient evaluation budget; default 100000 */
+  int terms;            /* MMSD_* mask; default MMSD_ALL */
+  int nonmono_M;        /* nonmonotone memory (1..64); default 20 (end of Method section) */
+  double pcg_rtol;      /* potential solve: stop at |r| <= rtol |b|; default 1e-10 (FP64),
+                           1e-6 (mixed) */
+  int pcg_maxit;        /* default 5000 */
+  int step_rule;        /* MMSD_STEP_*; default adaptive */
+  double refine_tol_T;  /* hysteresis: > 0 bisects each switching field to this width (T) */
+} mmsd_options;
+
+/* Defaults: every field zero selects its default. */
+void mmsd_options_default(mmsd_options* o);
+
+typedef struct {
+  int status;                 /* MMSD_OK or a warning */
+  double energy_J;            /* total energy */
+  double e_exch_J, e_anis_J, e_zeem_J, e_demag_J;
+  double max_torque;          /* max_i |m_i x h_i| */
+  double sum_V_torque2;       /* sum_i V_i |m_i x h_i|^2, m^3 */
+  double sum_torque2;         /* sum_i |m_i x h_i|^2, the paper's stopping quantity */
+  double m_avg[3];            /* volume average of m */
+  int64_t iterations;         /* accepted steps */
+  int64_t evals;              /* energy-gradient evaluations, line-search trials included */
+  int64_t pcg_iters;          /* potential-solver iterations, summed */
+  int64_t launches;           /* device step launches issued */
+  double seconds;             /* wall time of the call */
+} mmsd_result;
+
+/* Minimize from the current m at the current field.  Returns the status
+ * (also in out->status): MMSD_OK, MMSD_W_MAXEVALS, MMSD_W_FLOOR, or an error
+ * (MMSD_E_NONFINITE when the energy or torque became non-finite; m is then
+ * the last accepted state).  The potential is warm-started from the last
+ * solve. */
+int mmsd_minimize(mmsd_problem p, const mmsd_options* o, mmsd_result* out);
+
+/* One evaluation (no step) at the current m: energies and torque in *out;
+ * the field is then available from mmsd_get_field and the potential from
+ * mmsd_get_potential. */
+int mmsd_evaluate(mmsd_problem p, const mmsd_options* o, mmsd_result* out);
+int mmsd_get_field(mmsd_problem p, double* h_out);        /* [N*3] AoS, units of Ms */
+int mmsd_get_potential(mmsd_problem p, double* u_out);    /* [n_nodes] input node order, A;
+                                                             Dirichlet and unused nodes 0 */
+
+/* Hysteresis (Introduction: continuation of local minima): for each field
+ * b_T[k] (n x 3, T) minimize starting from the previous minimum, with a fresh
+ * step-length state.  per_step[k] receives each result.  Switching is a sign
+ * change of <m>.u between consecutive steps, u = b_T[0]/|b_T[0]|.  If
+ * o->refine_tol_T > 0 each switching field is bisected from the last
+ * unswitched minimum.  b_switch_out (nullable, capacity n) receives the
+ * switching fields projected on u (T); *n_switch_out (nullable) their count. */
+int mmsd_hysteresis(mmsd_problem p, const double* b_T, int64_t n, const mmsd_options* o,
+                    mmsd_result* per_step, double* b_switch_out, int64_t* n_switch_out);
+
+/* Minimize n independent problems of one context together: every device
+ * launch advances all unfinished problems by one phase (one persistent
+ * kernel over a problem table; a captured launch graph is replayed until all
+ * are done).  Each problem's result equals its own mmsd_minimize result
+ * bit for bit.  out: [n]. */
+int mmsd_minimize_batch(mmsd_problem* probs, int n, const mmsd_options* o, mmsd_result* out);
+
+/* Checkpoint: m, potential warm start and field.  bytes: in = capacity, out =
+ * size; buf NULL queries the size.  set_state restores a state taken from a
+ * problem on the same mesh and precision. */
+int mmsd_get_state(mmsd_problem p, void* buf, size_t* bytes);
+int mmsd_set_state(mmsd_problem p, const void* buf, size_t bytes);
+
+/* Kernel timing (measurement aid): when enabled, the library brackets every
+ * `stride`-th step launch with HIP events on the context stream.  stats:
+ * [0] summed milliseconds of the timed launches, [1] number timed,
+ * [2] algorithmic bytes of those launches (model documented with the kernels). */
+int mmsd_timing_enable(mmsd_ctx ctx, int stride);
+int mmsd_timing_read(mmsd_ctx ctx, double stats[3], int reset);
+
+/* Launch configuration of the step kernel: lanes per CSR row (4, 8 or 16)
+ * and maximum blocks per problem (multiple of 8).  0 keeps the current
+ * value.  Applies to problems created afterwards. */
+int mmsd_set_launch_config(mmsd_ctx ctx, int lanes_per_row, int max_blocks);
+
+/* ---- serving ----------------------------------------------------------- */
+/* A server owns a worker thread that admits submitted minimizations while
+ * their device footprint fits in hbm_budget bytes and a slot is free (at
+ * most max_slots resident), assembles and uploads them off the critical
+ * path, advances every resident problem by one phase per device launch
+ * (continuous batching), and releases a slot as soon as its problem is done. */
+int mmsd_server_create(mmsd_ctx ctx, size_t hbm_budget, int max_slots, mmsd_server* out);
+int mmsd_submit(mmsd_server s, const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats,
+                const double b_T[3], int precision, const double* m0 /* nullable: +z */,
+                const mmsd_options* o, uint64_t* ticket);
+/* MMSD_E_BUSY until done; then the result (and m if m_out != NULL, [N*3]). */
+int mmsd_poll(mmsd_server s, uint64_t ticket, mmsd_result* out, double* m_out);
+int mmsd_cancel(mmsd_server s, uint64_t ticket);
+/* stats: [0] submitted, [1] completed, [2] resident, [3] queued, [4] bytes resident,
+ * [5] device launches, [6] node-evaluations completed */
+int mmsd_server_stats(mmsd_server s, double stats[7]);
+int mmsd_server_destroy(mmsd_server s);
+
+const char* mmsd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MMSD_H */

@@ -1,0 +1,1063 @@
+// C ABI of the minimizer: contexts, problem upload, device-driven
+// minimization runs, hysteresis continuation, batched runs, checkpoints and
+// kernel timing.  All device work goes through the step kernel; the host
+// only arms a run and polls a small control block (one batch of launches of
+// lookahead), so no host round trip sits between phases.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+
+#include "runtime.h"
+
+using namespace mmsd;
+
+namespace mmsd {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+int hip_fail(hipError_t e, const char* what) {
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return e == hipErrorOutOfMemory ? MMSD_E_NOMEM : MMSD_E_HIP;
+}
+
+namespace {
+
+constexpr double kNmCube = 1e-27;
+
+int invalid(const std::string& m) {
+  set_error(m);
+  return MMSD_E_INVALID;
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Layout of one problem's device arena.
+struct Layout {
+  size_t mrp, mci, K, D1[3], D2[3], Q[6], V, m[2][3], H[2][3], h[3];
+  size_t lrp, lci, L, invd, u, r, z, p[2], q;
+  size_t part, gpart, cnt, ctrl, prob, blk;
+  size_t snap[2][2];
+  size_t total;
+};
+
+int blocks_for(int64_t rows, int lpr, int max_blocks) {
+  const int64_t rpp = kBlock / lpr;
+  int64_t g = (rows + rpp - 1) / rpp;
+  g = std::max<int64_t>(8, std::min<int64_t>(g, max_blocks));
+  return (int)((g + 7) / 8 * 8);
+}
+
+Layout make_layout(int64_t N, int64_t nnzM, int64_t Nt, int64_t nnzL, int G, size_t s) {
+  Layout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += align_up(bytes);
+    return at;
+  };
+  L.mrp = take(4 * (N + 1));
+  L.mci = take(4 * nnzM);
+  L.K = take(s * nnzM);
+  for (int c = 0; c < 3; ++c) L.D1[c] = take(s * nnzM);
+  for (int c = 0; c < 3; ++c) L.D2[c] = take(s * nnzM);
+  for (int c = 0; c < 6; ++c) L.Q[c] = take(s * N);
+  L.V = take(s * N);
+  for (int k = 0; k < 2; ++k)
+    for (int c = 0; c < 3; ++c) L.m[k][c] = take(s * N);
+  for (int k = 0; k < 2; ++k)
+    for (int c = 0; c < 3; ++c) L.H[k][c] = take(s * N);
+  for (int c = 0; c < 3; ++c) L.h[c] = take(s * N);
+  L.lrp = take(4 * (Nt + 1));
+  L.lci = take(4 * nnzL);
+  L.L = take(s * nnzL);
+  L.invd = take(s * Nt);
+  L.u = take(s * Nt);
+  L.r = take(s * Nt);
+  L.z = take(s * Nt);
+  L.p[0] = take(s * Nt);
+  L.p[1] = take(s * Nt);
+  L.q = take(s * Nt);
+  const int ng = (G + kGroup - 1) / kGroup;
+  L.part = take(8 * (size_t)G * kNPart);
+  L.gpart = take(8 * (size_t)ng * kNPart);
+  L.cnt = take(4 * (size_t)(1 + ng));
+  L.ctrl = take(sizeof(Ctrl));
+  L.prob = take(sizeof(Prob<double>));
+  L.blk = take(8);
+  for (int k = 0; k < 2; ++k) {
+    L.snap[k][0] = take(s * 3 * N);
+    L.snap[k][1] = take(s * std::max<int64_t>(Nt, 1));
+  }
+  L.total = o;
+  return L;
+}
+
+template <typename real>
+int upload_vec(hipStream_t st, char* dst, const std::vector<double>& v) {
+  if (v.empty()) return MMSD_OK;
+  if constexpr (sizeof(real) == sizeof(double)) {
+    MMSD_HIP(hipMemcpyAsync(dst, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    MMSD_HIP(hipStreamSynchronize(st));
+  } else {
+    std::vector<float> f(v.begin(), v.end());
+    MMSD_HIP(hipMemcpyAsync(dst, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice, st));
+    MMSD_HIP(hipStreamSynchronize(st));
+  }
+  return MMSD_OK;
+}
+
+int upload_int(hipStream_t st, char* dst, const std::vector<int>& v) {
+  if (v.empty()) return MMSD_OK;
+  MMSD_HIP(hipMemcpyAsync(dst, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  MMSD_HIP(hipStreamSynchronize(st));
+  return MMSD_OK;
+}
+
+template <typename real>
+Prob<real>& desc_of(mmsd_problem p) {
+  return *reinterpret_cast<Prob<real>*>(p->desc);
+}
+
+// Algorithmic bytes per executed phase: every matrix entry, index and
+// row-local vector value moved once; gathered neighbour values counted as
+// cache hits.
+template <typename real>
+void bytes_model(mmsd_problem p) {
+  const Assembly& A = p->A;
+  const double s = sizeof(real), N = A.N, Nt = A.Nt, zM = (double)A.mci.size(), zL = (double)A.lci.size();
+  p->phase_bytes[0] = 4 * (N + 1) + 4 * zM + 3 * s * zM + 9 * s * N +            // trial m, b = D1 m
+                      4 * (Nt + 1) + 4 * zL + s * zL + 4 * s * Nt;                // r = b - L u, z
+  p->phase_bytes[1] = 4 * (Nt + 1) + 4 * zL + s * zL + 4 * s * Nt;                // q = L (z + beta p)
+  p->phase_bytes[2] = 8 * s * Nt;                                                 // u, r, z updates
+  p->phase_bytes[3] = 4 * (N + 1) + 4 * zM + 4 * s * zM + s * N * (3 + 1 + 6 + 1 + 6 + 3);
+  p->phase_bytes_h = 3 * s * N;
+  p->prep_bytes_nodemag = 9 * s * N;
+}
+
+template <typename real>
+int build_device(mmsd_problem p) {
+  mmsd_ctx c = p->ctx;
+  const Assembly& A = p->A;
+  const int64_t N = A.N, Nt = A.Nt, nnzM = (int64_t)A.mci.size(), nnzL = (int64_t)A.lci.size();
+  p->lpr = c->lpr;
+  p->G = blocks_for(std::max<int64_t>(N, Nt), p->lpr, c->max_blocks);
+  const int G = p->G;
+  Layout L = make_layout(N, nnzM, Nt, nnzL, G, sizeof(real));
+  p->arena = (char*)c->dalloc(L.total);
+  if (!p->arena) {
+    set_error("device allocation of " + std::to_string(L.total) + " bytes failed");
+    return MMSD_E_NOMEM;
+  }
+  p->arena_bytes = L.total;
+  hipStream_t st = c->stream;
+  char* base = p->arena;
+  MMSD_HIP(hipMemsetAsync(base, 0, L.total, st));
+  int rc;
+  if ((rc = upload_int(st, base + L.mrp, A.mrp)) || (rc = upload_int(st, base + L.mci, A.mci)) ||
+      (rc = upload_vec<real>(st, base + L.K, A.K)) || (rc = upload_vec<real>(st, base + L.V, A.V)))
+    return rc;
+  for (int k = 0; k < 3; ++k)
+    if ((rc = upload_vec<real>(st, base + L.D1[k], A.D1[k])) || (rc = upload_vec<real>(st, base + L.D2[k], A.D2[k])))
+      return rc;
+  for (int k = 0; k < 6; ++k)
+    if ((rc = upload_vec<real>(st, base + L.Q[k], A.Q[k]))) return rc;
+  if (Nt > 0) {
+    if ((rc = upload_int(st, base + L.lrp, A.lrp)) || (rc = upload_int(st, base + L.lci, A.lci)) ||
+        (rc = upload_vec<real>(st, base + L.L, A.L)) || (rc = upload_vec<real>(st, base + L.invd, A.invd)))
+      return rc;
+  }
+  // initial state: m = +z in slot 0
+  {
+    std::vector<double> one(N, 1.0);
+    if ((rc = upload_vec<real>(st, base + L.m[0][2], one))) return rc;
+  }
+  Prob<real>& P = desc_of<real>(p);
+  std::memset(&P, 0, sizeof(P));
+  P.N = (int)N;
+  P.Nt = (int)Nt;
+  P.G = G;
+  P.blk0 = 0;
+  P.mrp = (const int*)(base + L.mrp);
+  P.mci = (const int*)(base + L.mci);
+  P.K = (const real*)(base + L.K);
+  for (int k = 0; k < 3; ++k) {
+    P.D1[k] = (const real*)(base + L.D1[k]);
+    P.D2[k] = (const real*)(base + L.D2[k]);
+    P.h[k] = (real*)(base + L.h[k]);
+    for (int s = 0; s < 2; ++s) {
+      P.m[s][k] = (real*)(base + L.m[s][k]);
+      P.H[s][k] = (real*)(base + L.H[s][k]);
+    }
+  }
+  for (int k = 0; k < 6; ++k) P.Q[k] = (const real*)(base + L.Q[k]);
+  P.V = (const real*)(base + L.V);
+  P.lrp = (const int*)(base + L.lrp);
+  P.lci = (const int*)(base + L.lci);
+  P.L = (const real*)(base + L.L);
+  P.invd = (const real*)(base + L.invd);
+  P.u = (real*)(base + L.u);
+  P.r = (real*)(base + L.r);
+  P.z = (real*)(base + L.z);
+  P.p[0] = (real*)(base + L.p[0]);
+  P.p[1] = (real*)(base + L.p[1]);
+  P.q = (real*)(base + L.q);
+  P.ndone = nullptr;
+  P.part = (double*)(base + L.part);
+  P.gpart = (double*)(base + L.gpart);
+  P.cnt = (unsigned*)(base + L.cnt);
+  P.ctrl = (Ctrl*)(base + L.ctrl);
+  p->dctrl = P.ctrl;
+  p->dprob = base + L.prob;
+  p->dblk = (int*)(base + L.blk);
+  for (int k = 0; k < 2; ++k)
+    for (int j = 0; j < 2; ++j) p->snap[k][j] = base + L.snap[k][j];
+  int blk[2] = {0, G};
+  MMSD_HIP(hipMemcpyAsync(p->dprob, &P, sizeof(P), hipMemcpyHostToDevice, st));
+  MMSD_HIP(hipMemcpyAsync(p->dblk, blk, sizeof(blk), hipMemcpyHostToDevice, st));
+  MMSD_HIP(hipStreamSynchronize(st));
+  bytes_model<real>(p);
+  return MMSD_OK;
+}
+
+}  // namespace
+
+int resolve(mmsd_problem p, const mmsd_options* o, Resolved* r) {
+  mmsd_options d;
+  mmsd_options_default(&d);
+  if (o) {
+    if (o->tol_torque > 0) d.tol_torque = o->tol_torque;
+    if (o->max_evals > 0) d.max_evals = o->max_evals;
+    if (o->terms > 0) d.terms = o->terms;
+    if (o->nonmono_M > 0) d.nonmono_M = o->nonmono_M;
+    if (o->pcg_rtol > 0) d.pcg_rtol = o->pcg_rtol;
+    if (o->pcg_maxit > 0) d.pcg_maxit = o->pcg_maxit;
+    if (o->step_rule > 0) d.step_rule = o->step_rule;
+    if (o->refine_tol_T > 0) d.refine_tol_T = o->refine_tol_T;
+    if (o->terms < 0 || o->terms > MMSD_ALL || o->nonmono_M > kMaxHist || o->step_rule < 0 ||
+        o->step_rule > MMSD_STEP_BB2)
+      return invalid("options out of range");
+  }
+  if (!o || !(o->pcg_rtol > 0)) d.pcg_rtol = p->precision == MMSD_MIXED ? 1e-6 : 1e-10;
+  if ((d.terms & MMSD_DEMAG) && p->A.Nt == 0)
+    return invalid("stray field requested on a mesh without Dirichlet (outer boundary) nodes");
+  r->tol = d.tol_torque;
+  r->rtol = d.pcg_rtol;
+  r->max_evals = d.max_evals;
+  r->terms = d.terms;
+  r->M = d.nonmono_M;
+  r->rule = d.step_rule;
+  r->maxit = d.pcg_maxit;
+  r->refine = d.refine_tol_T;
+  return MMSD_OK;
+}
+
+int arm(mmsd_problem p, const Resolved& r, int stage, int store_h) {
+  const Assembly& A = p->A;
+  const double dp[14] = {r.tol, r.rtol * r.rtol, 1e-4, 0.5, 0.5, 0.1, 1e-10, 1e10, 1e-14,
+                         p->b_ext[0] / A.Js, p->b_ext[1] / A.Js, p->b_ext[2] / A.Js, A.c_an, A.vol};
+  MMSD_HIP(launch_ctrl_init(p->dctrl, stage, r.terms, r.M, r.rule, r.maxit, store_h,
+                            (r.terms & MMSD_DEMAG) ? 1 : 0, p->acc, (long long)r.max_evals, dp, p->ctx->stream));
+  return MMSD_OK;
+}
+
+int launch_table(const Table& t, hipStream_t st) {
+  hipError_t e = t.precision == MMSD_MIXED
+                     ? launch_step<float>(t.lpr, (const Prob<float>*)t.dprobs, t.nprob, t.dblk, t.grid, st)
+                     : launch_step<double>(t.lpr, (const Prob<double>*)t.dprobs, t.nprob, t.dblk, t.grid, st);
+  if (e != hipSuccess) return hip_fail(e, "step launch");
+  return MMSD_OK;
+}
+
+// Issue B ticks (one launch per table per tick), through a cached graph
+// when allowed and timing is off.
+int issue(mmsd_ctx c, const std::vector<Table>& tabs, int B, std::map<int, hipGraphExec_t>* graphs) {
+  hipStream_t st = c->stream;
+  TimingState& T = c->timing;
+  if (T.stride > 0) {
+    for (int b = 0; b < B; ++b)
+      for (const Table& t : tabs) {
+        hipEvent_t e0, e1;
+        if (T.pool.size() < 2) {
+          MMSD_HIP(hipEventCreate(&e0));
+          MMSD_HIP(hipEventCreate(&e1));
+        } else {
+          e1 = T.pool.back();
+          T.pool.pop_back();
+          e0 = T.pool.back();
+          T.pool.pop_back();
+        }
+        MMSD_HIP(hipEventRecord(e0, st));
+        int rc = launch_table(t, st);
+        if (rc) return rc;
+        MMSD_HIP(hipEventRecord(e1, st));
+        T.pending.push_back(e0);
+        T.pending.push_back(e1);
+      }
+    return MMSD_OK;
+  }
+  if (c->use_graph && graphs) {
+    auto it = graphs->find(B);
+    if (it == graphs->end()) {
+      hipGraph_t g;
+      MMSD_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      for (int b = 0; b < B; ++b)
+        for (const Table& t : tabs) {
+          int rc = launch_table(t, st);
+          if (rc) {
+            hipStreamEndCapture(st, &g);
+            return rc;
+          }
+        }
+      MMSD_HIP(hipStreamEndCapture(st, &g));
+      hipGraphExec_t ex;
+      hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+      it = graphs->emplace(B, ex).first;
+    }
+    MMSD_HIP(hipGraphLaunch(it->second, st));
+    return MMSD_OK;
+  }
+  for (int b = 0; b < B; ++b)
+    for (const Table& t : tabs) {
+      int rc = launch_table(t, st);
+      if (rc) return rc;
+    }
+  return MMSD_OK;
+}
+
+// Collect the event timings of finished launches.
+int drain_timing(mmsd_ctx c) {
+  TimingState& T = c->timing;
+  for (size_t k = 0; k + 1 < T.pending.size(); k += 2) {
+    float ms = 0;
+    MMSD_HIP(hipEventElapsedTime(&ms, T.pending[k], T.pending[k + 1]));
+    T.ms += ms;
+    T.count += 1;
+    T.pool.push_back(T.pending[k]);
+    T.pool.push_back(T.pending[k + 1]);
+  }
+  T.pending.clear();
+  return MMSD_OK;
+}
+
+double run_bytes(mmsd_problem p, const Ctrl& C) {
+  double b = 0;
+  for (int k = 0; k < 4; ++k) b += (double)C.nphase[k] * p->phase_bytes[k];
+  if (!C.demag) b += (double)C.nphase[0] * (p->prep_bytes_nodemag - p->phase_bytes[0]);
+  if (C.store_h) b += (double)C.nphase[3] * p->phase_bytes_h;
+  return b;
+}
+
+void fill_result(mmsd_problem p, const Ctrl& C, mmsd_result* out, double secs, int64_t launches) {
+  const Assembly& A = p->A;
+  const double E0 = A.mu0Ms2 * kNmCube;
+  out->status = C.status;
+  out->e_exch_J = C.eterm_acc[0] * E0;
+  out->e_anis_J = C.eterm_acc[1] * E0;
+  out->e_zeem_J = C.eterm_acc[2] * E0;
+  out->e_demag_J = C.eterm_acc[3] * E0;
+  out->energy_J = out->e_exch_J + out->e_anis_J + out->e_zeem_J + out->e_demag_J;
+  out->max_torque = C.T_acc;
+  out->sum_V_torque2 = C.d_acc * kNmCube;
+  out->sum_torque2 = C.h2_acc;
+  for (int k = 0; k < 3; ++k) out->m_avg[k] = C.mavg_acc[k];
+  out->iterations = C.iters;
+  out->evals = C.evals;
+  out->pcg_iters = C.pcg_total;
+  out->launches = launches;
+  out->seconds = secs;
+}
+
+// Host-side bound on one run's wall time (env MMSD_RUN_TIMEOUT_S, default 1800 s).
+bool run_timed_out(std::chrono::steady_clock::time_point t0) {
+  static const double limit = [] {
+    const char* e = std::getenv("MMSD_RUN_TIMEOUT_S");
+    double v = e ? std::atof(e) : 0.0;
+    return v > 0 ? v : 1800.0;
+  }();
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > limit;
+}
+
+int ensure_pinned(mmsd_problem p) {
+  if (!p->hctrl) MMSD_HIP(hipHostMalloc((void**)&p->hctrl, 2 * sizeof(Ctrl), hipHostMallocDefault));
+  return MMSD_OK;
+}
+
+namespace {
+
+// Arm, then launch batches until the control block reports DONE.
+int run_single(mmsd_problem p, const Resolved& r, int stage, int store_h, mmsd_result* out) {
+  mmsd_ctx c = p->ctx;
+  std::lock_guard<std::mutex> lk(c->mu);
+  auto t0 = std::chrono::steady_clock::now();
+  MMSD_HIP(hipSetDevice(c->device));
+  int rc;
+  if ((rc = ensure_pinned(p)) || (rc = arm(p, r, stage, store_h))) return rc;
+  hipStream_t st = c->stream;
+  std::vector<Table> tabs{{p->precision, p->dprob, p->dblk, 1, p->G, p->lpr}};
+  int B = 8, cur = 0, stalls = 0;
+  long long last_done = -1;
+  bool have_prev = false;
+  int64_t launched = 0;
+  hipEvent_t ev[2];
+  MMSD_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+  MMSD_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+  for (;;) {
+    if ((rc = issue(c, tabs, B, &p->graphs))) break;
+    launched += B;
+    if (hipMemcpyAsync(&p->hctrl[cur], p->dctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipEventRecord(ev[cur], st) != hipSuccess) {
+      rc = hip_fail(hipGetLastError(), "poll copy");
+      break;
+    }
+    if (have_prev) {
+      hipError_t e = hipEventSynchronize(ev[1 - cur]);
+      if (e != hipSuccess) {
+        rc = hip_fail(e, "poll wait");
+        break;
+      }
+      const Ctrl& H = p->hctrl[1 - cur];
+      if (H.phase == PH_DONE) break;
+      // every launch of an unfinished problem executes one phase; a counter
+      // that stops moving means the phase machine is stuck
+      if (H.launches_done == last_done) {
+        if (++stalls >= 3) {
+          set_error("device phase machine stalled");
+          rc = MMSD_E_HIP;
+          break;
+        }
+      } else {
+        stalls = 0;
+        last_done = H.launches_done;
+      }
+      if (run_timed_out(t0)) {
+        set_error("run exceeded MMSD_RUN_TIMEOUT_S");
+        rc = MMSD_E_HIP;
+        break;
+      }
+    }
+    have_prev = true;
+    cur ^= 1;
+    B = std::min(B * 2, 64);
+  }
+  hipError_t e = hipStreamSynchronize(st);
+  hipEventDestroy(ev[0]);
+  hipEventDestroy(ev[1]);
+  if (rc) return rc;
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  if (c->timing.stride > 0) {
+    if ((rc = drain_timing(c))) return rc;
+    c->timing.bytes += run_bytes(p, p->hctrl[cur]);
+  }
+  const Ctrl& C = p->hctrl[cur];
+  p->acc = C.acc;
+  p->h_valid = store_h != 0 && C.status == MMSD_OK;
+  p->last_launches = launched;
+  double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  fill_result(p, C, out, secs, C.launches_done);
+  return C.status;
+}
+
+template <typename real>
+int copy_m_to_host(mmsd_problem p, double* m_out) {
+  const Prob<real>& P = desc_of<real>(p);
+  const int N = p->A.N;
+  std::vector<real> tmp(3 * (size_t)N);
+  hipStream_t st = p->ctx->stream;
+  for (int k = 0; k < 3; ++k)
+    MMSD_HIP(hipMemcpyAsync(tmp.data() + (size_t)k * N, P.m[p->acc][k], sizeof(real) * N, hipMemcpyDeviceToHost, st));
+  MMSD_HIP(hipStreamSynchronize(st));
+  for (int i = 0; i < N; ++i)
+    for (int k = 0; k < 3; ++k) m_out[3 * (size_t)i + k] = (double)tmp[(size_t)k * N + i];
+  return MMSD_OK;
+}
+
+template <typename real>
+int copy_m_to_device(mmsd_problem p, const double* m) {
+  const Prob<real>& P = desc_of<real>(p);
+  const int N = p->A.N;
+  std::vector<real> tmp(3 * (size_t)N);
+  for (int i = 0; i < N; ++i) {
+    const double x = m[3 * (size_t)i], y = m[3 * (size_t)i + 1], z = m[3 * (size_t)i + 2];
+    const double n = std::sqrt(x * x + y * y + z * z);
+    if (!(n > 0) || !std::isfinite(n)) return invalid("zero or non-finite magnetization at node " + std::to_string(i));
+    tmp[i] = (real)(x / n);
+    tmp[(size_t)N + i] = (real)(y / n);
+    tmp[2 * (size_t)N + i] = (real)(z / n);
+  }
+  hipStream_t st = p->ctx->stream;
+  for (int k = 0; k < 3; ++k)
+    MMSD_HIP(hipMemcpyAsync(P.m[p->acc][k], tmp.data() + (size_t)k * N, sizeof(real) * N, hipMemcpyHostToDevice, st));
+  MMSD_HIP(hipStreamSynchronize(st));
+  p->h_valid = false;
+  return MMSD_OK;
+}
+
+// Device-side copies of (m, u) between the live state and snapshot `k`.
+template <typename real>
+int snapshot(mmsd_problem p, int k, bool save) {
+  const Prob<real>& P = desc_of<real>(p);
+  const size_t N = p->A.N, Nt = p->A.Nt;
+  hipStream_t st = p->ctx->stream;
+  real* sm = (real*)p->snap[k][0];
+  for (int c = 0; c < 3; ++c) {
+    real* live = P.m[p->acc][c];
+    if (save) MMSD_HIP(hipMemcpyAsync(sm + c * N, live, sizeof(real) * N, hipMemcpyDeviceToDevice, st));
+    else MMSD_HIP(hipMemcpyAsync(live, sm + c * N, sizeof(real) * N, hipMemcpyDeviceToDevice, st));
+  }
+  if (Nt) {
+    if (save) MMSD_HIP(hipMemcpyAsync(p->snap[k][1], P.u, sizeof(real) * Nt, hipMemcpyDeviceToDevice, st));
+    else MMSD_HIP(hipMemcpyAsync(P.u, p->snap[k][1], sizeof(real) * Nt, hipMemcpyDeviceToDevice, st));
+  }
+  return MMSD_OK;
+}
+
+int snap_locked(mmsd_problem p, int k, bool save) {
+  std::lock_guard<std::mutex> lk(p->ctx->mu);
+  hipSetDevice(p->ctx->device);
+  int rc = p->precision == MMSD_MIXED ? snapshot<float>(p, k, save) : snapshot<double>(p, k, save);
+  if (rc) return rc;
+  MMSD_HIP(hipStreamSynchronize(p->ctx->stream));
+  return MMSD_OK;
+}
+
+double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+}  // namespace
+}  // namespace mmsd
+
+void* mmsd_ctx_s::dalloc(size_t bytes) {
+  if (alloc) return alloc(bytes, user);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  return p;
+}
+
+void mmsd_ctx_s::dfree(void* p) {
+  if (!p) return;
+  if (free_fn) free_fn(p, user);
+  else hipFree(p);
+}
+
+// ============================ C ABI =======================================
+extern "C" {
+
+const char* mmsd_last_error(void) { return mmsd::g_err.c_str(); }
+
+void mmsd_options_default(mmsd_options* o) {
+  if (!o) return;
+  o->tol_torque = 1e-6;
+  o->max_evals = 100000;
+  o->terms = MMSD_ALL;
+  o->nonmono_M = 20;
+  o->pcg_rtol = 1e-10;
+  o->pcg_maxit = 5000;
+  o->step_rule = MMSD_STEP_ADAPTIVE;
+  o->refine_tol_T = 0;
+}
+
+int mmsd_ctx_create(int device, void* hip_stream, mmsd_alloc_fn alloc, mmsd_free_fn free_fn, void* user,
+                    mmsd_ctx* out) {
+  if (!out) return invalid("null output handle");
+  if ((alloc == nullptr) != (free_fn == nullptr)) return invalid("alloc and free must both be set or both NULL");
+  int n = 0;
+  MMSD_HIP(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return invalid("no such HIP device");
+  MMSD_HIP(hipSetDevice(device));
+  auto* c = new mmsd_ctx_s;
+  c->device = device;
+  c->alloc = alloc;
+  c->free_fn = free_fn;
+  c->user = user;
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else {
+    hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete c;
+      return hip_fail(e, "hipStreamCreate");
+    }
+    c->own_stream = true;
+  }
+  *out = c;
+  return MMSD_OK;
+}
+
+int mmsd_ctx_destroy(mmsd_ctx c) {
+  if (!c) return invalid("null context");
+  hipSetDevice(c->device);
+  hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->timing.pool) hipEventDestroy(e);
+  for (hipEvent_t e : c->timing.pending) hipEventDestroy(e);
+  if (c->own_stream) hipStreamDestroy(c->stream);
+  delete c;
+  return MMSD_OK;
+}
+
+int mmsd_set_launch_config(mmsd_ctx c, int lanes_per_row, int max_blocks) {
+  if (!c) return invalid("null context");
+  if (lanes_per_row && lanes_per_row != 4 && lanes_per_row != 8 && lanes_per_row != 16)
+    return invalid("lanes_per_row must be 4, 8 or 16");
+  if (max_blocks && (max_blocks < 8 || max_blocks > kMaxBlocks || max_blocks % 8))
+    return invalid("max_blocks must be a multiple of 8 in [8, 4096]");
+  if (lanes_per_row) c->lpr = lanes_per_row;
+  if (max_blocks) c->max_blocks = max_blocks;
+  return MMSD_OK;
+}
+
+int mmsd_timing_enable(mmsd_ctx c, int stride) {
+  if (!c || stride < 0) return invalid("bad timing request");
+  c->timing.stride = stride;
+  return MMSD_OK;
+}
+
+int mmsd_timing_read(mmsd_ctx c, double stats[3], int reset) {
+  if (!c || !stats) return invalid("bad timing request");
+  stats[0] = c->timing.ms;
+  stats[1] = c->timing.count;
+  stats[2] = c->timing.bytes;
+  if (reset) c->timing.ms = c->timing.count = c->timing.bytes = 0;
+  return MMSD_OK;
+}
+
+int mmsd_footprint(const mmsd_mesh* mesh, int precision, size_t* bytes_out) {
+  if (!bytes_out || (precision != MMSD_FP64 && precision != MMSD_MIXED)) return invalid("bad footprint request");
+  std::string err;
+  PatternSizes ps;
+  int rc = pattern_sizes(mesh, &ps, &err);
+  if (rc) {
+    set_error(err);
+    return rc;
+  }
+  const int G = blocks_for(std::max(ps.N, ps.Nt), 8, 2048);
+  *bytes_out = make_layout(ps.N, ps.nnzM, ps.Nt, ps.nnzL, G, precision == MMSD_MIXED ? 4 : 8).total;
+  return MMSD_OK;
+}
+
+int mmsd_problem_create(mmsd_ctx c, const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats, int precision,
+                        mmsd_problem* out) {
+  if (!c || !out) return invalid("null handle");
+  if (precision != MMSD_FP64 && precision != MMSD_MIXED) return invalid("precision must be MMSD_FP64 or MMSD_MIXED");
+  if (n_mats < 0 || (n_mats > 0 && !mats)) return invalid("bad material table");
+  auto* p = new mmsd_problem_s;
+  p->ctx = c;
+  p->precision = precision;
+  std::string err;
+  int rc = assemble(mesh, mats, n_mats, &p->A, &err);
+  if (rc) {
+    delete p;
+    set_error(err);
+    return rc;
+  }
+  std::lock_guard<std::mutex> lk(c->mu);
+  hipSetDevice(c->device);
+  rc = precision == MMSD_MIXED ? build_device<float>(p) : build_device<double>(p);
+  if (rc) {
+    if (p->arena) c->dfree(p->arena);
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return MMSD_OK;
+}
+
+int mmsd_problem_destroy(mmsd_problem p) {
+  if (!p) return invalid("null problem");
+  mmsd_ctx c = p->ctx;
+  std::lock_guard<std::mutex> lk(c->mu);
+  hipSetDevice(c->device);
+  hipStreamSynchronize(c->stream);
+  for (auto& kv : p->graphs) hipGraphExecDestroy(kv.second);
+  if (p->hctrl) hipHostFree(p->hctrl);
+  c->dfree(p->arena);
+  delete p;
+  return MMSD_OK;
+}
+
+int mmsd_n_magnetic(mmsd_problem p, int64_t* n) {
+  if (!p || !n) return invalid("null argument");
+  *n = p->A.N;
+  return MMSD_OK;
+}
+
+int mmsd_n_potential(mmsd_problem p, int64_t* n) {
+  if (!p || !n) return invalid("null argument");
+  *n = p->A.Nt;
+  return MMSD_OK;
+}
+
+int mmsd_set_material(mmsd_problem p, const mmsd_material* m) {
+  if (!p || !m) return invalid("null argument");
+  double un = std::sqrt(dot3(m->easy_axis, m->easy_axis));
+  if (m->region < 1 || !(un > 0) || !(m->Js_T > 0) || !(m->A_Jm >= 0) || !std::isfinite(m->K1_Jm3))
+    return invalid("invalid material");
+  auto saved = p->A.mats;
+  p->A.mats[m->region] = MatLine{m->Js_T, m->K1_Jm3, m->A_Jm, {m->easy_axis[0], m->easy_axis[1], m->easy_axis[2]}};
+  std::string err;
+  int rc = assemble_material_values(&p->A, &err);
+  if (rc) {
+    p->A.mats = saved;
+    assemble_material_values(&p->A, &err);
+    set_error(err);
+    return rc;
+  }
+  std::lock_guard<std::mutex> lk(p->ctx->mu);
+  hipSetDevice(p->ctx->device);
+  hipStream_t st = p->ctx->stream;
+  if (p->precision == MMSD_MIXED) {
+    Prob<float>& P = desc_of<float>(p);
+    if ((rc = upload_vec<float>(st, (char*)P.K, p->A.K))) return rc;
+    for (int k = 0; k < 6; ++k)
+      if ((rc = upload_vec<float>(st, (char*)P.Q[k], p->A.Q[k]))) return rc;
+  } else {
+    Prob<double>& P = desc_of<double>(p);
+    if ((rc = upload_vec<double>(st, (char*)P.K, p->A.K))) return rc;
+    for (int k = 0; k < 6; ++k)
+      if ((rc = upload_vec<double>(st, (char*)P.Q[k], p->A.Q[k]))) return rc;
+  }
+  return MMSD_OK;
+}
+
+int mmsd_set_field(mmsd_problem p, const double b[3]) {
+  if (!p || !b) return invalid("null argument");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(b[k])) return invalid("non-finite field");
+  for (int k = 0; k < 3; ++k) p->b_ext[k] = b[k];
+  return MMSD_OK;
+}
+
+int mmsd_set_m(mmsd_problem p, const double* m) {
+  if (!p || !m) return invalid("null argument");
+  std::lock_guard<std::mutex> lk(p->ctx->mu);
+  hipSetDevice(p->ctx->device);
+  return p->precision == MMSD_MIXED ? copy_m_to_device<float>(p, m) : copy_m_to_device<double>(p, m);
+}
+
+int mmsd_get_m(mmsd_problem p, double* m_out) {
+  if (!p || !m_out) return invalid("null argument");
+  std::lock_guard<std::mutex> lk(p->ctx->mu);
+  hipSetDevice(p->ctx->device);
+  return p->precision == MMSD_MIXED ? copy_m_to_host<float>(p, m_out) : copy_m_to_host<double>(p, m_out);
+}
+
+int mmsd_minimize(mmsd_problem p, const mmsd_options* o, mmsd_result* out) {
+  if (!p || !out) return invalid("null argument");
+  Resolved r;
+  int rc = resolve(p, o, &r);
+  if (rc) return rc;
+  return run_single(p, r, ST_INIT, 0, out);
+}
+
+int mmsd_evaluate(mmsd_problem p, const mmsd_options* o, mmsd_result* out) {
+  if (!p || !out) return invalid("null argument");
+  Resolved r;
+  int rc = resolve(p, o, &r);
+  if (rc) return rc;
+  return run_single(p, r, ST_EVAL, 1, out);
+}
+
+int mmsd_get_field(mmsd_problem p, double* h_out) {
+  if (!p || !h_out) return invalid("null argument");
+  if (!p->h_valid) return invalid("no field stored: call mmsd_evaluate first");
+  std::lock_guard<std::mutex> lk(p->ctx->mu);
+  hipSetDevice(p->ctx->device);
+  const int N = p->A.N;
+  hipStream_t st = p->ctx->stream;
+  std::vector<double> tmp(3 * (size_t)N);
+  for (int k = 0; k < 3; ++k) {
+    if (p->precision == MMSD_MIXED) {
+      std::vector<float> f(N);
+      MMSD_HIP(hipMemcpyAsync(f.data(), desc_of<float>(p).h[k], 4 * (size_t)N, hipMemcpyDeviceToHost, st));
+      MMSD_HIP(hipStreamSynchronize(st));
+      for (int i = 0; i < N; ++i) tmp[(size_t)k * N + i] = f[i];
+    } else {
+      MMSD_HIP(hipMemcpyAsync(tmp.data() + (size_t)k * N, desc_of<double>(p).h[k], 8 * (size_t)N,
+                              hipMemcpyDeviceToHost, st));
+    }
+  }
+  MMSD_HIP(hipStreamSynchronize(st));
+  for (int i = 0; i < N; ++i)
+    for (int k = 0; k < 3; ++k) h_out[3 * (size_t)i + k] = tmp[(size_t)k * N + i];
+  return MMSD_OK;
+}
+
+int mmsd_get_potential(mmsd_problem p, double* u_out) {
+  if (!p || !u_out) return invalid("null argument");
+  std::lock_guard<std::mutex> lk(p->ctx->mu);
+  hipSetDevice(p->ctx->device);
+  const Assembly& A = p->A;
+  std::fill(u_out, u_out + A.n_nodes, 0.0);
+  if (!A.Nt) return MMSD_OK;
+  hipStream_t st = p->ctx->stream;
+  std::vector<double> u(A.Nt);
+  if (p->precision == MMSD_MIXED) {
+    std::vector<float> f(A.Nt);
+    MMSD_HIP(hipMemcpyAsync(f.data(), desc_of<float>(p).u, 4 * (size_t)A.Nt, hipMemcpyDeviceToHost, st));
+    MMSD_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < A.Nt; ++i) u[i] = f[i];
+  } else {
+    MMSD_HIP(hipMemcpyAsync(u.data(), desc_of<double>(p).u, 8 * (size_t)A.Nt, hipMemcpyDeviceToHost, st));
+    MMSD_HIP(hipStreamSynchronize(st));
+  }
+  const double scale = A.Ms * 1e-9;   // internal unit of the potential: Ms nm
+  for (int i = 0; i < A.Nt; ++i) u_out[A.pot_global[i]] = u[i] * scale;
+  return MMSD_OK;
+}
+
+int mmsd_hysteresis(mmsd_problem p, const double* bT, int64_t n, const mmsd_options* o, mmsd_result* per_step,
+                    double* b_switch_out, int64_t* n_switch_out) {
+  if (!p || !bT || n <= 0 || !per_step) return invalid("bad hysteresis arguments");
+  Resolved r;
+  int rc = resolve(p, o, &r);
+  if (rc) return rc;
+  double uh[3] = {0, 0, 0};
+  for (int64_t k = 0; k < n; ++k) {
+    double nb = std::sqrt(dot3(bT + 3 * k, bT + 3 * k));
+    if (nb > 0) {
+      for (int c = 0; c < 3; ++c) uh[c] = bT[3 * k + c] / nb;
+      break;
+    }
+  }
+  if (dot3(uh, uh) == 0) return invalid("all fields are zero");
+  int64_t nsw = 0;
+  int prev_sign = 0;
+  for (int64_t k = 0; k < n; ++k) {
+    if ((rc = mmsd_set_field(p, bT + 3 * k))) return rc;
+    rc = run_single(p, r, ST_INIT, 0, &per_step[k]);
+    if (rc < 0) return rc;
+    const double proj = dot3(per_step[k].m_avg, uh);
+    const int sgn = proj > 0 ? 1 : (proj < 0 ? -1 : 0);
+    if (k > 0 && sgn != prev_sign) {
+      const double* B0 = bT + 3 * (k - 1);
+      const double* B1 = bT + 3 * k;
+      double bsw = 0.5 * (dot3(B0, uh) + dot3(B1, uh));
+      if (r.refine > 0) {
+        // bisect from the last unswitched minimum (snapshot 0); the switched
+        // state of step k waits in snapshot 1
+        if ((rc = snap_locked(p, 1, true))) return rc;
+        double lo[3], hi[3];
+        for (int c = 0; c < 3; ++c) {
+          lo[c] = B0[c];
+          hi[c] = B1[c];
+        }
+        for (;;) {
+          const double d[3] = {hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]};
+          if (std::sqrt(dot3(d, d)) <= r.refine) break;
+          double mid[3] = {0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]), 0.5 * (lo[2] + hi[2])};
+          if ((rc = snap_locked(p, 0, false))) return rc;
+          mmsd_set_field(p, mid);
+          mmsd_result rm;
+          rc = run_single(p, r, ST_INIT, 0, &rm);
+          if (rc < 0) return rc;
+          const double pm = dot3(rm.m_avg, uh);
+          const int sm = pm > 0 ? 1 : (pm < 0 ? -1 : 0);
+          if (sm != prev_sign) {
+            for (int c = 0; c < 3; ++c) hi[c] = mid[c];
+          } else {
+            for (int c = 0; c < 3; ++c) lo[c] = mid[c];
+            if ((rc = snap_locked(p, 0, true))) return rc;
+          }
+        }
+        bsw = 0.5 * (dot3(lo, uh) + dot3(hi, uh));
+        if ((rc = snap_locked(p, 1, false))) return rc;
+        mmsd_set_field(p, B1);
+      }
+      if (b_switch_out) b_switch_out[nsw] = bsw;
+      ++nsw;
+    }
+    if ((rc = snap_locked(p, 0, true))) return rc;
+    prev_sign = sgn;
+  }
+  if (n_switch_out) *n_switch_out = nsw;
+  return MMSD_OK;
+}
+
+int mmsd_minimize_batch(mmsd_problem* probs, int n, const mmsd_options* o, mmsd_result* out) {
+  if (!probs || n <= 0 || !out) return invalid("bad batch arguments");
+  mmsd_ctx c = probs[0]->ctx;
+  for (int i = 0; i < n; ++i)
+    if (!probs[i] || probs[i]->ctx != c) return invalid("batch problems must share one context");
+  std::vector<Resolved> rs(n);
+  for (int i = 0; i < n; ++i) {
+    int rc = resolve(probs[i], o, &rs[i]);
+    if (rc) return rc;
+  }
+  std::lock_guard<std::mutex> lk(c->mu);
+  auto t0 = std::chrono::steady_clock::now();
+  MMSD_HIP(hipSetDevice(c->device));
+  hipStream_t st = c->stream;
+  // one table per precision, problems keep their own block decomposition
+  std::vector<int> idx[2];
+  for (int i = 0; i < n; ++i) idx[probs[i]->precision == MMSD_MIXED ? 1 : 0].push_back(i);
+  size_t bytes = 0;
+  for (int q = 0; q < 2; ++q) bytes += align_up(sizeof(Prob<double>) * idx[q].size()) + align_up(4 * (idx[q].size() + 1));
+  bytes += 256;
+  char* tab = (char*)c->dalloc(bytes);
+  if (!tab) return invalid("batch table allocation failed");
+  unsigned* dndone = (unsigned*)(tab + bytes - 256);
+  std::vector<Table> tabs;
+  size_t off = 0;
+  int rc = MMSD_OK;
+  for (int q = 0; q < 2 && !rc; ++q) {
+    if (idx[q].empty()) continue;
+    const size_t ps = q ? sizeof(Prob<float>) : sizeof(Prob<double>);
+    std::vector<unsigned char> h(ps * idx[q].size());
+    std::vector<int> blk(idx[q].size() + 1, 0);
+    int lpr = probs[idx[q][0]]->lpr;
+    for (size_t k = 0; k < idx[q].size(); ++k) {
+      mmsd_problem p = probs[idx[q][k]];
+      if (p->lpr != lpr) rc = invalid("batch problems of one precision must share lanes per row");
+      blk[k + 1] = blk[k] + p->G;
+      std::memcpy(&h[k * ps], p->desc, ps);
+      if (q) {
+        reinterpret_cast<Prob<float>*>(&h[k * ps])->blk0 = blk[k];
+        reinterpret_cast<Prob<float>*>(&h[k * ps])->ndone = dndone;
+      } else {
+        reinterpret_cast<Prob<double>*>(&h[k * ps])->blk0 = blk[k];
+        reinterpret_cast<Prob<double>*>(&h[k * ps])->ndone = dndone;
+      }
+    }
+    char* dp = tab + off;
+    off += align_up(h.size());
+    char* db = tab + off;
+    off += align_up(4 * blk.size());
+    if (!rc && (hipMemcpyAsync(dp, h.data(), h.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+                hipMemcpyAsync(db, blk.data(), 4 * blk.size(), hipMemcpyHostToDevice, st) != hipSuccess))
+      rc = hip_fail(hipGetLastError(), "batch table upload");
+    tabs.push_back(Table{q ? MMSD_MIXED : MMSD_FP64, dp, (const int*)db, (int)idx[q].size(), blk.back(), lpr});
+  }
+  unsigned* hdone = nullptr;
+  if (!rc && hipHostMalloc((void**)&hdone, 2 * sizeof(unsigned), hipHostMallocDefault) != hipSuccess)
+    rc = hip_fail(hipGetLastError(), "pinned poll buffer");
+  if (!rc && hipMemsetAsync(dndone, 0, 4, st) != hipSuccess) rc = hip_fail(hipGetLastError(), "memset");
+  for (int i = 0; i < n && !rc; ++i) {
+    if ((rc = ensure_pinned(probs[i]))) break;
+    rc = arm(probs[i], rs[i], ST_INIT, 0);
+  }
+  std::map<int, hipGraphExec_t> graphs;
+  int64_t launched = 0;
+  if (!rc) {
+    int B = 8, cur = 0;
+    bool have_prev = false;
+    hipEvent_t ev[2];
+    hipEventCreateWithFlags(&ev[0], hipEventDisableTiming);
+    hipEventCreateWithFlags(&ev[1], hipEventDisableTiming);
+    for (;;) {
+      if ((rc = issue(c, tabs, B, &graphs))) break;
+      launched += B;
+      hipMemcpyAsync(&hdone[cur], dndone, sizeof(unsigned), hipMemcpyDeviceToHost, st);
+      hipEventRecord(ev[cur], st);
+      if (have_prev) {
+        hipError_t e = hipEventSynchronize(ev[1 - cur]);
+        if (e != hipSuccess) {
+          rc = hip_fail(e, "batch poll");
+          break;
+        }
+        if (hdone[1 - cur] >= (unsigned)n) break;
+        if (run_timed_out(t0)) {
+          set_error("run exceeded MMSD_RUN_TIMEOUT_S");
+          rc = MMSD_E_HIP;
+          break;
+        }
+      }
+      have_prev = true;
+      cur ^= 1;
+      B = std::min(B * 2, 64);
+    }
+    hipStreamSynchronize(st);
+    hipEventDestroy(ev[0]);
+    hipEventDestroy(ev[1]);
+  }
+  for (auto& kv : graphs) hipGraphExecDestroy(kv.second);
+  if (!rc && c->timing.stride > 0) rc = drain_timing(c);
+  double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int worst = MMSD_OK;
+  for (int i = 0; i < n && !rc; ++i) {
+    mmsd_problem p = probs[i];
+    if (hipMemcpy(&p->hctrl[0], p->dctrl, sizeof(Ctrl), hipMemcpyDeviceToHost) != hipSuccess) {
+      rc = hip_fail(hipGetLastError(), "batch result copy");
+      break;
+    }
+    const Ctrl& C = p->hctrl[0];
+    p->acc = C.acc;
+    p->h_valid = false;
+    if (c->timing.stride > 0) c->timing.bytes += run_bytes(p, C);
+    fill_result(p, C, &out[i], secs, C.launches_done);
+    if (C.status < 0) worst = C.status;
+    else if (worst == MMSD_OK && C.status > 0) worst = C.status;
+  }
+  if (hdone) hipHostFree(hdone);
+  c->dfree(tab);
+  return rc ? rc : worst;
+}
+
+int mmsd_get_state(mmsd_problem p, void* buf, size_t* bytes) {
+  if (!p || !bytes) return invalid("null argument");
+  const size_t N = p->A.N, Nt = p->A.Nt;
+  const size_t need = 64 + 8 * (3 * N + Nt);
+  if (!buf) {
+    *bytes = need;
+    return MMSD_OK;
+  }
+  if (*bytes < need) return invalid("state buffer too small");
+  char* b = (char*)buf;
+  std::memset(b, 0, 64);
+  std::memcpy(b, "MMSDST01", 8);
+  int64_t hdr[4] = {(int64_t)p->precision, (int64_t)N, (int64_t)Nt, 0};
+  std::memcpy(b + 8, hdr, sizeof(hdr));
+  std::memcpy(b + 40, p->b_ext, 24);
+  int rc = mmsd_get_m(p, (double*)(b + 64));
+  if (rc) return rc;
+  double* u = (double*)(b + 64 + 24 * N);
+  if (Nt) {
+    std::lock_guard<std::mutex> lk(p->ctx->mu);
+    hipStream_t st = p->ctx->stream;
+    if (p->precision == MMSD_MIXED) {
+      std::vector<float> f(Nt);
+      MMSD_HIP(hipMemcpyAsync(f.data(), desc_of<float>(p).u, 4 * Nt, hipMemcpyDeviceToHost, st));
+      MMSD_HIP(hipStreamSynchronize(st));
+      for (size_t i = 0; i < Nt; ++i) u[i] = f[i];
+    } else {
+      MMSD_HIP(hipMemcpyAsync(u, desc_of<double>(p).u, 8 * Nt, hipMemcpyDeviceToHost, st));
+      MMSD_HIP(hipStreamSynchronize(st));
+    }
+  }
+  *bytes = need;
+  return MMSD_OK;
+}
+
+int mmsd_set_state(mmsd_problem p, const void* buf, size_t bytes) {
+  if (!p || !buf) return invalid("null argument");
+  const size_t N = p->A.N, Nt = p->A.Nt;
+  const char* b = (const char*)buf;
+  if (bytes < 64 || std::memcmp(b, "MMSDST01", 8)) return invalid("not a state buffer");
+  int64_t hdr[4];
+  std::memcpy(hdr, b + 8, sizeof(hdr));
+  if (hdr[0] != p->precision || hdr[1] != (int64_t)N || hdr[2] != (int64_t)Nt || bytes < 64 + 8 * (3 * N + Nt))
+    return invalid("state does not match this problem");
+  double bf[3];
+  std::memcpy(bf, b + 40, 24);
+  int rc = mmsd_set_m(p, (const double*)(b + 64));
+  if (rc) return rc;
+  mmsd_set_field(p, bf);
+  if (Nt) {
+    std::lock_guard<std::mutex> lk(p->ctx->mu);
+    hipStream_t st = p->ctx->stream;
+    const double* u = (const double*)(b + 64 + 24 * N);
+    if (p->precision == MMSD_MIXED) {
+      std::vector<float> f(u, u + Nt);
+      MMSD_HIP(hipMemcpyAsync(desc_of<float>(p).u, f.data(), 4 * Nt, hipMemcpyHostToDevice, st));
+      MMSD_HIP(hipStreamSynchronize(st));
+    } else {
+      MMSD_HIP(hipMemcpyAsync(desc_of<double>(p).u, u, 8 * Nt, hipMemcpyHostToDevice, st));
+      MMSD_HIP(hipStreamSynchronize(st));
+    }
+  }
+  return MMSD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,60 @@
+// Host-side finite-element assembly of the operators the step kernel uses.
+#pragma once
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "mmsd.h"
+
+namespace mmsd {
+
+constexpr double kMu0 = 4e-7 * 3.14159265358979323846;
+
+struct MatLine {
+  double Js, K1, A, u[3];
+};
+
+// Operators of one mesh in internal units (nm, mu0 Ms^2 nm^3, Ms).
+struct Assembly {
+  int64_t n_nodes = 0;
+  int N = 0;                     // magnetic nodes
+  int Nt = 0;                    // free potential nodes (magnetic ones first)
+  double Js = 0, Ms = 0, mu0Ms2 = 0;
+  double c_an = 0;               // sum_e V_e K1_e / (mu0 Ms^2)
+  double vol = 0;                // sum_i V_i
+  std::vector<int> mag_global;   // [N] global id of magnetic node i (ascending)
+  std::vector<int> pot_global;   // [Nt] global id of potential row p
+  // magnet CSR (rows and columns are magnetic nodes)
+  std::vector<int> mrp, mci;
+  std::vector<double> K;         // 2 K_ij / V_i
+  std::vector<double> D1[3];     // sum_e V_e/4 grad(phi_i)|_e
+  std::vector<double> D2[3];     // sum_e V_e/4 grad(phi_j)|_e / V_i
+  std::vector<double> Q[6];      // 2 Q_i / V_i (xx yy zz xy xz yz)
+  std::vector<double> V;         // lumped nodal volume
+  // potential CSR over free nodes
+  std::vector<int> lrp, lci;
+  std::vector<double> L, invd;
+  // kept for re-assembly of the material-dependent values
+  std::vector<int> mtet;         // [Em*4] magnetic-node indices of magnetic tets
+  std::vector<double> mgeo;      // [Em*13] V_e, grad[4][3]
+  std::vector<int> mregion;      // [Em]
+  std::vector<int> mnode_tets_ptr, mnode_tets;   // magnetic node -> (tet, vertex) pairs
+  std::map<int, MatLine> mats;
+};
+
+struct PatternSizes {
+  int64_t N, nnzM, Nt, nnzL;
+};
+
+// Validate the mesh and count rows and nonzeros (no values).
+int pattern_sizes(const mmsd_mesh* mesh, PatternSizes* out, std::string* err);
+
+// Full assembly.  Returns an MMSD_* status.
+int assemble(const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats, Assembly* out,
+             std::string* err);
+
+// Recompute K, Q and c_an from a.mats (after a material change).
+int assemble_material_values(Assembly* a, std::string* err);
+
+}  // namespace mmsd

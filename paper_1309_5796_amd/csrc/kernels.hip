@@ -1,0 +1,675 @@
+// Step kernel of the curvilinear steepest-descent minimizer for gfx950.
+//
+// One launch advances every unfinished problem of a table by one phase (see
+// device.h).  Work layout:
+//  * CSR rows are split over `LPR` lanes (4, 8 or 16) of a 64-wide wavefront;
+//    a block of 256 threads walks a contiguous chunk of rows in passes of
+//    256/LPR rows.  Column indices and values stream coalesced; node vectors
+//    are gathered (they stay in L2: every entry is reused by ~15 rows).
+//  * Block b of a problem takes chunk (b % 8) * (G / 8) + b / 8: blocks are
+//    dealt to the 8 XCDs round-robin, so this gives each XCD one contiguous
+//    eighth of the rows and keeps neighbour gathers inside its own L2.
+//  * Reductions are deterministic: wavefront butterfly, then the 4 waves in
+//    order, then per-block partials summed in block order by the last block
+//    of each group of 32, then the group partials in group order by the last
+//    group.  That last block also runs the phase transition and, after a
+//    FIELD phase, the step-length logic.
+// All node arrays are structure-of-arrays.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "device.h"
+#include "mmsd.h"
+
+namespace mmsd {
+namespace {
+
+template <typename T, int W>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Explicit solution of the curvilinear step m+ = m - tau (m + m+)/2 x H
+// (eq. (7)): with a = (tau/2) H and c = a x m, m+ = m + 2 (c + a x c) / (1 + a.a).
+// ht = tau / 2.  In FP32 the result is renormalized to keep |m| = 1 at
+// single-precision rounding.
+template <typename real>
+__device__ __forceinline__ void cayley(real mx, real my, real mz, real Hx, real Hy, real Hz, real ht,
+                                       real& ox, real& oy, real& oz) {
+  if (ht == real(0)) {
+    ox = mx;
+    oy = my;
+    oz = mz;
+    return;
+  }
+  const real ax = ht * Hx, ay = ht * Hy, az = ht * Hz;
+  const real cx = ay * mz - az * my, cy = az * mx - ax * mz, cz = ax * my - ay * mx;
+  const real dx = ay * cz - az * cy, dy = az * cx - ax * cz, dz = ax * cy - ay * cx;
+  const real f = real(2) / (real(1) + ax * ax + ay * ay + az * az);
+  ox = mx + f * (cx + dx);
+  oy = my + f * (cy + dy);
+  oz = mz + f * (cz + dz);
+  if constexpr (std::is_same<real, float>::value) {
+    const float s = rsqrtf(ox * ox + oy * oy + oz * oz);
+    ox *= s;
+    oy *= s;
+    oz *= s;
+  }
+}
+
+// Rows [r0, r1) of chunk t out of G for R rows, chunk rounded to `rpp`.
+__device__ __forceinline__ void chunk_rows(int R, int G, int t, int rpp, int& r0, int& r1) {
+  long long c = ((long long)R + G - 1) / G;
+  c = (c + rpp - 1) / rpp * rpp;
+  long long a = c * t;
+  r0 = (int)(a < R ? a : R);
+  long long b = a + c;
+  r1 = (int)(b < R ? b : R);
+}
+
+// ---- PREP: trial magnetization, Poisson right-hand side, initial residual ----
+template <typename real, int LPR>
+__device__ void phase_prep(const Prob<real>& P, const Ctrl* C, int t, double* acc) {
+  constexpr int RPP = kBlock / LPR;
+  const int lane = threadIdx.x & (LPR - 1);
+  const int slot = threadIdx.x / LPR;
+  const bool demag = C->demag != 0;
+  const int R = demag ? P.Nt : P.N;
+  int r0, r1;
+  chunk_rows(R, P.G, t, RPP, r0, r1);
+  const int a = C->acc, tr = 1 - a;
+  const real ht = real(0.5 * C->tau);
+  const real* __restrict__ max_ = P.m[a][0];
+  const real* __restrict__ may = P.m[a][1];
+  const real* __restrict__ maz = P.m[a][2];
+  const real* __restrict__ Hax = P.H[a][0];
+  const real* __restrict__ Hay = P.H[a][1];
+  const real* __restrict__ Haz = P.H[a][2];
+  for (int base = r0; base < r1; base += RPP) {
+    const int i = base + slot;
+    const bool valid = i < r1;
+    real bi = 0, lu = 0;
+    if (valid && i < P.N) {
+      if (lane == 0) {
+        real ox, oy, oz;
+        cayley<real>(max_[i], may[i], maz[i], Hax[i], Hay[i], Haz[i], ht, ox, oy, oz);
+        P.m[tr][0][i] = ox;
+        P.m[tr][1][i] = oy;
+        P.m[tr][2][i] = oz;
+      }
+      if (demag) {
+        const int k1 = P.mrp[i + 1];
+        for (int k = P.mrp[i] + lane; k < k1; k += LPR) {
+          const int j = P.mci[k];
+          real ox, oy, oz;
+          cayley<real>(max_[j], may[j], maz[j], Hax[j], Hay[j], Haz[j], ht, ox, oy, oz);
+          bi += P.D1[0][k] * ox + P.D1[1][k] * oy + P.D1[2][k] * oz;
+        }
+      }
+    }
+    if (demag) {
+      if (valid) {
+        const int k1 = P.lrp[i + 1];
+        for (int k = P.lrp[i] + lane; k < k1; k += LPR) lu += P.L[k] * P.u[P.lci[k]];
+      }
+      bi = group_sum<real, LPR>(bi);
+      lu = group_sum<real, LPR>(lu);
+      if (valid && lane == 0) {
+        const real ri = bi - lu;
+        const real zi = ri * P.invd[i];
+        P.r[i] = ri;
+        P.z[i] = zi;
+        acc[0] += (double)ri * (double)zi;
+        acc[1] += (double)bi * (double)bi;
+        acc[2] += (double)ri * (double)ri;
+        acc[3] += (double)ri * (double)P.u[i];
+      }
+    }
+  }
+}
+
+// ---- PCG_A: search direction (recomputed at neighbours) and q = L p ----
+template <typename real, int LPR>
+__device__ void phase_pcg_a(const Prob<real>& P, const Ctrl* C, int t, double* acc) {
+  constexpr int RPP = kBlock / LPR;
+  const int lane = threadIdx.x & (LPR - 1);
+  const int slot = threadIdx.x / LPR;
+  int r0, r1;
+  chunk_rows(P.Nt, P.G, t, RPP, r0, r1);
+  const real beta = real(C->beta);
+  const real* __restrict__ pold = P.p[C->pcur];
+  real* __restrict__ pnew = P.p[1 - C->pcur];
+  const real* __restrict__ z = P.z;
+  for (int base = r0; base < r1; base += RPP) {
+    const int i = base + slot;
+    const bool valid = i < r1;
+    real s = 0;
+    if (valid) {
+      const int k1 = P.lrp[i + 1];
+      for (int k = P.lrp[i] + lane; k < k1; k += LPR) {
+        const int j = P.lci[k];
+        s += P.L[k] * (z[j] + beta * pold[j]);
+      }
+    }
+    s = group_sum<real, LPR>(s);
+    if (valid && lane == 0) {
+      const real pi = z[i] + beta * pold[i];
+      pnew[i] = pi;
+      P.q[i] = s;
+      acc[0] += (double)pi * (double)s;
+    }
+  }
+}
+
+// ---- PCG_B: potential and residual update, preconditioned residual ----
+template <typename real>
+__device__ void phase_pcg_b(const Prob<real>& P, const Ctrl* C, int t, double* acc) {
+  int r0, r1;
+  chunk_rows(P.Nt, P.G, t, kBlock, r0, r1);
+  const real alpha = real(C->alpha);
+  const real* __restrict__ p = P.p[C->pcur];
+  for (int i = r0 + threadIdx.x; i < r1; i += kBlock) {
+    const real ui = P.u[i] + alpha * p[i];
+    const real ri = P.r[i] - alpha * P.q[i];
+    const real zi = ri * P.invd[i];
+    P.u[i] = ui;
+    P.r[i] = ri;
+    P.z[i] = zi;
+    acc[0] += (double)ri * (double)zi;
+    acc[1] += (double)ri * (double)ri;
+    acc[2] += (double)ri * (double)ui;
+  }
+}
+
+// ---- FIELD: effective field, torque, fused reductions ----
+template <typename real, int LPR>
+__device__ void phase_field(const Prob<real>& P, const Ctrl* C, int t, double* acc) {
+  constexpr int RPP = kBlock / LPR;
+  const int lane = threadIdx.x & (LPR - 1);
+  const int slot = threadIdx.x / LPR;
+  int r0, r1;
+  chunk_rows(P.N, P.G, t, RPP, r0, r1);
+  const int a = C->acc, tr = 1 - a;
+  const int terms = C->terms;
+  const bool exch = terms & MMSD_EXCH, anis = terms & MMSD_ANIS, zeem = terms & MMSD_ZEEM;
+  const bool demag = C->demag != 0;
+  const real bzx = zeem ? real(C->bz[0]) : real(0);
+  const real bzy = zeem ? real(C->bz[1]) : real(0);
+  const real bzz = zeem ? real(C->bz[2]) : real(0);
+  const real* __restrict__ mx = P.m[tr][0];
+  const real* __restrict__ my = P.m[tr][1];
+  const real* __restrict__ mz = P.m[tr][2];
+  for (int base = r0; base < r1; base += RPP) {
+    const int i = base + slot;
+    const bool valid = i < r1;
+    real kx = 0, ky = 0, kz = 0, dx = 0, dy = 0, dz = 0;
+    if (valid) {
+      const int k1 = P.mrp[i + 1];
+      for (int k = P.mrp[i] + lane; k < k1; k += LPR) {
+        const int j = P.mci[k];
+        if (exch) {
+          const real kv = P.K[k];
+          kx += kv * mx[j];
+          ky += kv * my[j];
+          kz += kv * mz[j];
+        }
+        if (demag) {
+          const real uj = P.u[j];
+          dx += P.D2[0][k] * uj;
+          dy += P.D2[1][k] * uj;
+          dz += P.D2[2][k] * uj;
+        }
+      }
+    }
+    kx = group_sum<real, LPR>(kx);
+    ky = group_sum<real, LPR>(ky);
+    kz = group_sum<real, LPR>(kz);
+    dx = group_sum<real, LPR>(dx);
+    dy = group_sum<real, LPR>(dy);
+    dz = group_sum<real, LPR>(dz);
+    if (valid && lane == 0) {
+      const real m0 = mx[i], m1 = my[i], m2 = mz[i];
+      real ax = 0, ay = 0, az = 0;
+      if (anis) {
+        ax = P.Q[0][i] * m0 + P.Q[3][i] * m1 + P.Q[4][i] * m2;
+        ay = P.Q[3][i] * m0 + P.Q[1][i] * m1 + P.Q[5][i] * m2;
+        az = P.Q[4][i] * m0 + P.Q[5][i] * m1 + P.Q[2][i] * m2;
+      }
+      const real hx = -kx - dx + ax + bzx;
+      const real hy = -ky - dy + ay + bzy;
+      const real hz = -kz - dz + az + bzz;
+      const real Hx = m1 * hz - m2 * hy, Hy = m2 * hx - m0 * hz, Hz = m0 * hy - m1 * hx;
+      P.H[tr][0][i] = Hx;
+      P.H[tr][1][i] = Hy;
+      P.H[tr][2][i] = Hz;
+      if (C->store_h) {
+        P.h[0][i] = hx;
+        P.h[1][i] = hy;
+        P.h[2][i] = hz;
+      }
+      const double V = (double)P.V[i];
+      acc[FP_EEX] += 0.5 * V * (double)(m0 * kx + m1 * ky + m2 * kz);
+      acc[FP_EAN] -= 0.5 * V * (double)(m0 * ax + m1 * ay + m2 * az);
+      acc[FP_EZ] -= V * (double)(m0 * bzx + m1 * bzy + m2 * bzz);
+      acc[FP_ED] += 0.5 * V * (double)(m0 * dx + m1 * dy + m2 * dz);
+      const double H2 = (double)Hx * Hx + (double)Hy * Hy + (double)Hz * Hz;
+      acc[FP_TMAX] = fmax(acc[FP_TMAX], sqrt(H2));
+      acc[FP_D] += V * H2;
+      acc[FP_H2] += H2;
+      // BB differences against the accepted state: s = m_t - m, y = g_t - g, g = m x H
+      const real n0 = P.m[a][0][i], n1 = P.m[a][1][i], n2 = P.m[a][2][i];
+      const real G0 = P.H[a][0][i], G1 = P.H[a][1][i], G2 = P.H[a][2][i];
+      const double s0 = (double)m0 - n0, s1 = (double)m1 - n1, s2 = (double)m2 - n2;
+      const double y0 = (double)(m1 * Hz - m2 * Hy) - (double)(n1 * G2 - n2 * G1);
+      const double y1 = (double)(m2 * Hx - m0 * Hz) - (double)(n2 * G0 - n0 * G2);
+      const double y2 = (double)(m0 * Hy - m1 * Hx) - (double)(n0 * G1 - n1 * G0);
+      acc[FP_SS] += V * (s0 * s0 + s1 * s1 + s2 * s2);
+      acc[FP_SY] += V * (s0 * y0 + s1 * y1 + s2 * y2);
+      acc[FP_YY] += V * (y0 * y0 + y1 * y1 + y2 * y2);
+      acc[FP_MX] += V * (double)m0;
+      acc[FP_MY] += V * (double)m1;
+      acc[FP_MZ] += V * (double)m2;
+    }
+  }
+}
+
+__device__ __forceinline__ int n_parts(int phase) {
+  return phase == PH_PREP ? 4 : phase == PH_PCG_A ? 1 : phase == PH_PCG_B ? 3 : kNPart;
+}
+
+__device__ void push_hist(Ctrl* C, double e) {
+  const int M = C->nonmono_M;
+  C->hist[C->hist_pos] = e;
+  C->hist_pos = (C->hist_pos + 1) % M;
+  if (C->hist_n < M) C->hist_n++;
+}
+
+__device__ void accept_trial(Ctrl* C, const double* v, double e_t, const double* eterm) {
+  C->acc = 1 - C->acc;
+  C->e_acc = e_t;
+  C->T_acc = v[FP_TMAX];
+  C->d_acc = v[FP_D];
+  C->h2_acc = v[FP_H2];
+  for (int k = 0; k < 4; ++k) C->eterm_acc[k] = eterm[k];
+  C->mavg_acc[0] = v[FP_MX] / C->vol;
+  C->mavg_acc[1] = v[FP_MY] / C->vol;
+  C->mavg_acc[2] = v[FP_MZ] / C->vol;
+  push_hist(C, e_t);
+}
+
+__device__ void finish_done(Ctrl* C, int status) {
+  C->status = status;
+  C->phase = PH_DONE;
+}
+
+template <typename real>
+__device__ __forceinline__ void signal_done(const Prob<real>& P, const Ctrl* C) {
+  if (P.ndone && C->phase == PH_DONE) {
+    const unsigned k = atomicAdd(P.ndone, 1u);
+    if (P.done_list) P.done_list[k] = P.slot;
+  }
+}
+
+// Step-length logic after an evaluated trial (Method section, step length
+// selection): acceptance against the nonmonotone reference, Armijo
+// backtracking for the first step and for rejected BB steps, then the BB
+// step lengths tau1 = s.s/s.y, tau2 = s.y/y.y (eq. (9)) chosen by the rule.
+__device__ void step_logic(Ctrl* C, const double* v) {
+  const bool anis = C->terms & MMSD_ANIS;
+  double eterm[4] = {v[FP_EEX], v[FP_EAN] + (anis ? C->c_an : 0.0), v[FP_EZ],
+                     v[FP_ED] + (C->demag ? 0.5 * C->ru : 0.0)};
+  const double e_t = eterm[0] + eterm[1] + eterm[2] + eterm[3];
+  C->evals++;
+  if (!isfinite(e_t) || !isfinite(v[FP_TMAX])) {
+    finish_done(C, MMSD_E_NONFINITE);
+    return;
+  }
+  if (C->stage == ST_EVAL) {
+    accept_trial(C, v, e_t, eterm);
+    finish_done(C, MMSD_OK);
+    return;
+  }
+  if (C->stage == ST_INIT) {
+    accept_trial(C, v, e_t, eterm);
+    if (C->T_acc < C->tol) {
+      finish_done(C, MMSD_OK);
+      return;
+    }
+    C->tau = C->theta0 / C->T_acc;
+    C->first = 1;
+    C->backtrack = 0;
+    C->kappa = C->kappa0;
+    C->win_n = 0;
+    C->win_pos = 0;
+    C->alt = 0;
+    C->stage = ST_RUN;
+    C->phase = PH_PREP;
+    return;
+  }
+  double e_ref = C->hist[0];
+  for (int k = 1; k < C->hist_n; ++k) e_ref = fmax(e_ref, C->hist[k]);
+  const bool armijo = C->first || C->backtrack;
+  const bool ok = armijo ? (e_t <= e_ref - C->c1 * C->tau * C->d_acc) : (e_t <= e_ref);
+  if (!ok) {
+    if (C->evals >= C->max_evals) {
+      finish_done(C, MMSD_W_MAXEVALS);
+      return;
+    }
+    C->tau *= C->rho;
+    C->backtrack = 1;
+    if (C->tau < C->tau_floor) {
+      finish_done(C, MMSD_W_FLOOR);
+      return;
+    }
+    C->phase = PH_PREP;
+    return;
+  }
+  const double ss = v[FP_SS], sy = v[FP_SY], yy = v[FP_YY];
+  accept_trial(C, v, e_t, eterm);
+  C->iters++;
+  if (C->T_acc < C->tol) {
+    finish_done(C, MMSD_OK);
+    return;
+  }
+  if (C->evals >= C->max_evals) {
+    finish_done(C, MMSD_W_MAXEVALS);
+    return;
+  }
+  C->first = 0;
+  C->backtrack = 0;
+  double tau = C->tau;
+  if (sy <= 0.0) {
+    tau = fmin(10.0 * tau, C->tau_max);
+  } else {
+    const double t1 = ss / sy, t2 = sy / yy;
+    switch (C->step_rule) {
+      case MMSD_STEP_BB1:
+        tau = t1;
+        break;
+      case MMSD_STEP_BB2:
+        tau = t2;
+        break;
+      case MMSD_STEP_ALTERNATE:
+        tau = (C->alt & 1) ? t2 : t1;
+        C->alt ^= 1;
+        break;
+      default: {
+        // adaptive switching (min of the last 3 tau2 when tau2/tau1 < kappa)
+        const int W = 3;
+        C->win[C->win_pos] = t2;
+        C->win_pos = (C->win_pos + 1) % W;
+        if (C->win_n < W) C->win_n++;
+        if (t2 / t1 < C->kappa) {
+          double mn = C->win[0];
+          for (int k = 1; k < C->win_n; ++k) mn = fmin(mn, C->win[k]);
+          tau = mn;
+          C->kappa *= 0.9;
+        } else {
+          tau = t1;
+          C->kappa *= 1.1;
+        }
+      }
+    }
+  }
+  C->tau = fmin(fmax(tau, C->tau_min), C->tau_max);
+  C->phase = PH_PREP;
+}
+
+template <typename real>
+__device__ void finish(Ctrl* C, int phase, const double* v) {
+  C->launches_done++;
+  C->nphase[phase - PH_PREP]++;
+  switch (phase) {
+    case PH_PREP:
+      if (!C->demag) {
+        C->ru = 0;
+        C->phase = PH_FIELD;
+        return;
+      }
+      C->rz = v[0];
+      C->bb = v[1];
+      C->rr = v[2];
+      C->ru = v[3];
+      C->pcg_it = 0;
+      if (C->rr <= C->pcg_rtol2 * C->bb) {
+        C->phase = PH_FIELD;
+      } else {
+        C->beta = 0.0;
+        C->phase = PH_PCG_A;
+      }
+      return;
+    case PH_PCG_A:
+      C->pq = v[0];
+      C->alpha = C->rz / C->pq;
+      C->pcur ^= 1;
+      C->phase = PH_PCG_B;
+      return;
+    case PH_PCG_B:
+      C->beta = v[0] / C->rz;
+      C->rz = v[0];
+      C->rr = v[1];
+      C->ru = v[2];
+      C->pcg_it++;
+      C->pcg_total++;
+      C->phase = (C->rr <= C->pcg_rtol2 * C->bb || C->pcg_it >= C->pcg_maxit) ? PH_FIELD : PH_PCG_A;
+      return;
+    case PH_FIELD:
+      step_logic(C, v);
+      return;
+  }
+}
+
+template <typename real, int LPR>
+__global__ void __launch_bounds__(kBlock) k_step(const Prob<real>* __restrict__ probs, int nprob,
+                                                 const int* __restrict__ blk_start) {
+  __shared__ double s_red[kBlock / 64][kNPart];
+  __shared__ double s_tot[kNPart];
+  __shared__ int s_last;
+  const int b = blockIdx.x;
+  int lo = 0, hi = nprob;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (blk_start[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  const Prob<real>& P = probs[lo];
+  Ctrl* C = P.ctrl;
+  const int phase = C->phase;
+  if (phase == PH_IDLE || phase == PH_DONE) return;
+  const int lb = b - P.blk0;
+  const int t = (lb & 7) * (P.G >> 3) + (lb >> 3);
+
+  double acc[kNPart];
+#pragma unroll
+  for (int k = 0; k < kNPart; ++k) acc[k] = 0.0;
+  switch (phase) {
+    case PH_PREP:
+      phase_prep<real, LPR>(P, C, t, acc);
+      break;
+    case PH_PCG_A:
+      phase_pcg_a<real, LPR>(P, C, t, acc);
+      break;
+    case PH_PCG_B:
+      phase_pcg_b<real>(P, C, t, acc);
+      break;
+    case PH_FIELD:
+      phase_field<real, LPR>(P, C, t, acc);
+      break;
+  }
+
+  // block partials: butterfly in each wave, then the waves in order
+  const int np = n_parts(phase);
+  const int wid = threadIdx.x >> 6, lid = threadIdx.x & 63;
+  for (int k = 0; k < np; ++k) {
+    const double v = (phase == PH_FIELD && k == FP_TMAX) ? wave_max(acc[k]) : wave_sum(acc[k]);
+    if (lid == 0) s_red[wid][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < np) {
+    const int k = threadIdx.x;
+    const bool mx = (phase == PH_FIELD && k == FP_TMAX);
+    double v = s_red[0][k];
+    for (int w = 1; w < kBlock / 64; ++w) v = mx ? fmax(v, s_red[w][k]) : v + s_red[w][k];
+    P.part[(size_t)lb * kNPart + k] = v;
+  }
+  __threadfence();
+  __syncthreads();
+  const int g = lb / kGroup;
+  const int gsize = min(kGroup, P.G - g * kGroup);
+  if (threadIdx.x == 0) s_last = (atomicAdd(&P.cnt[1 + g], 1u) == (unsigned)(gsize - 1));
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  if (threadIdx.x < np) {
+    const int k = threadIdx.x;
+    const bool mx = (phase == PH_FIELD && k == FP_TMAX);
+    const double* src = P.part + (size_t)g * kGroup * kNPart + k;
+    double v = src[0];
+    for (int q = 1; q < gsize; ++q) v = mx ? fmax(v, src[(size_t)q * kNPart]) : v + src[(size_t)q * kNPart];
+    P.gpart[(size_t)g * kNPart + k] = v;
+  }
+  if (threadIdx.x == 0) P.cnt[1 + g] = 0u;
+  __threadfence();
+  __syncthreads();
+  const int ng = (P.G + kGroup - 1) / kGroup;
+  if (threadIdx.x == 0) s_last = (atomicAdd(&P.cnt[0], 1u) == (unsigned)(ng - 1));
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  if (threadIdx.x < np) {
+    const int k = threadIdx.x;
+    const bool mx = (phase == PH_FIELD && k == FP_TMAX);
+    double v = P.gpart[k];
+    for (int q = 1; q < ng; ++q) v = mx ? fmax(v, P.gpart[(size_t)q * kNPart + k]) : v + P.gpart[(size_t)q * kNPart + k];
+    s_tot[k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    P.cnt[0] = 0u;
+    finish<real>(C, phase, s_tot);
+    signal_done<real>(P, C);
+  }
+}
+
+// Arm a problem for a new minimization or evaluation.
+struct CtrlInit {
+  int stage, terms, nonmono_M, step_rule, pcg_maxit, store_h, demag, acc;
+  long long max_evals;
+  double tol, pcg_rtol2, c1, rho, kappa0, theta0, tau_min, tau_max, tau_floor;
+  double bz[3], c_an, vol;
+};
+
+__global__ void k_ctrl_init(Ctrl* C, CtrlInit a) {
+  if (threadIdx.x != 0) return;
+  C->phase = PH_PREP;
+  C->stage = a.stage;
+  C->acc = a.acc;
+  C->pcur = 0;
+  C->first = 0;
+  C->backtrack = 0;
+  C->status = 0;
+  C->pcg_it = 0;
+  C->hist_n = 0;
+  C->hist_pos = 0;
+  C->win_n = 0;
+  C->win_pos = 0;
+  C->terms = a.terms;
+  C->nonmono_M = a.nonmono_M;
+  C->step_rule = a.step_rule;
+  C->alt = 0;
+  C->pcg_maxit = a.pcg_maxit;
+  C->store_h = a.store_h;
+  C->demag = a.demag;
+  C->evals = 0;
+  C->iters = 0;
+  C->pcg_total = 0;
+  C->max_evals = a.max_evals;
+  C->launches_done = 0;
+  for (int k = 0; k < 4; ++k) C->nphase[k] = 0;
+  C->tol = a.tol;
+  C->pcg_rtol2 = a.pcg_rtol2;
+  C->c1 = a.c1;
+  C->rho = a.rho;
+  C->kappa0 = a.kappa0;
+  C->theta0 = a.theta0;
+  C->tau_min = a.tau_min;
+  C->tau_max = a.tau_max;
+  C->tau_floor = a.tau_floor;
+  for (int k = 0; k < 3; ++k) C->bz[k] = a.bz[k];
+  C->c_an = a.c_an;
+  C->vol = a.vol;
+  C->tau = 0.0;
+  C->kappa = a.kappa0;
+  C->rz = C->pq = C->bb = C->rr = C->ru = C->alpha = C->beta = 0.0;
+}
+
+}  // namespace
+
+// ---- host-side launch wrappers -------------------------------------------
+template <typename real>
+hipError_t launch_step(int lpr, const Prob<real>* probs, int nprob, const int* blk_start, int grid,
+                       hipStream_t s) {
+  switch (lpr) {
+    case 4:
+      hipLaunchKernelGGL((k_step<real, 4>), dim3(grid), dim3(kBlock), 0, s, probs, nprob, blk_start);
+      break;
+    case 16:
+      hipLaunchKernelGGL((k_step<real, 16>), dim3(grid), dim3(kBlock), 0, s, probs, nprob, blk_start);
+      break;
+    default:
+      hipLaunchKernelGGL((k_step<real, 8>), dim3(grid), dim3(kBlock), 0, s, probs, nprob, blk_start);
+      break;
+  }
+  return hipGetLastError();
+}
+
+template hipError_t launch_step<double>(int, const Prob<double>*, int, const int*, int, hipStream_t);
+template hipError_t launch_step<float>(int, const Prob<float>*, int, const int*, int, hipStream_t);
+
+hipError_t launch_ctrl_init(Ctrl* C, int stage, int terms, int nonmono_M, int step_rule, int pcg_maxit,
+                            int store_h, int demag, int acc, long long max_evals, const double* dparams,
+                            hipStream_t s) {
+  CtrlInit a;
+  a.stage = stage;
+  a.terms = terms;
+  a.nonmono_M = nonmono_M;
+  a.step_rule = step_rule;
+  a.pcg_maxit = pcg_maxit;
+  a.store_h = store_h;
+  a.demag = demag;
+  a.acc = acc;
+  a.max_evals = max_evals;
+  a.tol = dparams[0];
+  a.pcg_rtol2 = dparams[1];
+  a.c1 = dparams[2];
+  a.rho = dparams[3];
+  a.kappa0 = dparams[4];
+  a.theta0 = dparams[5];
+  a.tau_min = dparams[6];
+  a.tau_max = dparams[7];
+  a.tau_floor = dparams[8];
+  a.bz[0] = dparams[9];
+  a.bz[1] = dparams[10];
+  a.bz[2] = dparams[11];
+  a.c_an = dparams[12];
+  a.vol = dparams[13];
+  hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, s, C, a);
+  return hipGetLastError();
+}
+
+}  // namespace mmsd

@@ -1,0 +1,111 @@
+// Host runtime objects behind the C ABI: contexts, problems, batched runs.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <chrono>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "assemble.h"
+#include "device.h"
+#include "mmsd.h"
+
+namespace mmsd {
+
+void set_error(const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define MMSD_HIP(call)                         \
+  do {                                         \
+    hipError_t _e = (call);                    \
+    if (_e != hipSuccess) return hip_fail(_e, #call); \
+  } while (0)
+
+template <typename real>
+hipError_t launch_step(int lpr, const Prob<real>* probs, int nprob, const int* blk_start, int grid,
+                       hipStream_t s);
+hipError_t launch_ctrl_init(Ctrl* C, int stage, int terms, int nonmono_M, int step_rule, int pcg_maxit,
+                            int store_h, int demag, int acc, long long max_evals, const double* dparams,
+                            hipStream_t s);
+
+struct Resolved {
+  double tol, rtol;
+  int64_t max_evals;
+  int terms, M, rule, maxit;
+  double refine;
+};
+
+// One launch table: nprob problems of one precision.
+struct Table {
+  int precision;
+  const void* dprobs;
+  const int* dblk;
+  int nprob, grid, lpr;
+};
+
+struct TimingState {
+  int stride = 0;                      // 0 = off
+  double ms = 0, count = 0, bytes = 0;
+  std::vector<hipEvent_t> pool;        // free events
+  std::vector<hipEvent_t> pending;     // recorded (start, end) pairs not yet read
+};
+
+}  // namespace mmsd
+
+struct mmsd_ctx_s;
+struct mmsd_problem_s;
+
+namespace mmsd {
+int resolve(mmsd_problem_s* p, const mmsd_options* o, Resolved* r);
+int arm(mmsd_problem_s* p, const Resolved& r, int stage, int store_h);
+int launch_table(const Table& t, hipStream_t st);
+void fill_result(mmsd_problem_s* p, const Ctrl& C, mmsd_result* out, double secs, int64_t launches);
+int ensure_pinned(mmsd_problem_s* p);
+int issue(mmsd_ctx_s* c, const std::vector<Table>& tabs, int B, std::map<int, hipGraphExec_t>* graphs);
+double run_bytes(mmsd_problem_s* p, const Ctrl& C);
+}  // namespace mmsd
+
+struct mmsd_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  mmsd_alloc_fn alloc = nullptr;
+  mmsd_free_fn free_fn = nullptr;
+  void* user = nullptr;
+  int lpr = 8;
+  int max_blocks = 2048;
+  bool use_graph = true;
+  mmsd::TimingState timing;
+  std::mutex mu;            // serializes device work issued through this context
+  void* dalloc(size_t bytes);
+  void dfree(void* p);
+};
+
+struct mmsd_problem_s {
+  mmsd_ctx ctx = nullptr;
+  int precision = MMSD_FP64;
+  mmsd::Assembly A;
+  // device arena
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  // descriptor (host copy; device copy at dprob) and launch table
+  alignas(16) unsigned char desc[sizeof(mmsd::Prob<double>)];
+  void* dprob = nullptr;     // device Prob<real>
+  int* dblk = nullptr;       // device blk_start [2]
+  mmsd::Ctrl* dctrl = nullptr;
+  void* snap[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [set][m | u]
+  int G = 0, lpr = 8;
+  int acc = 0;
+  bool h_valid = false;
+  double b_ext[3] = {0, 0, 0};
+  double phase_bytes[4] = {0, 0, 0, 0};   // algorithmic bytes per executed phase
+  double phase_bytes_h = 0;               // extra FIELD bytes when h is stored
+  double prep_bytes_nodemag = 0;
+  mmsd::Ctrl* hctrl = nullptr;            // pinned mirrors [2]
+  std::map<int, hipGraphExec_t> graphs;   // batch size -> instantiated graph
+  int64_t last_launches = 0;
+};

@@ -1,0 +1,157 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances: the FP64 path matches the oracle to 1e-10 relative in energy
+(relative to the sum of the magnitudes of the four energy terms, so a total
+that crosses zero stays meaningful) and to 1e-10 relative in the field when
+the potential solve is converged to 1e-14; the mixed path (FP32 storage and
+SpMV, FP64 reductions) to 1e-6 relative in energy.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.fem import ANIS, DEMAG, EXCH, ZEEM
+from oracle.minimize import Options
+from paper_1309_5796_amd import meshgen
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1309_5796_amd import binding
+    say("context create")
+    c = binding.Context(0)
+    yield c
+    c.close()
+
+
+def rel_energy_err(E_gpu, ev):
+    scale = sum(abs(ev[k]) for k in ("E_ex", "E_an", "E_Z", "E_d"))
+    return abs(E_gpu - ev["E"]) / scale
+
+
+def test_evaluate_matches_oracle_config1(ctx, cfg1, cfg1_system):
+    from paper_1309_5796_amd import binding
+    say("evaluate config1 fp64")
+    s = cfg1_system
+    rng = np.random.default_rng(11)
+    m = cfg1["m0"] + 0.3 * rng.normal(size=cfg1["m0"].shape)
+    m /= np.linalg.norm(m, axis=1, keepdims=True)
+    p = binding.Problem(ctx, cfg1["mesh"])
+    assert p.N == s.N and p.Nt == s.Nt
+    p.set_m(m)
+    p.set_field(cfg1["b_ext"])
+    r = p.evaluate(pcg_rtol=1e-14)
+    ev = s.evaluate(m, cfg1["b_ext"])
+    assert rel_energy_err(r.energy_J, ev) < 1e-12
+    for k_gpu, k_or in (("e_exch_J", "E_ex"), ("e_anis_J", "E_an"), ("e_zeem_J", "E_Z"), ("e_demag_J", "E_d")):
+        assert abs(getattr(r, k_gpu) - ev[k_or]) <= 1e-12 * abs(ev[k_or]) + 1e-30, k_gpu
+    h = p.get_field()
+    assert np.abs(h - ev["h"]).max() < 1e-10 * np.abs(ev["h"]).max()
+    u = p.get_potential()
+    u_or = np.zeros(cfg1["mesh"].n_nodes)
+    u_or[s.free] = ev["u"]
+    assert np.abs(u - u_or).max() < 1e-10 * np.abs(u_or).max()
+    H = np.cross(m, ev["h"])
+    assert abs(r.max_torque - np.linalg.norm(H, axis=1).max()) < 1e-10 * r.max_torque
+    np.testing.assert_allclose(r.m_avg, s.mean_m(m), rtol=0, atol=1e-14)
+    p.close()
+
+
+@pytest.mark.parametrize("terms", [EXCH, ANIS, ZEEM, DEMAG, EXCH | ANIS | ZEEM])
+def test_evaluate_single_terms(ctx, cfg1, cfg1_system, terms):
+    from paper_1309_5796_amd import binding
+    say(f"evaluate config1 terms={terms}")
+    s = cfg1_system
+    rng = np.random.default_rng(12)
+    m = rng.normal(size=(s.N, 3))
+    m /= np.linalg.norm(m, axis=1, keepdims=True)
+    p = binding.Problem(ctx, cfg1["mesh"])
+    p.set_m(m)
+    p.set_field(cfg1["b_ext"])
+    r = p.evaluate(pcg_rtol=1e-14, terms=terms)
+    ev = s.evaluate(m, cfg1["b_ext"], terms)
+    assert abs(r.energy_J - ev["E"]) <= 1e-12 * max(abs(ev[k]) for k in ("E_ex", "E_an", "E_Z", "E_d"))
+    h = p.get_field()
+    assert np.abs(h - ev["h"]).max() <= 1e-10 * max(np.abs(ev["h"]).max(), 1e-300)
+    p.close()
+
+
+def test_minimize_config1_fp64_matches_oracle(ctx, cfg1, cfg1_system):
+    from paper_1309_5796_amd import binding
+    say("minimize config1 fp64")
+    s = cfg1_system
+    ro = oracle.minimize(s, cfg1["m0"], cfg1["b_ext"], Options())
+    p = binding.Problem(ctx, cfg1["mesh"])
+    p.set_m(cfg1["m0"])
+    p.set_field(cfg1["b_ext"])
+    r = p.minimize()
+    assert r.status == 0 and r.max_torque < 1e-6
+    ev = s.evaluate(ro.m, cfg1["b_ext"])
+    assert rel_energy_err(r.energy_J, ev) < 1e-10
+    m = p.get_m()
+    assert np.abs(np.linalg.norm(m, axis=1) - 1).max() < 1e-12
+    assert np.abs(m - ro.m).max() < 1e-5
+    assert abs(r.iterations - ro.iterations) <= 3
+    say(f"gpu iters={r.iterations} evals={r.evals} pcg={r.pcg_iters} oracle iters={ro.iterations}")
+    p.close()
+
+
+def test_minimize_config1_mixed_matches_oracle(ctx, cfg1, cfg1_system):
+    from paper_1309_5796_amd import binding
+    say("minimize config1 mixed")
+    s = cfg1_system
+    ro = oracle.minimize(s, cfg1["m0"], cfg1["b_ext"], Options())
+    p = binding.Problem(ctx, cfg1["mesh"], precision=binding.MIXED)
+    p.set_m(cfg1["m0"])
+    p.set_field(cfg1["b_ext"])
+    r = p.minimize()
+    assert r.status in (0, 2)
+    ev = s.evaluate(ro.m, cfg1["b_ext"])
+    assert rel_energy_err(r.energy_J, ev) < 1e-6
+    m = p.get_m()
+    assert np.abs(np.linalg.norm(m, axis=1) - 1).max() < 1e-6
+    p.close()
+
+
+def test_fp64_runs_are_bitwise_repeatable(ctx, cfg1):
+    from paper_1309_5796_amd import binding
+    say("repeatability config1")
+    out = []
+    for _ in range(3):
+        p = binding.Problem(ctx, cfg1["mesh"])
+        p.set_m(cfg1["m0"])
+        p.set_field(cfg1["b_ext"])
+        r = p.minimize()
+        out.append((r.energy_J, r.iterations, r.evals, r.pcg_iters, p.get_m().tobytes()))
+        p.close()
+    assert out[0] == out[1] == out[2]
+
+
+def test_stoner_wohlfarth_cube_without_stray_field(ctx):
+    """Demag off: the oracle's uniform-rotation cube; GPU minimum equals the
+    oracle's at a field below switching."""
+    from paper_1309_5796_amd import binding
+    say("SW cube no demag")
+    mesh = meshgen.kuhn_box((1e-9,) * 3, (2, 2, 2), air=False)
+    s = oracle.System(mesh)
+    u = meshgen.U_H_1DEG
+    B = -6.5 * u
+    m0 = np.tile([0.0, 0.0, 1.0], (s.N, 1))
+    terms = EXCH | ANIS | ZEEM
+    ro = oracle.minimize(s, m0, B, Options(terms=terms, tol=1e-9))
+    p = binding.Problem(ctx, mesh)
+    p.set_field(B)
+    r = p.minimize(terms=terms, tol=1e-9)
+    assert r.status == 0
+    assert abs(r.energy_J - ro.E) < 1e-10 * abs(ro.E)
+    np.testing.assert_allclose(p.get_m(), ro.m, atol=1e-8)
+    p.close()
