@@ -11,6 +11,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 from dataclasses import dataclass, field
 from typing import List, Optional, Sequence
 
@@ -217,6 +218,7 @@ class Context:
         _check(rc)
         self.handle = h
         self.lib = lib
+        self._children = weakref.WeakSet()   # problems and servers to close first
 
     def set_launch_config(self, lanes_per_row: int = 0, max_blocks: int = 0):
         _check(self.lib.mmsd_set_launch_config(self.handle, lanes_per_row, max_blocks))
@@ -231,6 +233,8 @@ class Context:
 
     def close(self):
         if getattr(self, "handle", None):
+            for ch in list(self._children):
+                ch.close()
             self.lib.mmsd_ctx_destroy(self.handle)
             self.handle = None
 
@@ -284,6 +288,7 @@ class Problem:
         h = C.c_void_p()
         _check(self.lib.mmsd_problem_create(ctx.handle, C.byref(a.c), a.mats, a.n_mats, precision, C.byref(h)))
         self.handle = h
+        ctx._children.add(self)
         self.precision = precision
         self.n_nodes = a.xyz.shape[0]
         n = C.c_int64()
@@ -382,6 +387,7 @@ class Server:
         h = C.c_void_p()
         _check(self.lib.mmsd_server_create(ctx.handle, hbm_budget, max_slots, C.byref(h)))
         self.handle = h
+        ctx._children.add(self)
 
     def submit(self, mesh, b_ext, precision: int = FP64, m0=None, materials=None, **opts) -> int:
         a = MeshArgs(mesh, materials)

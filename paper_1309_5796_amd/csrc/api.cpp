@@ -476,8 +476,9 @@ int copy_m_to_host(mmsd_problem p, double* m_out) {
   return MMSD_OK;
 }
 
+// normalize = false restores a checkpointed m bit for bit.
 template <typename real>
-int copy_m_to_device(mmsd_problem p, const double* m) {
+int copy_m_to_device(mmsd_problem p, const double* m, bool normalize) {
   const Prob<real>& P = desc_of<real>(p);
   const int N = p->A.N;
   std::vector<real> tmp(3 * (size_t)N);
@@ -485,9 +486,10 @@ int copy_m_to_device(mmsd_problem p, const double* m) {
     const double x = m[3 * (size_t)i], y = m[3 * (size_t)i + 1], z = m[3 * (size_t)i + 2];
     const double n = std::sqrt(x * x + y * y + z * z);
     if (!(n > 0) || !std::isfinite(n)) return invalid("zero or non-finite magnetization at node " + std::to_string(i));
-    tmp[i] = (real)(x / n);
-    tmp[(size_t)N + i] = (real)(y / n);
-    tmp[2 * (size_t)N + i] = (real)(z / n);
+    const double s = normalize ? 1.0 / n : 1.0;
+    tmp[i] = (real)(normalize ? x / n : x * s);
+    tmp[(size_t)N + i] = (real)(normalize ? y / n : y * s);
+    tmp[2 * (size_t)N + i] = (real)(normalize ? z / n : z * s);
   }
   hipStream_t st = p->ctx->stream;
   for (int k = 0; k < 3; ++k)
@@ -603,7 +605,7 @@ int mmsd_set_launch_config(mmsd_ctx c, int lanes_per_row, int max_blocks) {
   if (lanes_per_row && lanes_per_row != 4 && lanes_per_row != 8 && lanes_per_row != 16)
     return invalid("lanes_per_row must be 4, 8 or 16");
   if (max_blocks && (max_blocks < 8 || max_blocks > kMaxBlocks || max_blocks % 8))
-    return invalid("max_blocks must be a multiple of 8 in [8, 4096]");
+    return invalid("max_blocks must be a multiple of 8 in [8, 65536]");
   if (lanes_per_row) c->lpr = lanes_per_row;
   if (max_blocks) c->max_blocks = max_blocks;
   return MMSD_OK;
@@ -633,7 +635,7 @@ int mmsd_footprint(const mmsd_mesh* mesh, int precision, size_t* bytes_out) {
     set_error(err);
     return rc;
   }
-  const int G = blocks_for(std::max(ps.N, ps.Nt), 8, 2048);
+  const int G = blocks_for(std::max(ps.N, ps.Nt), 8, kMaxBlocks);
   *bytes_out = make_layout(ps.N, ps.nnzM, ps.Nt, ps.nnzL, G, precision == MMSD_MIXED ? 4 : 8).total;
   return MMSD_OK;
 }
@@ -734,7 +736,7 @@ int mmsd_set_m(mmsd_problem p, const double* m) {
   if (!p || !m) return invalid("null argument");
   std::lock_guard<std::mutex> lk(p->ctx->mu);
   hipSetDevice(p->ctx->device);
-  return p->precision == MMSD_MIXED ? copy_m_to_device<float>(p, m) : copy_m_to_device<double>(p, m);
+  return p->precision == MMSD_MIXED ? copy_m_to_device<float>(p, m, true) : copy_m_to_device<double>(p, m, true);
 }
 
 int mmsd_get_m(mmsd_problem p, double* m_out) {
@@ -1041,7 +1043,13 @@ int mmsd_set_state(mmsd_problem p, const void* buf, size_t bytes) {
     return invalid("state does not match this problem");
   double bf[3];
   std::memcpy(bf, b + 40, 24);
-  int rc = mmsd_set_m(p, (const double*)(b + 64));
+  int rc;
+  {
+    std::lock_guard<std::mutex> lk(p->ctx->mu);
+    hipSetDevice(p->ctx->device);
+    rc = p->precision == MMSD_MIXED ? copy_m_to_device<float>(p, (const double*)(b + 64), false)
+                                    : copy_m_to_device<double>(p, (const double*)(b + 64), false);
+  }
   if (rc) return rc;
   mmsd_set_field(p, bf);
   if (Nt) {

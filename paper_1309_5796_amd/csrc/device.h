@@ -28,10 +28,10 @@ enum Phase : int { PH_IDLE = 0, PH_PREP = 1, PH_PCG_A = 2, PH_PCG_B = 3, PH_FIEL
 enum Stage : int { ST_INIT = 0, ST_RUN = 1, ST_EVAL = 2 };
 
 constexpr int kBlock = 256;        // threads per block (4 wavefronts of 64)
-constexpr int kGroup = 32;         // blocks per first-level reduction group
+constexpr int kGroup = 64;         // blocks per first-level reduction group
 constexpr int kNPart = 13;         // partial sums per block (FIELD needs 13)
 constexpr int kMaxHist = 64;       // nonmonotone memory capacity
-constexpr int kMaxBlocks = 4096;   // per problem
+constexpr int kMaxBlocks = 1 << 16;  // per problem
 constexpr int kMaxGroups = kMaxBlocks / kGroup;
 
 // FIELD partial slots

@@ -3,16 +3,18 @@
 // One launch advances every unfinished problem of a table by one phase (see
 // device.h).  Work layout:
 //  * CSR rows are split over `LPR` lanes (4, 8 or 16) of a 64-wide wavefront;
-//    a block of 256 threads walks a contiguous chunk of rows in passes of
-//    256/LPR rows.  Column indices and values stream coalesced; node vectors
-//    are gathered (they stay in L2: every entry is reused by ~15 rows).
+//    a block of 256 threads takes one tile of 256/LPR rows, so a launch has
+//    about rows/tile blocks and the hardware keeps many row tiles in flight
+//    (the loop over passes only runs when a problem is capped in blocks).
+//    Column indices and values stream coalesced; node vectors are gathered
+//    (they stay in L2: every entry is reused by ~15 rows).
 //  * Block b of a problem takes chunk (b % 8) * (G / 8) + b / 8: blocks are
 //    dealt to the 8 XCDs round-robin, so this gives each XCD one contiguous
 //    eighth of the rows and keeps neighbour gathers inside its own L2.
 //  * Reductions are deterministic: wavefront butterfly, then the 4 waves in
-//    order, then per-block partials summed in block order by the last block
-//    of each group of 32, then the group partials in group order by the last
-//    group.  That last block also runs the phase transition and, after a
+//    order, then the per-block partials of each group of 64 blocks combined by
+//    the group's last block (lanes load in parallel, fixed butterfly), then
+//    the group partials the same way by the last group.  That last block also runs the phase transition and, after a
 //    FIELD phase, the step-length logic.
 // All node arrays are structure-of-arrays.
 #include <hip/hip_runtime.h>
@@ -30,6 +32,16 @@ __device__ __forceinline__ T group_sum(T v) {
 #pragma unroll
   for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
   return v;
+}
+
+template <typename T>
+__device__ __forceinline__ void store_agent(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__device__ __forceinline__ T load_agent(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -474,6 +486,23 @@ __device__ void finish(Ctrl* C, int phase, const double* v) {
   }
 }
 
+// out[k] = sum (max for the torque slot) over q < n of src[q * kNPart + k],
+// k < np.  Wavefront w takes slots w, w + 4, ...; each lane loads up to
+// n / 64 values with agent-scope loads, then a butterfly combines the lanes.
+__device__ void reduce_slots(const double* src, int n, int np, int phase, double* out) {
+  const int wid = threadIdx.x >> 6, lid = threadIdx.x & 63;
+  for (int k = wid; k < np; k += kBlock / 64) {
+    const bool mx = (phase == PH_FIELD && k == FP_TMAX);
+    double v = 0.0;
+    for (int q = lid; q < n; q += 64) {
+      const double x = load_agent(src + (size_t)q * kNPart + k);
+      v = mx ? fmax(v, x) : v + x;
+    }
+    v = mx ? wave_max(v) : wave_sum(v);
+    if (lid == 0) out[k] = v;
+  }
+}
+
 template <typename real, int LPR>
 __global__ void __launch_bounds__(kBlock) k_step(const Prob<real>* __restrict__ probs, int nprob,
                                                  const int* __restrict__ blk_start) {
@@ -520,47 +549,39 @@ __global__ void __launch_bounds__(kBlock) k_step(const Prob<real>* __restrict__ 
     if (lid == 0) s_red[wid][k] = v;
   }
   __syncthreads();
+  // Publication protocol: partials are written with agent-scope atomic
+  // stores (write-through to memory, no L2 write-back of the whole cache),
+  // the wave waits for their completion, and only then bumps the counter.
+  // The last arriver reads them back with agent-scope atomic loads.
   if (threadIdx.x < np) {
     const int k = threadIdx.x;
     const bool mx = (phase == PH_FIELD && k == FP_TMAX);
     double v = s_red[0][k];
     for (int w = 1; w < kBlock / 64; ++w) v = mx ? fmax(v, s_red[w][k]) : v + s_red[w][k];
-    P.part[(size_t)lb * kNPart + k] = v;
+    store_agent(&P.part[(size_t)lb * kNPart + k], v);
   }
-  __threadfence();
-  __syncthreads();
+  __builtin_amdgcn_s_waitcnt(0);
   const int g = lb / kGroup;
   const int gsize = min(kGroup, P.G - g * kGroup);
   if (threadIdx.x == 0) s_last = (atomicAdd(&P.cnt[1 + g], 1u) == (unsigned)(gsize - 1));
   __syncthreads();
   if (!s_last) return;
-  __threadfence();
-  if (threadIdx.x < np) {
-    const int k = threadIdx.x;
-    const bool mx = (phase == PH_FIELD && k == FP_TMAX);
-    const double* src = P.part + (size_t)g * kGroup * kNPart + k;
-    double v = src[0];
-    for (int q = 1; q < gsize; ++q) v = mx ? fmax(v, src[(size_t)q * kNPart]) : v + src[(size_t)q * kNPart];
-    P.gpart[(size_t)g * kNPart + k] = v;
-  }
-  if (threadIdx.x == 0) P.cnt[1 + g] = 0u;
-  __threadfence();
+  // group level: reduce the group's partials, one wavefront per slot, loads
+  // spread over the lanes (fixed butterfly order keeps it deterministic)
+  reduce_slots(P.part + (size_t)g * kGroup * kNPart, gsize, np, phase, s_tot);
+  __syncthreads();
+  if (threadIdx.x < np) store_agent(&P.gpart[(size_t)g * kNPart + threadIdx.x], s_tot[threadIdx.x]);
+  if (threadIdx.x == 0) store_agent(&P.cnt[1 + g], 0u);
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   const int ng = (P.G + kGroup - 1) / kGroup;
   if (threadIdx.x == 0) s_last = (atomicAdd(&P.cnt[0], 1u) == (unsigned)(ng - 1));
   __syncthreads();
   if (!s_last) return;
-  __threadfence();
-  if (threadIdx.x < np) {
-    const int k = threadIdx.x;
-    const bool mx = (phase == PH_FIELD && k == FP_TMAX);
-    double v = P.gpart[k];
-    for (int q = 1; q < ng; ++q) v = mx ? fmax(v, P.gpart[(size_t)q * kNPart + k]) : v + P.gpart[(size_t)q * kNPart + k];
-    s_tot[k] = v;
-  }
+  reduce_slots(P.gpart, ng, np, phase, s_tot);
   __syncthreads();
   if (threadIdx.x == 0) {
-    P.cnt[0] = 0u;
+    store_agent(&P.cnt[0], 0u);
     finish<real>(C, phase, s_tot);
     signal_done<real>(P, C);
   }

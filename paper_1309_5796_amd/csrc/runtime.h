@@ -77,7 +77,7 @@ struct mmsd_ctx_s {
   mmsd_free_fn free_fn = nullptr;
   void* user = nullptr;
   int lpr = 8;
-  int max_blocks = 2048;
+  int max_blocks = 1 << 16;
   bool use_graph = true;
   mmsd::TimingState timing;
   std::mutex mu;            // serializes device work issued through this context
