@@ -119,7 +119,7 @@ def main():
         achieved = tm["bytes"] / tm["launches"] / avg_s / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "kernel": "k_step<double,8>", "avg_launch_us": avg_s * 1e6,
+                "kernel": f"k_step<double,{args.lanes or 4}>", "avg_launch_us": avg_s * 1e6,
                 "alg_bytes_per_launch": tm["bytes"] / tm["launches"], "launches_timed": tm["launches"]}
     line = {
         "metric": METRIC, "value": value, "unit": "node-iterations/s", "n_gpus": 1,

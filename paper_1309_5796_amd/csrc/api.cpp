@@ -37,8 +37,8 @@ size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 // Layout of one problem's device arena.
 struct Layout {
   size_t mrp, mci, K, D1[3], D2[3], Q[6], V, m[2][3], H[2][3], h[3];
-  size_t lrp, lci, L, invd, u, r, z, p[2], q;
-  size_t part, gpart, cnt, ctrl, prob, blk;
+  size_t lrp, lci, L, u, p, rec[2];
+  size_t part, ctrl, prob, blk;
   size_t snap[2][2];
   size_t total;
 };
@@ -73,18 +73,11 @@ Layout make_layout(int64_t N, int64_t nnzM, int64_t Nt, int64_t nnzL, int G, siz
   L.lrp = take(4 * (Nt + 1));
   L.lci = take(4 * nnzL);
   L.L = take(s * nnzL);
-  L.invd = take(s * Nt);
   L.u = take(s * Nt);
-  L.r = take(s * Nt);
-  L.z = take(s * Nt);
-  L.p[0] = take(s * Nt);
-  L.p[1] = take(s * Nt);
-  L.q = take(s * Nt);
-  const int ng = (G + kGroup - 1) / kGroup;
-  L.part = take(8 * (size_t)G * kNPart);
-  L.gpart = take(8 * (size_t)ng * kNPart);
-  L.cnt = take(4 * (size_t)(1 + ng));
-  L.ctrl = take(sizeof(Ctrl));
+  L.p = take(s * Nt);
+  for (int k = 0; k < 2; ++k) L.rec[k] = take(4 * s * Nt);
+  L.part = take(8 * 2 * (size_t)G * kNPart);
+  L.ctrl = take(2 * sizeof(Ctrl));
   L.prob = take(sizeof(Prob<double>));
   L.blk = take(8);
   for (int k = 0; k < 2; ++k) {
@@ -129,9 +122,9 @@ void bytes_model(mmsd_problem p) {
   const Assembly& A = p->A;
   const double s = sizeof(real), N = A.N, Nt = A.Nt, zM = (double)A.mci.size(), zL = (double)A.lci.size();
   p->phase_bytes[0] = 4 * (N + 1) + 4 * zM + 3 * s * zM + 9 * s * N +            // trial m, b = D1 m
-                      4 * (Nt + 1) + 4 * zL + s * zL + 4 * s * Nt;                // r = b - L u, z
-  p->phase_bytes[1] = 4 * (Nt + 1) + 4 * zL + s * zL + 4 * s * Nt;                // q = L (z + beta p)
-  p->phase_bytes[2] = 8 * s * Nt;                                                 // u, r, z updates
+                      4 * (Nt + 1) + 4 * zL + s * zL + 2 * s * Nt;                // r = b - L u
+  p->phase_bytes[1] = 4 * (Nt + 1) + 4 * zL + s * zL + 5 * s * Nt;                // w = L D^-1 r
+  p->phase_bytes[2] = 4 * (Nt + 1) + 4 * zL + s * zL + 12 * s * Nt;               // one CG iteration
   p->phase_bytes[3] = 4 * (N + 1) + 4 * zM + 4 * s * zM + s * N * (3 + 1 + 6 + 1 + 6 + 3);
   p->phase_bytes_h = 3 * s * N;
   p->prep_bytes_nodemag = 9 * s * N;
@@ -166,7 +159,12 @@ int build_device(mmsd_problem p) {
     if ((rc = upload_vec<real>(st, base + L.Q[k], A.Q[k]))) return rc;
   if (Nt > 0) {
     if ((rc = upload_int(st, base + L.lrp, A.lrp)) || (rc = upload_int(st, base + L.lci, A.lci)) ||
-        (rc = upload_vec<real>(st, base + L.L, A.L)) || (rc = upload_vec<real>(st, base + L.invd, A.invd)))
+        (rc = upload_vec<real>(st, base + L.L, A.L)))
+      return rc;
+    // Jacobi factors live in the d field of both CG record buffers
+    std::vector<double> rec(4 * (size_t)Nt, 0.0);
+    for (int64_t i = 0; i < Nt; ++i) rec[4 * i + 3] = A.invd[i];
+    if ((rc = upload_vec<real>(st, base + L.rec[0], rec)) || (rc = upload_vec<real>(st, base + L.rec[1], rec)))
       return rc;
   }
   // initial state: m = +z in slot 0
@@ -197,17 +195,11 @@ int build_device(mmsd_problem p) {
   P.lrp = (const int*)(base + L.lrp);
   P.lci = (const int*)(base + L.lci);
   P.L = (const real*)(base + L.L);
-  P.invd = (const real*)(base + L.invd);
   P.u = (real*)(base + L.u);
-  P.r = (real*)(base + L.r);
-  P.z = (real*)(base + L.z);
-  P.p[0] = (real*)(base + L.p[0]);
-  P.p[1] = (real*)(base + L.p[1]);
-  P.q = (real*)(base + L.q);
+  P.p = (real*)(base + L.p);
+  for (int k = 0; k < 2; ++k) P.rec[k] = (Rec<real>*)(base + L.rec[k]);
   P.ndone = nullptr;
   P.part = (double*)(base + L.part);
-  P.gpart = (double*)(base + L.gpart);
-  P.cnt = (unsigned*)(base + L.cnt);
   P.ctrl = (Ctrl*)(base + L.ctrl);
   p->dctrl = P.ctrl;
   p->dprob = base + L.prob;
@@ -258,15 +250,16 @@ int arm(mmsd_problem p, const Resolved& r, int stage, int store_h) {
   const Assembly& A = p->A;
   const double dp[14] = {r.tol, r.rtol * r.rtol, 1e-4, 0.5, 0.5, 0.1, 1e-10, 1e10, 1e-14,
                          p->b_ext[0] / A.Js, p->b_ext[1] / A.Js, p->b_ext[2] / A.Js, A.c_an, A.vol};
-  MMSD_HIP(launch_ctrl_init(p->dctrl, stage, r.terms, r.M, r.rule, r.maxit, store_h,
+  MMSD_HIP(launch_ctrl_init(p->dctrl, kArmSlot, stage, r.terms, r.M, r.rule, r.maxit, store_h,
                             (r.terms & MMSD_DEMAG) ? 1 : 0, p->acc, (long long)r.max_evals, dp, p->ctx->stream));
   return MMSD_OK;
 }
 
-int launch_table(const Table& t, hipStream_t st) {
-  hipError_t e = t.precision == MMSD_MIXED
-                     ? launch_step<float>(t.lpr, (const Prob<float>*)t.dprobs, t.nprob, t.dblk, t.grid, st)
-                     : launch_step<double>(t.lpr, (const Prob<double>*)t.dprobs, t.nprob, t.dblk, t.grid, st);
+int launch_table(const Table& t, int parity, hipStream_t st) {
+  hipError_t e =
+      t.precision == MMSD_MIXED
+          ? launch_step<float>(t.lpr, (const Prob<float>*)t.dprobs, t.nprob, t.dblk, t.grid, parity, st)
+          : launch_step<double>(t.lpr, (const Prob<double>*)t.dprobs, t.nprob, t.dblk, t.grid, parity, st);
   if (e != hipSuccess) return hip_fail(e, "step launch");
   return MMSD_OK;
 }
@@ -275,6 +268,7 @@ int launch_table(const Table& t, hipStream_t st) {
 // when allowed and timing is off.
 int issue(mmsd_ctx c, const std::vector<Table>& tabs, int B, std::map<int, hipGraphExec_t>* graphs) {
   hipStream_t st = c->stream;
+  if (B <= 0 || (B & 1)) return invalid("launch batches must have an even length");
   TimingState& T = c->timing;
   if (T.stride > 0) {
     for (int b = 0; b < B; ++b)
@@ -290,7 +284,7 @@ int issue(mmsd_ctx c, const std::vector<Table>& tabs, int B, std::map<int, hipGr
           T.pool.pop_back();
         }
         MMSD_HIP(hipEventRecord(e0, st));
-        int rc = launch_table(t, st);
+        int rc = launch_table(t, b & 1, st);
         if (rc) return rc;
         MMSD_HIP(hipEventRecord(e1, st));
         T.pending.push_back(e0);
@@ -305,7 +299,7 @@ int issue(mmsd_ctx c, const std::vector<Table>& tabs, int B, std::map<int, hipGr
       MMSD_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
       for (int b = 0; b < B; ++b)
         for (const Table& t : tabs) {
-          int rc = launch_table(t, st);
+          int rc = launch_table(t, b & 1, st);
           if (rc) {
             hipStreamEndCapture(st, &g);
             return rc;
@@ -323,7 +317,7 @@ int issue(mmsd_ctx c, const std::vector<Table>& tabs, int B, std::map<int, hipGr
   }
   for (int b = 0; b < B; ++b)
     for (const Table& t : tabs) {
-      int rc = launch_table(t, st);
+      int rc = launch_table(t, b & 1, st);
       if (rc) return rc;
     }
   return MMSD_OK;
@@ -383,7 +377,7 @@ bool run_timed_out(std::chrono::steady_clock::time_point t0) {
 }
 
 int ensure_pinned(mmsd_problem p) {
-  if (!p->hctrl) MMSD_HIP(hipHostMalloc((void**)&p->hctrl, 2 * sizeof(Ctrl), hipHostMallocDefault));
+  if (!p->hctrl) MMSD_HIP(hipHostMalloc((void**)&p->hctrl, 4 * sizeof(Ctrl), hipHostMallocDefault));
   return MMSD_OK;
 }
 
@@ -409,7 +403,7 @@ int run_single(mmsd_problem p, const Resolved& r, int stage, int store_h, mmsd_r
   for (;;) {
     if ((rc = issue(c, tabs, B, &p->graphs))) break;
     launched += B;
-    if (hipMemcpyAsync(&p->hctrl[cur], p->dctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st) != hipSuccess ||
+    if (hipMemcpyAsync(&p->hctrl[2 * cur], p->dctrl, 2 * sizeof(Ctrl), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipEventRecord(ev[cur], st) != hipSuccess) {
       rc = hip_fail(hipGetLastError(), "poll copy");
       break;
@@ -420,7 +414,7 @@ int run_single(mmsd_problem p, const Resolved& r, int stage, int store_h, mmsd_r
         rc = hip_fail(e, "poll wait");
         break;
       }
-      const Ctrl& H = p->hctrl[1 - cur];
+      const Ctrl& H = latest(&p->hctrl[2 * (1 - cur)]);
       if (H.phase == PH_DONE) break;
       // every launch of an unfinished problem executes one phase; a counter
       // that stops moving means the phase machine is stuck
@@ -449,11 +443,11 @@ int run_single(mmsd_problem p, const Resolved& r, int stage, int store_h, mmsd_r
   hipEventDestroy(ev[1]);
   if (rc) return rc;
   if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  const Ctrl& C = latest(&p->hctrl[2 * cur]);
   if (c->timing.stride > 0) {
     if ((rc = drain_timing(c))) return rc;
-    c->timing.bytes += run_bytes(p, p->hctrl[cur]);
+    c->timing.bytes += run_bytes(p, C);
   }
-  const Ctrl& C = p->hctrl[cur];
   p->acc = C.acc;
   p->h_valid = store_h != 0 && C.status == MMSD_OK;
   p->last_launches = launched;
@@ -605,7 +599,7 @@ int mmsd_set_launch_config(mmsd_ctx c, int lanes_per_row, int max_blocks) {
   if (lanes_per_row && lanes_per_row != 4 && lanes_per_row != 8 && lanes_per_row != 16)
     return invalid("lanes_per_row must be 4, 8 or 16");
   if (max_blocks && (max_blocks < 8 || max_blocks > kMaxBlocks || max_blocks % 8))
-    return invalid("max_blocks must be a multiple of 8 in [8, 65536]");
+    return invalid("max_blocks must be a multiple of 8 in [8, 2048]");
   if (lanes_per_row) c->lpr = lanes_per_row;
   if (max_blocks) c->max_blocks = max_blocks;
   return MMSD_OK;
@@ -635,7 +629,7 @@ int mmsd_footprint(const mmsd_mesh* mesh, int precision, size_t* bytes_out) {
     set_error(err);
     return rc;
   }
-  const int G = blocks_for(std::max(ps.N, ps.Nt), 8, kMaxBlocks);
+  const int G = blocks_for(std::max(ps.N, ps.Nt), 4, 512);
   *bytes_out = make_layout(ps.N, ps.nnzM, ps.Nt, ps.nnzL, G, precision == MMSD_MIXED ? 4 : 8).total;
   return MMSD_OK;
 }
@@ -980,11 +974,11 @@ int mmsd_minimize_batch(mmsd_problem* probs, int n, const mmsd_options* o, mmsd_
   int worst = MMSD_OK;
   for (int i = 0; i < n && !rc; ++i) {
     mmsd_problem p = probs[i];
-    if (hipMemcpy(&p->hctrl[0], p->dctrl, sizeof(Ctrl), hipMemcpyDeviceToHost) != hipSuccess) {
+    if (hipMemcpy(&p->hctrl[0], p->dctrl, 2 * sizeof(Ctrl), hipMemcpyDeviceToHost) != hipSuccess) {
       rc = hip_fail(hipGetLastError(), "batch result copy");
       break;
     }
-    const Ctrl& C = p->hctrl[0];
+    const Ctrl& C = latest(&p->hctrl[0]);
     p->acc = C.acc;
     p->h_valid = false;
     if (c->timing.stride > 0) c->timing.bytes += run_bytes(p, C);

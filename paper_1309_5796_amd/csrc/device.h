@@ -2,19 +2,29 @@
 // drives it.  Shared by the kernels and the host runtime of the library.
 //
 // One evaluation of the energy gradient (Method section; the paper's Table 2
-// lists its linear-algebra parts) is a sequence of phases; every launch of
-// the step kernel advances every unfinished problem of its table by exactly
-// one phase, and the last block of a problem to finish decides the next phase:
+// lists its linear-algebra parts) is a sequence of phases, one per launch of
+// the step kernel:
 //
 //   PREP   trial m_t = Cayley(m, h, tau) (eq. (7), explicit form) on magnet
-//          rows; b = G m_t; r = b - L u (warm start); z = D^-1 r
-//   PCG_A  p = z + beta p_old (recomputed at every gathered neighbour);
-//          q = L p; partial p.q
-//   PCG_B  u += alpha p; r -= alpha q; z = D^-1 r; partial r.z, r.r, r.u
+//          rows; b = G m_t; r = b - L u (warm start from the last solve)
+//   CG0    w = L D^-1 r; partial r.D^-1 r and w.D^-1 r
+//   CG     one Jacobi-preconditioned CG iteration in the single-reduction
+//          (Chronopoulos-Gear) arrangement: p = D^-1 r + beta p,
+//          s = w + beta s, u += alpha p, r -= alpha s, w = L D^-1 r, with both
+//          dot products of the next step from the same sweep; neighbour
+//          values of r, s, w are recomputed where they are gathered
 //   FIELD  h = -K m - D2 u + Q m + b_ext/Js; H = m x h; fused reductions of
 //          the energy, max|H|, sum V|H|^2 and the BB dots s.s, s.y, y.y
-//          (eq. (9)); the last block then runs the step-length logic
-//          (acceptance, BB / adaptive switching, line search, stopping test).
+//          (eq. (9)).
+//
+// Launches alternate a parity bit.  A launch of parity p reads the control
+// state and the per-block partial sums that the previous launch (parity
+// 1 - p) left in slot 1 - p, and every block runs the same deterministic
+// transition on them (finishing the reductions, PCG scalars, and after a
+// FIELD phase the step-length logic: acceptance, BB / adaptive switching,
+// line search, stopping test).  Block 0 stores the new state in slot p; all
+// blocks then execute the new phase and leave their partials in slot p.
+// The kernel boundary publishes them, so no atomics or fences are needed.
 //
 // Internal units: lengths in nm, energies in mu0 Ms^2 nm^3, fields in Ms,
 // potential in Ms nm.
@@ -24,15 +34,13 @@
 
 namespace mmsd {
 
-enum Phase : int { PH_IDLE = 0, PH_PREP = 1, PH_PCG_A = 2, PH_PCG_B = 3, PH_FIELD = 4, PH_DONE = 5 };
+enum Phase : int { PH_IDLE = 0, PH_PREP = 1, PH_CG0 = 2, PH_CG = 3, PH_FIELD = 4, PH_DONE = 5, PH_START = 6 };
 enum Stage : int { ST_INIT = 0, ST_RUN = 1, ST_EVAL = 2 };
 
-constexpr int kBlock = 256;        // threads per block (4 wavefronts of 64)
-constexpr int kGroup = 64;         // blocks per first-level reduction group
+constexpr int kBlock = 512;        // threads per block (8 wavefronts of 64)
 constexpr int kNPart = 13;         // partial sums per block (FIELD needs 13)
 constexpr int kMaxHist = 64;       // nonmonotone memory capacity
-constexpr int kMaxBlocks = 1 << 16;  // per problem
-constexpr int kMaxGroups = kMaxBlocks / kGroup;
+constexpr int kMaxBlocks = 2048;   // per problem (every block reads all partials)
 
 // FIELD partial slots
 enum FieldPart : int {
@@ -40,10 +48,10 @@ enum FieldPart : int {
   FP_SS = 6, FP_SY = 7, FP_YY = 8, FP_MX = 9, FP_MY = 10, FP_MZ = 11, FP_H2 = 12
 };
 
-// Control block of one problem.  Written only by the finishing block of a
-// launch (thread 0) and by the host-side init kernel; read by every block at
-// the start of a launch.
+// Control state of one problem (two slots, one per launch parity).  `phase`
+// is the phase the launch that wrote the slot executes.
 struct Ctrl {
+  long long seq;                 // launches since the state was armed (newest slot wins)
   // phase machine
   int phase, stage, acc, pcur;
   int first, backtrack, status, pcg_it;
@@ -52,7 +60,7 @@ struct Ctrl {
   int pcg_maxit, store_h, demag, pad0;
   long long evals, iters, pcg_total, max_evals;
   long long launches_done;       // phases executed
-  long long nphase[4];           // executed PREP, PCG_A, PCG_B, FIELD phases
+  long long nphase[4];           // executed PREP, CG0, CG, FIELD phases
   // options and constants
   double tol, pcg_rtol2, c1, rho, kappa0, theta0, tau_min, tau_max, tau_floor;
   double bz[3];                  // applied field / Js
@@ -66,8 +74,17 @@ struct Ctrl {
   double eterm_acc[4];
   double mavg_acc[3];
   // PCG scalars
-  double rz, pq, bb, rr, ru, alpha, beta;
+  double gam, dlt, bb, rr, ru, alpha, beta;
   double pad1[4];
+};
+static_assert(sizeof(Ctrl) % 8 == 0, "Ctrl is copied as 8-byte words");
+
+// Per-node state of the potential solve, packed so that one gathered
+// neighbour costs one 4-wide load: residual r, L p (s), L D^-1 r (w) and the
+// Jacobi factor d = 1/diag(L).
+template <typename real>
+struct __align__(4 * sizeof(real)) Rec {
+  real r, s, w, d;
 };
 
 template <typename real>
@@ -88,20 +105,15 @@ struct Prob {
   const int* lrp;
   const int* lci;
   const real* L;
-  const real* invd;       // 1 / diag(L)
-  real* u;
-  real* r;
-  real* z;
-  real* p[2];
-  real* q;
-  // reductions
+  real* u;                // potential (the CG iterate), warm start across solves
+  real* p;                // search direction (row-local)
+  Rec<real>* rec[2];      // CG state by buffer parity (pcur)
+  // reductions and control
   unsigned* ndone;        // nullable: incremented once when the problem finishes
   int* done_list;         // nullable: receives `slot` at position ndone - 1
   int slot;
-  double* part;           // [G][kNPart]
-  double* gpart;          // [G/kGroup][kNPart]
-  unsigned* cnt;          // [0] top level, [1 + g] group g
-  Ctrl* ctrl;
+  double* part;           // [2][G][kNPart] per-block partials, by launch parity
+  Ctrl* ctrl;             // [2] control state, by launch parity
 };
 
 }  // namespace mmsd

@@ -1,21 +1,17 @@
 // Step kernel of the curvilinear steepest-descent minimizer for gfx950.
 //
 // One launch advances every unfinished problem of a table by one phase (see
-// device.h).  Work layout:
+// device.h for the phases and the parity protocol).  Work layout:
 //  * CSR rows are split over `LPR` lanes (4, 8 or 16) of a 64-wide wavefront;
-//    a block of 256 threads takes one tile of 256/LPR rows, so a launch has
-//    about rows/tile blocks and the hardware keeps many row tiles in flight
-//    (the loop over passes only runs when a problem is capped in blocks).
-//    Column indices and values stream coalesced; node vectors are gathered
-//    (they stay in L2: every entry is reused by ~15 rows).
+//    a block of 512 threads walks a contiguous chunk of rows in passes of
+//    512/LPR rows.  Column indices and values stream coalesced; node vectors
+//    are gathered (they stay in L2: every entry is reused by ~15 rows).
 //  * Block b of a problem takes chunk (b % 8) * (G / 8) + b / 8: blocks are
 //    dealt to the 8 XCDs round-robin, so this gives each XCD one contiguous
 //    eighth of the rows and keeps neighbour gathers inside its own L2.
-//  * Reductions are deterministic: wavefront butterfly, then the 4 waves in
-//    order, then the per-block partials of each group of 64 blocks combined by
-//    the group's last block (lanes load in parallel, fixed butterfly), then
-//    the group partials the same way by the last group.  That last block also runs the phase transition and, after a
-//    FIELD phase, the step-length logic.
+//  * Reductions are deterministic and need no atomics: wavefront butterfly,
+//    then the 8 waves in order, one partial per block; the next launch's
+//    blocks each combine those G partials in the same fixed order.
 // All node arrays are structure-of-arrays.
 #include <hip/hip_runtime.h>
 
@@ -32,16 +28,6 @@ __device__ __forceinline__ T group_sum(T v) {
 #pragma unroll
   for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
   return v;
-}
-
-template <typename T>
-__device__ __forceinline__ void store_agent(T* p, T v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-template <typename T>
-__device__ __forceinline__ T load_agent(const T* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -83,6 +69,11 @@ __device__ __forceinline__ void cayley(real mx, real my, real mz, real Hx, real 
     oz *= s;
   }
 }
+
+// Row loops load kUnroll column indices per lane first, then issue all the
+// gathers, then accumulate: two dependent memory round trips per row batch
+// instead of two per nonzero.
+constexpr int kUnroll = 4;
 
 // Rows [r0, r1) of chunk t out of G for R rows, chunk rounded to `rpp`.
 __device__ __forceinline__ void chunk_rows(int R, int G, int t, int rpp, int& r0, int& r1) {
@@ -136,75 +127,145 @@ __device__ void phase_prep(const Prob<real>& P, const Ctrl* C, int t, double* ac
     }
     if (demag) {
       if (valid) {
-        const int k1 = P.lrp[i + 1];
-        for (int k = P.lrp[i] + lane; k < k1; k += LPR) lu += P.L[k] * P.u[P.lci[k]];
+        const int ke = P.lrp[i + 1];
+        for (int k0 = P.lrp[i] + lane; k0 < ke; k0 += kUnroll * LPR) {
+          int j[kUnroll];
+          real lv[kUnroll];
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+            const int k = k0 + u * LPR;
+            const int ks = k < ke ? k : k0;
+            j[u] = P.lci[ks];
+            lv[u] = k < ke ? P.L[ks] : real(0);
+          }
+          real uj[kUnroll];
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) uj[u] = P.u[j[u]];
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) lu += lv[u] * uj[u];
+        }
       }
       bi = group_sum<real, LPR>(bi);
       lu = group_sum<real, LPR>(lu);
       if (valid && lane == 0) {
         const real ri = bi - lu;
-        const real zi = ri * P.invd[i];
-        P.r[i] = ri;
-        P.z[i] = zi;
-        acc[0] += (double)ri * (double)zi;
-        acc[1] += (double)bi * (double)bi;
-        acc[2] += (double)ri * (double)ri;
-        acc[3] += (double)ri * (double)P.u[i];
+        P.rec[C->pcur][i].r = ri;
+        acc[0] += (double)bi * (double)bi;
+        acc[1] += (double)ri * (double)ri;
+        acc[2] += (double)ri * (double)P.u[i];
       }
     }
   }
 }
 
-// ---- PCG_A: search direction (recomputed at neighbours) and q = L p ----
+// ---- CG0: w = L D^-1 r for the starting residual ----
 template <typename real, int LPR>
-__device__ void phase_pcg_a(const Prob<real>& P, const Ctrl* C, int t, double* acc) {
+__device__ void phase_cg0(const Prob<real>& P, const Ctrl* C, int t, double* acc) {
   constexpr int RPP = kBlock / LPR;
   const int lane = threadIdx.x & (LPR - 1);
   const int slot = threadIdx.x / LPR;
   int r0, r1;
   chunk_rows(P.Nt, P.G, t, RPP, r0, r1);
-  const real beta = real(C->beta);
-  const real* __restrict__ pold = P.p[C->pcur];
-  real* __restrict__ pnew = P.p[1 - C->pcur];
-  const real* __restrict__ z = P.z;
+  Rec<real>* __restrict__ rec = P.rec[C->pcur];
   for (int base = r0; base < r1; base += RPP) {
     const int i = base + slot;
     const bool valid = i < r1;
-    real s = 0;
+    real sw = 0;
+    Rec<real> own{};
     if (valid) {
-      const int k1 = P.lrp[i + 1];
-      for (int k = P.lrp[i] + lane; k < k1; k += LPR) {
-        const int j = P.lci[k];
-        s += P.L[k] * (z[j] + beta * pold[j]);
+      own = rec[i];
+      const int ke = P.lrp[i + 1];
+      for (int k0 = P.lrp[i] + lane; k0 < ke; k0 += kUnroll * LPR) {
+        int j[kUnroll];
+        real lv[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int k = k0 + u * LPR;
+          const int ks = k < ke ? k : k0;
+          j[u] = P.lci[ks];
+          lv[u] = k < ke ? P.L[ks] : real(0);
+        }
+        Rec<real> nb[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) nb[u] = rec[j[u]];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) sw += lv[u] * (nb[u].d * nb[u].r);
       }
     }
-    s = group_sum<real, LPR>(s);
+    sw = group_sum<real, LPR>(sw);
     if (valid && lane == 0) {
-      const real pi = z[i] + beta * pold[i];
-      pnew[i] = pi;
-      P.q[i] = s;
-      acc[0] += (double)pi * (double)s;
+      const real ui = own.d * own.r;
+      rec[i].w = sw;
+      acc[0] += (double)own.r * (double)ui;
+      acc[1] += (double)sw * (double)ui;
     }
   }
 }
 
-// ---- PCG_B: potential and residual update, preconditioned residual ----
-template <typename real>
-__device__ void phase_pcg_b(const Prob<real>& P, const Ctrl* C, int t, double* acc) {
+// ---- CG: one single-reduction PCG iteration ----
+// Reads records of buffer c = pcur (r_i, s_{i-1}, w_i) and writes buffer
+// 1 - c.  A gathered neighbour's new residual is recomputed as
+// r_j - alpha (w_j + beta s_j), so the sweep needs no grid-wide barrier
+// between the vector updates and w = L D^-1 r.
+template <typename real, int LPR>
+__device__ void phase_cg(const Prob<real>& P, const Ctrl* C, int t, double* acc) {
+  constexpr int RPP = kBlock / LPR;
+  const int lane = threadIdx.x & (LPR - 1);
+  const int slot = threadIdx.x / LPR;
   int r0, r1;
-  chunk_rows(P.Nt, P.G, t, kBlock, r0, r1);
-  const real alpha = real(C->alpha);
-  const real* __restrict__ p = P.p[C->pcur];
-  for (int i = r0 + threadIdx.x; i < r1; i += kBlock) {
-    const real ui = P.u[i] + alpha * p[i];
-    const real ri = P.r[i] - alpha * P.q[i];
-    const real zi = ri * P.invd[i];
-    P.u[i] = ui;
-    P.r[i] = ri;
-    P.z[i] = zi;
-    acc[0] += (double)ri * (double)zi;
-    acc[1] += (double)ri * (double)ri;
-    acc[2] += (double)ri * (double)ui;
+  chunk_rows(P.Nt, P.G, t, RPP, r0, r1);
+  const int c = C->pcur;
+  const real alpha = real(C->alpha), beta = real(C->beta);
+  const Rec<real>* __restrict__ ro = P.rec[c];
+  Rec<real>* __restrict__ rn = P.rec[1 - c];
+  for (int base = r0; base < r1; base += RPP) {
+    const int i = base + slot;
+    const bool valid = i < r1;
+    real sw = 0;
+    Rec<real> own{};
+    real pi = 0, ui = 0;
+    if (valid) {
+      own = ro[i];
+      pi = P.p[i];
+      ui = P.u[i];
+      const int ke = P.lrp[i + 1];
+      for (int k0 = P.lrp[i] + lane; k0 < ke; k0 += kUnroll * LPR) {
+        int j[kUnroll];
+        real lv[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int k = k0 + u * LPR;
+          const int ks = k < ke ? k : k0;
+          j[u] = P.lci[ks];
+          lv[u] = k < ke ? P.L[ks] : real(0);
+        }
+        Rec<real> nb[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) nb[u] = ro[j[u]];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) sw += lv[u] * (nb[u].d * (nb[u].r - alpha * (nb[u].w + beta * nb[u].s)));
+      }
+    }
+    sw = group_sum<real, LPR>(sw);
+    if (valid && lane == 0) {
+      pi = own.d * own.r + beta * pi;
+      const real si = own.w + beta * own.s;
+      ui = ui + alpha * pi;
+      const real ri = own.r - alpha * si;
+      const real zi = own.d * ri;
+      P.p[i] = pi;
+      P.u[i] = ui;
+      Rec<real> out;
+      out.r = ri;
+      out.s = si;
+      out.w = sw;
+      out.d = own.d;
+      rn[i] = out;
+      acc[0] += (double)ri * (double)zi;
+      acc[1] += (double)sw * (double)zi;
+      acc[2] += (double)ri * (double)ri;
+      acc[3] += (double)ri * (double)ui;
+    }
   }
 }
 
@@ -231,20 +292,50 @@ __device__ void phase_field(const Prob<real>& P, const Ctrl* C, int t, double* a
     const bool valid = i < r1;
     real kx = 0, ky = 0, kz = 0, dx = 0, dy = 0, dz = 0;
     if (valid) {
-      const int k1 = P.mrp[i + 1];
-      for (int k = P.mrp[i] + lane; k < k1; k += LPR) {
-        const int j = P.mci[k];
+      const int ke = P.mrp[i + 1];
+      for (int k0 = P.mrp[i] + lane; k0 < ke; k0 += kUnroll * LPR) {
+        int j[kUnroll];
+        bool ok[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int k = k0 + u * LPR;
+          ok[u] = k < ke;
+          j[u] = P.mci[ok[u] ? k : k0];
+        }
         if (exch) {
-          const real kv = P.K[k];
-          kx += kv * mx[j];
-          ky += kv * my[j];
-          kz += kv * mz[j];
+          real kv[kUnroll], gx[kUnroll], gy[kUnroll], gz[kUnroll];
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+            const int k = ok[u] ? k0 + u * LPR : k0;
+            kv[u] = ok[u] ? P.K[k] : real(0);
+            gx[u] = mx[j[u]];
+            gy[u] = my[j[u]];
+            gz[u] = mz[j[u]];
+          }
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+            kx += kv[u] * gx[u];
+            ky += kv[u] * gy[u];
+            kz += kv[u] * gz[u];
+          }
         }
         if (demag) {
-          const real uj = P.u[j];
-          dx += P.D2[0][k] * uj;
-          dy += P.D2[1][k] * uj;
-          dz += P.D2[2][k] * uj;
+          real ex[kUnroll], ey[kUnroll], ez[kUnroll], uj[kUnroll];
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+            const int k = ok[u] ? k0 + u * LPR : k0;
+            const real f = ok[u] ? real(1) : real(0);
+            ex[u] = f * P.D2[0][k];
+            ey[u] = f * P.D2[1][k];
+            ez[u] = f * P.D2[2][k];
+            uj[u] = P.u[j[u]];
+          }
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+            dx += ex[u] * uj[u];
+            dy += ey[u] * uj[u];
+            dz += ez[u] * uj[u];
+          }
         }
       }
     }
@@ -301,7 +392,7 @@ __device__ void phase_field(const Prob<real>& P, const Ctrl* C, int t, double* a
 }
 
 __device__ __forceinline__ int n_parts(int phase) {
-  return phase == PH_PREP ? 4 : phase == PH_PCG_A ? 1 : phase == PH_PCG_B ? 3 : kNPart;
+  return phase == PH_PREP ? 3 : phase == PH_CG0 ? 2 : phase == PH_CG ? 4 : kNPart;
 }
 
 __device__ void push_hist(Ctrl* C, double e) {
@@ -442,8 +533,17 @@ __device__ void step_logic(Ctrl* C, const double* v) {
   C->phase = PH_PREP;
 }
 
-template <typename real>
-__device__ void finish(Ctrl* C, int phase, const double* v) {
+
+// Advance the state by the outcome of the phase it records (v: the finished
+// reductions of that phase's partials).
+__device__ void transition(Ctrl* C, const double* v) {
+  C->seq++;
+  const int phase = C->phase;
+  if (phase == PH_IDLE || phase == PH_DONE) return;
+  if (phase == PH_START) {
+    C->phase = PH_PREP;
+    return;
+  }
   C->launches_done++;
   C->nphase[phase - PH_PREP]++;
   switch (phase) {
@@ -453,49 +553,51 @@ __device__ void finish(Ctrl* C, int phase, const double* v) {
         C->phase = PH_FIELD;
         return;
       }
-      C->rz = v[0];
-      C->bb = v[1];
-      C->rr = v[2];
-      C->ru = v[3];
-      C->pcg_it = 0;
-      if (C->rr <= C->pcg_rtol2 * C->bb) {
-        C->phase = PH_FIELD;
-      } else {
-        C->beta = 0.0;
-        C->phase = PH_PCG_A;
-      }
-      return;
-    case PH_PCG_A:
-      C->pq = v[0];
-      C->alpha = C->rz / C->pq;
-      C->pcur ^= 1;
-      C->phase = PH_PCG_B;
-      return;
-    case PH_PCG_B:
-      C->beta = v[0] / C->rz;
-      C->rz = v[0];
+      C->bb = v[0];
       C->rr = v[1];
       C->ru = v[2];
+      C->pcg_it = 0;
+      C->phase = (C->rr <= C->pcg_rtol2 * C->bb) ? PH_FIELD : PH_CG0;
+      return;
+    case PH_CG0:
+      C->gam = v[0];
+      C->dlt = v[1];
+      C->alpha = C->gam / C->dlt;
+      C->beta = 0.0;
+      C->phase = PH_CG;
+      return;
+    case PH_CG: {
+      // gamma = r.D^-1 r, delta = (L D^-1 r).D^-1 r of the new residual
+      const double gam = v[0], dlt = v[1];
+      const double beta = gam / C->gam;
+      C->alpha = gam / (dlt - beta * gam / C->alpha);
+      C->beta = beta;
+      C->gam = gam;
+      C->dlt = dlt;
+      C->rr = v[2];
+      C->ru = v[3];
+      C->pcur ^= 1;
       C->pcg_it++;
       C->pcg_total++;
-      C->phase = (C->rr <= C->pcg_rtol2 * C->bb || C->pcg_it >= C->pcg_maxit) ? PH_FIELD : PH_PCG_A;
+      C->phase = (C->rr <= C->pcg_rtol2 * C->bb || C->pcg_it >= C->pcg_maxit) ? PH_FIELD : PH_CG;
       return;
+    }
     case PH_FIELD:
       step_logic(C, v);
       return;
   }
 }
 
-// out[k] = sum (max for the torque slot) over q < n of src[q * kNPart + k],
-// k < np.  Wavefront w takes slots w, w + 4, ...; each lane loads up to
-// n / 64 values with agent-scope loads, then a butterfly combines the lanes.
-__device__ void reduce_slots(const double* src, int n, int np, int phase, double* out) {
+// out[k] = sum (max for the torque slot) over the G block partials of slot k.
+// Wavefront w takes slots w, w + 8, ...; lanes stride over the blocks, then a
+// butterfly combines them: the same fixed order in every block.
+__device__ void reduce_partials(const double* src, int G, int np, int phase, double* out) {
   const int wid = threadIdx.x >> 6, lid = threadIdx.x & 63;
   for (int k = wid; k < np; k += kBlock / 64) {
     const bool mx = (phase == PH_FIELD && k == FP_TMAX);
     double v = 0.0;
-    for (int q = lid; q < n; q += 64) {
-      const double x = load_agent(src + (size_t)q * kNPart + k);
+    for (int q = lid; q < G; q += 64) {
+      const double x = src[(size_t)q * kNPart + k];
       v = mx ? fmax(v, x) : v + x;
     }
     v = mx ? wave_max(v) : wave_sum(v);
@@ -505,10 +607,11 @@ __device__ void reduce_slots(const double* src, int n, int np, int phase, double
 
 template <typename real, int LPR>
 __global__ void __launch_bounds__(kBlock) k_step(const Prob<real>* __restrict__ probs, int nprob,
-                                                 const int* __restrict__ blk_start) {
+                                                 const int* __restrict__ blk_start, int parity) {
+  __shared__ Ctrl s_c;
   __shared__ double s_red[kBlock / 64][kNPart];
   __shared__ double s_tot[kNPart];
-  __shared__ int s_last;
+  __shared__ int s_newly_done;
   const int b = blockIdx.x;
   int lo = 0, hi = nprob;
   while (hi - lo > 1) {
@@ -517,10 +620,33 @@ __global__ void __launch_bounds__(kBlock) k_step(const Prob<real>* __restrict__ 
     else hi = mid;
   }
   const Prob<real>& P = probs[lo];
-  Ctrl* C = P.ctrl;
-  const int phase = C->phase;
-  if (phase == PH_IDLE || phase == PH_DONE) return;
   const int lb = b - P.blk0;
+  const int prev = parity ^ 1;
+
+  // prologue: the previous launch's state and the reductions of its phase
+  {
+    const long long* src = reinterpret_cast<const long long*>(&P.ctrl[prev]);
+    long long* dst = reinterpret_cast<long long*>(&s_c);
+    for (int w = threadIdx.x; w < (int)(sizeof(Ctrl) / 8); w += kBlock) dst[w] = src[w];
+  }
+  __syncthreads();
+  const int ran = s_c.phase;
+  if (ran >= PH_PREP && ran <= PH_FIELD)
+    reduce_partials(P.part + (size_t)prev * P.G * kNPart, P.G, n_parts(ran), ran, s_tot);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    transition(&s_c, s_tot);
+    s_newly_done = (ran != PH_DONE && s_c.phase == PH_DONE);
+  }
+  __syncthreads();
+  if (lb == 0) {
+    const long long* src = reinterpret_cast<const long long*>(&s_c);
+    long long* dst = reinterpret_cast<long long*>(&P.ctrl[parity]);
+    for (int w = threadIdx.x; w < (int)(sizeof(Ctrl) / 8); w += kBlock) dst[w] = src[w];
+    if (threadIdx.x == 0 && s_newly_done) signal_done<real>(P, &s_c);
+  }
+  const int phase = s_c.phase;
+  if (phase < PH_PREP || phase > PH_FIELD) return;
   const int t = (lb & 7) * (P.G >> 3) + (lb >> 3);
 
   double acc[kNPart];
@@ -528,20 +654,21 @@ __global__ void __launch_bounds__(kBlock) k_step(const Prob<real>* __restrict__ 
   for (int k = 0; k < kNPart; ++k) acc[k] = 0.0;
   switch (phase) {
     case PH_PREP:
-      phase_prep<real, LPR>(P, C, t, acc);
+      phase_prep<real, LPR>(P, &s_c, t, acc);
       break;
-    case PH_PCG_A:
-      phase_pcg_a<real, LPR>(P, C, t, acc);
+    case PH_CG0:
+      phase_cg0<real, LPR>(P, &s_c, t, acc);
       break;
-    case PH_PCG_B:
-      phase_pcg_b<real>(P, C, t, acc);
+    case PH_CG:
+      phase_cg<real, LPR>(P, &s_c, t, acc);
       break;
     case PH_FIELD:
-      phase_field<real, LPR>(P, C, t, acc);
+      phase_field<real, LPR>(P, &s_c, t, acc);
       break;
   }
 
-  // block partials: butterfly in each wave, then the waves in order
+  // block partials: butterfly in each wave, then the waves in order; plain
+  // stores, published to the next launch by the kernel boundary
   const int np = n_parts(phase);
   const int wid = threadIdx.x >> 6, lid = threadIdx.x & 63;
   for (int k = 0; k < np; ++k) {
@@ -549,45 +676,18 @@ __global__ void __launch_bounds__(kBlock) k_step(const Prob<real>* __restrict__ 
     if (lid == 0) s_red[wid][k] = v;
   }
   __syncthreads();
-  // Publication protocol: partials are written with agent-scope atomic
-  // stores (write-through to memory, no L2 write-back of the whole cache),
-  // the wave waits for their completion, and only then bumps the counter.
-  // The last arriver reads them back with agent-scope atomic loads.
   if (threadIdx.x < np) {
     const int k = threadIdx.x;
     const bool mx = (phase == PH_FIELD && k == FP_TMAX);
     double v = s_red[0][k];
     for (int w = 1; w < kBlock / 64; ++w) v = mx ? fmax(v, s_red[w][k]) : v + s_red[w][k];
-    store_agent(&P.part[(size_t)lb * kNPart + k], v);
-  }
-  __builtin_amdgcn_s_waitcnt(0);
-  const int g = lb / kGroup;
-  const int gsize = min(kGroup, P.G - g * kGroup);
-  if (threadIdx.x == 0) s_last = (atomicAdd(&P.cnt[1 + g], 1u) == (unsigned)(gsize - 1));
-  __syncthreads();
-  if (!s_last) return;
-  // group level: reduce the group's partials, one wavefront per slot, loads
-  // spread over the lanes (fixed butterfly order keeps it deterministic)
-  reduce_slots(P.part + (size_t)g * kGroup * kNPart, gsize, np, phase, s_tot);
-  __syncthreads();
-  if (threadIdx.x < np) store_agent(&P.gpart[(size_t)g * kNPart + threadIdx.x], s_tot[threadIdx.x]);
-  if (threadIdx.x == 0) store_agent(&P.cnt[1 + g], 0u);
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  const int ng = (P.G + kGroup - 1) / kGroup;
-  if (threadIdx.x == 0) s_last = (atomicAdd(&P.cnt[0], 1u) == (unsigned)(ng - 1));
-  __syncthreads();
-  if (!s_last) return;
-  reduce_slots(P.gpart, ng, np, phase, s_tot);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    store_agent(&P.cnt[0], 0u);
-    finish<real>(C, phase, s_tot);
-    signal_done<real>(P, C);
+    P.part[((size_t)parity * P.G + lb) * kNPart + k] = v;
   }
 }
 
-// Arm a problem for a new minimization or evaluation.
+// Arm a problem for a new minimization or evaluation: the state goes into
+// slot `slot` (the one the next step launch reads), with a sequence number
+// above both slots' so the host always picks the newest.
 struct CtrlInit {
   int stage, terms, nonmono_M, step_rule, pcg_maxit, store_h, demag, acc;
   long long max_evals;
@@ -595,9 +695,12 @@ struct CtrlInit {
   double bz[3], c_an, vol;
 };
 
-__global__ void k_ctrl_init(Ctrl* C, CtrlInit a) {
+__global__ void k_ctrl_init(Ctrl* ctrl, int slot, CtrlInit a) {
   if (threadIdx.x != 0) return;
-  C->phase = PH_PREP;
+  const long long seq = ctrl[0].seq > ctrl[1].seq ? ctrl[0].seq : ctrl[1].seq;
+  Ctrl* C = &ctrl[slot];
+  C->seq = seq + 1;
+  C->phase = PH_START;
   C->stage = a.stage;
   C->acc = a.acc;
   C->pcur = 0;
@@ -636,35 +739,35 @@ __global__ void k_ctrl_init(Ctrl* C, CtrlInit a) {
   C->vol = a.vol;
   C->tau = 0.0;
   C->kappa = a.kappa0;
-  C->rz = C->pq = C->bb = C->rr = C->ru = C->alpha = C->beta = 0.0;
+  C->gam = C->dlt = C->bb = C->rr = C->ru = C->alpha = C->beta = 0.0;
 }
 
 }  // namespace
 
 // ---- host-side launch wrappers -------------------------------------------
 template <typename real>
-hipError_t launch_step(int lpr, const Prob<real>* probs, int nprob, const int* blk_start, int grid,
+hipError_t launch_step(int lpr, const Prob<real>* probs, int nprob, const int* blk_start, int grid, int parity,
                        hipStream_t s) {
   switch (lpr) {
     case 4:
-      hipLaunchKernelGGL((k_step<real, 4>), dim3(grid), dim3(kBlock), 0, s, probs, nprob, blk_start);
+      hipLaunchKernelGGL((k_step<real, 4>), dim3(grid), dim3(kBlock), 0, s, probs, nprob, blk_start, parity);
       break;
     case 16:
-      hipLaunchKernelGGL((k_step<real, 16>), dim3(grid), dim3(kBlock), 0, s, probs, nprob, blk_start);
+      hipLaunchKernelGGL((k_step<real, 16>), dim3(grid), dim3(kBlock), 0, s, probs, nprob, blk_start, parity);
       break;
     default:
-      hipLaunchKernelGGL((k_step<real, 8>), dim3(grid), dim3(kBlock), 0, s, probs, nprob, blk_start);
+      hipLaunchKernelGGL((k_step<real, 8>), dim3(grid), dim3(kBlock), 0, s, probs, nprob, blk_start, parity);
       break;
   }
   return hipGetLastError();
 }
 
-template hipError_t launch_step<double>(int, const Prob<double>*, int, const int*, int, hipStream_t);
-template hipError_t launch_step<float>(int, const Prob<float>*, int, const int*, int, hipStream_t);
+template hipError_t launch_step<double>(int, const Prob<double>*, int, const int*, int, int, hipStream_t);
+template hipError_t launch_step<float>(int, const Prob<float>*, int, const int*, int, int, hipStream_t);
 
-hipError_t launch_ctrl_init(Ctrl* C, int stage, int terms, int nonmono_M, int step_rule, int pcg_maxit,
-                            int store_h, int demag, int acc, long long max_evals, const double* dparams,
-                            hipStream_t s) {
+hipError_t launch_ctrl_init(Ctrl* ctrl, int slot, int stage, int terms, int nonmono_M, int step_rule,
+                            int pcg_maxit, int store_h, int demag, int acc, long long max_evals,
+                            const double* dparams, hipStream_t s) {
   CtrlInit a;
   a.stage = stage;
   a.terms = terms;
@@ -689,7 +792,7 @@ hipError_t launch_ctrl_init(Ctrl* C, int stage, int terms, int nonmono_M, int st
   a.bz[2] = dparams[11];
   a.c_an = dparams[12];
   a.vol = dparams[13];
-  hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, s, C, a);
+  hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, s, ctrl, slot, a);
   return hipGetLastError();
 }
 

@@ -26,11 +26,18 @@ int hip_fail(hipError_t e, const char* what);
   } while (0)
 
 template <typename real>
-hipError_t launch_step(int lpr, const Prob<real>* probs, int nprob, const int* blk_start, int grid,
+hipError_t launch_step(int lpr, const Prob<real>* probs, int nprob, const int* blk_start, int grid, int parity,
                        hipStream_t s);
-hipError_t launch_ctrl_init(Ctrl* C, int stage, int terms, int nonmono_M, int step_rule, int pcg_maxit,
-                            int store_h, int demag, int acc, long long max_evals, const double* dparams,
-                            hipStream_t s);
+hipError_t launch_ctrl_init(Ctrl* ctrl, int slot, int stage, int terms, int nonmono_M, int step_rule,
+                            int pcg_maxit, int store_h, int demag, int acc, long long max_evals,
+                            const double* dparams, hipStream_t s);
+
+// Every batch of step launches starts with parity 0 and has an even length,
+// so the state a run is armed with goes into slot 1.
+constexpr int kArmSlot = 1;
+
+// The newer of the two control slots.
+inline const Ctrl& latest(const Ctrl* two) { return two[1].seq > two[0].seq ? two[1] : two[0]; }
 
 struct Resolved {
   double tol, rtol;
@@ -62,7 +69,7 @@ struct mmsd_problem_s;
 namespace mmsd {
 int resolve(mmsd_problem_s* p, const mmsd_options* o, Resolved* r);
 int arm(mmsd_problem_s* p, const Resolved& r, int stage, int store_h);
-int launch_table(const Table& t, hipStream_t st);
+int launch_table(const Table& t, int parity, hipStream_t st);
 void fill_result(mmsd_problem_s* p, const Ctrl& C, mmsd_result* out, double secs, int64_t launches);
 int ensure_pinned(mmsd_problem_s* p);
 int issue(mmsd_ctx_s* c, const std::vector<Table>& tabs, int B, std::map<int, hipGraphExec_t>* graphs);
@@ -76,8 +83,8 @@ struct mmsd_ctx_s {
   mmsd_alloc_fn alloc = nullptr;
   mmsd_free_fn free_fn = nullptr;
   void* user = nullptr;
-  int lpr = 8;
-  int max_blocks = 1 << 16;
+  int lpr = 4;
+  int max_blocks = 512;
   bool use_graph = true;
   mmsd::TimingState timing;
   std::mutex mu;            // serializes device work issued through this context
@@ -96,16 +103,16 @@ struct mmsd_problem_s {
   alignas(16) unsigned char desc[sizeof(mmsd::Prob<double>)];
   void* dprob = nullptr;     // device Prob<real>
   int* dblk = nullptr;       // device blk_start [2]
-  mmsd::Ctrl* dctrl = nullptr;
+  mmsd::Ctrl* dctrl = nullptr;            // [2] slots
   void* snap[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [set][m | u]
-  int G = 0, lpr = 8;
+  int G = 0, lpr = 4;
   int acc = 0;
   bool h_valid = false;
   double b_ext[3] = {0, 0, 0};
   double phase_bytes[4] = {0, 0, 0, 0};   // algorithmic bytes per executed phase
   double phase_bytes_h = 0;               // extra FIELD bytes when h is stored
   double prep_bytes_nodemag = 0;
-  mmsd::Ctrl* hctrl = nullptr;            // pinned mirrors [2]
+  mmsd::Ctrl* hctrl = nullptr;            // pinned mirrors [2 polls][2 slots]
   std::map<int, hipGraphExec_t> graphs;   // batch size -> instantiated graph
   int64_t last_launches = 0;
 };

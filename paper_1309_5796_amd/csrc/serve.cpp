@@ -296,8 +296,9 @@ void mmsd_server_s::device_loop() {
     for (int slot : fin) {
       Request* r = resident[slot];
       mmsd_problem p = r->prob;
-      Ctrl C;
-      hipMemcpy(&C, p->dctrl, sizeof(Ctrl), hipMemcpyDeviceToHost);
+      Ctrl two[2];
+      hipMemcpy(two, p->dctrl, 2 * sizeof(Ctrl), hipMemcpyDeviceToHost);
+      const Ctrl& C = latest(two);
       p->acc = C.acc;
       fill_result(p, C, &r->result, 0.0, C.launches_done);
       r->m_final.resize(3 * (size_t)p->A.N);
