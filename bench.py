@@ -6,7 +6,8 @@ cells: 68,921 magnet nodes, 274,625 potential nodes), field +8 -> -8 -> +8 T
 in 0.1 T steps along z tilted by 1 degree, each point warm-started from the
 previous minimum.  A "step" is one field point of the sweep (a full
 minimization: trial steps, potential solves, field, step logic, stopping
-test, continuation); --steps K times the first K points (321 = whole loop).
+test, continuation); --steps K times the first K points (default 161, the
+descending branch +8 -> -8 T with its switching field; 321 = whole loop).
 
 Prints one JSON line with node-iterations/s (magnet nodes x energy-gradient
 evaluations, line-search trials included, per second of wall time), the
@@ -59,20 +60,209 @@ print(json.dumps(dict(evals=r.evals, seconds=dt, N=s.N)))
                       f"(FP64 NumPy/SciPy, potential by Jacobi-CG to 1e-13), {d['seconds']:.1f} s on one core"}
 
 
+def roofline_of(tm, lanes):
+    if tm["launches"] <= 0 or tm["ms"] <= 0:
+        return None
+    avg_s = tm["ms"] / 1e3 / tm["launches"]
+    achieved = tm["bytes"] / tm["launches"] / avg_s / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": f"k_step<double,{lanes}>",
+            "avg_launch_us": avg_s * 1e6, "alg_bytes_per_launch": tm["bytes"] / tm["launches"],
+            "launches_timed": tm["launches"]}
+
+
+def base_line(value, K, warmup, wall, dtype, config):
+    return {"metric": METRIC, "value": value, "unit": "node-iterations/s", "n_gpus": 1, "steps": K,
+            "warmup": warmup, "ms_per_step": wall / max(K, 1) * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+
+
+def run_poly(args):
+    """Config 3: 1.03M-node 64-grain polycrystal, one minimization at -2 T from
+    +z + noise in the mixed form and in FP64; energies compared."""
+    import numpy as np
+    import torch
+    from paper_1309_5796_amd import binding, meshgen
+    t0 = time.perf_counter()
+    cfg = meshgen.config3()
+    print(f"[bench] mesh {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    ctx = binding.Context(0)
+    out = {}
+    for name, prec in (("mixed", binding.MIXED), ("fp64", binding.FP64)):
+        t0 = time.perf_counter()
+        p = binding.Problem(ctx, cfg["mesh"], precision=prec)
+        print(f"[bench] {name} setup {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        p.set_m(cfg["m0"])
+        p.set_field(cfg["b_ext"])
+        ctx.timing(True)
+        ctx.timing_read(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = p.minimize(max_evals=args.max_evals)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        tm = ctx.timing_read(reset=True)
+        ctx.timing(False)
+        out[name] = dict(r=r, wall=wall, tm=tm, N=p.N, Nt=p.Nt)
+        print(f"[bench] {name}: status {r.status} evals {r.evals} pcg {r.pcg_iters} {wall:.1f} s "
+              f"E={r.energy_J:.12e} torque {r.max_torque:.2e}", file=sys.stderr, flush=True)
+        p.close()
+    mx, fp = out["mixed"], out["fp64"]
+    scale = sum(abs(getattr(fp["r"], k)) for k in ("e_exch_J", "e_anis_J", "e_zeem_J", "e_demag_J"))
+    line = base_line(mx["N"] * mx["r"].evals / mx["wall"], 1, 0, mx["wall"], "f32+f64-reductions",
+                     {"workload": "mixed-precision polycrystal, 200x200x100 nm box, 126x126x63 Kuhn cells, "
+                                  "64 grains, -2 T at 1 deg, one minimization",
+                      "magnet_nodes": mx["N"], "potential_nodes": mx["Nt"]})
+    line["roofline"] = roofline_of(mx["tm"], 4)
+    line["roofline"]["kernel"] = "k_step<float,4>"
+    line["detail"] = {
+        "mixed": {"evals": mx["r"].evals, "pcg_iters": mx["r"].pcg_iters, "wall_s": mx["wall"],
+                  "status": mx["r"].status, "max_torque": mx["r"].max_torque, "energy_J": mx["r"].energy_J},
+        "fp64": {"evals": fp["r"].evals, "pcg_iters": fp["r"].pcg_iters, "wall_s": fp["wall"],
+                 "status": fp["r"].status, "max_torque": fp["r"].max_torque, "energy_J": fp["r"].energy_J,
+                 "node_iterations_per_s": fp["N"] * fp["r"].evals / fp["wall"],
+                 "roofline": roofline_of(fp["tm"], 4)},
+        "rel_energy_mixed_vs_fp64": abs(mx["r"].energy_J - fp["r"].energy_J) / scale,
+    }
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+def run_grains(args):
+    """Config 4: 256 independent grain cubes in the mixed form, one batched
+    run (shared launches, autotuned shape) against the same solves one by one."""
+    import numpy as np
+    import torch
+    from paper_1309_5796_amd import binding, meshgen
+    t0 = time.perf_counter()
+    cfgs = meshgen.config4(args.grains)
+    print(f"[bench] {len(cfgs)} meshes {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    ctx = binding.Context(0)
+    probs = []
+    for c in cfgs:
+        p = binding.Problem(ctx, c["mesh"], precision=binding.MIXED)
+        p.set_m(c["m0"])
+        p.set_field(c["b_ext"])
+        probs.append(p)
+    big = max(probs, key=lambda q: q.Nt)
+    lanes, blocks, us = big.autotune()
+    for p in probs:
+        p.set_launch(lanes, blocks)
+    states = [p.get_state() for p in probs]
+    print(f"[bench] setup done, tuned lanes={lanes} blocks={blocks} ({us:.1f} us/launch)", file=sys.stderr, flush=True)
+    Nsum = sum(p.N for p in probs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = binding.minimize_batch(probs)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    evals = sum(r.evals for r in res)
+    node_evals = sum(p.N * r.evals for p, r in zip(probs, res))
+    finals = [p.get_m() for p in probs]
+    print(f"[bench] batch {t_batch:.1f} s", file=sys.stderr, flush=True)
+    for p, st in zip(probs, states):
+        p.set_state(st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    single = [p.minimize() for p in probs]
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    same = sum(int(a.energy_J == b.energy_J and np.array_equal(m, p.get_m()))
+               for a, b, m, p in zip(res, single, finals, probs))
+    line = base_line(node_evals / t_batch, 1, 0, t_batch, "f32+f64-reductions",
+                     {"workload": f"{len(probs)} grain cubes (edges log-uniform 10-60 nm), mixed precision, "
+                                  f"-1 T, one batched run", "magnet_nodes_total": Nsum})
+    line["roofline"] = None
+    line["detail"] = {"batched_s": t_batch, "one_by_one_s": t_seq, "speedup": t_seq / t_batch,
+                      "evals": evals, "identical_to_one_by_one": f"{same}/{len(probs)}",
+                      "tuned_lanes": lanes, "tuned_blocks": blocks,
+                      "statuses": sorted(set(r.status for r in res))}
+    for p in probs:
+        p.close()
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+def run_serve(args):
+    """Config 5: the first --requests of the seeded Poisson stream (200 req/s)
+    submitted at their arrival times to a server with an HBM budget; reports
+    submit-to-result latency percentiles and node-iterations/s."""
+    import numpy as np
+    import torch
+    from paper_1309_5796_amd import binding, meshgen
+    reqs = meshgen.config5_requests()[: args.requests]
+    t0 = time.perf_counter()
+    built = [meshgen.request_mesh(r) for r in reqs]
+    print(f"[bench] {len(built)} request meshes {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    ctx = binding.Context(0)
+    srv = binding.Server(ctx, hbm_budget=int(args.hbm_gb * (1 << 30)), max_slots=args.slots)
+    t_start = time.perf_counter()
+    pending = {}
+    lat, node_evals, statuses = [], 0.0, []
+    k = 0
+    while k < len(reqs) or pending:
+        now = time.perf_counter() - t_start
+        while k < len(reqs) and reqs[k].arrival_s <= now:
+            b = built[k]
+            t = srv.submit(b["mesh"], b["b_ext"], precision=reqs[k].precision)
+            pending[t] = (time.perf_counter(), meshgen.n_magnetic(b["mesh"]))
+            k += 1
+        for t in list(pending):
+            got = srv.poll(t)
+            if got is not None:
+                r, _ = got
+                t_sub, n = pending.pop(t)
+                lat.append(time.perf_counter() - t_sub)
+                node_evals += n * r.evals
+                statuses.append(r.status)
+        time.sleep(0.001)
+        if time.perf_counter() - t_start > args.serve_timeout:
+            print("[bench] serve timeout", file=sys.stderr, flush=True)
+            break
+    wall = time.perf_counter() - t_start
+    st = srv.stats()
+    srv.close()
+    ctx.close()
+    lat = np.array(lat)
+    line = base_line(node_evals / wall, len(lat), 0, wall, "mixed f64/f32 per request",
+                     {"workload": f"served minimizations: first {len(reqs)} requests of the seeded 200 req/s "
+                                  f"Poisson stream, 2:2:1 boxes 1.2k-520k nodes, 64-grain density, "
+                                  f"B ~ U(-4,4) T, FP64/mixed coin", "hbm_budget_GB": args.hbm_gb,
+                      "slots": args.slots})
+    line["roofline"] = None
+    line["detail"] = {"p50_s": float(np.percentile(lat, 50)) if len(lat) else None,
+                      "p99_s": float(np.percentile(lat, 99)) if len(lat) else None,
+                      "completed": int(len(lat)), "statuses": sorted(set(statuses)),
+                      "device_launches": st["launches"], "offered_rate_req_s": 200.0,
+                      "served_rate_req_s": len(lat) / wall}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=321)
+    ap.add_argument("--steps", type=int, default=161,
+                    help="field points timed from +8 T (161 = descending branch, 321 = whole loop)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=20, help="field points per library call")
+    ap.add_argument("--workload", default="sweep80", choices=["sweep80", "poly", "grains", "serve"])
+    ap.add_argument("--max-evals", type=int, default=100000)
+    ap.add_argument("--grains", type=int, default=256)
+    ap.add_argument("--requests", type=int, default=60)
+    ap.add_argument("--hbm-gb", type=float, default=64.0)
+    ap.add_argument("--slots", type=int, default=32)
+    ap.add_argument("--serve-timeout", type=float, default=900.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is "
               f"described but not built", file=sys.stderr)
         sys.exit(2)
+    if args.workload != "sweep80":
+        {"poly": run_poly, "grains": run_grains, "serve": run_serve}[args.workload](args)
+        return
 
     import numpy as np
     import torch

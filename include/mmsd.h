@@ -204,10 +204,11 @@ int mmsd_minimize_batch(mmsd_problem* probs, int n, const mmsd_options* o, mmsd_
 int mmsd_get_state(mmsd_problem p, void* buf, size_t* bytes);
 int mmsd_set_state(mmsd_problem p, const void* buf, size_t bytes);
 
-/* Kernel timing (measurement aid): when enabled, the library brackets every
- * `stride`-th step launch with HIP events on the context stream.  stats:
- * [0] summed milliseconds of the timed launches, [1] number timed,
- * [2] algorithmic bytes of those launches (model documented with the kernels). */
+/* Kernel timing (measurement aid): when stride > 0 the library brackets every
+ * batch of step launches it issues with a pair of HIP events on the context
+ * stream (kernels back to back plus the gaps between them).  stats:
+ * [0] summed milliseconds, [1] step launches inside the timed batches,
+ * [2] algorithmic bytes of the phases those launches executed. */
 int mmsd_timing_enable(mmsd_ctx ctx, int stride);
 int mmsd_timing_read(mmsd_ctx ctx, double stats[3], int reset);
 
@@ -215,6 +216,29 @@ int mmsd_timing_read(mmsd_ctx ctx, double stats[3], int reset);
  * and maximum blocks per problem (multiple of 8).  0 keeps the current
  * value.  Applies to problems created afterwards. */
 int mmsd_set_launch_config(mmsd_ctx ctx, int lanes_per_row, int max_blocks);
+
+/* Launch shape of one problem: lanes per CSR row (4, 8, 16) and the block
+ * cap (multiple of 8, <= 2048).  Takes effect at the next run. */
+int mmsd_set_problem_launch(mmsd_problem p, int lanes_per_row, int max_blocks);
+
+/* Autotuner: times a fixed slice of this problem's potential solve for every
+ * lanes-per-row x block-cap shape, keeps the fastest on the problem and in a
+ * per-context cache keyed by (precision, log2 N, log2 N_t) (a cached class
+ * is applied without timing; *us_out is then -1).  The problem's state (m,
+ * potential) is unchanged.  Outputs are nullable. */
+int mmsd_autotune(mmsd_problem p, int* lanes_out, int* blocks_out, double* us_out);
+
+/* Host-side assembly only (no device): sizes[4] = {N, nnz of the magnet
+ * pattern, N_t, nnz of the potential matrix}; every array pointer may be
+ * NULL (query sizes first).  Values are in the library's internal units
+ * (nm, mu0 Ms^2 nm^3): mrp[N+1], mci[nnzM], K[nnzM] (= 2 K_ij / V_i),
+ * D1[3*nnzM] and D2[3*nnzM] (component-major), Q[6*N] (xx yy zz xy xz yz,
+ * = 2 Q_i / V_i), V[N], pot_global[N_t] (input node of each potential row),
+ * lrp[N_t+1], lci[nnzL], L[nnzL], scalars[4] = {sum V_e K1_e / (mu0 Ms^2),
+ * sum V_i, Ms, mu0 Ms^2}.  For inspection and tests of the assembly. */
+int mmsd_assembly_export(const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats, int64_t sizes[4],
+                         int32_t* mrp, int32_t* mci, double* K, double* D1, double* D2, double* Q, double* V,
+                         int32_t* pot_global, int32_t* lrp, int32_t* lci, double* L, double* scalars);
 
 /* ---- serving ----------------------------------------------------------- */
 /* A server owns a worker thread that admits submitted minimizations while

@@ -83,6 +83,10 @@ SIGNATURES = [
     ("mmsd_timing_enable", C.c_int, [C.c_void_p, C.c_int]),
     ("mmsd_timing_read", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int]),
     ("mmsd_set_launch_config", C.c_int, [C.c_void_p, C.c_int, C.c_int]),
+    ("mmsd_set_problem_launch", C.c_int, [C.c_void_p, C.c_int, C.c_int]),
+    ("mmsd_autotune", C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double)]),
+    ("mmsd_assembly_export", C.c_int, [C.POINTER(MeshC), C.POINTER(MaterialC), C.c_int, C.POINTER(C.c_int64)]
+     + [C.c_void_p] * 12),
     ("mmsd_server_create", C.c_int, [C.c_void_p, C.c_size_t, C.c_int, C.POINTER(C.c_void_p)]),
     ("mmsd_submit", C.c_int, [C.c_void_p, C.POINTER(MeshC), C.POINTER(MaterialC), C.c_int, C.POINTER(C.c_double),
                               C.c_int, C.POINTER(C.c_double), C.POINTER(OptionsC), C.POINTER(C.c_uint64)]),
@@ -357,6 +361,15 @@ class Problem:
         _check(self.lib.mmsd_hysteresis(self.handle, _dp(f), n, C.byref(o), res, _dp(bsw), C.byref(nsw)))
         return [Result.from_c(r) for r in res], bsw[: nsw.value].copy()
 
+    def set_launch(self, lanes_per_row: int, max_blocks: int):
+        _check(self.lib.mmsd_set_problem_launch(self.handle, lanes_per_row, max_blocks))
+
+    def autotune(self):
+        """Pick lanes per row and block cap by timing; returns (lanes, blocks, us)."""
+        lanes, blocks, us = C.c_int(), C.c_int(), C.c_double()
+        _check(self.lib.mmsd_autotune(self.handle, C.byref(lanes), C.byref(blocks), C.byref(us)))
+        return lanes.value, blocks.value, us.value
+
     def get_state(self) -> bytes:
         n = C.c_size_t()
         _check(self.lib.mmsd_get_state(self.handle, None, C.byref(n)))
@@ -367,6 +380,29 @@ class Problem:
     def set_state(self, state: bytes):
         buf = C.create_string_buffer(state, len(state))
         _check(self.lib.mmsd_set_state(self.handle, buf, len(state)))
+
+
+def assembly_export(mesh, materials=None) -> dict:
+    """Host-side assembly of a mesh (no device): the library's operators in
+    its internal units (see mmsd_assembly_export in include/mmsd.h)."""
+    lib = load_library()
+    a = MeshArgs(mesh, materials)
+    sizes = (C.c_int64 * 4)()
+    null = [None] * 12
+    _check(lib.mmsd_assembly_export(C.byref(a.c), a.mats, a.n_mats, sizes, *null))
+    N, nnzM, Nt, nnzL = (int(x) for x in sizes)
+    out = dict(mrp=np.empty(N + 1, np.int32), mci=np.empty(nnzM, np.int32), K=np.empty(nnzM),
+               D1=np.empty(3 * nnzM), D2=np.empty(3 * nnzM), Q=np.empty(6 * N), V=np.empty(N),
+               pot_global=np.empty(Nt, np.int32), lrp=np.empty(Nt + 1, np.int32), lci=np.empty(nnzL, np.int32),
+               L=np.empty(nnzL), scalars=np.empty(4))
+    order = ["mrp", "mci", "K", "D1", "D2", "Q", "V", "pot_global", "lrp", "lci", "L", "scalars"]
+    ptrs = [out[k].ctypes.data_as(C.c_void_p) for k in order]
+    _check(lib.mmsd_assembly_export(C.byref(a.c), a.mats, a.n_mats, sizes, *ptrs))
+    out["D1"] = out["D1"].reshape(3, nnzM)
+    out["D2"] = out["D2"].reshape(3, nnzM)
+    out["Q"] = out["Q"].reshape(6, N)
+    out.update(N=N, Nt=Nt)
+    return out
 
 
 def minimize_batch(problems: Sequence[Problem], **opts) -> List[Result]:

@@ -76,7 +76,7 @@ Layout make_layout(int64_t N, int64_t nnzM, int64_t Nt, int64_t nnzL, int G, siz
   L.u = take(s * Nt);
   L.p = take(s * Nt);
   for (int k = 0; k < 2; ++k) L.rec[k] = take(4 * s * Nt);
-  L.part = take(8 * 2 * (size_t)G * kNPart);
+  L.part = take(8 * 2 * (size_t)kMaxBlocks * kNPart);   // G may change between runs
   L.ctrl = take(2 * sizeof(Ctrl));
   L.prob = take(sizeof(Prob<double>));
   L.blk = take(8);
@@ -214,6 +214,24 @@ int build_device(mmsd_problem p) {
   return MMSD_OK;
 }
 
+// Change a problem's launch shape (lanes per row, block cap) between runs.
+int set_launch(mmsd_problem p, int lpr, int max_blocks) {
+  const int G = blocks_for(std::max<int64_t>(p->A.N, p->A.Nt), lpr, max_blocks);
+  if (G == p->G && lpr == p->lpr) return MMSD_OK;
+  for (auto& kv : p->graphs) hipGraphExecDestroy(kv.second);
+  p->graphs.clear();
+  p->lpr = lpr;
+  p->G = G;
+  if (p->precision == MMSD_MIXED) desc_of<float>(p).G = G;
+  else desc_of<double>(p).G = G;
+  const int blk[2] = {0, G};
+  hipStream_t st = p->ctx->stream;
+  MMSD_HIP(hipMemcpyAsync(p->dprob, p->desc, sizeof(Prob<double>), hipMemcpyHostToDevice, st));
+  MMSD_HIP(hipMemcpyAsync(p->dblk, blk, sizeof(blk), hipMemcpyHostToDevice, st));
+  MMSD_HIP(hipStreamSynchronize(st));
+  return MMSD_OK;
+}
+
 }  // namespace
 
 int resolve(mmsd_problem p, const mmsd_options* o, Resolved* r) {
@@ -270,42 +288,33 @@ int issue(mmsd_ctx c, const std::vector<Table>& tabs, int B, std::map<int, hipGr
   hipStream_t st = c->stream;
   if (B <= 0 || (B & 1)) return invalid("launch batches must have an even length");
   TimingState& T = c->timing;
+  // With timing on, one event pair brackets the whole batch: it measures the
+  // kernels back to back plus the gaps between them, the same launches a
+  // kernel trace records.
+  hipEvent_t e0 = nullptr, e1 = nullptr;
   if (T.stride > 0) {
-    for (int b = 0; b < B; ++b)
-      for (const Table& t : tabs) {
-        hipEvent_t e0, e1;
-        if (T.pool.size() < 2) {
-          MMSD_HIP(hipEventCreate(&e0));
-          MMSD_HIP(hipEventCreate(&e1));
-        } else {
-          e1 = T.pool.back();
-          T.pool.pop_back();
-          e0 = T.pool.back();
-          T.pool.pop_back();
-        }
-        MMSD_HIP(hipEventRecord(e0, st));
-        int rc = launch_table(t, b & 1, st);
-        if (rc) return rc;
-        MMSD_HIP(hipEventRecord(e1, st));
-        T.pending.push_back(e0);
-        T.pending.push_back(e1);
+    for (hipEvent_t* e : {&e0, &e1}) {
+      if (T.pool.empty()) {
+        MMSD_HIP(hipEventCreate(e));
+      } else {
+        *e = T.pool.back();
+        T.pool.pop_back();
       }
-    return MMSD_OK;
+    }
+    MMSD_HIP(hipEventRecord(e0, st));
   }
+  int rc = MMSD_OK;
   if (c->use_graph && graphs) {
     auto it = graphs->find(B);
     if (it == graphs->end()) {
       hipGraph_t g;
       MMSD_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-      for (int b = 0; b < B; ++b)
-        for (const Table& t : tabs) {
-          int rc = launch_table(t, b & 1, st);
-          if (rc) {
-            hipStreamEndCapture(st, &g);
-            return rc;
-          }
-        }
-      MMSD_HIP(hipStreamEndCapture(st, &g));
+      for (int b = 0; b < B && !rc; ++b)
+        for (const Table& t : tabs)
+          if (!rc) rc = launch_table(t, b & 1, st);
+      hipError_t ec = hipStreamEndCapture(st, &g);
+      if (rc) return rc;
+      if (ec != hipSuccess) return hip_fail(ec, "hipStreamEndCapture");
       hipGraphExec_t ex;
       hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
       hipGraphDestroy(g);
@@ -313,13 +322,18 @@ int issue(mmsd_ctx c, const std::vector<Table>& tabs, int B, std::map<int, hipGr
       it = graphs->emplace(B, ex).first;
     }
     MMSD_HIP(hipGraphLaunch(it->second, st));
-    return MMSD_OK;
+  } else {
+    for (int b = 0; b < B && !rc; ++b)
+      for (const Table& t : tabs)
+        if (!rc) rc = launch_table(t, b & 1, st);
+    if (rc) return rc;
   }
-  for (int b = 0; b < B; ++b)
-    for (const Table& t : tabs) {
-      int rc = launch_table(t, b & 1, st);
-      if (rc) return rc;
-    }
+  if (T.stride > 0) {
+    MMSD_HIP(hipEventRecord(e1, st));
+    T.pending.push_back(e0);
+    T.pending.push_back(e1);
+    T.pending_launches.push_back((double)B * (double)tabs.size());
+  }
   return MMSD_OK;
 }
 
@@ -330,11 +344,12 @@ int drain_timing(mmsd_ctx c) {
     float ms = 0;
     MMSD_HIP(hipEventElapsedTime(&ms, T.pending[k], T.pending[k + 1]));
     T.ms += ms;
-    T.count += 1;
+    T.count += T.pending_launches[k / 2];
     T.pool.push_back(T.pending[k]);
     T.pool.push_back(T.pending[k + 1]);
   }
   T.pending.clear();
+  T.pending_launches.clear();
   return MMSD_OK;
 }
 
@@ -989,6 +1004,145 @@ int mmsd_minimize_batch(mmsd_problem* probs, int n, const mmsd_options* o, mmsd_
   if (hdone) hipHostFree(hdone);
   c->dfree(tab);
   return rc ? rc : worst;
+}
+
+int mmsd_set_problem_launch(mmsd_problem p, int lanes_per_row, int max_blocks) {
+  if (!p) return invalid("null problem");
+  if (lanes_per_row != 4 && lanes_per_row != 8 && lanes_per_row != 16)
+    return invalid("lanes_per_row must be 4, 8 or 16");
+  if (max_blocks < 8 || max_blocks > kMaxBlocks || max_blocks % 8)
+    return invalid("max_blocks must be a multiple of 8 in [8, 2048]");
+  std::lock_guard<std::mutex> lk(p->ctx->mu);
+  MMSD_HIP(hipSetDevice(p->ctx->device));
+  return set_launch(p, lanes_per_row, max_blocks);
+}
+
+int mmsd_autotune(mmsd_problem p, int* lanes_out, int* blocks_out, double* us_out) {
+  if (!p) return invalid("null problem");
+  mmsd_ctx c = p->ctx;
+  // cache: (precision, log2 N, log2 Nt) -> best shape, per context
+  const int64_t key = ((int64_t)p->precision << 40) | ((int64_t)std::ilogb((double)p->A.N + 1) << 20) |
+                      (int64_t)std::ilogb((double)p->A.Nt + 1);
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    auto it = c->tuned.find(key);
+    if (it != c->tuned.end()) {
+      MMSD_HIP(hipSetDevice(c->device));
+      int rc = set_launch(p, it->second.first, it->second.second);
+      if (rc) return rc;
+      if (lanes_out) *lanes_out = p->lpr;
+      if (blocks_out) *blocks_out = it->second.second;
+      if (us_out) *us_out = -1.0;
+      return MMSD_OK;
+    }
+  }
+  // Time a fixed slice of the potential solve (PREP, CG0 and CG iterations,
+  // no convergence test) for each shape; the potential is restored after.
+  Resolved r;
+  mmsd_options o;
+  mmsd_options_default(&o);
+  o.pcg_rtol = 1e-300;
+  o.pcg_maxit = 1 << 30;
+  o.terms = p->A.Nt ? MMSD_ALL : (MMSD_EXCH | MMSD_ANIS | MMSD_ZEEM);
+  int rc = resolve(p, &o, &r);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(c->mu);
+  MMSD_HIP(hipSetDevice(c->device));
+  hipStream_t st = c->stream;
+  const int B = 32;
+  const int saved_stride = c->timing.stride;
+  c->timing.stride = 0;
+  hipEvent_t e0, e1;
+  MMSD_HIP(hipEventCreate(&e0));
+  MMSD_HIP(hipEventCreate(&e1));
+  double best = 1e300;
+  int best_l = p->lpr, best_b = c->max_blocks;
+  for (int lpr : {4, 8, 16}) {
+    int lastG = -1;
+    for (int mb : {128, 256, 512, 1024, 2048}) {
+      if ((rc = set_launch(p, lpr, mb))) break;
+      if (p->G == lastG) continue;
+      lastG = p->G;
+      double t_best = 1e300;
+      for (int rep = 0; rep < 2 && !rc; ++rep) {
+        if ((rc = (p->precision == MMSD_MIXED ? snapshot<float>(p, 1, true) : snapshot<double>(p, 1, true)))) break;
+        if ((rc = arm(p, r, ST_EVAL, 0))) break;
+        std::vector<Table> tabs{{p->precision, p->dprob, p->dblk, 1, p->G, p->lpr}};
+        MMSD_HIP(hipEventRecord(e0, st));
+        if ((rc = issue(c, tabs, B, nullptr))) break;
+        MMSD_HIP(hipEventRecord(e1, st));
+        MMSD_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        MMSD_HIP(hipEventElapsedTime(&ms, e0, e1));
+        t_best = std::min(t_best, (double)ms * 1e3 / B);
+        if ((rc = (p->precision == MMSD_MIXED ? snapshot<float>(p, 1, false) : snapshot<double>(p, 1, false)))) break;
+        MMSD_HIP(hipStreamSynchronize(st));
+      }
+      if (rc) break;
+      if (t_best < best) {
+        best = t_best;
+        best_l = lpr;
+        best_b = mb;
+      }
+    }
+    if (rc) break;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  c->timing.stride = saved_stride;
+  if (rc) return rc;
+  // leave the problem idle at the chosen shape
+  if ((rc = set_launch(p, best_l, best_b))) return rc;
+  c->tuned[key] = {best_l, best_b};
+  if (lanes_out) *lanes_out = best_l;
+  if (blocks_out) *blocks_out = best_b;
+  if (us_out) *us_out = best;
+  return MMSD_OK;
+}
+
+int mmsd_assembly_export(const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats, int64_t sizes[4],
+                         int32_t* mrp, int32_t* mci, double* K, double* D1, double* D2, double* Q, double* V,
+                         int32_t* pot_global, int32_t* lrp, int32_t* lci, double* L, double* scalars) {
+  if (!sizes) return invalid("null sizes");
+  Assembly A;
+  std::string err;
+  int rc = assemble(mesh, mats, n_mats, &A, &err);
+  if (rc) {
+    set_error(err);
+    return rc;
+  }
+  const int64_t nnzM = (int64_t)A.mci.size(), nnzL = (int64_t)A.lci.size();
+  sizes[0] = A.N;
+  sizes[1] = nnzM;
+  sizes[2] = A.Nt;
+  sizes[3] = nnzL;
+  auto put_i = [](int32_t* dst, const std::vector<int>& v) {
+    if (dst) std::copy(v.begin(), v.end(), dst);
+  };
+  auto put_d = [](double* dst, const std::vector<double>& v) {
+    if (dst) std::copy(v.begin(), v.end(), dst);
+  };
+  put_i(mrp, A.mrp);
+  put_i(mci, A.mci);
+  put_d(K, A.K);
+  for (int c3 = 0; c3 < 3; ++c3) {
+    if (D1) std::copy(A.D1[c3].begin(), A.D1[c3].end(), D1 + c3 * nnzM);
+    if (D2) std::copy(A.D2[c3].begin(), A.D2[c3].end(), D2 + c3 * nnzM);
+  }
+  for (int c6 = 0; c6 < 6; ++c6)
+    if (Q) std::copy(A.Q[c6].begin(), A.Q[c6].end(), Q + c6 * (int64_t)A.N);
+  put_d(V, A.V);
+  put_i(pot_global, A.pot_global);
+  put_i(lrp, A.lrp);
+  put_i(lci, A.lci);
+  put_d(L, A.L);
+  if (scalars) {
+    scalars[0] = A.c_an;
+    scalars[1] = A.vol;
+    scalars[2] = A.Ms;
+    scalars[3] = A.mu0Ms2;
+  }
+  return MMSD_OK;
 }
 
 int mmsd_get_state(mmsd_problem p, void* buf, size_t* bytes) {

@@ -59,6 +59,7 @@ struct TimingState {
   double ms = 0, count = 0, bytes = 0;
   std::vector<hipEvent_t> pool;        // free events
   std::vector<hipEvent_t> pending;     // recorded (start, end) pairs not yet read
+  std::vector<double> pending_launches;  // step launches inside each pair
 };
 
 }  // namespace mmsd
@@ -87,6 +88,7 @@ struct mmsd_ctx_s {
   int max_blocks = 512;
   bool use_graph = true;
   mmsd::TimingState timing;
+  std::map<int64_t, std::pair<int, int>> tuned;   // autotuner results by problem class
   std::mutex mu;            // serializes device work issued through this context
   void* dalloc(size_t bytes);
   void dfree(void* p);

@@ -199,13 +199,10 @@ def assign_grains(mesh: Mesh, n_grains: int, rng: np.random.Generator,
     if n_grains == 1:
         reg = np.ones(cen.shape[0], dtype=np.int32)
     else:
-        d2 = np.empty((cen.shape[0], n_grains))
-        for g in range(n_grains):
-            d2[:, g] = ((cen - centres[g]) ** 2).sum(axis=1)
-        order = np.argsort(d2, axis=1)[:, :2]
-        c1, c2 = order[:, 0], order[:, 1]
-        d1 = d2[np.arange(cen.shape[0]), c1]
-        dd = d2[np.arange(cen.shape[0]), c2]
+        from scipy.spatial import cKDTree
+        dist, idx = cKDTree(centres).query(cen, k=2)
+        c1, c2 = idx[:, 0], idx[:, 1]
+        d1, dd = dist[:, 0] ** 2, dist[:, 1] ** 2
         sep = np.linalg.norm(centres[c2] - centres[c1], axis=1)
         dist_face = (dd - d1) / (2 * sep)
         reg = (c1 + 1).astype(np.int32)

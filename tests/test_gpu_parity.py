@@ -155,3 +155,47 @@ def test_stoner_wohlfarth_cube_without_stray_field(ctx):
     assert abs(r.energy_J - ro.E) < 1e-10 * abs(ro.E)
     np.testing.assert_allclose(p.get_m(), ro.m, atol=1e-8)
     p.close()
+
+
+def test_evaluate_config2_full_size_matches_oracle(ctx):
+    """The full 80 nm cube (68,921 magnet / 250,047 free potential nodes) in
+    the launch configuration the benchmark times: energies and the field at
+    every node against one oracle evaluation."""
+    from paper_1309_5796_amd import binding
+    say("evaluate config2 full size")
+    cfg = meshgen.config2()
+    s = oracle.System(cfg["mesh"])
+    rng = np.random.default_rng(21)
+    m = np.tile([0.0, 0.0, 1.0], (s.N, 1)) + 0.2 * rng.normal(size=(s.N, 3))
+    m /= np.linalg.norm(m, axis=1, keepdims=True)
+    B = cfg["fields"][100]
+    p = binding.Problem(ctx, cfg["mesh"])
+    p.set_m(m)
+    p.set_field(B)
+    r = p.evaluate(pcg_rtol=1e-13, pcg_maxit=20000)
+    ev = s.evaluate(m, B)
+    assert rel_energy_err(r.energy_J, ev) < 1e-11
+    h = p.get_field()
+    assert np.abs(h - ev["h"]).max() < 1e-9 * np.abs(ev["h"]).max()
+    p.close()
+
+
+def test_autotune_keeps_state_and_result(ctx, cfg1):
+    from paper_1309_5796_amd import binding
+    say("autotune")
+    p = binding.Problem(ctx, cfg1["mesh"])
+    p.set_m(cfg1["m0"])
+    p.set_field(cfg1["b_ext"])
+    st = p.get_state()
+    r0 = p.minimize()
+    p.set_state(st)
+    lanes, blocks, us = p.autotune()
+    assert lanes in (4, 8, 16) and blocks % 8 == 0 and us > 0
+    assert p.get_state() == st
+    r1 = p.minimize()
+    scale = abs(r0.e_exch_J) + abs(r0.e_anis_J) + abs(r0.e_zeem_J) + abs(r0.e_demag_J)
+    assert abs(r1.energy_J - r0.energy_J) < 1e-11 * scale
+    q = binding.Problem(ctx, cfg1["mesh"])
+    assert q.autotune()[:2] == (lanes, blocks)        # cached class, no timing
+    p.close()
+    q.close()
