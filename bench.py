@@ -60,6 +60,26 @@ print(json.dumps(dict(evals=r.evals, seconds=dt, N=s.N)))
                       f"(FP64 NumPy/SciPy, potential by Jacobi-CG to 1e-13), {d['seconds']:.1f} s on one core"}
 
 
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("paper_1309_5796_amd/csrc/kernels.hip", "paper_1309_5796_amd/csrc/device.h"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(name: str):
+    """HBM bytes per launch from the committed counter runs (calibrated
+    FETCH_SIZE + WRITE_SIZE), or None when the kernel source has changed since."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    return rec["traffic_bytes_per_launch"] if rec.get("kernel_source_sha256") == kernel_source_hash() else None
+
+
 def roofline_of(tm, lanes):
     if tm["launches"] <= 0 or tm["ms"] <= 0:
         return None
@@ -238,6 +258,17 @@ def run_serve(args):
     print(json.dumps(line), flush=True)
 
 
+def run_copy(args):
+    """Counter calibration: a plain 256 MiB device copy (read 256 MiB, write 256 MiB)."""
+    from paper_1309_5796_amd import binding
+    ctx = binding.Context(0)
+    nbytes = 256 << 20
+    ms = ctx.copy_probe(nbytes, reps=args.steps if args.steps != 161 else 10)
+    print(json.dumps({"workload": "copy probe", "bytes_read": nbytes, "bytes_written": nbytes,
+                      "ms": ms, "GBps": 2 * nbytes / ms / 1e6}), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -248,7 +279,7 @@ def main():
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=20, help="field points per library call")
-    ap.add_argument("--workload", default="sweep80", choices=["sweep80", "poly", "grains", "serve"])
+    ap.add_argument("--workload", default="sweep80", choices=["sweep80", "poly", "grains", "serve", "copy"])
     ap.add_argument("--max-evals", type=int, default=100000)
     ap.add_argument("--grains", type=int, default=256)
     ap.add_argument("--requests", type=int, default=60)
@@ -261,7 +292,7 @@ def main():
               f"described but not built", file=sys.stderr)
         sys.exit(2)
     if args.workload != "sweep80":
-        {"poly": run_poly, "grains": run_grains, "serve": run_serve}[args.workload](args)
+        {"poly": run_poly, "grains": run_grains, "serve": run_serve, "copy": run_copy}[args.workload](args)
         return
 
     import numpy as np
@@ -304,11 +335,12 @@ def main():
     value = p.N * evals / wall
 
     roof = None
+    traffic = measured_traffic("k_step_fp64_sweep80")
     if tm["launches"] > 0 and tm["ms"] > 0:
         avg_s = tm["ms"] / 1e3 / tm["launches"]
         achieved = tm["bytes"] / tm["launches"] / avg_s / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "kernel": f"k_step<double,{args.lanes or 4}>", "avg_launch_us": avg_s * 1e6,
                 "alg_bytes_per_launch": tm["bytes"] / tm["launches"], "launches_timed": tm["launches"]}
     line = {

@@ -217,6 +217,12 @@ int mmsd_timing_read(mmsd_ctx ctx, double stats[3], int reset);
  * value.  Applies to problems created afterwards. */
 int mmsd_set_launch_config(mmsd_ctx ctx, int lanes_per_row, int max_blocks);
 
+/* Measurement aid: `reps` launches of a plain device-to-device copy kernel
+ * (k_copy_probe) of `bytes` bytes each; *ms_out (nullable) gets the mean
+ * time per launch.  Used to calibrate hardware traffic counters against a
+ * known byte count. */
+int mmsd_copy_probe(mmsd_ctx ctx, size_t bytes, int reps, double* ms_out);
+
 /* Launch shape of one problem: lanes per CSR row (4, 8, 16) and the block
  * cap (multiple of 8, <= 2048).  Takes effect at the next run. */
 int mmsd_set_problem_launch(mmsd_problem p, int lanes_per_row, int max_blocks);

@@ -83,6 +83,7 @@ SIGNATURES = [
     ("mmsd_timing_enable", C.c_int, [C.c_void_p, C.c_int]),
     ("mmsd_timing_read", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int]),
     ("mmsd_set_launch_config", C.c_int, [C.c_void_p, C.c_int, C.c_int]),
+    ("mmsd_copy_probe", C.c_int, [C.c_void_p, C.c_size_t, C.c_int, C.POINTER(C.c_double)]),
     ("mmsd_set_problem_launch", C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     ("mmsd_autotune", C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     ("mmsd_assembly_export", C.c_int, [C.POINTER(MeshC), C.POINTER(MaterialC), C.c_int, C.POINTER(C.c_int64)]
@@ -234,6 +235,12 @@ class Context:
         s = (C.c_double * 3)()
         _check(self.lib.mmsd_timing_read(self.handle, s, 1 if reset else 0))
         return dict(ms=s[0], launches=int(s[1]), bytes=s[2])
+
+    def copy_probe(self, nbytes: int, reps: int = 10) -> float:
+        """Mean milliseconds of a plain copy kernel of nbytes (counter calibration)."""
+        ms = C.c_double()
+        _check(self.lib.mmsd_copy_probe(self.handle, nbytes, reps, C.byref(ms)))
+        return ms.value
 
     def close(self):
         if getattr(self, "handle", None):

@@ -1006,6 +1006,42 @@ int mmsd_minimize_batch(mmsd_problem* probs, int n, const mmsd_options* o, mmsd_
   return rc ? rc : worst;
 }
 
+int mmsd_copy_probe(mmsd_ctx c, size_t bytes, int reps, double* ms_out) {
+  if (!c || bytes < 16 || reps < 1) return invalid("bad copy probe request");
+  std::lock_guard<std::mutex> lk(c->mu);
+  MMSD_HIP(hipSetDevice(c->device));
+  bytes &= ~size_t(15);
+  void* a = c->dalloc(bytes);
+  void* b = c->dalloc(bytes);
+  if (!a || !b) {
+    c->dfree(a);
+    c->dfree(b);
+    return invalid("copy probe allocation failed");
+  }
+  hipStream_t st = c->stream;
+  hipEvent_t e0, e1;
+  int rc = MMSD_OK;
+  if (hipMemsetAsync(a, 0, bytes, st) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+      hipEventCreate(&e1) != hipSuccess) {
+    rc = hip_fail(hipGetLastError(), "copy probe setup");
+  } else {
+    hipEventRecord(e0, st);
+    for (int k = 0; k < reps && !rc; ++k)
+      if (launch_copy_probe(a, b, bytes, st) != hipSuccess) rc = hip_fail(hipGetLastError(), "copy probe");
+    hipEventRecord(e1, st);
+    hipEventSynchronize(e1);
+    float ms = 0;
+    hipEventElapsedTime(&ms, e0, e1);
+    if (ms_out) *ms_out = ms / reps;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+  }
+  hipStreamSynchronize(st);
+  c->dfree(a);
+  c->dfree(b);
+  return rc;
+}
+
 int mmsd_set_problem_launch(mmsd_problem p, int lanes_per_row, int max_blocks) {
   if (!p) return invalid("null problem");
   if (lanes_per_row != 4 && lanes_per_row != 8 && lanes_per_row != 16)

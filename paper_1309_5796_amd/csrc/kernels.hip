@@ -742,7 +742,20 @@ __global__ void k_ctrl_init(Ctrl* ctrl, int slot, CtrlInit a) {
   C->gam = C->dlt = C->bb = C->rr = C->ru = C->alpha = C->beta = 0.0;
 }
 
+// Plain streaming copy, 16 bytes per thread per step: the reference kernel
+// for calibrating hardware traffic counters against a known byte count.
+__global__ void __launch_bounds__(256) k_copy_probe(const double2* __restrict__ src, double2* __restrict__ dst,
+                                                    long long n) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) dst[i] = src[i];
+}
+
 }  // namespace
+
+hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream_t s) {
+  const long long n = (long long)(bytes / 16);
+  hipLaunchKernelGGL(k_copy_probe, dim3(2048), dim3(256), 0, s, (const double2*)src, (double2*)dst, n);
+  return hipGetLastError();
+}
 
 // ---- host-side launch wrappers -------------------------------------------
 template <typename real>

@@ -32,6 +32,8 @@ hipError_t launch_ctrl_init(Ctrl* ctrl, int slot, int stage, int terms, int nonm
                             int pcg_maxit, int store_h, int demag, int acc, long long max_evals,
                             const double* dparams, hipStream_t s);
 
+hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream_t s);
+
 // Every batch of step launches starts with parity 0 and has an even length,
 // so the state a run is armed with goes into slot 1.
 constexpr int kArmSlot = 1;
