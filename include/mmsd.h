@@ -63,6 +63,11 @@ extern "C" {
 #define MMSD_DEMAG 8
 #define MMSD_ALL 15
 
+/* preconditioner of the scalar-potential solve */
+#define MMSD_PRECOND_AUTO 0   /* multigrid when its setup succeeded, else Jacobi */
+#define MMSD_PRECOND_JACOBI 1 /* Jacobi, single-reduction CG: one launch per iteration */
+#define MMSD_PRECOND_AMG 2    /* smoothed-aggregation multigrid V(1,1) cycle, PCG */
+
 /* step-length rules (eq. (9)); ADAPTIVE is the rule the paper uses */
 #define MMSD_STEP_ADAPTIVE 0  /* adaptive tau1/tau2 switching with a min-window */
 #define MMSD_STEP_ALTERNATE 1 /* plain alternation of tau1 and tau2 */
@@ -146,6 +151,8 @@ typedef struct {
   int pcg_maxit;        /* default 5000 */
   int step_rule;        /* MMSD_STEP_*; default adaptive */
   double refine_tol_T;  /* hysteresis: > 0 bisects each switching field to this width (T) */
+  int precond;          /* MMSD_PRECOND_*; default AUTO */
+  int pad0;
 } mmsd_options;
 
 /* Defaults: every field zero selects its default. */

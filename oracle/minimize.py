@@ -50,6 +50,7 @@ class Options:
     tau_max: float = 1e10
     tau_floor: float = 1e-14
     theta0: float = 0.1
+    step_rule: str = "adaptive"  # "adaptive" (the paper's choice), "alternate", "bb1", "bb2"
     record: bool = False       # keep per-step diagnostics
 
 
@@ -120,6 +121,7 @@ def minimize(sys, m0: np.ndarray, b_ext, opts: Optional[Options] = None) -> Resu
     tau = o.theta0 / T
     kappa = o.kappa0
     window: List[float] = []
+    alt = False
     first = True
     iters = 0
     while True:
@@ -162,14 +164,23 @@ def minimize(sys, m0: np.ndarray, b_ext, opts: Optional[Options] = None) -> Resu
             tau = min(10.0 * tau, o.tau_max)
         else:
             t1, t2 = ss / sy, sy / yy
-            window.append(t2)
-            window = window[-(o.M_alpha + 1):]
-            if t2 / t1 < kappa:
-                tau = min(window)
-                kappa *= 0.9
-            else:
+            if o.step_rule == "bb1":
                 tau = t1
-                kappa *= 1.1
+            elif o.step_rule == "bb2":
+                tau = t2
+            elif o.step_rule == "alternate":
+                # plain alternation, starting with tau1 (step-length subsection)
+                tau = t2 if alt else t1
+                alt = not alt
+            else:
+                window.append(t2)
+                window = window[-(o.M_alpha + 1):]
+                if t2 / t1 < kappa:
+                    tau = min(window)
+                    kappa *= 0.9
+                else:
+                    tau = t1
+                    kappa *= 1.1
         tau = min(max(tau, o.tau_min), o.tau_max)
 
 

@@ -25,6 +25,7 @@ E_INVALID, E_MESH, E_NOMEM, E_HIP, E_NONFINITE, E_BUSY, E_CANCELLED = -1, -2, -3
 FP64, MIXED = 0, 1
 EXCH, ANIS, ZEEM, DEMAG, ALL = 1, 2, 4, 8, 15
 STEP_ADAPTIVE, STEP_ALTERNATE, STEP_BB1, STEP_BB2 = 0, 1, 2, 3
+PRECOND_AUTO, PRECOND_JACOBI, PRECOND_AMG = 0, 1, 2
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -45,7 +46,8 @@ class MaterialC(C.Structure):
 class OptionsC(C.Structure):
     _fields_ = [("tol_torque", C.c_double), ("max_evals", C.c_int64), ("terms", C.c_int),
                 ("nonmono_M", C.c_int), ("pcg_rtol", C.c_double), ("pcg_maxit", C.c_int),
-                ("step_rule", C.c_int), ("refine_tol_T", C.c_double)]
+                ("step_rule", C.c_int), ("refine_tol_T", C.c_double), ("precond", C.c_int),
+                ("pad0", C.c_int)]
 
 
 class ResultC(C.Structure):
@@ -166,9 +168,9 @@ class Result:
 
 def make_options(tol: float = 0.0, max_evals: int = 0, terms: int = 0, nonmono_M: int = 0,
                  pcg_rtol: float = 0.0, pcg_maxit: int = 0, step_rule: int = 0,
-                 refine_tol_T: float = 0.0) -> OptionsC:
+                 refine_tol_T: float = 0.0, precond: int = 0) -> OptionsC:
     """Options struct; zero fields select the library defaults."""
-    return OptionsC(tol, max_evals, terms, nonmono_M, pcg_rtol, pcg_maxit, step_rule, refine_tol_T)
+    return OptionsC(tol, max_evals, terms, nonmono_M, pcg_rtol, pcg_maxit, step_rule, refine_tol_T, precond, 0)
 
 
 class _TorchAllocator:

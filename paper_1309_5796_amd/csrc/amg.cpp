@@ -1,0 +1,313 @@
+// Smoothed-aggregation AMG setup (host, C++17).
+//
+// Level l -> l + 1:
+//   strength:   j is a strong neighbour of i if |a_ij| >= theta sqrt(|a_ii a_jj|)
+//   aggregates: pass 1 takes every node whose strong neighbours are all free,
+//               with those neighbours; pass 2 joins leftover nodes to a
+//               neighbouring aggregate; pass 3 groups what is still left
+//   tentative:  T_i,agg(i) = 1 (the constants, the Laplacian's near-kernel)
+//   smoothing:  P = (I - omega D^-1 A) T on the first `smooth_levels` levels,
+//               P = T below (keeps coarse stencils sparse)
+//   Galerkin:   A_{l+1} = P^T A P
+// The coarsest operator is inverted densely (Cholesky, then the inverse).
+#include "amg.h"
+
+#include <algorithm>
+#include <cmath>
+#include <functional>
+#include <random>
+#include <thread>
+
+namespace mmsd {
+namespace {
+
+void pfor(int64_t n, const std::function<void(int64_t, int64_t)>& f) {
+  unsigned hw = std::thread::hardware_concurrency();
+  int nt = (int)std::max<unsigned>(1, std::min<unsigned>(hw ? hw : 4, 16));
+  if (n < 2048) nt = 1;
+  if (nt == 1) {
+    f(0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  const int64_t c = (n + nt - 1) / nt;
+  for (int t = 0; t < nt; ++t) {
+    const int64_t a = t * c, b = std::min(n, a + c);
+    if (a < b) th.emplace_back(f, a, b);
+  }
+  for (auto& x : th) x.join();
+}
+
+std::vector<double> diagonal(const Csr& A) {
+  std::vector<double> d(A.nrows, 0.0);
+  for (int i = 0; i < A.nrows; ++i)
+    for (int k = A.rp[i]; k < A.rp[i + 1]; ++k)
+      if (A.ci[k] == i) d[i] = A.v[k];
+  return d;
+}
+
+// Largest eigenvalue of D^-1 A by power iteration (fixed seed).
+double spectral_radius(const Csr& A, const std::vector<double>& dinv) {
+  const int n = A.nrows;
+  std::vector<double> x(n), y(n);
+  std::mt19937_64 rng(12345);
+  std::uniform_real_distribution<double> U(-1.0, 1.0);
+  for (auto& v : x) v = U(rng);
+  double lam = 1.0;
+  for (int it = 0; it < 20; ++it) {
+    pfor(n, [&](int64_t a, int64_t b) {
+      for (int64_t i = a; i < b; ++i) {
+        double s = 0;
+        for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) s += A.v[k] * x[A.ci[k]];
+        y[i] = dinv[i] * s;
+      }
+    });
+    double nrm = 0, nx = 0;
+    for (int i = 0; i < n; ++i) {
+      nrm += y[i] * y[i];
+      nx += x[i] * x[i];
+    }
+    lam = std::sqrt(nrm / nx);
+    const double s = 1.0 / std::sqrt(nrm);
+    for (int i = 0; i < n; ++i) x[i] = y[i] * s;
+  }
+  return lam;
+}
+
+int aggregate(const Csr& A, const std::vector<double>& d, double theta, std::vector<int>& agg) {
+  const int n = A.nrows;
+  // strength graph
+  std::vector<int> sp(n + 1, 0), sc;
+  sc.reserve(A.ci.size());
+  for (int i = 0; i < n; ++i) {
+    for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+      const int j = A.ci[k];
+      if (j != i && std::fabs(A.v[k]) >= theta * std::sqrt(std::fabs(d[i] * d[j]))) sc.push_back(j);
+    }
+    sp[i + 1] = (int)sc.size();
+  }
+  agg.assign(n, -1);
+  int na = 0;
+  for (int i = 0; i < n; ++i) {
+    if (agg[i] >= 0) continue;
+    bool free_nb = true;
+    for (int k = sp[i]; k < sp[i + 1] && free_nb; ++k) free_nb = agg[sc[k]] < 0;
+    if (!free_nb) continue;
+    agg[i] = na;
+    for (int k = sp[i]; k < sp[i + 1]; ++k) agg[sc[k]] = na;
+    ++na;
+  }
+  std::vector<int> pass2(n, -1);
+  for (int i = 0; i < n; ++i) {
+    if (agg[i] >= 0) continue;
+    for (int k = sp[i]; k < sp[i + 1]; ++k)
+      if (agg[sc[k]] >= 0) {
+        pass2[i] = agg[sc[k]];
+        break;
+      }
+  }
+  for (int i = 0; i < n; ++i)
+    if (agg[i] < 0 && pass2[i] >= 0) agg[i] = pass2[i];
+  for (int i = 0; i < n; ++i) {
+    if (agg[i] >= 0) continue;
+    agg[i] = na;
+    for (int k = sp[i]; k < sp[i + 1]; ++k)
+      if (agg[sc[k]] < 0) agg[sc[k]] = na;
+    ++na;
+  }
+  return na;
+}
+
+Csr transpose(const Csr& M) {
+  Csr T;
+  T.nrows = M.ncols;
+  T.ncols = M.nrows;
+  T.rp.assign(T.nrows + 1, 0);
+  for (int c : M.ci) T.rp[c + 1]++;
+  for (int i = 0; i < T.nrows; ++i) T.rp[i + 1] += T.rp[i];
+  T.ci.resize(M.ci.size());
+  T.v.resize(M.v.size());
+  std::vector<int> fill(T.rp.begin(), T.rp.end() - 1);
+  for (int i = 0; i < M.nrows; ++i)
+    for (int k = M.rp[i]; k < M.rp[i + 1]; ++k) {
+      const int pos = fill[M.ci[k]]++;
+      T.ci[pos] = i;
+      T.v[pos] = M.v[k];
+    }
+  return T;   // rows come out with ascending columns
+}
+
+// C = A B (Gustavson, rows in parallel, sorted columns).
+Csr spgemm(const Csr& A, const Csr& B) {
+  Csr C;
+  C.nrows = A.nrows;
+  C.ncols = B.ncols;
+  std::vector<std::vector<int>> cols(A.nrows);
+  std::vector<std::vector<double>> vals(A.nrows);
+  pfor(A.nrows, [&](int64_t a, int64_t b) {
+    std::vector<double> acc(B.ncols, 0.0);
+    std::vector<int> mark(B.ncols, -1), list;
+    for (int64_t i = a; i < b; ++i) {
+      list.clear();
+      for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+        const int kk = A.ci[k];
+        const double av = A.v[k];
+        for (int m = B.rp[kk]; m < B.rp[kk + 1]; ++m) {
+          const int j = B.ci[m];
+          if (mark[j] != (int)i) {
+            mark[j] = (int)i;
+            acc[j] = 0.0;
+            list.push_back(j);
+          }
+          acc[j] += av * B.v[m];
+        }
+      }
+      std::sort(list.begin(), list.end());
+      cols[i] = list;
+      vals[i].resize(list.size());
+      for (size_t q = 0; q < list.size(); ++q) vals[i][q] = acc[list[q]];
+    }
+  });
+  C.rp.assign(C.nrows + 1, 0);
+  for (int i = 0; i < C.nrows; ++i) C.rp[i + 1] = C.rp[i] + (int)cols[i].size();
+  C.ci.resize(C.rp.back());
+  C.v.resize(C.rp.back());
+  pfor(C.nrows, [&](int64_t a, int64_t b) {
+    for (int64_t i = a; i < b; ++i) {
+      std::copy(cols[i].begin(), cols[i].end(), C.ci.begin() + C.rp[i]);
+      std::copy(vals[i].begin(), vals[i].end(), C.v.begin() + C.rp[i]);
+    }
+  });
+  return C;
+}
+
+// Dense SPD inverse by Cholesky (n is small).
+bool dense_inverse(const Csr& A, std::vector<double>& inv) {
+  const int n = A.nrows;
+  std::vector<double> L((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) L[(size_t)i * n + A.ci[k]] = A.v[k];
+  for (int j = 0; j < n; ++j) {
+    double s = L[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) s -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+    if (!(s > 0)) return false;
+    const double ljj = std::sqrt(s);
+    L[(size_t)j * n + j] = ljj;
+    for (int i = j + 1; i < n; ++i) {
+      double t = L[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) t -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+      L[(size_t)i * n + j] = t / ljj;
+    }
+    for (int i = 0; i < j; ++i) L[(size_t)i * n + j] = 0.0;
+  }
+  // inverse column by column: L L^T x = e_c
+  inv.assign((size_t)n * n, 0.0);
+  std::vector<double> y(n);
+  for (int c = 0; c < n; ++c) {
+    for (int i = 0; i < n; ++i) {
+      double t = (i == c) ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) t -= L[(size_t)i * n + k] * y[k];
+      y[i] = t / L[(size_t)i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double t = y[i];
+      for (int k = i + 1; k < n; ++k) t -= L[(size_t)k * n + i] * inv[(size_t)k * n + c];
+      inv[(size_t)i * n + c] = t / L[(size_t)i * n + i];
+    }
+  }
+  // symmetrize against rounding
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j) {
+      const double m = 0.5 * (inv[(size_t)i * n + j] + inv[(size_t)j * n + i]);
+      inv[(size_t)i * n + j] = inv[(size_t)j * n + i] = m;
+    }
+  return true;
+}
+
+}  // namespace
+
+bool amg_setup(const Csr& A0, const AmgParams& prm, AmgHierarchy* h) {
+  h->lv.clear();
+  Csr A = A0;
+  double nnz_total = (double)A0.ci.size();
+  while (A.nrows > prm.coarse_max && (int)h->lv.size() < prm.max_levels) {
+    AmgLevel L;
+    std::vector<double> d = diagonal(A);
+    L.dinv.resize(A.nrows);
+    for (int i = 0; i < A.nrows; ++i) L.dinv[i] = 1.0 / d[i];
+    const double rho = spectral_radius(A, L.dinv);
+    L.omega = 4.0 / (3.0 * rho);
+    std::vector<int> agg;
+    const int na = aggregate(A, d, prm.theta, agg);
+    if (na >= (int)(0.8 * A.nrows) || na < 1) break;   // no useful coarsening
+    Csr T;
+    T.nrows = A.nrows;
+    T.ncols = na;
+    T.rp.resize(A.nrows + 1);
+    T.ci.resize(A.nrows);
+    T.v.assign(A.nrows, 1.0);
+    for (int i = 0; i <= A.nrows; ++i) T.rp[i] = i;
+    for (int i = 0; i < A.nrows; ++i) T.ci[i] = agg[i];
+    if ((int)h->lv.size() < prm.smooth_levels) {
+      // P = T - omega D^-1 A T
+      Csr AT = spgemm(A, T);
+      for (int i = 0; i < AT.nrows; ++i)
+        for (int k = AT.rp[i]; k < AT.rp[i + 1]; ++k) AT.v[k] *= -L.omega * L.dinv[i];
+      // add T (one entry per row, column agg[i])
+      Csr P;
+      P.nrows = A.nrows;
+      P.ncols = na;
+      P.rp.assign(A.nrows + 1, 0);
+      std::vector<std::vector<std::pair<int, double>>> rows(A.nrows);
+      pfor(A.nrows, [&](int64_t a, int64_t b) {
+        for (int64_t i = a; i < b; ++i) {
+          auto& r = rows[i];
+          bool found = false;
+          for (int k = AT.rp[i]; k < AT.rp[i + 1]; ++k) {
+            double v = AT.v[k];
+            if (AT.ci[k] == agg[i]) {
+              v += 1.0;
+              found = true;
+            }
+            r.emplace_back(AT.ci[k], v);
+          }
+          if (!found) {
+            r.emplace_back(agg[i], 1.0);
+            std::sort(r.begin(), r.end());
+          }
+        }
+      });
+      for (int i = 0; i < A.nrows; ++i) P.rp[i + 1] = P.rp[i] + (int)rows[i].size();
+      P.ci.resize(P.rp.back());
+      P.v.resize(P.rp.back());
+      for (int i = 0; i < A.nrows; ++i)
+        for (size_t q = 0; q < rows[i].size(); ++q) {
+          P.ci[P.rp[i] + q] = rows[i][q].first;
+          P.v[P.rp[i] + q] = rows[i][q].second;
+        }
+      L.P = std::move(P);
+    } else {
+      L.P = std::move(T);
+    }
+    L.R = transpose(L.P);
+    Csr AP = spgemm(A, L.P);
+    Csr Ac = spgemm(L.R, AP);
+    L.A = std::move(A);
+    h->lv.push_back(std::move(L));
+    A = std::move(Ac);
+    nnz_total += (double)A.ci.size();
+  }
+  if (h->lv.empty() || A.nrows > 4 * prm.coarse_max + 2000) {
+    h->lv.clear();
+    return false;
+  }
+  h->nc = A.nrows;
+  if (!dense_inverse(A, h->Ainv)) {
+    h->lv.clear();
+    return false;
+  }
+  h->complexity = nnz_total / (double)A0.ci.size();
+  return true;
+}
+
+}  // namespace mmsd

@@ -1,0 +1,41 @@
+// Host setup of the algebraic multigrid preconditioner for the scalar-potential
+// solve: smoothed aggregation on the finest level, plain aggregation below,
+// Galerkin coarse operators, dense inverse on the coarsest level.
+#pragma once
+#include <vector>
+
+namespace mmsd {
+
+struct Csr {
+  int nrows = 0, ncols = 0;
+  std::vector<int> rp, ci;
+  std::vector<double> v;
+};
+
+struct AmgLevel {
+  Csr A;                   // operator of this level
+  std::vector<double> dinv;
+  double omega = 0;        // Jacobi smoothing weight 4 / (3 rho(D^-1 A))
+  Csr P;                   // prolongation to this level from the next coarser one
+  Csr R;                   // restriction, the transpose of P
+};
+
+struct AmgHierarchy {
+  std::vector<AmgLevel> lv;      // levels 0 .. L-1 (each with P/R to level l+1)
+  int nc = 0;                    // size of the coarsest level L
+  std::vector<double> Ainv;      // dense inverse of the coarsest operator, row-major
+  double complexity = 0;         // total nonzeros of all operators / nonzeros of A_0
+};
+
+struct AmgParams {
+  double theta = 0.04;           // strength of connection |a_ij| >= theta sqrt(a_ii a_jj)
+  int smooth_levels = 1;         // levels whose prolongation is Jacobi-smoothed
+  int coarse_max = 600;          // stop coarsening at or below this size
+  int max_levels = 10;
+};
+
+// Build the hierarchy for the symmetric positive definite CSR matrix A.
+// Returns false (and leaves h empty) when the matrix does not coarsen.
+bool amg_setup(const Csr& A, const AmgParams& prm, AmgHierarchy* h);
+
+}  // namespace mmsd

@@ -38,7 +38,7 @@ size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 struct Layout {
   size_t mrp, mci, K, D1[3], D2[3], Q[6], V, m[2][3], H[2][3], h[3];
   size_t lrp, lci, L, u, p, rec[2];
-  size_t part, ctrl, prob, blk;
+  size_t part, ctrl, prob, blk, btab;
   size_t snap[2][2];
   size_t total;
 };
@@ -80,6 +80,7 @@ Layout make_layout(int64_t N, int64_t nnzM, int64_t Nt, int64_t nnzL, int G, siz
   L.ctrl = take(2 * sizeof(Ctrl));
   L.prob = take(sizeof(Prob<double>));
   L.blk = take(8);
+  L.btab = take(8 * kByteSlots);
   for (int k = 0; k < 2; ++k) {
     L.snap[k][0] = take(s * 3 * N);
     L.snap[k][1] = take(s * std::max<int64_t>(Nt, 1));
@@ -121,13 +122,139 @@ template <typename real>
 void bytes_model(mmsd_problem p) {
   const Assembly& A = p->A;
   const double s = sizeof(real), N = A.N, Nt = A.Nt, zM = (double)A.mci.size(), zL = (double)A.lci.size();
-  p->phase_bytes[0] = 4 * (N + 1) + 4 * zM + 3 * s * zM + 9 * s * N +            // trial m, b = D1 m
-                      4 * (Nt + 1) + 4 * zL + s * zL + 2 * s * Nt;                // r = b - L u
-  p->phase_bytes[1] = 4 * (Nt + 1) + 4 * zL + s * zL + 5 * s * Nt;                // w = L D^-1 r
-  p->phase_bytes[2] = 4 * (Nt + 1) + 4 * zL + s * zL + 12 * s * Nt;               // one CG iteration
-  p->phase_bytes[3] = 4 * (N + 1) + 4 * zM + 4 * s * zM + s * N * (3 + 1 + 6 + 1 + 6 + 3);
+  const double spmvL = 4 * (Nt + 1) + 4 * zL + s * zL;
+  double* b = p->btab;
+  for (int k = 0; k < kByteSlots; ++k) b[k] = 0;
+  b[PH_PREP] = 4 * (N + 1) + 4 * zM + 3 * s * zM + 9 * s * N + spmvL + 2 * s * Nt;   // trial m, b = D1 m, r = b - L u
+  b[PH_CG0] = spmvL + 5 * s * Nt;                                                       // w = L D^-1 r
+  b[PH_CG] = spmvL + 12 * s * Nt;                                                       // one CG iteration
+  b[PH_FIELD] = 4 * (N + 1) + 4 * zM + 4 * s * zM + s * N * (3 + 1 + 6 + 1 + 6 + 3);
+  b[PH_PCG_A] = spmvL + 4 * s * Nt;                                                     // z, p in; p, q out
+  b[PH_PCG_B] = spmvL + 8 * s * Nt;                                                     // r, q, p, u, wd in; r, u, res out
+  if (p->has_amg) {
+    const auto& H = p->amg;
+    for (size_t l = 0; l < H.lv.size(); ++l) {
+      const AmgLevel& L = H.lv[l];
+      const double n = L.A.nrows, nn = L.P.ncols;
+      const double zA = (double)L.A.ci.size(), zP = (double)L.P.ci.size();
+      const double spA = 4 * (n + 1) + (4 + s) * zA, spP = 4 * (n + 1) + (4 + s) * zP, spR = 4 * (nn + 1) + (4 + s) * zP;
+      b[byte_slot(PH_MG, MG_DOWN, (int)l)] = spA + 3 * s * n;     // b, wd in; res out
+      b[byte_slot(PH_MG, MG_REST, (int)l)] = spR + s * n + s * nn;
+      b[byte_slot(PH_MG, MG_PROL, (int)l)] = spP + 3 * s * n + s * nn;
+      b[byte_slot(PH_MG, MG_POST, (int)l)] = spA + 4 * s * n;     // xa, b, wd in; xb out
+    }
+    b[byte_slot(PH_MG, MG_SOLVE, 0)] = s * (double)H.nc * (H.nc + 2);
+  }
   p->phase_bytes_h = 3 * s * N;
   p->prep_bytes_nodemag = 9 * s * N;
+}
+
+// Upload the multigrid hierarchy into its own arena and fill the level
+// descriptors and the level-0 CG vectors of the descriptor.
+template <typename real>
+int build_amg(mmsd_problem p) {
+  mmsd_ctx c = p->ctx;
+  const AmgHierarchy& H = p->amg;
+  const int nl = (int)H.lv.size();
+  const size_t s = sizeof(real);
+  const int64_t Nt = p->A.Nt;
+  // layout
+  std::vector<size_t> off;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += align_up(bytes);
+    off.push_back(at);
+    return at;
+  };
+  struct LvOff { size_t arp, aci, av, wd, prp, pci, pv, rrp, rci, rv, b, res, xa, xb; };
+  std::vector<LvOff> lo(nl);
+  for (int l = 0; l < nl; ++l) {
+    const AmgLevel& L = H.lv[l];
+    const size_t n = L.A.nrows, nn = L.P.ncols;
+    if (l > 0) {
+      lo[l].arp = take(4 * (n + 1));
+      lo[l].aci = take(4 * L.A.ci.size());
+      lo[l].av = take(s * L.A.ci.size());
+    }
+    lo[l].wd = take(s * n);
+    lo[l].prp = take(4 * (n + 1));
+    lo[l].pci = take(4 * L.P.ci.size());
+    lo[l].pv = take(s * L.P.ci.size());
+    lo[l].rrp = take(4 * (nn + 1));
+    lo[l].rci = take(4 * L.R.ci.size());
+    lo[l].rv = take(s * L.R.ci.size());
+    lo[l].b = take(s * n);
+    lo[l].res = take(s * n);
+    lo[l].xa = take(s * n);
+    lo[l].xb = take(s * n);
+  }
+  const size_t o_ainv = take(s * (size_t)H.nc * H.nc), o_bc = take(s * H.nc), o_xc = take(s * H.nc);
+  size_t o_r2[2], o_p2[2];
+  for (int k = 0; k < 2; ++k) {
+    o_r2[k] = take(s * Nt);
+    o_p2[k] = take(s * Nt);
+  }
+  const size_t o_q = take(s * Nt), o_lev = take(sizeof(MgLevel<real>) * nl);
+  p->amg_arena = (char*)c->dalloc(o);
+  if (!p->amg_arena) {
+    set_error("device allocation of the multigrid hierarchy failed");
+    return MMSD_E_NOMEM;
+  }
+  p->amg_bytes = o;
+  char* base = p->amg_arena;
+  hipStream_t st = c->stream;
+  MMSD_HIP(hipMemsetAsync(base, 0, o, st));
+  Prob<real>& P = desc_of<real>(p);
+  std::vector<MgLevel<real>> lv(nl);
+  int rc;
+  for (int l = 0; l < nl; ++l) {
+    const AmgLevel& L = H.lv[l];
+    std::vector<double> wd(L.dinv.size());
+    for (size_t i = 0; i < wd.size(); ++i) wd[i] = L.omega * L.dinv[i];
+    if (l > 0) {
+      if ((rc = upload_int(st, base + lo[l].arp, L.A.rp)) || (rc = upload_int(st, base + lo[l].aci, L.A.ci)) ||
+          (rc = upload_vec<real>(st, base + lo[l].av, L.A.v)))
+        return rc;
+    }
+    if ((rc = upload_vec<real>(st, base + lo[l].wd, wd)) || (rc = upload_int(st, base + lo[l].prp, L.P.rp)) ||
+        (rc = upload_int(st, base + lo[l].pci, L.P.ci)) || (rc = upload_vec<real>(st, base + lo[l].pv, L.P.v)) ||
+        (rc = upload_int(st, base + lo[l].rrp, L.R.rp)) || (rc = upload_int(st, base + lo[l].rci, L.R.ci)) ||
+        (rc = upload_vec<real>(st, base + lo[l].rv, L.R.v)))
+      return rc;
+    MgLevel<real>& d = lv[l];
+    d.n = L.A.nrows;
+    d.n_next = L.P.ncols;
+    d.arp = l == 0 ? P.lrp : (const int*)(base + lo[l].arp);
+    d.aci = l == 0 ? P.lci : (const int*)(base + lo[l].aci);
+    d.av = l == 0 ? P.L : (const real*)(base + lo[l].av);
+    d.wd = (const real*)(base + lo[l].wd);
+    d.prp = (const int*)(base + lo[l].prp);
+    d.pci = (const int*)(base + lo[l].pci);
+    d.pv = (const real*)(base + lo[l].pv);
+    d.rrp = (const int*)(base + lo[l].rrp);
+    d.rci = (const int*)(base + lo[l].rci);
+    d.rv = (const real*)(base + lo[l].rv);
+    d.b = (real*)(base + lo[l].b);
+    d.res = (real*)(base + lo[l].res);
+    d.xa = (real*)(base + lo[l].xa);
+    d.xb = (real*)(base + lo[l].xb);
+  }
+  if ((rc = upload_vec<real>(st, base + o_ainv, H.Ainv))) return rc;
+  MMSD_HIP(hipMemcpyAsync(base + o_lev, lv.data(), sizeof(MgLevel<real>) * nl, hipMemcpyHostToDevice, st));
+  MMSD_HIP(hipStreamSynchronize(st));
+  P.n_lev = nl;
+  P.nc = H.nc;
+  P.lev = (const MgLevel<real>*)(base + o_lev);
+  P.Ainv = (const real*)(base + o_ainv);
+  P.bc = (real*)(base + o_bc);
+  P.xc = (real*)(base + o_xc);
+  for (int k = 0; k < 2; ++k) {
+    P.r2[k] = (real*)(base + o_r2[k]);
+    P.p2[k] = (real*)(base + o_p2[k]);
+  }
+  P.q = (real*)(base + o_q);
+  return MMSD_OK;
 }
 
 template <typename real>
@@ -206,11 +333,14 @@ int build_device(mmsd_problem p) {
   p->dblk = (int*)(base + L.blk);
   for (int k = 0; k < 2; ++k)
     for (int j = 0; j < 2; ++j) p->snap[k][j] = base + L.snap[k][j];
+  if (p->has_amg && (rc = build_amg<real>(p))) return rc;
+  bytes_model<real>(p);
+  P.btab = (const double*)(base + L.btab);
+  MMSD_HIP(hipMemcpyAsync(base + L.btab, p->btab, 8 * kByteSlots, hipMemcpyHostToDevice, st));
   int blk[2] = {0, G};
   MMSD_HIP(hipMemcpyAsync(p->dprob, &P, sizeof(P), hipMemcpyHostToDevice, st));
   MMSD_HIP(hipMemcpyAsync(p->dblk, blk, sizeof(blk), hipMemcpyHostToDevice, st));
   MMSD_HIP(hipStreamSynchronize(st));
-  bytes_model<real>(p);
   return MMSD_OK;
 }
 
@@ -246,6 +376,8 @@ int resolve(mmsd_problem p, const mmsd_options* o, Resolved* r) {
     if (o->pcg_maxit > 0) d.pcg_maxit = o->pcg_maxit;
     if (o->step_rule > 0) d.step_rule = o->step_rule;
     if (o->refine_tol_T > 0) d.refine_tol_T = o->refine_tol_T;
+    if (o->precond > 0) d.precond = o->precond;
+    if (o->precond < 0 || o->precond > MMSD_PRECOND_AMG) return invalid("unknown preconditioner");
     if (o->terms < 0 || o->terms > MMSD_ALL || o->nonmono_M > kMaxHist || o->step_rule < 0 ||
         o->step_rule > MMSD_STEP_BB2)
       return invalid("options out of range");
@@ -261,6 +393,9 @@ int resolve(mmsd_problem p, const mmsd_options* o, Resolved* r) {
   r->rule = d.step_rule;
   r->maxit = d.pcg_maxit;
   r->refine = d.refine_tol_T;
+  if (d.precond == MMSD_PRECOND_AMG && !p->has_amg)
+    return invalid("multigrid preconditioner requested but not available for this mesh");
+  r->precond = (d.precond == MMSD_PRECOND_JACOBI || !p->has_amg) ? PC_JACOBI : PC_AMG;
   return MMSD_OK;
 }
 
@@ -269,7 +404,8 @@ int arm(mmsd_problem p, const Resolved& r, int stage, int store_h) {
   const double dp[14] = {r.tol, r.rtol * r.rtol, 1e-4, 0.5, 0.5, 0.1, 1e-10, 1e10, 1e-14,
                          p->b_ext[0] / A.Js, p->b_ext[1] / A.Js, p->b_ext[2] / A.Js, A.c_an, A.vol};
   MMSD_HIP(launch_ctrl_init(p->dctrl, kArmSlot, stage, r.terms, r.M, r.rule, r.maxit, store_h,
-                            (r.terms & MMSD_DEMAG) ? 1 : 0, p->acc, (long long)r.max_evals, dp, p->ctx->stream));
+                            (r.terms & MMSD_DEMAG) ? 1 : 0, p->acc, r.precond, (long long)r.max_evals, dp,
+                            p->ctx->stream));
   return MMSD_OK;
 }
 
@@ -354,9 +490,8 @@ int drain_timing(mmsd_ctx c) {
 }
 
 double run_bytes(mmsd_problem p, const Ctrl& C) {
-  double b = 0;
-  for (int k = 0; k < 4; ++k) b += (double)C.nphase[k] * p->phase_bytes[k];
-  if (!C.demag) b += (double)C.nphase[0] * (p->prep_bytes_nodemag - p->phase_bytes[0]);
+  double b = C.alg_bytes;
+  if (!C.demag) b += (double)C.nphase[0] * (p->prep_bytes_nodemag - p->btab[PH_PREP]);
   if (C.store_h) b += (double)C.nphase[3] * p->phase_bytes_h;
   return b;
 }
@@ -569,6 +704,8 @@ void mmsd_options_default(mmsd_options* o) {
   o->pcg_maxit = 5000;
   o->step_rule = MMSD_STEP_ADAPTIVE;
   o->refine_tol_T = 0;
+  o->precond = MMSD_PRECOND_AUTO;
+  o->pad0 = 0;
 }
 
 int mmsd_ctx_create(int device, void* hip_stream, mmsd_alloc_fn alloc, mmsd_free_fn free_fn, void* user,
@@ -664,11 +801,21 @@ int mmsd_problem_create(mmsd_ctx c, const mmsd_mesh* mesh, const mmsd_material* 
     set_error(err);
     return rc;
   }
+  if (p->A.Nt > 0) {
+    Csr L0;
+    L0.nrows = L0.ncols = p->A.Nt;
+    L0.rp = p->A.lrp;
+    L0.ci = p->A.lci;
+    L0.v = p->A.L;
+    p->has_amg = amg_setup(L0, AmgParams{}, &p->amg) && (int)p->amg.lv.size() <= kMaxLevels;
+    // the level operators are kept only for sizes and byte counts
+  }
   std::lock_guard<std::mutex> lk(c->mu);
   hipSetDevice(c->device);
   rc = precision == MMSD_MIXED ? build_device<float>(p) : build_device<double>(p);
   if (rc) {
     if (p->arena) c->dfree(p->arena);
+    if (p->amg_arena) c->dfree(p->amg_arena);
     delete p;
     return rc;
   }
@@ -685,6 +832,7 @@ int mmsd_problem_destroy(mmsd_problem p) {
   for (auto& kv : p->graphs) hipGraphExecDestroy(kv.second);
   if (p->hctrl) hipHostFree(p->hctrl);
   c->dfree(p->arena);
+  if (p->amg_arena) c->dfree(p->amg_arena);
   delete p;
   return MMSD_OK;
 }

@@ -34,7 +34,15 @@
 
 namespace mmsd {
 
-enum Phase : int { PH_IDLE = 0, PH_PREP = 1, PH_CG0 = 2, PH_CG = 3, PH_FIELD = 4, PH_DONE = 5, PH_START = 6 };
+enum Phase : int {
+  PH_IDLE = 0, PH_PREP = 1, PH_CG0 = 2, PH_CG = 3, PH_FIELD = 4, PH_DONE = 5, PH_START = 6,
+  PH_MG = 7,     // one multigrid V-cycle operation (sub-op and level in Ctrl)
+  PH_PCG_A = 8,  // AMG-preconditioned CG: p = z + beta p, q = L p, p.q
+  PH_PCG_B = 9   // u += alpha p, r -= alpha q, and the finest pre-smoothing residual
+};
+enum MgOp : int { MG_DOWN = 0, MG_REST = 1, MG_SOLVE = 2, MG_PROL = 3, MG_POST = 4 };
+enum Precond : int { PC_AUTO = 0, PC_JACOBI = 1, PC_AMG = 2 };
+constexpr int kMaxLevels = 12;
 enum Stage : int { ST_INIT = 0, ST_RUN = 1, ST_EVAL = 2 };
 
 constexpr int kBlock = 512;        // threads per block (8 wavefronts of 64)
@@ -60,7 +68,10 @@ struct Ctrl {
   int pcg_maxit, store_h, demag, pad0;
   long long evals, iters, pcg_total, max_evals;
   long long launches_done;       // phases executed
-  long long nphase[4];           // executed PREP, CG0, CG, FIELD phases
+  long long nphase[4];           // executed PREP, CG0 / MG, CG / PCG_A + PCG_B, FIELD phases
+  int precond, mg_op, mg_lev, rcur;   // preconditioner in use; V-cycle position; residual parity
+  int mg_first, pad2;
+  double alg_bytes;              // algorithmic bytes of the executed phases (roofline accounting)
   // options and constants
   double tol, pcg_rtol2, c1, rho, kappa0, theta0, tau_min, tau_max, tau_floor;
   double bz[3];                  // applied field / Js
@@ -79,6 +90,27 @@ struct Ctrl {
 };
 static_assert(sizeof(Ctrl) % 8 == 0, "Ctrl is copied as 8-byte words");
 
+// One level of the multigrid hierarchy (level 0 is the potential matrix).
+// wd = omega / diag: damped-Jacobi smoothing factor.
+template <typename real>
+struct MgLevel {
+  int n, n_next;
+  const int* arp;
+  const int* aci;
+  const real* av;
+  const real* wd;
+  const int* prp;          // P: n x n_next
+  const int* pci;
+  const real* pv;
+  const int* rrp;          // R = P^T: n_next x n
+  const int* rci;
+  const real* rv;
+  real* b;                 // right-hand side (level 0 uses the CG residual)
+  real* res;               // residual after pre-smoothing
+  real* xa;                // after prolongation of the coarse correction
+  real* xb;                // after post-smoothing (level 0: the preconditioned residual z)
+};
+
 // Per-node state of the potential solve, packed so that one gathered
 // neighbour costs one 4-wide load: residual r, L p (s), L D^-1 r (w) and the
 // Jacobi factor d = 1/diag(L).
@@ -86,6 +118,13 @@ template <typename real>
 struct __align__(4 * sizeof(real)) Rec {
   real r, s, w, d;
 };
+
+// Index of a phase in the per-problem byte table: plain phases by number,
+// V-cycle operations by (op, level).
+constexpr int kByteSlots = 16 + 5 * kMaxLevels;
+__host__ __device__ inline int byte_slot(int phase, int op, int lev) {
+  return phase == PH_MG ? 16 + op * kMaxLevels + lev : phase;
+}
 
 template <typename real>
 struct Prob {
@@ -108,6 +147,17 @@ struct Prob {
   real* u;                // potential (the CG iterate), warm start across solves
   real* p;                // search direction (row-local)
   Rec<real>* rec[2];      // CG state by buffer parity (pcur)
+  // multigrid-preconditioned CG (absent when n_lev == 0)
+  int n_lev;              // levels with a coarser level below them
+  int nc;                 // size of the coarsest level
+  const MgLevel<real>* lev;
+  const real* Ainv;       // dense inverse of the coarsest operator, row-major nc x nc
+  real* bc;               // coarsest right-hand side and solution
+  real* xc;
+  real* r2[2];            // residual by parity (rcur)
+  real* p2[2];            // search direction by parity (pcur)
+  real* q;                // L p
+  const double* btab;     // algorithmic bytes per executed phase, indexed by byte_slot()
   // reductions and control
   unsigned* ndone;        // nullable: incremented once when the problem finishes
   int* done_list;         // nullable: receives `slot` at position ndone - 1

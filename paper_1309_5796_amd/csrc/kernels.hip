@@ -149,7 +149,8 @@ __device__ void phase_prep(const Prob<real>& P, const Ctrl* C, int t, double* ac
       lu = group_sum<real, LPR>(lu);
       if (valid && lane == 0) {
         const real ri = bi - lu;
-        P.rec[C->pcur][i].r = ri;
+        if (C->precond == PC_AMG) P.r2[C->rcur][i] = ri;
+        else P.rec[C->pcur][i].r = ri;
         acc[0] += (double)bi * (double)bi;
         acc[1] += (double)ri * (double)ri;
         acc[2] += (double)ri * (double)P.u[i];
@@ -265,6 +266,178 @@ __device__ void phase_cg(const Prob<real>& P, const Ctrl* C, int t, double* acc)
       acc[1] += (double)sw * (double)zi;
       acc[2] += (double)ri * (double)ri;
       acc[3] += (double)ri * (double)ui;
+    }
+  }
+}
+
+// ---- multigrid-preconditioned CG ----
+// Lane-partial sum over row i of a CSR matrix of v[k] * g(column): column
+// indices and values first, then all the gathers, then the products.
+template <typename real, int LPR, typename G>
+__device__ __forceinline__ real row_sum(const int* __restrict__ rp, const int* __restrict__ ci,
+                                        const real* __restrict__ v, int i, int lane, G&& g) {
+  real acc = 0;
+  const int ke = rp[i + 1];
+  for (int k0 = rp[i] + lane; k0 < ke; k0 += kUnroll * LPR) {
+    int j[kUnroll];
+    real lv[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int k = k0 + u * LPR;
+      const int ks = k < ke ? k : k0;
+      j[u] = ci[ks];
+      lv[u] = k < ke ? v[ks] : real(0);
+    }
+    real x[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) x[u] = g(j[u]);
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) acc += lv[u] * x[u];
+  }
+  return acc;
+}
+
+// One operation of the symmetric V(1,1) cycle with damped-Jacobi smoothing
+// (x = wd b before the coarse correction, one sweep after it):
+//   DOWN(l)  res = b - A (wd b)
+//   REST(l)  b_{l+1} = R res
+//   SOLVE    x_c = A_c^-1 b_c (dense)
+//   PROL(l)  xa = wd b + P x_{l+1}
+//   POST(l)  xb = xa + wd (b - A xa); at level 0 xb is z and b.z is reduced
+template <typename real, int LPR>
+__device__ void phase_mg(const Prob<real>& P, const Ctrl* C, int t, double* acc) {
+  constexpr int RPP = kBlock / LPR;
+  const int lane = threadIdx.x & (LPR - 1);
+  const int slot = threadIdx.x / LPR;
+  const int op = C->mg_op, l = C->mg_lev;
+  int r0, r1;
+  if (op == MG_SOLVE) {
+    const int nc = P.nc;
+    chunk_rows(nc, P.G, t, RPP, r0, r1);
+    for (int base = r0; base < r1; base += RPP) {
+      const int i = base + slot;
+      const bool valid = i < r1;
+      real sum = 0;
+      if (valid) {
+        const real* __restrict__ row = P.Ainv + (size_t)i * nc;
+        for (int j = lane; j < nc; j += LPR) sum += row[j] * P.bc[j];
+      }
+      sum = group_sum<real, LPR>(sum);
+      if (valid && lane == 0) P.xc[i] = sum;
+    }
+    return;
+  }
+  const MgLevel<real>& L = P.lev[l];
+  const real* __restrict__ b = l == 0 ? P.r2[C->rcur] : L.b;
+  const real* __restrict__ wd = L.wd;
+  const bool last = l + 1 == P.n_lev;
+  if (op == MG_REST) {
+    real* __restrict__ bn = last ? P.bc : P.lev[l + 1].b;
+    const real* __restrict__ res = L.res;
+    chunk_rows(L.n_next, P.G, t, RPP, r0, r1);
+    for (int base = r0; base < r1; base += RPP) {
+      const int i = base + slot;
+      const bool valid = i < r1;
+      real sum = valid ? row_sum<real, LPR>(L.rrp, L.rci, L.rv, i, lane, [&](int j) { return res[j]; }) : real(0);
+      sum = group_sum<real, LPR>(sum);
+      if (valid && lane == 0) bn[i] = sum;
+    }
+    return;
+  }
+  chunk_rows(L.n, P.G, t, RPP, r0, r1);
+  if (op == MG_DOWN) {
+    for (int base = r0; base < r1; base += RPP) {
+      const int i = base + slot;
+      const bool valid = i < r1;
+      real sum = valid ? row_sum<real, LPR>(L.arp, L.aci, L.av, i, lane, [&](int j) { return wd[j] * b[j]; })
+                       : real(0);
+      sum = group_sum<real, LPR>(sum);
+      if (valid && lane == 0) L.res[i] = b[i] - sum;
+    }
+  } else if (op == MG_PROL) {
+    const real* __restrict__ xn = last ? P.xc : P.lev[l + 1].xb;
+    for (int base = r0; base < r1; base += RPP) {
+      const int i = base + slot;
+      const bool valid = i < r1;
+      real sum = valid ? row_sum<real, LPR>(L.prp, L.pci, L.pv, i, lane, [&](int j) { return xn[j]; }) : real(0);
+      sum = group_sum<real, LPR>(sum);
+      if (valid && lane == 0) L.xa[i] = wd[i] * b[i] + sum;
+    }
+  } else {   // MG_POST
+    const real* __restrict__ xa = L.xa;
+    for (int base = r0; base < r1; base += RPP) {
+      const int i = base + slot;
+      const bool valid = i < r1;
+      real sum = valid ? row_sum<real, LPR>(L.arp, L.aci, L.av, i, lane, [&](int j) { return xa[j]; }) : real(0);
+      sum = group_sum<real, LPR>(sum);
+      if (valid && lane == 0) {
+        const real bi = b[i];
+        const real zi = xa[i] + wd[i] * (bi - sum);
+        L.xb[i] = zi;
+        if (l == 0) acc[0] += (double)bi * (double)zi;
+      }
+    }
+  }
+}
+
+// PCG_A: p = z + beta p_old (recomputed at gathered neighbours), q = L p, p.q
+template <typename real, int LPR>
+__device__ void phase_pcg_a(const Prob<real>& P, const Ctrl* C, int t, double* acc) {
+  constexpr int RPP = kBlock / LPR;
+  const int lane = threadIdx.x & (LPR - 1);
+  const int slot = threadIdx.x / LPR;
+  int r0, r1;
+  chunk_rows(P.Nt, P.G, t, RPP, r0, r1);
+  const real beta = real(C->beta);
+  const real* __restrict__ z = P.lev[0].xb;
+  const real* __restrict__ po = P.p2[C->pcur];
+  real* __restrict__ pn = P.p2[1 - C->pcur];
+  for (int base = r0; base < r1; base += RPP) {
+    const int i = base + slot;
+    const bool valid = i < r1;
+    real sum = valid ? row_sum<real, LPR>(P.lrp, P.lci, P.L, i, lane, [&](int j) { return z[j] + beta * po[j]; })
+                     : real(0);
+    sum = group_sum<real, LPR>(sum);
+    if (valid && lane == 0) {
+      const real pi = z[i] + beta * po[i];
+      pn[i] = pi;
+      P.q[i] = sum;
+      acc[0] += (double)pi * (double)sum;
+    }
+  }
+}
+
+// PCG_B: r -= alpha q, u += alpha p, then the finest pre-smoothing residual
+// of the next V-cycle, res = r - L (wd r), with neighbours' new residuals
+// recomputed where they are gathered.  Partials: r.r, r.u.
+template <typename real, int LPR>
+__device__ void phase_pcg_b(const Prob<real>& P, const Ctrl* C, int t, double* acc) {
+  constexpr int RPP = kBlock / LPR;
+  const int lane = threadIdx.x & (LPR - 1);
+  const int slot = threadIdx.x / LPR;
+  int r0, r1;
+  chunk_rows(P.Nt, P.G, t, RPP, r0, r1);
+  const real alpha = real(C->alpha);
+  const real* __restrict__ p = P.p2[C->pcur];
+  const real* __restrict__ ro = P.r2[C->rcur];
+  real* __restrict__ rn = P.r2[1 - C->rcur];
+  const real* __restrict__ q = P.q;
+  const real* __restrict__ wd = P.lev[0].wd;
+  for (int base = r0; base < r1; base += RPP) {
+    const int i = base + slot;
+    const bool valid = i < r1;
+    real sum = valid ? row_sum<real, LPR>(P.lrp, P.lci, P.L, i, lane,
+                                          [&](int j) { return wd[j] * (ro[j] - alpha * q[j]); })
+                     : real(0);
+    sum = group_sum<real, LPR>(sum);
+    if (valid && lane == 0) {
+      const real ri = ro[i] - alpha * q[i];
+      const real ui = P.u[i] + alpha * p[i];
+      rn[i] = ri;
+      P.u[i] = ui;
+      P.lev[0].res[i] = ri - sum;
+      acc[0] += (double)ri * (double)ri;
+      acc[1] += (double)ri * (double)ui;
     }
   }
 }
@@ -391,8 +564,21 @@ __device__ void phase_field(const Prob<real>& P, const Ctrl* C, int t, double* a
   }
 }
 
-__device__ __forceinline__ int n_parts(int phase) {
-  return phase == PH_PREP ? 3 : phase == PH_CG0 ? 2 : phase == PH_CG ? 4 : kNPart;
+__device__ __forceinline__ int n_parts(int phase, int mg_op = 0, int mg_lev = 0) {
+  switch (phase) {
+    case PH_PREP: return 3;
+    case PH_CG0: return 2;
+    case PH_CG: return 4;
+    case PH_FIELD: return kNPart;
+    case PH_MG: return (mg_op == MG_POST && mg_lev == 0) ? 1 : 0;
+    case PH_PCG_A: return 1;
+    case PH_PCG_B: return 2;
+    default: return 0;
+  }
+}
+
+__device__ __forceinline__ bool is_work(int phase) {
+  return (phase >= PH_PREP && phase <= PH_FIELD) || phase == PH_MG || phase == PH_PCG_A || phase == PH_PCG_B;
 }
 
 __device__ void push_hist(Ctrl* C, double e) {
@@ -536,7 +722,7 @@ __device__ void step_logic(Ctrl* C, const double* v) {
 
 // Advance the state by the outcome of the phase it records (v: the finished
 // reductions of that phase's partials).
-__device__ void transition(Ctrl* C, const double* v) {
+__device__ void transition(Ctrl* C, const double* v, const double* btab, int n_lev) {
   C->seq++;
   const int phase = C->phase;
   if (phase == PH_IDLE || phase == PH_DONE) return;
@@ -545,7 +731,8 @@ __device__ void transition(Ctrl* C, const double* v) {
     return;
   }
   C->launches_done++;
-  C->nphase[phase - PH_PREP]++;
+  C->alg_bytes += btab[byte_slot(phase, C->mg_op, C->mg_lev)];
+  C->nphase[phase == PH_FIELD ? 3 : phase == PH_PREP ? 0 : (phase == PH_CG0 || phase == PH_MG) ? 1 : 2]++;
   switch (phase) {
     case PH_PREP:
       if (!C->demag) {
@@ -557,7 +744,69 @@ __device__ void transition(Ctrl* C, const double* v) {
       C->rr = v[1];
       C->ru = v[2];
       C->pcg_it = 0;
-      C->phase = (C->rr <= C->pcg_rtol2 * C->bb) ? PH_FIELD : PH_CG0;
+      if (C->rr <= C->pcg_rtol2 * C->bb) {
+        C->phase = PH_FIELD;
+      } else if (C->precond == PC_AMG) {
+        C->phase = PH_MG;
+        C->mg_op = MG_DOWN;
+        C->mg_lev = 0;
+        C->mg_first = 1;
+      } else {
+        C->phase = PH_CG0;
+      }
+      return;
+    case PH_MG:
+      switch (C->mg_op) {
+        case MG_DOWN:
+          C->mg_op = MG_REST;
+          return;
+        case MG_REST:
+          if (C->mg_lev + 1 < n_lev) {
+            C->mg_lev++;
+            C->mg_op = MG_DOWN;
+          } else {
+            C->mg_op = MG_SOLVE;
+            C->mg_lev = 0;
+          }
+          return;
+        case MG_SOLVE:
+          C->mg_op = MG_PROL;
+          C->mg_lev = n_lev - 1;
+          return;
+        case MG_PROL:
+          C->mg_op = MG_POST;
+          return;
+        default:   // MG_POST
+          if (C->mg_lev > 0) {
+            C->mg_lev--;
+            C->mg_op = MG_PROL;
+            return;
+          }
+          // z = M r is complete: next search direction
+          C->beta = C->mg_first ? 0.0 : v[0] / C->gam;
+          C->gam = v[0];
+          C->mg_first = 0;
+          C->phase = PH_PCG_A;
+          return;
+      }
+    case PH_PCG_A:
+      C->alpha = C->gam / v[0];
+      C->pcur ^= 1;
+      C->phase = PH_PCG_B;
+      return;
+    case PH_PCG_B:
+      C->rr = v[0];
+      C->ru = v[1];
+      C->rcur ^= 1;
+      C->pcg_it++;
+      C->pcg_total++;
+      if (C->rr <= C->pcg_rtol2 * C->bb || C->pcg_it >= C->pcg_maxit) {
+        C->phase = PH_FIELD;
+      } else {   // the finest pre-smoothing residual is already done
+        C->phase = PH_MG;
+        C->mg_op = MG_REST;
+        C->mg_lev = 0;
+      }
       return;
     case PH_CG0:
       C->gam = v[0];
@@ -631,11 +880,11 @@ __global__ void __launch_bounds__(kBlock) k_step(const Prob<real>* __restrict__ 
   }
   __syncthreads();
   const int ran = s_c.phase;
-  if (ran >= PH_PREP && ran <= PH_FIELD)
-    reduce_partials(P.part + (size_t)prev * P.G * kNPart, P.G, n_parts(ran), ran, s_tot);
+  const int np_prev = n_parts(ran, s_c.mg_op, s_c.mg_lev);
+  if (np_prev > 0) reduce_partials(P.part + (size_t)prev * P.G * kNPart, P.G, np_prev, ran, s_tot);
   __syncthreads();
   if (threadIdx.x == 0) {
-    transition(&s_c, s_tot);
+    transition(&s_c, s_tot, P.btab, P.n_lev);
     s_newly_done = (ran != PH_DONE && s_c.phase == PH_DONE);
   }
   __syncthreads();
@@ -646,7 +895,7 @@ __global__ void __launch_bounds__(kBlock) k_step(const Prob<real>* __restrict__ 
     if (threadIdx.x == 0 && s_newly_done) signal_done<real>(P, &s_c);
   }
   const int phase = s_c.phase;
-  if (phase < PH_PREP || phase > PH_FIELD) return;
+  if (!is_work(phase)) return;
   const int t = (lb & 7) * (P.G >> 3) + (lb >> 3);
 
   double acc[kNPart];
@@ -665,11 +914,21 @@ __global__ void __launch_bounds__(kBlock) k_step(const Prob<real>* __restrict__ 
     case PH_FIELD:
       phase_field<real, LPR>(P, &s_c, t, acc);
       break;
+    case PH_MG:
+      phase_mg<real, LPR>(P, &s_c, t, acc);
+      break;
+    case PH_PCG_A:
+      phase_pcg_a<real, LPR>(P, &s_c, t, acc);
+      break;
+    case PH_PCG_B:
+      phase_pcg_b<real, LPR>(P, &s_c, t, acc);
+      break;
   }
 
   // block partials: butterfly in each wave, then the waves in order; plain
   // stores, published to the next launch by the kernel boundary
-  const int np = n_parts(phase);
+  const int np = n_parts(phase, s_c.mg_op, s_c.mg_lev);
+  if (np == 0) return;
   const int wid = threadIdx.x >> 6, lid = threadIdx.x & 63;
   for (int k = 0; k < np; ++k) {
     const double v = (phase == PH_FIELD && k == FP_TMAX) ? wave_max(acc[k]) : wave_sum(acc[k]);
@@ -689,7 +948,7 @@ __global__ void __launch_bounds__(kBlock) k_step(const Prob<real>* __restrict__ 
 // slot `slot` (the one the next step launch reads), with a sequence number
 // above both slots' so the host always picks the newest.
 struct CtrlInit {
-  int stage, terms, nonmono_M, step_rule, pcg_maxit, store_h, demag, acc;
+  int stage, terms, nonmono_M, step_rule, pcg_maxit, store_h, demag, acc, precond, pad;
   long long max_evals;
   double tol, pcg_rtol2, c1, rho, kappa0, theta0, tau_min, tau_max, tau_floor;
   double bz[3], c_an, vol;
@@ -725,6 +984,12 @@ __global__ void k_ctrl_init(Ctrl* ctrl, int slot, CtrlInit a) {
   C->max_evals = a.max_evals;
   C->launches_done = 0;
   for (int k = 0; k < 4; ++k) C->nphase[k] = 0;
+  C->precond = a.precond;
+  C->mg_op = 0;
+  C->mg_lev = 0;
+  C->rcur = 0;
+  C->mg_first = 0;
+  C->alg_bytes = 0.0;
   C->tol = a.tol;
   C->pcg_rtol2 = a.pcg_rtol2;
   C->c1 = a.c1;
@@ -779,9 +1044,11 @@ template hipError_t launch_step<double>(int, const Prob<double>*, int, const int
 template hipError_t launch_step<float>(int, const Prob<float>*, int, const int*, int, int, hipStream_t);
 
 hipError_t launch_ctrl_init(Ctrl* ctrl, int slot, int stage, int terms, int nonmono_M, int step_rule,
-                            int pcg_maxit, int store_h, int demag, int acc, long long max_evals,
+                            int pcg_maxit, int store_h, int demag, int acc, int precond, long long max_evals,
                             const double* dparams, hipStream_t s) {
   CtrlInit a;
+  a.precond = precond;
+  a.pad = 0;
   a.stage = stage;
   a.terms = terms;
   a.nonmono_M = nonmono_M;

@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "amg.h"
 #include "assemble.h"
 #include "device.h"
 #include "mmsd.h"
@@ -29,7 +30,7 @@ template <typename real>
 hipError_t launch_step(int lpr, const Prob<real>* probs, int nprob, const int* blk_start, int grid, int parity,
                        hipStream_t s);
 hipError_t launch_ctrl_init(Ctrl* ctrl, int slot, int stage, int terms, int nonmono_M, int step_rule,
-                            int pcg_maxit, int store_h, int demag, int acc, long long max_evals,
+                            int pcg_maxit, int store_h, int demag, int acc, int precond, long long max_evals,
                             const double* dparams, hipStream_t s);
 
 hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream_t s);
@@ -44,7 +45,7 @@ inline const Ctrl& latest(const Ctrl* two) { return two[1].seq > two[0].seq ? tw
 struct Resolved {
   double tol, rtol;
   int64_t max_evals;
-  int terms, M, rule, maxit;
+  int terms, M, rule, maxit, precond;
   double refine;
 };
 
@@ -113,9 +114,14 @@ struct mmsd_problem_s {
   int acc = 0;
   bool h_valid = false;
   double b_ext[3] = {0, 0, 0};
-  double phase_bytes[4] = {0, 0, 0, 0};   // algorithmic bytes per executed phase
+  double btab[mmsd::kByteSlots] = {};     // algorithmic bytes per executed phase (also on the device)
   double phase_bytes_h = 0;               // extra FIELD bytes when h is stored
   double prep_bytes_nodemag = 0;
+  // multigrid preconditioner of the potential solve
+  bool has_amg = false;
+  mmsd::AmgHierarchy amg;                 // host copy (sizes; values uploaded)
+  char* amg_arena = nullptr;
+  size_t amg_bytes = 0;
   mmsd::Ctrl* hctrl = nullptr;            // pinned mirrors [2 polls][2 slots]
   std::map<int, hipGraphExec_t> graphs;   // batch size -> instantiated graph
   int64_t last_launches = 0;

@@ -43,7 +43,7 @@ def test_options_default_and_struct_layout():
     o = binding.OptionsC()
     lib.mmsd_options_default(ctypes.byref(o))
     assert o.tol_torque == 1e-6 and o.max_evals == 100000 and o.terms == 15 and o.nonmono_M == 20
-    assert ctypes.sizeof(binding.OptionsC) == 48
+    assert ctypes.sizeof(binding.OptionsC) == 56
     assert ctypes.sizeof(binding.ResultC) == 8 * 17
 
 

@@ -199,3 +199,57 @@ def test_autotune_keeps_state_and_result(ctx, cfg1):
     assert q.autotune()[:2] == (lanes, blocks)        # cached class, no timing
     p.close()
     q.close()
+
+
+@pytest.mark.parametrize("precond", [1, 2])
+def test_evaluate_config1_each_preconditioner(ctx, cfg1, cfg1_system, precond):
+    from paper_1309_5796_amd import binding
+    say(f"evaluate config1 precond={precond}")
+    s = cfg1_system
+    rng = np.random.default_rng(31)
+    m = rng.normal(size=(s.N, 3))
+    m /= np.linalg.norm(m, axis=1, keepdims=True)
+    for prec, tol_e in ((binding.FP64, 1e-12), (binding.MIXED, 2e-6)):
+        p = binding.Problem(ctx, cfg1["mesh"], precision=prec)
+        p.set_m(m)
+        p.set_field(cfg1["b_ext"])
+        r = p.evaluate(pcg_rtol=1e-14 if prec == binding.FP64 else 1e-7, precond=precond)
+        ev = s.evaluate(m, cfg1["b_ext"])
+        assert rel_energy_err(r.energy_J, ev) < tol_e, (prec, precond)
+        h = p.get_field()
+        assert np.abs(h - ev["h"]).max() < (1e-10 if prec == binding.FP64 else 1e-5) * np.abs(ev["h"]).max()
+        p.close()
+
+
+def test_multigrid_cuts_potential_iterations_with_the_same_minimum(ctx, cfg1, cfg1_system):
+    from paper_1309_5796_amd import binding
+    say("minimize config1 jacobi vs amg")
+    s = cfg1_system
+    ro = oracle.minimize(s, cfg1["m0"], cfg1["b_ext"], Options())
+    ev = s.evaluate(ro.m, cfg1["b_ext"])
+    out = {}
+    for pc in (binding.PRECOND_JACOBI, binding.PRECOND_AMG):
+        p = binding.Problem(ctx, cfg1["mesh"])
+        p.set_m(cfg1["m0"])
+        p.set_field(cfg1["b_ext"])
+        out[pc] = p.minimize(precond=pc)
+        assert out[pc].status == 0 and rel_energy_err(out[pc].energy_J, ev) < 1e-10
+        p.close()
+    say(f"pcg iterations jacobi {out[1].pcg_iters} amg {out[2].pcg_iters}")
+    assert out[binding.PRECOND_AMG].pcg_iters * 4 < out[binding.PRECOND_JACOBI].pcg_iters
+
+
+@pytest.mark.parametrize("rule,name", [(1, "alternate"), (2, "bb1"), (3, "bb2")])
+def test_step_rules_match_oracle(ctx, cfg1, cfg1_system, rule, name):
+    from paper_1309_5796_amd import binding
+    say(f"step rule {name}")
+    s = cfg1_system
+    ro = oracle.minimize(s, cfg1["m0"], cfg1["b_ext"], Options(step_rule=name))
+    p = binding.Problem(ctx, cfg1["mesh"])
+    p.set_m(cfg1["m0"])
+    p.set_field(cfg1["b_ext"])
+    r = p.minimize(step_rule=rule)
+    assert r.status == 0 and r.max_torque < 1e-6
+    assert rel_energy_err(r.energy_J, s.evaluate(ro.m, cfg1["b_ext"])) < 1e-10
+    assert abs(r.iterations - ro.iterations) <= 3
+    p.close()

@@ -178,3 +178,17 @@ def test_bloch_wall_energy_and_width_converge_second_order():
     f1, f2 = (w1 - w_exact) / w_exact, (w2 - w_exact) / w_exact
     assert abs(f1) < 0.10 and abs(f2) < 0.025
     assert 3.0 < f1 / f2 < 6.0                        # O(h^2)
+
+
+@pytest.mark.parametrize("rule", ["alternate", "bb1", "bb2"])
+def test_other_step_rules_reach_the_same_minimum(cfg1, cfg1_system, rule):
+    """The paper mentions plain alternation of tau1/tau2 before choosing the
+    adaptive rule; every rule must reach the same local minimum."""
+    ref = minimize(cfg1_system, cfg1["m0"], cfg1["b_ext"], Options())
+    r = minimize(cfg1_system, cfg1["m0"], cfg1["b_ext"], Options(step_rule=rule, record=True))
+    assert r.status == 0 and r.max_torque < 1e-6
+    scale = sum(abs(v) for v in ref.terms.values())
+    assert abs(r.E - ref.E) < 1e-9 * scale
+    E = r.energies
+    for k in range(1, len(E)):
+        assert E[k] <= max(E[max(0, k - 20):k])
