@@ -278,6 +278,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--blocks", type=int, default=0, help="blocks per problem (multiple of 8; 0 = library default)")
     ap.add_argument("--chunk", type=int, default=20, help="field points per library call")
     ap.add_argument("--workload", default="sweep80", choices=["sweep80", "poly", "grains", "serve", "copy"])
     ap.add_argument("--max-evals", type=int, default=100000)
@@ -286,6 +287,8 @@ def main():
     ap.add_argument("--hbm-gb", type=float, default=64.0)
     ap.add_argument("--slots", type=int, default=32)
     ap.add_argument("--serve-timeout", type=float, default=900.0)
+    ap.add_argument("--precond", default="auto", choices=["auto", "jacobi", "amg"],
+                    help="preconditioner of the potential solve")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is "
@@ -303,12 +306,13 @@ def main():
     fields = cfg["fields"]
     K = max(1, min(args.steps, len(fields)))
     ctx = binding.Context(0)
-    if args.lanes:
-        ctx.set_launch_config(lanes_per_row=args.lanes)
+    if args.lanes or args.blocks:
+        ctx.set_launch_config(lanes_per_row=args.lanes, max_blocks=args.blocks)
     p = binding.Problem(ctx, cfg["mesh"], precision=binding.FP64)
     state0 = p.get_state()
+    pc = {"auto": binding.PRECOND_AUTO, "jacobi": binding.PRECOND_JACOBI, "amg": binding.PRECOND_AMG}[args.precond]
     if args.warmup > 0:
-        p.hysteresis(fields[: args.warmup])
+        p.hysteresis(fields[: args.warmup], precond=pc)
         p.set_state(state0)
     ctx.timing(not args.no_kernel_timing)
     ctx.timing_read(reset=True)
@@ -316,7 +320,7 @@ def main():
     t0 = time.perf_counter()
     res = []
     for k0 in range(0, K, args.chunk):
-        r_chunk, _ = p.hysteresis(fields[k0:min(K, k0 + args.chunk)])
+        r_chunk, _ = p.hysteresis(fields[k0:min(K, k0 + args.chunk)], precond=pc)
         res.extend(r_chunk)
         print(f"[bench] field points {len(res)}/{K}: {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -349,7 +353,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "FP64 hysteresis sweep, 80 nm cube, 40^3 Kuhn cells (68,921 magnet / "
                                "274,625 potential nodes), +8 -> -8 -> +8 T in 0.1 T steps at 1 deg",
-                   "field_points": K, "magnet_nodes": p.N, "potential_nodes": p.Nt},
+                   "field_points": K, "magnet_nodes": p.N, "potential_nodes": p.Nt,
+                   "potential_preconditioner": args.precond},
         "roofline": roof,
         "detail": {"evals": evals, "iterations": iters, "pcg_iters": pcg, "launches": launches,
                    "wall_s": wall, "switching_fields_T": [float(b) for b in bsw],

@@ -115,6 +115,18 @@ Prob<real>& desc_of(mmsd_problem p) {
   return *reinterpret_cast<Prob<real>*>(p->desc);
 }
 
+// Average row length above which a multigrid operator is swept with 16
+// lanes per row.
+constexpr size_t kWideRow = 24;
+
+// P is plain aggregation: every row holds a single entry 1 (the post-smoothing
+// of such a level recomputes the prolongation where it gathers).
+static bool plain_prolongation(const Csr& P) {
+  for (int i = 0; i < P.nrows; ++i)
+    if (P.rp[i + 1] - P.rp[i] != 1 || P.v[P.rp[i]] != 1.0) return false;
+  return true;
+}
+
 // Algorithmic bytes per executed phase: every matrix entry, index and
 // row-local vector value moved once; gathered neighbour values counted as
 // cache hits.
@@ -129,8 +141,8 @@ void bytes_model(mmsd_problem p) {
   b[PH_CG0] = spmvL + 5 * s * Nt;                                                       // w = L D^-1 r
   b[PH_CG] = spmvL + 12 * s * Nt;                                                       // one CG iteration
   b[PH_FIELD] = 4 * (N + 1) + 4 * zM + 4 * s * zM + s * N * (3 + 1 + 6 + 1 + 6 + 3);
-  b[PH_PCG_A] = spmvL + 4 * s * Nt;                                                     // z, p in; p, q out
-  b[PH_PCG_B] = spmvL + 8 * s * Nt;                                                     // r, q, p, u, wd in; r, u, res out
+  b[PH_PCG_A] = spmvL + 7 * s * Nt;        // {z, p}, r, wd in; q, {wd r, wd q} out
+  b[PH_PCG_B] = spmvL + 13 * s * Nt;       // {wd r, wd q}, r, q, {z, p}, u in; {z, p}, r, u, res out
   if (p->has_amg) {
     const auto& H = p->amg;
     for (size_t l = 0; l < H.lv.size(); ++l) {
@@ -139,11 +151,22 @@ void bytes_model(mmsd_problem p) {
       const double zA = (double)L.A.ci.size(), zP = (double)L.P.ci.size();
       const double spA = 4 * (n + 1) + (4 + s) * zA, spP = 4 * (n + 1) + (4 + s) * zP, spR = 4 * (nn + 1) + (4 + s) * zP;
       b[byte_slot(PH_MG, MG_DOWN, (int)l)] = spA + 3 * s * n;     // b, wd in; res out
-      b[byte_slot(PH_MG, MG_REST, (int)l)] = spR + s * n + s * nn;
+      b[byte_slot(PH_MG, MG_REST, (int)l)] = spR + s * n + s * nn;   // res in; b out
+      if (l + 1 < H.lv.size()) b[byte_slot(PH_MG, MG_REST, (int)l)] += 2 * s * nn;   // wd in; wd b out
       b[byte_slot(PH_MG, MG_PROL, (int)l)] = spP + 3 * s * n + s * nn;
       b[byte_slot(PH_MG, MG_POST, (int)l)] = spA + 4 * s * n;     // xa, b, wd in; xb out
+      if (l == 0) b[byte_slot(PH_MG, MG_POST, 0)] += 2 * s * n;     // p carried over into the {z, p} records
     }
     b[byte_slot(PH_MG, MG_SOLVE, 0)] = s * (double)H.nc * (H.nc + 2);
+    // a plain level's xa is written by the operation that produces the
+    // coarser solution (POST of the level below, or SOLVE)
+    for (size_t l = 0; l < H.lv.size(); ++l) {
+      const AmgLevel& L = H.lv[l];
+      if (!plain_prolongation(L.P)) continue;
+      const double n = L.A.nrows, nn = L.P.ncols;
+      const double sc = 4 * (nn + 1) + (4 + s) * (double)L.P.ci.size() + 2 * s * n;   // R rows, wd b in; xa out
+      b[l + 1 < H.lv.size() ? byte_slot(PH_MG, MG_POST, (int)l + 1) : byte_slot(PH_MG, MG_SOLVE, 0)] += sc;
+    }
   }
   p->phase_bytes_h = 3 * s * N;
   p->prep_bytes_nodemag = 9 * s * N;
@@ -167,7 +190,7 @@ int build_amg(mmsd_problem p) {
     off.push_back(at);
     return at;
   };
-  struct LvOff { size_t arp, aci, av, wd, prp, pci, pv, rrp, rci, rv, b, res, xa, xb; };
+  struct LvOff { size_t arp, aci, av, wd, prp, pci, pv, rrp, rci, rv, b, wb, res, xa, xb; };
   std::vector<LvOff> lo(nl);
   for (int l = 0; l < nl; ++l) {
     const AmgLevel& L = H.lv[l];
@@ -185,17 +208,16 @@ int build_amg(mmsd_problem p) {
     lo[l].rci = take(4 * L.R.ci.size());
     lo[l].rv = take(s * L.R.ci.size());
     lo[l].b = take(s * n);
+    lo[l].wb = take(s * n);
     lo[l].res = take(s * n);
     lo[l].xa = take(s * n);
     lo[l].xb = take(s * n);
   }
   const size_t o_ainv = take(s * (size_t)H.nc * H.nc), o_bc = take(s * H.nc), o_xc = take(s * H.nc);
-  size_t o_r2[2], o_p2[2];
-  for (int k = 0; k < 2; ++k) {
-    o_r2[k] = take(s * Nt);
-    o_p2[k] = take(s * Nt);
-  }
-  const size_t o_q = take(s * Nt), o_lev = take(sizeof(MgLevel<real>) * nl);
+  size_t o_r2[2];
+  for (int k = 0; k < 2; ++k) o_r2[k] = take(s * Nt);
+  const size_t o_zp = take(2 * s * Nt);
+  const size_t o_q = take(s * Nt), o_rq = take(2 * s * Nt), o_lev = take(sizeof(MgLevel<real>) * nl);
   p->amg_arena = (char*)c->dalloc(o);
   if (!p->amg_arena) {
     set_error("device allocation of the multigrid hierarchy failed");
@@ -225,6 +247,10 @@ int build_amg(mmsd_problem p) {
     MgLevel<real>& d = lv[l];
     d.n = L.A.nrows;
     d.n_next = L.P.ncols;
+    d.plain = plain_prolongation(L.P) ? 1 : 0;
+    d.wide_a = L.A.ci.size() > kWideRow * (size_t)L.A.nrows;
+    d.wide_p = L.P.ci.size() > kWideRow * (size_t)L.P.nrows;
+    d.wide_r = L.R.ci.size() > kWideRow * (size_t)L.R.nrows;
     d.arp = l == 0 ? P.lrp : (const int*)(base + lo[l].arp);
     d.aci = l == 0 ? P.lci : (const int*)(base + lo[l].aci);
     d.av = l == 0 ? P.L : (const real*)(base + lo[l].av);
@@ -236,6 +262,7 @@ int build_amg(mmsd_problem p) {
     d.rci = (const int*)(base + lo[l].rci);
     d.rv = (const real*)(base + lo[l].rv);
     d.b = (real*)(base + lo[l].b);
+    d.wb = (real*)(base + lo[l].wb);
     d.res = (real*)(base + lo[l].res);
     d.xa = (real*)(base + lo[l].xa);
     d.xb = (real*)(base + lo[l].xb);
@@ -244,6 +271,8 @@ int build_amg(mmsd_problem p) {
   MMSD_HIP(hipMemcpyAsync(base + o_lev, lv.data(), sizeof(MgLevel<real>) * nl, hipMemcpyHostToDevice, st));
   MMSD_HIP(hipStreamSynchronize(st));
   P.n_lev = nl;
+  P.mg_plain = 0;
+  for (int l = 0; l < nl; ++l) P.mg_plain |= lv[l].plain << l;
   P.nc = H.nc;
   P.lev = (const MgLevel<real>*)(base + o_lev);
   P.Ainv = (const real*)(base + o_ainv);
@@ -251,9 +280,10 @@ int build_amg(mmsd_problem p) {
   P.xc = (real*)(base + o_xc);
   for (int k = 0; k < 2; ++k) {
     P.r2[k] = (real*)(base + o_r2[k]);
-    P.p2[k] = (real*)(base + o_p2[k]);
   }
+  P.zp = (Pair<real>*)(base + o_zp);
   P.q = (real*)(base + o_q);
+  P.rq = (Pair<real>*)(base + o_rq);
   return MMSD_OK;
 }
 

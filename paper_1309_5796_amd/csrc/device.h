@@ -92,23 +92,44 @@ static_assert(sizeof(Ctrl) % 8 == 0, "Ctrl is copied as 8-byte words");
 
 // One level of the multigrid hierarchy (level 0 is the potential matrix).
 // wd = omega / diag: damped-Jacobi smoothing factor.
+// Two node values gathered together: one 16-byte (8-byte in FP32) load per
+// neighbour instead of two.
 template <typename real>
-struct MgLevel {
+struct alignas(2 * sizeof(real)) Pair {
+  real a, b;
+};
+
+// The descriptors below are filled by the host with plain pointers and read
+// by the kernels through global-address-space pointers of the same size and
+// value, so that their loads compile to global (not flat) memory
+// instructions.
+template <typename T>
+using HostPtr = T*;
+template <typename T>
+using DevPtr = __attribute__((address_space(1))) T*;
+template <typename T>
+using DevRef = __attribute__((address_space(1))) T&;
+
+template <typename real, template <typename> class Ptr>
+struct MgLevelT {
   int n, n_next;
-  const int* arp;
-  const int* aci;
-  const real* av;
-  const real* wd;
-  const int* prp;          // P: n x n_next
-  const int* pci;
-  const real* pv;
-  const int* rrp;          // R = P^T: n_next x n
-  const int* rci;
-  const real* rv;
-  real* b;                 // right-hand side (level 0 uses the CG residual)
-  real* res;               // residual after pre-smoothing
-  real* xa;                // after prolongation of the coarse correction
-  real* xb;                // after post-smoothing (level 0: the preconditioned residual z)
+  int plain;               // P is plain aggregation: row i holds a single 1 in column pci[i]
+  int wide_a, wide_p, wide_r;   // rows of A, P, R long enough for 16 lanes per row
+  Ptr<const int> arp;
+  Ptr<const int> aci;
+  Ptr<const real> av;
+  Ptr<const real> wd;
+  Ptr<const int> prp;          // P: n x n_next
+  Ptr<const int> pci;
+  Ptr<const real> pv;
+  Ptr<const int> rrp;          // R = P^T: n_next x n
+  Ptr<const int> rci;
+  Ptr<const real> rv;
+  Ptr<real> b;                 // right-hand side (level 0 uses the CG residual)
+  Ptr<real> wb;                // wd b (levels >= 1), written with b
+  Ptr<real> res;               // residual after pre-smoothing
+  Ptr<real> xa;                // after prolongation of the coarse correction
+  Ptr<real> xb;                // after post-smoothing (level 0: the preconditioned residual z)
 };
 
 // Per-node state of the potential solve, packed so that one gathered
@@ -126,44 +147,57 @@ __host__ __device__ inline int byte_slot(int phase, int op, int lev) {
   return phase == PH_MG ? 16 + op * kMaxLevels + lev : phase;
 }
 
-template <typename real>
-struct Prob {
+template <typename real, template <typename> class Ptr>
+struct ProbT {
   int N, Nt, G, blk0;
   // magnet rows: CSR pattern shared by K, D1 (b = D1 m) and D2 (h_d = -D2 u)
-  const int* mrp;
-  const int* mci;
-  const real* K;          // 2 K_ij / V_i
-  const real* D1[3];      // sum_e V_e/4 grad(phi_i)|_e
-  const real* D2[3];      // sum_e V_e/4 grad(phi_j)|_e / V_i
-  const real* Q[6];       // 2 Q_i / V_i: xx yy zz xy xz yz
-  const real* V;          // lumped nodal volume
-  real* m[2][3];          // accepted / trial slots, SoA
-  real* H[2][3];          // torque m x h per slot
-  real* h[3];             // effective field (written when store_h)
+  Ptr<const int> mrp;
+  Ptr<const int> mci;
+  Ptr<const real> K;          // 2 K_ij / V_i
+  Ptr<const real> D1[3];      // sum_e V_e/4 grad(phi_i)|_e
+  Ptr<const real> D2[3];      // sum_e V_e/4 grad(phi_j)|_e / V_i
+  Ptr<const real> Q[6];       // 2 Q_i / V_i: xx yy zz xy xz yz
+  Ptr<const real> V;          // lumped nodal volume
+  Ptr<real> m[2][3];          // accepted / trial slots, SoA
+  Ptr<real> H[2][3];          // torque m x h per slot
+  Ptr<real> h[3];             // effective field (written when store_h)
   // potential rows (magnet rows first): transformed Laplacian
-  const int* lrp;
-  const int* lci;
-  const real* L;
-  real* u;                // potential (the CG iterate), warm start across solves
-  real* p;                // search direction (row-local)
-  Rec<real>* rec[2];      // CG state by buffer parity (pcur)
+  Ptr<const int> lrp;
+  Ptr<const int> lci;
+  Ptr<const real> L;
+  Ptr<real> u;                // potential (the CG iterate), warm start across solves
+  Ptr<real> p;                // search direction (row-local)
+  Ptr<Rec<real>> rec[2];      // CG state by buffer parity (pcur)
   // multigrid-preconditioned CG (absent when n_lev == 0)
   int n_lev;              // levels with a coarser level below them
+  int mg_plain;           // bit l: level l's P is plain aggregation (see MgLevel::plain)
   int nc;                 // size of the coarsest level
-  const MgLevel<real>* lev;
-  const real* Ainv;       // dense inverse of the coarsest operator, row-major nc x nc
-  real* bc;               // coarsest right-hand side and solution
-  real* xc;
-  real* r2[2];            // residual by parity (rcur)
-  real* p2[2];            // search direction by parity (pcur)
-  real* q;                // L p
-  const double* btab;     // algorithmic bytes per executed phase, indexed by byte_slot()
+  Ptr<const MgLevelT<real, Ptr>> lev;
+  Ptr<const real> Ainv;       // dense inverse of the coarsest operator, row-major nc x nc
+  Ptr<real> bc;               // coarsest right-hand side and solution
+  Ptr<real> xc;
+  Ptr<real> r2[2];            // residual by parity (rcur)
+  Ptr<Pair<real>> zp;         // {z, p}: preconditioned residual and search direction
+  Ptr<Pair<real>> rq;         // {wd r, wd q} of the current iteration
+  Ptr<real> q;                // L p
+  Ptr<const double> btab;     // algorithmic bytes per executed phase, indexed by byte_slot()
   // reductions and control
-  unsigned* ndone;        // nullable: incremented once when the problem finishes
-  int* done_list;         // nullable: receives `slot` at position ndone - 1
+  Ptr<unsigned> ndone;        // nullable: incremented once when the problem finishes
+  Ptr<int> done_list;         // nullable: receives `slot` at position ndone - 1
   int slot;
-  double* part;           // [2][G][kNPart] per-block partials, by launch parity
-  Ctrl* ctrl;             // [2] control state, by launch parity
+  Ptr<double> part;           // [2][G][kNPart] per-block partials, by launch parity
+  Ptr<Ctrl> ctrl;             // [2] control state, by launch parity
 };
+
+template <typename real>
+using MgLevel = MgLevelT<real, HostPtr>;
+template <typename real>
+using MgLevelDev = MgLevelT<real, DevPtr>;
+template <typename real>
+using Prob = ProbT<real, HostPtr>;
+template <typename real>
+using ProbDev = ProbT<real, DevPtr>;
+static_assert(sizeof(ProbDev<double>) == sizeof(Prob<double>) && sizeof(MgLevelDev<float>) == sizeof(MgLevel<float>),
+              "device views must match the host layout");
 
 }  // namespace mmsd

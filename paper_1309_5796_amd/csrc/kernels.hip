@@ -74,6 +74,40 @@ __device__ __forceinline__ void cayley(real mx, real my, real mz, real Hx, real 
 // gathers, then accumulate: two dependent memory round trips per row batch
 // instead of two per nonzero.
 constexpr int kUnroll = 4;
+// Phases that gather several values per neighbour (CG records, the field's
+// m and u) take half the batch in FP64 to stay within 64 VGPRs, which lets
+// 8 wavefronts share a SIMD.
+template <typename real>
+constexpr int kUnrollWide = sizeof(real) == 8 ? 2 : 4;
+
+// Record loads and stores through global pointers, as one vector access each.
+template <typename real>
+using vec2 = real __attribute__((ext_vector_type(2)));
+template <typename real>
+using vec4 = real __attribute__((ext_vector_type(4)));
+template <typename real>
+__device__ __forceinline__ Pair<real> ld(DevPtr<const Pair<real>> p, int i) {
+  const vec2<real> v = reinterpret_cast<DevPtr<const vec2<real>>>(p)[i];
+  return Pair<real>{v.x, v.y};
+}
+template <typename real>
+__device__ __forceinline__ void st(DevPtr<Pair<real>> p, int i, Pair<real> x) {
+  reinterpret_cast<DevPtr<vec2<real>>>(p)[i] = vec2<real>{x.a, x.b};
+}
+template <typename real>
+__device__ __forceinline__ Rec<real> ld(DevPtr<const Rec<real>> p, int i) {
+  const vec4<real> v = reinterpret_cast<DevPtr<const vec4<real>>>(p)[i];
+  Rec<real> r;
+  r.r = v.x;
+  r.s = v.y;
+  r.w = v.z;
+  r.d = v.w;
+  return r;
+}
+template <typename real>
+__device__ __forceinline__ void st(DevPtr<Rec<real>> p, int i, const Rec<real>& x) {
+  reinterpret_cast<DevPtr<vec4<real>>>(p)[i] = vec4<real>{x.r, x.s, x.w, x.d};
+}
 
 // Rows [r0, r1) of chunk t out of G for R rows, chunk rounded to `rpp`.
 __device__ __forceinline__ void chunk_rows(int R, int G, int t, int rpp, int& r0, int& r1) {
@@ -87,7 +121,7 @@ __device__ __forceinline__ void chunk_rows(int R, int G, int t, int rpp, int& r0
 
 // ---- PREP: trial magnetization, Poisson right-hand side, initial residual ----
 template <typename real, int LPR>
-__device__ void phase_prep(const Prob<real>& P, const Ctrl* C, int t, double* acc) {
+__device__ void phase_prep(const ProbDev<real>& P, const Ctrl* C, int t, double* acc) {
   constexpr int RPP = kBlock / LPR;
   const int lane = threadIdx.x & (LPR - 1);
   const int slot = threadIdx.x / LPR;
@@ -97,12 +131,12 @@ __device__ void phase_prep(const Prob<real>& P, const Ctrl* C, int t, double* ac
   chunk_rows(R, P.G, t, RPP, r0, r1);
   const int a = C->acc, tr = 1 - a;
   const real ht = real(0.5 * C->tau);
-  const real* __restrict__ max_ = P.m[a][0];
-  const real* __restrict__ may = P.m[a][1];
-  const real* __restrict__ maz = P.m[a][2];
-  const real* __restrict__ Hax = P.H[a][0];
-  const real* __restrict__ Hay = P.H[a][1];
-  const real* __restrict__ Haz = P.H[a][2];
+  DevPtr<const real> __restrict__ max_ = P.m[a][0];
+  DevPtr<const real> __restrict__ may = P.m[a][1];
+  DevPtr<const real> __restrict__ maz = P.m[a][2];
+  DevPtr<const real> __restrict__ Hax = P.H[a][0];
+  DevPtr<const real> __restrict__ Hay = P.H[a][1];
+  DevPtr<const real> __restrict__ Haz = P.H[a][2];
   for (int base = r0; base < r1; base += RPP) {
     const int i = base + slot;
     const bool valid = i < r1;
@@ -161,36 +195,37 @@ __device__ void phase_prep(const Prob<real>& P, const Ctrl* C, int t, double* ac
 
 // ---- CG0: w = L D^-1 r for the starting residual ----
 template <typename real, int LPR>
-__device__ void phase_cg0(const Prob<real>& P, const Ctrl* C, int t, double* acc) {
+__device__ void phase_cg0(const ProbDev<real>& P, const Ctrl* C, int t, double* acc) {
   constexpr int RPP = kBlock / LPR;
+  constexpr int kU = kUnrollWide<real>;
   const int lane = threadIdx.x & (LPR - 1);
   const int slot = threadIdx.x / LPR;
   int r0, r1;
   chunk_rows(P.Nt, P.G, t, RPP, r0, r1);
-  Rec<real>* __restrict__ rec = P.rec[C->pcur];
+  DevPtr<Rec<real>> __restrict__ rec = P.rec[C->pcur];
   for (int base = r0; base < r1; base += RPP) {
     const int i = base + slot;
     const bool valid = i < r1;
     real sw = 0;
     Rec<real> own{};
     if (valid) {
-      own = rec[i];
+      own = ld<real>(rec, i);
       const int ke = P.lrp[i + 1];
-      for (int k0 = P.lrp[i] + lane; k0 < ke; k0 += kUnroll * LPR) {
-        int j[kUnroll];
-        real lv[kUnroll];
+      for (int k0 = P.lrp[i] + lane; k0 < ke; k0 += kU * LPR) {
+        int j[kU];
+        real lv[kU];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
+        for (int u = 0; u < kU; ++u) {
           const int k = k0 + u * LPR;
           const int ks = k < ke ? k : k0;
           j[u] = P.lci[ks];
           lv[u] = k < ke ? P.L[ks] : real(0);
         }
-        Rec<real> nb[kUnroll];
+        Rec<real> nb[kU];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) nb[u] = rec[j[u]];
+        for (int u = 0; u < kU; ++u) nb[u] = ld<real>(rec, j[u]);
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) sw += lv[u] * (nb[u].d * nb[u].r);
+        for (int u = 0; u < kU; ++u) sw += lv[u] * (nb[u].d * nb[u].r);
       }
     }
     sw = group_sum<real, LPR>(sw);
@@ -209,16 +244,17 @@ __device__ void phase_cg0(const Prob<real>& P, const Ctrl* C, int t, double* acc
 // r_j - alpha (w_j + beta s_j), so the sweep needs no grid-wide barrier
 // between the vector updates and w = L D^-1 r.
 template <typename real, int LPR>
-__device__ void phase_cg(const Prob<real>& P, const Ctrl* C, int t, double* acc) {
+__device__ void phase_cg(const ProbDev<real>& P, const Ctrl* C, int t, double* acc) {
   constexpr int RPP = kBlock / LPR;
+  constexpr int kU = kUnrollWide<real>;
   const int lane = threadIdx.x & (LPR - 1);
   const int slot = threadIdx.x / LPR;
   int r0, r1;
   chunk_rows(P.Nt, P.G, t, RPP, r0, r1);
   const int c = C->pcur;
   const real alpha = real(C->alpha), beta = real(C->beta);
-  const Rec<real>* __restrict__ ro = P.rec[c];
-  Rec<real>* __restrict__ rn = P.rec[1 - c];
+  DevPtr<const Rec<real>> __restrict__ ro = P.rec[c];
+  DevPtr<Rec<real>> __restrict__ rn = P.rec[1 - c];
   for (int base = r0; base < r1; base += RPP) {
     const int i = base + slot;
     const bool valid = i < r1;
@@ -226,25 +262,25 @@ __device__ void phase_cg(const Prob<real>& P, const Ctrl* C, int t, double* acc)
     Rec<real> own{};
     real pi = 0, ui = 0;
     if (valid) {
-      own = ro[i];
+      own = ld<real>(ro, i);
       pi = P.p[i];
       ui = P.u[i];
       const int ke = P.lrp[i + 1];
-      for (int k0 = P.lrp[i] + lane; k0 < ke; k0 += kUnroll * LPR) {
-        int j[kUnroll];
-        real lv[kUnroll];
+      for (int k0 = P.lrp[i] + lane; k0 < ke; k0 += kU * LPR) {
+        int j[kU];
+        real lv[kU];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
+        for (int u = 0; u < kU; ++u) {
           const int k = k0 + u * LPR;
           const int ks = k < ke ? k : k0;
           j[u] = P.lci[ks];
           lv[u] = k < ke ? P.L[ks] : real(0);
         }
-        Rec<real> nb[kUnroll];
+        Rec<real> nb[kU];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) nb[u] = ro[j[u]];
+        for (int u = 0; u < kU; ++u) nb[u] = ld<real>(ro, j[u]);
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) sw += lv[u] * (nb[u].d * (nb[u].r - alpha * (nb[u].w + beta * nb[u].s)));
+        for (int u = 0; u < kU; ++u) sw += lv[u] * (nb[u].d * (nb[u].r - alpha * (nb[u].w + beta * nb[u].s)));
       }
     }
     sw = group_sum<real, LPR>(sw);
@@ -261,7 +297,7 @@ __device__ void phase_cg(const Prob<real>& P, const Ctrl* C, int t, double* acc)
       out.s = si;
       out.w = sw;
       out.d = own.d;
-      rn[i] = out;
+      st<real>(rn, i, out);
       acc[0] += (double)ri * (double)zi;
       acc[1] += (double)sw * (double)zi;
       acc[2] += (double)ri * (double)ri;
@@ -274,8 +310,8 @@ __device__ void phase_cg(const Prob<real>& P, const Ctrl* C, int t, double* acc)
 // Lane-partial sum over row i of a CSR matrix of v[k] * g(column): column
 // indices and values first, then all the gathers, then the products.
 template <typename real, int LPR, typename G>
-__device__ __forceinline__ real row_sum(const int* __restrict__ rp, const int* __restrict__ ci,
-                                        const real* __restrict__ v, int i, int lane, G&& g) {
+__device__ __forceinline__ real row_sum(DevPtr<const int> __restrict__ rp, DevPtr<const int> __restrict__ ci,
+                                        DevPtr<const real> __restrict__ v, int i, int lane, G&& g) {
   real acc = 0;
   const int ke = rp[i + 1];
   for (int k0 = rp[i] + lane; k0 < ke; k0 += kUnroll * LPR) {
@@ -300,47 +336,45 @@ __device__ __forceinline__ real row_sum(const int* __restrict__ rp, const int* _
 // One operation of the symmetric V(1,1) cycle with damped-Jacobi smoothing
 // (x = wd b before the coarse correction, one sweep after it):
 //   DOWN(l)  res = b - A (wd b)
-//   REST(l)  b_{l+1} = R res
+//   REST(l)  b_{l+1} = R res (and wb_{l+1} = wd_{l+1} b_{l+1}, what DOWN and
+//            POST of level l + 1 gather)
 //   SOLVE    x_c = A_c^-1 b_c (dense)
 //   PROL(l)  xa = wd b + P x_{l+1}
-//   POST(l)  xb = xa + wd (b - A xa); at level 0 xb is z and b.z is reduced
-template <typename real, int LPR>
-__device__ void phase_mg(const Prob<real>& P, const Ctrl* C, int t, double* acc) {
-  constexpr int RPP = kBlock / LPR;
-  const int lane = threadIdx.x & (LPR - 1);
-  const int slot = threadIdx.x / LPR;
-  const int op = C->mg_op, l = C->mg_lev;
-  int r0, r1;
-  if (op == MG_SOLVE) {
-    const int nc = P.nc;
-    chunk_rows(nc, P.G, t, RPP, r0, r1);
-    for (int base = r0; base < r1; base += RPP) {
-      const int i = base + slot;
-      const bool valid = i < r1;
-      real sum = 0;
-      if (valid) {
-        const real* __restrict__ row = P.Ainv + (size_t)i * nc;
-        for (int j = lane; j < nc; j += LPR) sum += row[j] * P.bc[j];
-      }
-      sum = group_sum<real, LPR>(sum);
-      if (valid && lane == 0) P.xc[i] = sum;
-    }
-    return;
-  }
-  const MgLevel<real>& L = P.lev[l];
-  const real* __restrict__ b = l == 0 ? P.r2[C->rcur] : L.b;
-  const real* __restrict__ wd = L.wd;
+//   POST(l)  xb = xa + wd (b - A xa); at level 0 the result is z, stored in
+//            the {z, p} records (whole records are written: p is carried
+//            over), and b.z is reduced
+// On a level l whose P is plain aggregation (each row one entry), PROL(l) is
+// skipped: the operation that produces x_{l+1} (POST(l + 1), or SOLVE) also
+// writes xa_l = wd b + P x_{l+1} for the members of each aggregate it owns
+// (row I of R_l lists them), so no index is gathered twice.
+// W lanes share a row: the kernel's LPR, or 16 on levels whose rows are long.
+template <typename real, int W>
+__device__ void mg_rows(const ProbDev<real>& P, const Ctrl* C, DevRef<const MgLevelDev<real>> L, int op, int l, int t,
+                        double* acc) {
+  constexpr int RPP = kBlock / W;
+  const int lane = threadIdx.x & (W - 1);
+  const int slot = threadIdx.x / W;
+  DevPtr<const real> __restrict__ b = l == 0 ? P.r2[C->rcur] : L.b;
+  DevPtr<const real> __restrict__ wd = L.wd;
+  DevPtr<const real> __restrict__ wb = L.wb;
   const bool last = l + 1 == P.n_lev;
+  int r0, r1;
   if (op == MG_REST) {
-    real* __restrict__ bn = last ? P.bc : P.lev[l + 1].b;
-    const real* __restrict__ res = L.res;
+    DevPtr<real> __restrict__ bn = last ? P.bc : P.lev[l + 1].b;
+    DevPtr<real> __restrict__ wbn = last ? nullptr : P.lev[l + 1].wb;
+    DevPtr<const real> __restrict__ wdn = last ? nullptr : P.lev[l + 1].wd;
+    DevPtr<const real> __restrict__ res = L.res;
     chunk_rows(L.n_next, P.G, t, RPP, r0, r1);
     for (int base = r0; base < r1; base += RPP) {
       const int i = base + slot;
       const bool valid = i < r1;
-      real sum = valid ? row_sum<real, LPR>(L.rrp, L.rci, L.rv, i, lane, [&](int j) { return res[j]; }) : real(0);
-      sum = group_sum<real, LPR>(sum);
-      if (valid && lane == 0) bn[i] = sum;
+      const real wi = (valid && lane == 0 && !last) ? wdn[i] : real(0);
+      real sum = valid ? row_sum<real, W>(L.rrp, L.rci, L.rv, i, lane, [&](int j) { return res[j]; }) : real(0);
+      sum = group_sum<real, W>(sum);
+      if (valid && lane == 0) {
+        bn[i] = sum;
+        if (!last) wbn[i] = wi * sum;
+      }
     }
     return;
   }
@@ -349,90 +383,186 @@ __device__ void phase_mg(const Prob<real>& P, const Ctrl* C, int t, double* acc)
     for (int base = r0; base < r1; base += RPP) {
       const int i = base + slot;
       const bool valid = i < r1;
-      real sum = valid ? row_sum<real, LPR>(L.arp, L.aci, L.av, i, lane, [&](int j) { return wd[j] * b[j]; })
+      const real bi = (valid && lane == 0) ? b[i] : real(0);
+      real sum = valid ? row_sum<real, W>(L.arp, L.aci, L.av, i, lane,
+                                          [&](int j) { return l == 0 ? wd[j] * b[j] : wb[j]; })
                        : real(0);
-      sum = group_sum<real, LPR>(sum);
-      if (valid && lane == 0) L.res[i] = b[i] - sum;
+      sum = group_sum<real, W>(sum);
+      if (valid && lane == 0) L.res[i] = bi - sum;
     }
   } else if (op == MG_PROL) {
-    const real* __restrict__ xn = last ? P.xc : P.lev[l + 1].xb;
+    DevPtr<const real> __restrict__ xn = last ? P.xc : P.lev[l + 1].xb;
     for (int base = r0; base < r1; base += RPP) {
       const int i = base + slot;
       const bool valid = i < r1;
-      real sum = valid ? row_sum<real, LPR>(L.prp, L.pci, L.pv, i, lane, [&](int j) { return xn[j]; }) : real(0);
-      sum = group_sum<real, LPR>(sum);
-      if (valid && lane == 0) L.xa[i] = wd[i] * b[i] + sum;
+      const real wbi = (valid && lane == 0) ? wd[i] * b[i] : real(0);
+      real sum = valid ? row_sum<real, W>(L.prp, L.pci, L.pv, i, lane, [&](int j) { return xn[j]; }) : real(0);
+      sum = group_sum<real, W>(sum);
+      if (valid && lane == 0) L.xa[i] = wbi + sum;
     }
   } else {   // MG_POST
-    const real* __restrict__ xa = L.xa;
+    DevPtr<const real> __restrict__ xa = L.xa;
+    // level l - 1 plain: scatter its xa over the members of aggregate i
+    const bool scatter = l > 0 && P.lev[l - 1].plain;
+    DevRef<const MgLevelDev<real>> F = P.lev[l > 0 ? l - 1 : 0];
     for (int base = r0; base < r1; base += RPP) {
       const int i = base + slot;
       const bool valid = i < r1;
-      real sum = valid ? row_sum<real, LPR>(L.arp, L.aci, L.av, i, lane, [&](int j) { return xa[j]; }) : real(0);
-      sum = group_sum<real, LPR>(sum);
+      real bi = 0, wi = 0, xai = 0, pold = 0;
       if (valid && lane == 0) {
-        const real bi = b[i];
-        const real zi = xa[i] + wd[i] * (bi - sum);
-        L.xb[i] = zi;
-        if (l == 0) acc[0] += (double)bi * (double)zi;
+        bi = b[i];
+        wi = wd[i];
+        xai = xa[i];
+        if (l == 0) pold = P.zp[i].b;
+      }
+      real sum = valid ? row_sum<real, W>(L.arp, L.aci, L.av, i, lane, [&](int j) { return xa[j]; }) : real(0);
+      sum = group_sum<real, W>(sum);
+      real zi = 0;
+      if (valid && lane == 0) {
+        zi = xai + wi * (bi - sum);
+        if (l == 0) {
+          st<real>(P.zp, i, Pair<real>{zi, pold});
+          acc[0] += (double)bi * (double)zi;
+        } else {
+          L.xb[i] = zi;
+        }
+      }
+      if (scatter) {
+        zi = __shfl(zi, 0, W);
+        if (valid) {
+          for (int k = F.rrp[i] + lane; k < F.rrp[i + 1]; k += W) {
+            const int j = F.rci[k];
+            const real wbj = l == 1 ? F.wd[j] * P.r2[C->rcur][j] : F.wb[j];
+            F.xa[j] = wbj + F.rv[k] * zi;
+          }
+        }
       }
     }
   }
 }
 
-// PCG_A: p = z + beta p_old (recomputed at gathered neighbours), q = L p, p.q
 template <typename real, int LPR>
-__device__ void phase_pcg_a(const Prob<real>& P, const Ctrl* C, int t, double* acc) {
+__device__ void phase_mg(const ProbDev<real>& P, const Ctrl* C, int t, double* acc) {
+  const int op = C->mg_op, l = C->mg_lev;
+  if (op == MG_SOLVE) {
+    // dense coarsest solve: one row per block at a time, the whole block
+    // streams the row coalesced, then wavefront sums and the waves in order
+    __shared__ double s_row[kBlock / 64];
+    const int nc = P.nc;
+    DevRef<const MgLevelDev<real>> F = P.lev[P.n_lev - 1];
+    const int wid = threadIdx.x >> 6, lid = threadIdx.x & 63;
+    for (int i = t; i < nc; i += P.G) {
+      DevPtr<const real> __restrict__ row = P.Ainv + (size_t)i * nc;
+      double sum = 0;
+      for (int j = threadIdx.x; j < nc; j += kBlock) sum += (double)(row[j] * P.bc[j]);
+      sum = wave_sum(sum);
+      if (lid == 0) s_row[wid] = sum;
+      __syncthreads();
+      double v = s_row[0];
+      for (int w = 1; w < kBlock / 64; ++w) v += s_row[w];
+      if (threadIdx.x == 0) P.xc[i] = real(v);
+      if (F.plain) {   // xa of the last level over the members of aggregate i
+        const real xi = real(v);
+        for (int k = F.rrp[i] + threadIdx.x; k < F.rrp[i + 1]; k += kBlock) {
+          const int j = F.rci[k];
+          const real wbj = P.n_lev == 1 ? F.wd[j] * P.r2[C->rcur][j] : F.wb[j];
+          F.xa[j] = wbj + F.rv[k] * xi;
+        }
+      }
+      __syncthreads();
+    }
+    return;
+  }
+  DevRef<const MgLevelDev<real>> L = P.lev[l];
+  const int wide = op == MG_REST ? L.wide_r : op == MG_PROL ? L.wide_p : L.wide_a;
+  if (wide && LPR < 16)
+    mg_rows<real, 16>(P, C, L, op, l, t, acc);
+  else
+    mg_rows<real, LPR>(P, C, L, op, l, t, acc);
+}
+
+// PCG_A: p = z + beta p_old (recomputed at gathered neighbours from the
+// {z, p} records), q = L p, p.q; also the {wd r, wd q} records PCG_B gathers.
+// p itself is stored by PCG_B, which gathers no {z, p} record.
+template <typename real, int LPR>
+__device__ void phase_pcg_a(const ProbDev<real>& P, const Ctrl* C, int t, double* acc) {
   constexpr int RPP = kBlock / LPR;
   const int lane = threadIdx.x & (LPR - 1);
   const int slot = threadIdx.x / LPR;
   int r0, r1;
   chunk_rows(P.Nt, P.G, t, RPP, r0, r1);
   const real beta = real(C->beta);
-  const real* __restrict__ z = P.lev[0].xb;
-  const real* __restrict__ po = P.p2[C->pcur];
-  real* __restrict__ pn = P.p2[1 - C->pcur];
+  const bool first = C->beta == 0.0;
+  DevPtr<const Pair<real>> __restrict__ zp = P.zp;
+  DevPtr<const real> __restrict__ r = P.r2[C->rcur];
+  DevPtr<const real> __restrict__ wd = P.lev[0].wd;
   for (int base = r0; base < r1; base += RPP) {
     const int i = base + slot;
     const bool valid = i < r1;
-    real sum = valid ? row_sum<real, LPR>(P.lrp, P.lci, P.L, i, lane, [&](int j) { return z[j] + beta * po[j]; })
+    Pair<real> own{};
+    real ri = 0, wi = 0;
+    if (valid && lane == 0) {
+      own = ld<real>(zp, i);
+      ri = r[i];
+      wi = wd[i];
+    }
+    // beta = 0 starts a solve: the p half then holds the previous solve's
+    // direction and is not read
+    real sum = valid ? row_sum<real, LPR>(P.lrp, P.lci, P.L, i, lane, [&](int j) {
+      const Pair<real> e = ld<real>(zp, j);
+      return first ? e.a : e.a + beta * e.b;
+    })
                      : real(0);
     sum = group_sum<real, LPR>(sum);
     if (valid && lane == 0) {
-      const real pi = z[i] + beta * po[i];
-      pn[i] = pi;
+      const real pi = first ? own.a : own.a + beta * own.b;
       P.q[i] = sum;
+      st<real>(P.rq, i, Pair<real>{wi * ri, wi * sum});
       acc[0] += (double)pi * (double)sum;
     }
   }
 }
 
-// PCG_B: r -= alpha q, u += alpha p, then the finest pre-smoothing residual
-// of the next V-cycle, res = r - L (wd r), with neighbours' new residuals
-// recomputed where they are gathered.  Partials: r.r, r.u.
+// PCG_B: p = z + beta p_old (stored), r -= alpha q, u += alpha p, then the
+// finest pre-smoothing residual
+// of the next V-cycle, res = r - L (wd r), with neighbours' wd r_new
+// recomputed from their {wd r, wd q} records.  Partials: r.r, r.u.
 template <typename real, int LPR>
-__device__ void phase_pcg_b(const Prob<real>& P, const Ctrl* C, int t, double* acc) {
+__device__ void phase_pcg_b(const ProbDev<real>& P, const Ctrl* C, int t, double* acc) {
   constexpr int RPP = kBlock / LPR;
   const int lane = threadIdx.x & (LPR - 1);
   const int slot = threadIdx.x / LPR;
   int r0, r1;
   chunk_rows(P.Nt, P.G, t, RPP, r0, r1);
-  const real alpha = real(C->alpha);
-  const real* __restrict__ p = P.p2[C->pcur];
-  const real* __restrict__ ro = P.r2[C->rcur];
-  real* __restrict__ rn = P.r2[1 - C->rcur];
-  const real* __restrict__ q = P.q;
-  const real* __restrict__ wd = P.lev[0].wd;
+  const real alpha = real(C->alpha), beta = real(C->beta);
+  const bool first = C->beta == 0.0;
+  DevPtr<Pair<real>> __restrict__ zp = P.zp;
+  DevPtr<const real> __restrict__ ro = P.r2[C->rcur];
+  DevPtr<real> __restrict__ rn = P.r2[1 - C->rcur];
+  DevPtr<const real> __restrict__ q = P.q;
+  DevPtr<const Pair<real>> __restrict__ rq = P.rq;
   for (int base = r0; base < r1; base += RPP) {
     const int i = base + slot;
     const bool valid = i < r1;
-    real sum = valid ? row_sum<real, LPR>(P.lrp, P.lci, P.L, i, lane,
-                                          [&](int j) { return wd[j] * (ro[j] - alpha * q[j]); })
+    real roi = 0, qi = 0, uo = 0;
+    Pair<real> own{};
+    if (valid && lane == 0) {
+      roi = ro[i];
+      qi = q[i];
+      uo = P.u[i];
+      own = ld<real>(zp, i);
+    }
+    real sum = valid ? row_sum<real, LPR>(P.lrp, P.lci, P.L, i, lane, [&](int j) {
+      const Pair<real> e = ld<real>(rq, j);
+      return e.a - alpha * e.b;
+    })
                      : real(0);
     sum = group_sum<real, LPR>(sum);
     if (valid && lane == 0) {
-      const real ri = ro[i] - alpha * q[i];
-      const real ui = P.u[i] + alpha * p[i];
+      const real pi = first ? own.a : own.a + beta * own.b;
+      st<real>(zp, i, Pair<real>{own.a, pi});
+      const real ri = roi - alpha * qi;
+      const real ui = uo + alpha * pi;
       rn[i] = ri;
       P.u[i] = ui;
       P.lev[0].res[i] = ri - sum;
@@ -444,8 +574,9 @@ __device__ void phase_pcg_b(const Prob<real>& P, const Ctrl* C, int t, double* a
 
 // ---- FIELD: effective field, torque, fused reductions ----
 template <typename real, int LPR>
-__device__ void phase_field(const Prob<real>& P, const Ctrl* C, int t, double* acc) {
+__device__ void phase_field(const ProbDev<real>& P, const Ctrl* C, int t, double* acc) {
   constexpr int RPP = kBlock / LPR;
+  constexpr int kU = kUnrollWide<real>;
   const int lane = threadIdx.x & (LPR - 1);
   const int slot = threadIdx.x / LPR;
   int r0, r1;
@@ -457,28 +588,34 @@ __device__ void phase_field(const Prob<real>& P, const Ctrl* C, int t, double* a
   const real bzx = zeem ? real(C->bz[0]) : real(0);
   const real bzy = zeem ? real(C->bz[1]) : real(0);
   const real bzz = zeem ? real(C->bz[2]) : real(0);
-  const real* __restrict__ mx = P.m[tr][0];
-  const real* __restrict__ my = P.m[tr][1];
-  const real* __restrict__ mz = P.m[tr][2];
+  DevPtr<const real> __restrict__ mx = P.m[tr][0];
+  DevPtr<const real> __restrict__ my = P.m[tr][1];
+  DevPtr<const real> __restrict__ mz = P.m[tr][2];
+  // the row group's 13 running sums live in LDS, not in registers, during the
+  // sweep (same additions in the same order)
+  __shared__ double s_facc[RPP][kNPart];
+  double* fa = s_facc[slot];
+  if (lane == 0)
+    for (int k = 0; k < kNPart; ++k) fa[k] = 0.0;
   for (int base = r0; base < r1; base += RPP) {
     const int i = base + slot;
     const bool valid = i < r1;
     real kx = 0, ky = 0, kz = 0, dx = 0, dy = 0, dz = 0;
     if (valid) {
       const int ke = P.mrp[i + 1];
-      for (int k0 = P.mrp[i] + lane; k0 < ke; k0 += kUnroll * LPR) {
-        int j[kUnroll];
-        bool ok[kUnroll];
+      for (int k0 = P.mrp[i] + lane; k0 < ke; k0 += kU * LPR) {
+        int j[kU];
+        bool ok[kU];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
+        for (int u = 0; u < kU; ++u) {
           const int k = k0 + u * LPR;
           ok[u] = k < ke;
           j[u] = P.mci[ok[u] ? k : k0];
         }
         if (exch) {
-          real kv[kUnroll], gx[kUnroll], gy[kUnroll], gz[kUnroll];
+          real kv[kU], gx[kU], gy[kU], gz[kU];
 #pragma unroll
-          for (int u = 0; u < kUnroll; ++u) {
+          for (int u = 0; u < kU; ++u) {
             const int k = ok[u] ? k0 + u * LPR : k0;
             kv[u] = ok[u] ? P.K[k] : real(0);
             gx[u] = mx[j[u]];
@@ -486,16 +623,16 @@ __device__ void phase_field(const Prob<real>& P, const Ctrl* C, int t, double* a
             gz[u] = mz[j[u]];
           }
 #pragma unroll
-          for (int u = 0; u < kUnroll; ++u) {
+          for (int u = 0; u < kU; ++u) {
             kx += kv[u] * gx[u];
             ky += kv[u] * gy[u];
             kz += kv[u] * gz[u];
           }
         }
         if (demag) {
-          real ex[kUnroll], ey[kUnroll], ez[kUnroll], uj[kUnroll];
+          real ex[kU], ey[kU], ez[kU], uj[kU];
 #pragma unroll
-          for (int u = 0; u < kUnroll; ++u) {
+          for (int u = 0; u < kU; ++u) {
             const int k = ok[u] ? k0 + u * LPR : k0;
             const real f = ok[u] ? real(1) : real(0);
             ex[u] = f * P.D2[0][k];
@@ -504,7 +641,7 @@ __device__ void phase_field(const Prob<real>& P, const Ctrl* C, int t, double* a
             uj[u] = P.u[j[u]];
           }
 #pragma unroll
-          for (int u = 0; u < kUnroll; ++u) {
+          for (int u = 0; u < kU; ++u) {
             dx += ex[u] * uj[u];
             dy += ey[u] * uj[u];
             dz += ez[u] * uj[u];
@@ -539,14 +676,14 @@ __device__ void phase_field(const Prob<real>& P, const Ctrl* C, int t, double* a
         P.h[2][i] = hz;
       }
       const double V = (double)P.V[i];
-      acc[FP_EEX] += 0.5 * V * (double)(m0 * kx + m1 * ky + m2 * kz);
-      acc[FP_EAN] -= 0.5 * V * (double)(m0 * ax + m1 * ay + m2 * az);
-      acc[FP_EZ] -= V * (double)(m0 * bzx + m1 * bzy + m2 * bzz);
-      acc[FP_ED] += 0.5 * V * (double)(m0 * dx + m1 * dy + m2 * dz);
+      fa[FP_EEX] += 0.5 * V * (double)(m0 * kx + m1 * ky + m2 * kz);
+      fa[FP_EAN] -= 0.5 * V * (double)(m0 * ax + m1 * ay + m2 * az);
+      fa[FP_EZ] -= V * (double)(m0 * bzx + m1 * bzy + m2 * bzz);
+      fa[FP_ED] += 0.5 * V * (double)(m0 * dx + m1 * dy + m2 * dz);
       const double H2 = (double)Hx * Hx + (double)Hy * Hy + (double)Hz * Hz;
-      acc[FP_TMAX] = fmax(acc[FP_TMAX], sqrt(H2));
-      acc[FP_D] += V * H2;
-      acc[FP_H2] += H2;
+      fa[FP_TMAX] = fmax(fa[FP_TMAX], sqrt(H2));
+      fa[FP_D] += V * H2;
+      fa[FP_H2] += H2;
       // BB differences against the accepted state: s = m_t - m, y = g_t - g, g = m x H
       const real n0 = P.m[a][0][i], n1 = P.m[a][1][i], n2 = P.m[a][2][i];
       const real G0 = P.H[a][0][i], G1 = P.H[a][1][i], G2 = P.H[a][2][i];
@@ -554,13 +691,17 @@ __device__ void phase_field(const Prob<real>& P, const Ctrl* C, int t, double* a
       const double y0 = (double)(m1 * Hz - m2 * Hy) - (double)(n1 * G2 - n2 * G1);
       const double y1 = (double)(m2 * Hx - m0 * Hz) - (double)(n2 * G0 - n0 * G2);
       const double y2 = (double)(m0 * Hy - m1 * Hx) - (double)(n0 * G1 - n1 * G0);
-      acc[FP_SS] += V * (s0 * s0 + s1 * s1 + s2 * s2);
-      acc[FP_SY] += V * (s0 * y0 + s1 * y1 + s2 * y2);
-      acc[FP_YY] += V * (y0 * y0 + y1 * y1 + y2 * y2);
-      acc[FP_MX] += V * (double)m0;
-      acc[FP_MY] += V * (double)m1;
-      acc[FP_MZ] += V * (double)m2;
+      fa[FP_SS] += V * (s0 * s0 + s1 * s1 + s2 * s2);
+      fa[FP_SY] += V * (s0 * y0 + s1 * y1 + s2 * y2);
+      fa[FP_YY] += V * (y0 * y0 + y1 * y1 + y2 * y2);
+      fa[FP_MX] += V * (double)m0;
+      fa[FP_MY] += V * (double)m1;
+      fa[FP_MZ] += V * (double)m2;
     }
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < kNPart; ++k) acc[k] = fa[k];
   }
 }
 
@@ -607,9 +748,9 @@ __device__ void finish_done(Ctrl* C, int status) {
 }
 
 template <typename real>
-__device__ __forceinline__ void signal_done(const Prob<real>& P, const Ctrl* C) {
+__device__ __forceinline__ void signal_done(const ProbDev<real>& P, const Ctrl* C) {
   if (P.ndone && C->phase == PH_DONE) {
-    const unsigned k = atomicAdd(P.ndone, 1u);
+    const unsigned k = atomicAdd((unsigned*)P.ndone, 1u);
     if (P.done_list) P.done_list[k] = P.slot;
   }
 }
@@ -722,7 +863,7 @@ __device__ void step_logic(Ctrl* C, const double* v) {
 
 // Advance the state by the outcome of the phase it records (v: the finished
 // reductions of that phase's partials).
-__device__ void transition(Ctrl* C, const double* v, const double* btab, int n_lev) {
+__device__ void transition(Ctrl* C, const double* v, const double* btab, int n_lev, int plain) {
   C->seq++;
   const int phase = C->phase;
   if (phase == PH_IDLE || phase == PH_DONE) return;
@@ -731,7 +872,7 @@ __device__ void transition(Ctrl* C, const double* v, const double* btab, int n_l
     return;
   }
   C->launches_done++;
-  C->alg_bytes += btab[byte_slot(phase, C->mg_op, C->mg_lev)];
+  if (btab) C->alg_bytes += btab[byte_slot(phase, C->mg_op, C->mg_lev)];   // block 0 only: it publishes C
   C->nphase[phase == PH_FIELD ? 3 : phase == PH_PREP ? 0 : (phase == PH_CG0 || phase == PH_MG) ? 1 : 2]++;
   switch (phase) {
     case PH_PREP:
@@ -770,8 +911,8 @@ __device__ void transition(Ctrl* C, const double* v, const double* btab, int n_l
           }
           return;
         case MG_SOLVE:
-          C->mg_op = MG_PROL;
           C->mg_lev = n_lev - 1;
+          C->mg_op = ((plain >> C->mg_lev) & 1) ? MG_POST : MG_PROL;
           return;
         case MG_PROL:
           C->mg_op = MG_POST;
@@ -779,7 +920,7 @@ __device__ void transition(Ctrl* C, const double* v, const double* btab, int n_l
         default:   // MG_POST
           if (C->mg_lev > 0) {
             C->mg_lev--;
-            C->mg_op = MG_PROL;
+            C->mg_op = ((plain >> C->mg_lev) & 1) ? MG_POST : MG_PROL;
             return;
           }
           // z = M r is complete: next search direction
@@ -839,27 +980,78 @@ __device__ void transition(Ctrl* C, const double* v, const double* btab, int n_l
 
 // out[k] = sum (max for the torque slot) over the G block partials of slot k.
 // Wavefront w takes slots w, w + 8, ...; lanes stride over the blocks, then a
-// butterfly combines them: the same fixed order in every block.
-__device__ void reduce_partials(const double* src, int G, int np, int phase, double* out) {
+// butterfly combines them: the same fixed order in every block.  Slots 0 and
+// 1 were already fetched (`pre`, by waves 0 and 1) together with the control
+// block.
+constexpr int kPreParts = 8;   // partials per lane fetched early: G <= 64 * kPreParts
+__device__ void reduce_partials(DevPtr<const double> src, int G, int np, int phase, const double* pre, double* out) {
   const int wid = threadIdx.x >> 6, lid = threadIdx.x & 63;
   for (int k = wid; k < np; k += kBlock / 64) {
     const bool mx = (phase == PH_FIELD && k == FP_TMAX);
     double v = 0.0;
-    for (int q = lid; q < G; q += 64) {
-      const double x = src[(size_t)q * kNPart + k];
-      v = mx ? fmax(v, x) : v + x;
+    if (k < 2 && G <= 64 * kPreParts) {
+#pragma unroll
+      for (int u = 0; u < kPreParts; ++u) {
+        const double x = pre[u];
+        v = (lid + 64 * u < G) ? (mx ? fmax(v, x) : v + x) : v;
+      }
+    } else {
+      for (int q = lid; q < G; q += 64) {
+        const double x = src[(size_t)q * kNPart + k];
+        v = mx ? fmax(v, x) : v + x;
+      }
     }
     v = mx ? wave_max(v) : wave_sum(v);
     if (lid == 0) out[k] = v;
   }
 }
 
+// One phase on this block's rows, then its block partials: butterfly in each
+// wave, then the waves in order; plain stores, published to the next launch
+// by the kernel boundary.  The accumulators live only inside one phase, so
+// each phase is register-allocated on its own.
+template <typename real, int LPR, int PHASE>
+__device__ __forceinline__ void run_phase(const ProbDev<real>& P, const Ctrl* C, int t, int lb, int parity,
+                                          double (*s_red)[kNPart]) {
+  constexpr int NA = PHASE == PH_FIELD ? kNPart : PHASE == PH_PREP ? 3 : PHASE == PH_MG ? 1 : 4;
+  double acc[NA];
+#pragma unroll
+  for (int k = 0; k < NA; ++k) acc[k] = 0.0;
+  if constexpr (PHASE == PH_PREP) phase_prep<real, LPR>(P, C, t, acc);
+  else if constexpr (PHASE == PH_CG0) phase_cg0<real, LPR>(P, C, t, acc);
+  else if constexpr (PHASE == PH_CG) phase_cg<real, LPR>(P, C, t, acc);
+  else if constexpr (PHASE == PH_FIELD) phase_field<real, LPR>(P, C, t, acc);
+  else if constexpr (PHASE == PH_MG) phase_mg<real, LPR>(P, C, t, acc);
+  else if constexpr (PHASE == PH_PCG_A) phase_pcg_a<real, LPR>(P, C, t, acc);
+  else phase_pcg_b<real, LPR>(P, C, t, acc);
+
+  const int np = n_parts(PHASE, C->mg_op, C->mg_lev);
+  if (np == 0) return;
+  const int wid = threadIdx.x >> 6, lid = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < NA; ++k) {
+    if (k < np) {
+      const double v = (PHASE == PH_FIELD && k == FP_TMAX) ? wave_max(acc[k]) : wave_sum(acc[k]);
+      if (lid == 0) s_red[wid][k] = v;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < np) {
+    const int k = threadIdx.x;
+    const bool mx = (PHASE == PH_FIELD && k == FP_TMAX);
+    double v = s_red[0][k];
+    for (int w = 1; w < kBlock / 64; ++w) v = mx ? fmax(v, s_red[w][k]) : v + s_red[w][k];
+    P.part[((size_t)parity * P.G + lb) * kNPart + k] = v;
+  }
+}
+
 template <typename real, int LPR>
-__global__ void __launch_bounds__(kBlock) k_step(const Prob<real>* __restrict__ probs, int nprob,
-                                                 const int* __restrict__ blk_start, int parity) {
+__global__ void __launch_bounds__(kBlock, 4) k_step(const ProbDev<real>* __restrict__ probs, int nprob,
+                                                    const int* __restrict__ blk_start, int parity) {
   __shared__ Ctrl s_c;
   __shared__ double s_red[kBlock / 64][kNPart];
   __shared__ double s_tot[kNPart];
+  __shared__ double s_btab[kByteSlots];
   __shared__ int s_newly_done;
   const int b = blockIdx.x;
   int lo = 0, hi = nprob;
@@ -868,29 +1060,41 @@ __global__ void __launch_bounds__(kBlock) k_step(const Prob<real>* __restrict__ 
     if (blk_start[mid] <= b) lo = mid;
     else hi = mid;
   }
-  const Prob<real>& P = probs[lo];
+  const ProbDev<real>& P = probs[lo];
   const int lb = b - P.blk0;
   const int prev = parity ^ 1;
 
-  // prologue: the previous launch's state and the reductions of its phase
+  // prologue: the previous launch's state and the reductions of its phase.
+  // The control block, block 0's byte table and partial slots 0 and 1 are
+  // fetched in one round trip; the phase decides later what is used.
+  DevPtr<const double> part_prev = P.part + (size_t)prev * P.G * kNPart;
+  double pre[kPreParts];
   {
-    const long long* src = reinterpret_cast<const long long*>(&P.ctrl[prev]);
+    const int wid = threadIdx.x >> 6, lid = threadIdx.x & 63;
+#pragma unroll
+    for (int u = 0; u < kPreParts; ++u) {
+      const int q = lid + 64 * u;
+      pre[u] = (wid < 2 && q < P.G) ? part_prev[(size_t)q * kNPart + wid] : 0.0;
+    }
+    DevPtr<const long long> src = reinterpret_cast<DevPtr<const long long>>(P.ctrl + prev);
     long long* dst = reinterpret_cast<long long*>(&s_c);
     for (int w = threadIdx.x; w < (int)(sizeof(Ctrl) / 8); w += kBlock) dst[w] = src[w];
+    if (lb == 0)
+      for (int w = threadIdx.x; w < kByteSlots; w += kBlock) s_btab[w] = P.btab[w];
   }
   __syncthreads();
   const int ran = s_c.phase;
   const int np_prev = n_parts(ran, s_c.mg_op, s_c.mg_lev);
-  if (np_prev > 0) reduce_partials(P.part + (size_t)prev * P.G * kNPart, P.G, np_prev, ran, s_tot);
+  if (np_prev > 0) reduce_partials(part_prev, P.G, np_prev, ran, pre, s_tot);
   __syncthreads();
   if (threadIdx.x == 0) {
-    transition(&s_c, s_tot, P.btab, P.n_lev);
+    transition(&s_c, s_tot, lb == 0 ? s_btab : nullptr, P.n_lev, P.mg_plain);
     s_newly_done = (ran != PH_DONE && s_c.phase == PH_DONE);
   }
   __syncthreads();
   if (lb == 0) {
     const long long* src = reinterpret_cast<const long long*>(&s_c);
-    long long* dst = reinterpret_cast<long long*>(&P.ctrl[parity]);
+    DevPtr<long long> dst = reinterpret_cast<DevPtr<long long>>(P.ctrl + parity);
     for (int w = threadIdx.x; w < (int)(sizeof(Ctrl) / 8); w += kBlock) dst[w] = src[w];
     if (threadIdx.x == 0 && s_newly_done) signal_done<real>(P, &s_c);
   }
@@ -898,49 +1102,28 @@ __global__ void __launch_bounds__(kBlock) k_step(const Prob<real>* __restrict__ 
   if (!is_work(phase)) return;
   const int t = (lb & 7) * (P.G >> 3) + (lb >> 3);
 
-  double acc[kNPart];
-#pragma unroll
-  for (int k = 0; k < kNPart; ++k) acc[k] = 0.0;
   switch (phase) {
     case PH_PREP:
-      phase_prep<real, LPR>(P, &s_c, t, acc);
+      run_phase<real, LPR, PH_PREP>(P, &s_c, t, lb, parity, s_red);
       break;
     case PH_CG0:
-      phase_cg0<real, LPR>(P, &s_c, t, acc);
+      run_phase<real, LPR, PH_CG0>(P, &s_c, t, lb, parity, s_red);
       break;
     case PH_CG:
-      phase_cg<real, LPR>(P, &s_c, t, acc);
+      run_phase<real, LPR, PH_CG>(P, &s_c, t, lb, parity, s_red);
       break;
     case PH_FIELD:
-      phase_field<real, LPR>(P, &s_c, t, acc);
+      run_phase<real, LPR, PH_FIELD>(P, &s_c, t, lb, parity, s_red);
       break;
     case PH_MG:
-      phase_mg<real, LPR>(P, &s_c, t, acc);
+      run_phase<real, LPR, PH_MG>(P, &s_c, t, lb, parity, s_red);
       break;
     case PH_PCG_A:
-      phase_pcg_a<real, LPR>(P, &s_c, t, acc);
+      run_phase<real, LPR, PH_PCG_A>(P, &s_c, t, lb, parity, s_red);
       break;
     case PH_PCG_B:
-      phase_pcg_b<real, LPR>(P, &s_c, t, acc);
+      run_phase<real, LPR, PH_PCG_B>(P, &s_c, t, lb, parity, s_red);
       break;
-  }
-
-  // block partials: butterfly in each wave, then the waves in order; plain
-  // stores, published to the next launch by the kernel boundary
-  const int np = n_parts(phase, s_c.mg_op, s_c.mg_lev);
-  if (np == 0) return;
-  const int wid = threadIdx.x >> 6, lid = threadIdx.x & 63;
-  for (int k = 0; k < np; ++k) {
-    const double v = (phase == PH_FIELD && k == FP_TMAX) ? wave_max(acc[k]) : wave_sum(acc[k]);
-    if (lid == 0) s_red[wid][k] = v;
-  }
-  __syncthreads();
-  if (threadIdx.x < np) {
-    const int k = threadIdx.x;
-    const bool mx = (phase == PH_FIELD && k == FP_TMAX);
-    double v = s_red[0][k];
-    for (int w = 1; w < kBlock / 64; ++w) v = mx ? fmax(v, s_red[w][k]) : v + s_red[w][k];
-    P.part[((size_t)parity * P.G + lb) * kNPart + k] = v;
   }
 }
 
@@ -1026,15 +1209,16 @@ hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream
 template <typename real>
 hipError_t launch_step(int lpr, const Prob<real>* probs, int nprob, const int* blk_start, int grid, int parity,
                        hipStream_t s) {
+  const ProbDev<real>* dprobs = reinterpret_cast<const ProbDev<real>*>(probs);
   switch (lpr) {
     case 4:
-      hipLaunchKernelGGL((k_step<real, 4>), dim3(grid), dim3(kBlock), 0, s, probs, nprob, blk_start, parity);
+      hipLaunchKernelGGL((k_step<real, 4>), dim3(grid), dim3(kBlock), 0, s, dprobs, nprob, blk_start, parity);
       break;
     case 16:
-      hipLaunchKernelGGL((k_step<real, 16>), dim3(grid), dim3(kBlock), 0, s, probs, nprob, blk_start, parity);
+      hipLaunchKernelGGL((k_step<real, 16>), dim3(grid), dim3(kBlock), 0, s, dprobs, nprob, blk_start, parity);
       break;
     default:
-      hipLaunchKernelGGL((k_step<real, 8>), dim3(grid), dim3(kBlock), 0, s, probs, nprob, blk_start, parity);
+      hipLaunchKernelGGL((k_step<real, 8>), dim3(grid), dim3(kBlock), 0, s, dprobs, nprob, blk_start, parity);
       break;
   }
   return hipGetLastError();
