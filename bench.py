@@ -178,23 +178,29 @@ def run_grains(args):
     t_batch = time.perf_counter() - t0
     evals = sum(r.evals for r in res)
     node_evals = sum(p.N * r.evals for p, r in zip(probs, res))
-    finals = [p.get_m() for p in probs]
     print(f"[bench] batch {t_batch:.1f} s", file=sys.stderr, flush=True)
     for p, st in zip(probs, states):
         p.set_state(st)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    single = [p.minimize() for p in probs]
+    single = []
+    for k, p in enumerate(probs):
+        single.append(p.minimize())
+        if (k + 1) % 64 == 0:
+            print(f"[bench] one by one {k + 1}/{len(probs)}: {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+                  flush=True)
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
-    same = sum(int(a.energy_J == b.energy_J and np.array_equal(m, p.get_m()))
-               for a, b, m, p in zip(res, single, finals, probs))
+    # the shared launch runs small problems on fewer blocks than a lone run,
+    # so the two agree to rounding (bitwise at equal launch shapes: tests)
+    rel = [abs(a.energy_J - b.energy_J) / max(abs(b.e_exch_J) + abs(b.e_anis_J) + abs(b.e_zeem_J) + abs(b.e_demag_J),
+                                                1e-300) for a, b in zip(res, single)]
     line = base_line(node_evals / t_batch, 1, 0, t_batch, "f32+f64-reductions",
                      {"workload": f"{len(probs)} grain cubes (edges log-uniform 10-60 nm), mixed precision, "
                                   f"-1 T, one batched run", "magnet_nodes_total": Nsum})
     line["roofline"] = None
     line["detail"] = {"batched_s": t_batch, "one_by_one_s": t_seq, "speedup": t_seq / t_batch,
-                      "evals": evals, "identical_to_one_by_one": f"{same}/{len(probs)}",
+                      "evals": evals, "max_rel_energy_diff_vs_one_by_one": float(max(rel)),
                       "tuned_lanes": lanes, "tuned_blocks": blocks,
                       "statuses": sorted(set(r.status for r in res))}
     for p in probs:
@@ -217,6 +223,7 @@ def run_serve(args):
     ctx = binding.Context(0)
     srv = binding.Server(ctx, hbm_budget=int(args.hbm_gb * (1 << 30)), max_slots=args.slots)
     t_start = time.perf_counter()
+    t_last = t_start
     pending = {}
     lat, node_evals, statuses = [], 0.0, []
     k = 0
@@ -236,6 +243,10 @@ def run_serve(args):
                 node_evals += n * r.evals
                 statuses.append(r.status)
         time.sleep(0.001)
+        if time.perf_counter() - t_last > 15.0:
+            t_last = time.perf_counter()
+            print(f"[bench] serve t={t_last - t_start:.0f} s submitted {k}/{len(reqs)} completed {len(lat)}",
+                  file=sys.stderr, flush=True)
         if time.perf_counter() - t_start > args.serve_timeout:
             print("[bench] serve timeout", file=sys.stderr, flush=True)
             break

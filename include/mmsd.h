@@ -201,8 +201,11 @@ int mmsd_hysteresis(mmsd_problem p, const double* b_T, int64_t n, const mmsd_opt
 /* Minimize n independent problems of one context together: every device
  * launch advances all unfinished problems by one phase (one persistent
  * kernel over a problem table; a captured launch graph is replayed until all
- * are done).  Each problem's result equals its own mmsd_minimize result
- * bit for bit.  out: [n]. */
+ * are done, and finished problems are dropped from the table as they
+ * accumulate).  Inside the shared launch a problem runs on
+ * min(its own block count, a multiple of 8 covering its rows with about four
+ * passes of a 512-thread block) blocks; its result equals its own
+ * mmsd_minimize result at that block count bit for bit.  out: [n]. */
 int mmsd_minimize_batch(mmsd_problem* probs, int n, const mmsd_options* o, mmsd_result* out);
 
 /* Checkpoint: m, potential warm start and field.  bytes: in = capacity, out =
@@ -258,7 +261,8 @@ int mmsd_assembly_export(const mmsd_mesh* mesh, const mmsd_material* mats, int n
  * their device footprint fits in hbm_budget bytes and a slot is free (at
  * most max_slots resident), assembles and uploads them off the critical
  * path, advances every resident problem by one phase per device launch
- * (continuous batching), and releases a slot as soon as its problem is done. */
+ * (continuous batching), and releases a slot as soon as its problem is done.
+ * A request runs with the block count mmsd_minimize_batch would give it. */
 int mmsd_server_create(mmsd_ctx ctx, size_t hbm_budget, int max_slots, mmsd_server* out);
 int mmsd_submit(mmsd_server s, const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats,
                 const double b_T[3], int precision, const double* m0 /* nullable: +z */,

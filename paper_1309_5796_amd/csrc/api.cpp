@@ -704,6 +704,16 @@ int snap_locked(mmsd_problem p, int k, bool save) {
 double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
 }  // namespace
+
+// Blocks of one problem inside a shared launch: about four passes of a block
+// over its chunk of rows, a multiple of 8, capped by the problem's own shape.
+int batch_blocks(mmsd_problem_s* p, bool demag) {
+  const int64_t rows = std::max<int64_t>(p->A.N, demag ? p->A.Nt : 0);
+  const int64_t per_block = 4LL * (kBlock / p->lpr);
+  int64_t g = (rows + per_block - 1) / per_block;
+  g = (g + 7) / 8 * 8;
+  return (int)std::max<int64_t>(8, std::min<int64_t>(g, p->G));
+}
 }  // namespace mmsd
 
 void* mmsd_ctx_s::dalloc(size_t bytes) {
@@ -1079,46 +1089,69 @@ int mmsd_minimize_batch(mmsd_problem* probs, int n, const mmsd_options* o, mmsd_
   auto t0 = std::chrono::steady_clock::now();
   MMSD_HIP(hipSetDevice(c->device));
   hipStream_t st = c->stream;
-  // one table per precision, problems keep their own block decomposition
-  std::vector<int> idx[2];
-  for (int i = 0; i < n; ++i) idx[probs[i]->precision == MMSD_MIXED ? 1 : 0].push_back(i);
-  size_t bytes = 0;
-  for (int q = 0; q < 2; ++q) bytes += align_up(sizeof(Prob<double>) * idx[q].size()) + align_up(4 * (idx[q].size() + 1));
-  bytes += 256;
-  char* tab = (char*)c->dalloc(bytes);
-  if (!tab) return invalid("batch table allocation failed");
-  unsigned* dndone = (unsigned*)(tab + bytes - 256);
+  // Each problem gets blocks in proportion to its rows (about four passes of
+  // a block over its chunk), capped by its own launch shape; the count stays
+  // fixed for the run because a launch reduces the previous launch's G
+  // partials.
+  std::vector<int> gb(n);
+  for (int i = 0; i < n; ++i) gb[i] = batch_blocks(probs[i], (rs[i].terms & MMSD_DEMAG) != 0);
+  // scratch: the finished count and list, then the tables
+  const size_t list_bytes = align_up(256 + 4 * (size_t)n);
+  char* misc = (char*)c->dalloc(list_bytes);
+  if (!misc) return invalid("batch allocation failed");
+  unsigned* dndone = (unsigned*)misc;
+  int* dlist = (int*)(misc + 256);
+  char* tab = nullptr;
   std::vector<Table> tabs;
-  size_t off = 0;
-  int rc = MMSD_OK;
-  for (int q = 0; q < 2 && !rc; ++q) {
-    if (idx[q].empty()) continue;
-    const size_t ps = q ? sizeof(Prob<float>) : sizeof(Prob<double>);
-    std::vector<unsigned char> h(ps * idx[q].size());
-    std::vector<int> blk(idx[q].size() + 1, 0);
-    int lpr = probs[idx[q][0]]->lpr;
-    for (size_t k = 0; k < idx[q].size(); ++k) {
-      mmsd_problem p = probs[idx[q][k]];
-      if (p->lpr != lpr) rc = invalid("batch problems of one precision must share lanes per row");
-      blk[k + 1] = blk[k] + p->G;
-      std::memcpy(&h[k * ps], p->desc, ps);
-      if (q) {
-        reinterpret_cast<Prob<float>*>(&h[k * ps])->blk0 = blk[k];
-        reinterpret_cast<Prob<float>*>(&h[k * ps])->ndone = dndone;
-      } else {
-        reinterpret_cast<Prob<double>*>(&h[k * ps])->blk0 = blk[k];
-        reinterpret_cast<Prob<double>*>(&h[k * ps])->ndone = dndone;
+  // One table per precision over the unfinished problems; finished ones are
+  // dropped when the table is rebuilt (problems keep their block counts).
+  auto build_tables = [&](const std::vector<char>& done) -> int {
+    if (tab) c->dfree(tab);
+    tab = nullptr;
+    tabs.clear();
+    std::vector<int> idx[2];
+    for (int i = 0; i < n; ++i)
+      if (!done[i]) idx[probs[i]->precision == MMSD_MIXED ? 1 : 0].push_back(i);
+    size_t bytes = 256;
+    for (int q = 0; q < 2; ++q) bytes += align_up(sizeof(Prob<double>) * idx[q].size()) + align_up(4 * (idx[q].size() + 1));
+    tab = (char*)c->dalloc(bytes);
+    if (!tab) return invalid("batch table allocation failed");
+    size_t off = 0;
+    for (int q = 0; q < 2; ++q) {
+      if (idx[q].empty()) continue;
+      const size_t ps = q ? sizeof(Prob<float>) : sizeof(Prob<double>);
+      std::vector<unsigned char> h(ps * idx[q].size());
+      std::vector<int> blk(idx[q].size() + 1, 0);
+      const int lpr = probs[idx[q][0]]->lpr;
+      for (size_t k = 0; k < idx[q].size(); ++k) {
+        const int i = idx[q][k];
+        mmsd_problem p = probs[i];
+        if (p->lpr != lpr) return invalid("batch problems of one precision must share lanes per row");
+        blk[k + 1] = blk[k] + gb[i];
+        std::memcpy(&h[k * ps], p->desc, ps);
+        auto patch = [&](auto* d) {
+          d->G = gb[i];
+          d->blk0 = blk[k];
+          d->ndone = dndone;
+          d->done_list = dlist;
+          d->slot = i;
+        };
+        if (q) patch(reinterpret_cast<Prob<float>*>(&h[k * ps]));
+        else patch(reinterpret_cast<Prob<double>*>(&h[k * ps]));
       }
+      char* dp = tab + off;
+      off += align_up(h.size());
+      char* db = tab + off;
+      off += align_up(4 * blk.size());
+      if (hipMemcpyAsync(dp, h.data(), h.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+          hipMemcpyAsync(db, blk.data(), 4 * blk.size(), hipMemcpyHostToDevice, st) != hipSuccess)
+        return hip_fail(hipGetLastError(), "batch table upload");
+      tabs.push_back(Table{q ? MMSD_MIXED : MMSD_FP64, dp, (const int*)db, (int)idx[q].size(), blk.back(), lpr});
     }
-    char* dp = tab + off;
-    off += align_up(h.size());
-    char* db = tab + off;
-    off += align_up(4 * blk.size());
-    if (!rc && (hipMemcpyAsync(dp, h.data(), h.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
-                hipMemcpyAsync(db, blk.data(), 4 * blk.size(), hipMemcpyHostToDevice, st) != hipSuccess))
-      rc = hip_fail(hipGetLastError(), "batch table upload");
-    tabs.push_back(Table{q ? MMSD_MIXED : MMSD_FP64, dp, (const int*)db, (int)idx[q].size(), blk.back(), lpr});
-  }
+    return MMSD_OK;
+  };
+  std::vector<char> done(n, 0);
+  int rc = build_tables(done);
   unsigned* hdone = nullptr;
   if (!rc && hipHostMalloc((void**)&hdone, 2 * sizeof(unsigned), hipHostMallocDefault) != hipSuccess)
     rc = hip_fail(hipGetLastError(), "pinned poll buffer");
@@ -1132,6 +1165,7 @@ int mmsd_minimize_batch(mmsd_problem* probs, int n, const mmsd_options* o, mmsd_
   if (!rc) {
     int B = 8, cur = 0;
     bool have_prev = false;
+    unsigned compacted_at = 0;
     hipEvent_t ev[2];
     hipEventCreateWithFlags(&ev[0], hipEventDisableTiming);
     hipEventCreateWithFlags(&ev[1], hipEventDisableTiming);
@@ -1146,11 +1180,36 @@ int mmsd_minimize_batch(mmsd_problem* probs, int n, const mmsd_options* o, mmsd_
           rc = hip_fail(e, "batch poll");
           break;
         }
-        if (hdone[1 - cur] >= (unsigned)n) break;
+        const unsigned nd = hdone[1 - cur];
+        if (nd >= (unsigned)n) break;
         if (run_timed_out(t0)) {
           set_error("run exceeded MMSD_RUN_TIMEOUT_S");
           rc = MMSD_E_HIP;
           break;
+        }
+        // drop finished problems once an eighth of the rest has finished
+        if (nd > compacted_at && (nd - compacted_at) * 8 >= (unsigned)n - compacted_at) {
+          if (hipStreamSynchronize(st) != hipSuccess) {
+            rc = hip_fail(hipGetLastError(), "batch compaction");
+            break;
+          }
+          unsigned nd_now = 0;
+          std::vector<int> list(n);
+          if (hipMemcpy(&nd_now, dndone, 4, hipMemcpyDeviceToHost) != hipSuccess ||
+              (nd_now && hipMemcpy(list.data(), dlist, 4 * (size_t)nd_now, hipMemcpyDeviceToHost) != hipSuccess)) {
+            rc = hip_fail(hipGetLastError(), "batch compaction");
+            break;
+          }
+          if (nd_now >= (unsigned)n) break;
+          for (unsigned k = 0; k < nd_now; ++k) done[list[k]] = 1;
+          for (auto& kv : graphs) hipGraphExecDestroy(kv.second);
+          graphs.clear();
+          if ((rc = build_tables(done))) break;
+          compacted_at = nd_now;
+          have_prev = false;
+          cur = 0;
+          B = 8;
+          continue;
         }
       }
       have_prev = true;
@@ -1180,7 +1239,8 @@ int mmsd_minimize_batch(mmsd_problem* probs, int n, const mmsd_options* o, mmsd_
     else if (worst == MMSD_OK && C.status > 0) worst = C.status;
   }
   if (hdone) hipHostFree(hdone);
-  c->dfree(tab);
+  if (tab) c->dfree(tab);
+  c->dfree(misc);
   return rc ? rc : worst;
 }
 

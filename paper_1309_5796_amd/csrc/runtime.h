@@ -77,6 +77,7 @@ int launch_table(const Table& t, int parity, hipStream_t st);
 void fill_result(mmsd_problem_s* p, const Ctrl& C, mmsd_result* out, double secs, int64_t launches);
 int ensure_pinned(mmsd_problem_s* p);
 int issue(mmsd_ctx_s* c, const std::vector<Table>& tabs, int B, std::map<int, hipGraphExec_t>* graphs);
+int batch_blocks(mmsd_problem_s* p, bool demag);
 double run_bytes(mmsd_problem_s* p, const Ctrl& C);
 }  // namespace mmsd
 

@@ -52,6 +52,7 @@ struct Request {
   std::vector<double> m_final;
   Clock::time_point t_submit;
   int slot = -1;
+  bool demag = true;       // the resolved terms include the demagnetizing field
 
   mmsd_mesh mesh() const {
     mmsd_mesh m;
@@ -146,6 +147,7 @@ void mmsd_server_s::setup_loop() {
     if (!rc && !r->m0.empty()) rc = mmsd_set_m(p, r->m0.data());
     Resolved res;
     if (!rc) rc = resolve(p, &r->opts, &res);
+    if (!rc) r->demag = (res.terms & MMSD_DEMAG) != 0;
     if (!rc) {
       std::lock_guard<std::mutex> g(upload_ctx->mu);
       rc = ensure_pinned(p);
@@ -239,16 +241,19 @@ void mmsd_server_s::device_loop() {
         for (size_t k = 0; k < idx[q].size(); ++k) {
           Request* r = resident[idx[q][k]];
           mmsd_problem p = r->prob;
-          blk[k + 1] = blk[k] + p->G;
+          const int g = batch_blocks(p, r->demag);
+          blk[k + 1] = blk[k] + g;
           std::memcpy(&h[k * ps], p->desc, ps);
           if (q) {
             auto* d = reinterpret_cast<Prob<float>*>(&h[k * ps]);
+            d->G = g;
             d->blk0 = blk[k];
             d->ndone = dndone;
             d->done_list = dlist;
             d->slot = idx[q][k];
           } else {
             auto* d = reinterpret_cast<Prob<double>*>(&h[k * ps]);
+            d->G = g;
             d->blk0 = blk[k];
             d->ndone = dndone;
             d->done_list = dlist;

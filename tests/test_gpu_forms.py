@@ -29,6 +29,15 @@ def ctx():
     c.close()
 
 
+def shared_launch_blocks(p, lanes=4, cap=512):
+    """Blocks a problem gets inside a shared launch (batch or server): about
+    four passes of a 512-thread block over its rows, a multiple of 8, capped
+    by its own launch shape."""
+    rows = max(p.N, p.Nt)
+    g = -(-rows // (4 * (512 // lanes)))
+    return max(8, min(-(-g // 8) * 8, cap))
+
+
 def small_grain(edge_nm, seed, cells=None):
     rng = np.random.default_rng(seed)
     n = cells or meshgen.config4_cells(edge_nm * 1e-9)
@@ -89,6 +98,10 @@ def test_hysteresis_config1_short_sweep_matches_oracle(ctx, cfg1, cfg1_system):
 
 
 def test_batch_equals_one_by_one_bitwise(ctx):
+    """A shared launch gives each problem min(its own block count, a count
+    proportional to its rows); at a block count below the proportional one
+    (16 here) both runs use the same decomposition and reduction order, so the
+    results agree bit for bit."""
     from paper_1309_5796_amd import binding
     say("batch vs single")
     specs = [(10, 1), (14, 2), (12, 3), (16, 4)]
@@ -97,6 +110,7 @@ def test_batch_equals_one_by_one_bitwise(ctx):
         for edge, seed in specs:
             mesh, m0 = small_grain(edge, seed)
             p = binding.Problem(ctx, mesh, precision=prec)
+            p.set_launch(4, 16)
             p.set_m(m0)
             p.set_field(-1.0 * meshgen.U_H_1DEG)
             st = p.get_state()
@@ -177,6 +191,7 @@ def test_server_results_equal_alone_and_in_the_mix(ctx):
     for edge, seed, prec in reqs:
         mesh, m0 = small_grain(edge, seed)
         p = binding.Problem(ctx, mesh, precision=prec)
+        p.set_launch(4, shared_launch_blocks(p))   # the shape the server gives the request
         p.set_m(m0)
         p.set_field(-1.5 * meshgen.U_H_1DEG)
         r = p.minimize()
