@@ -2,7 +2,7 @@
 """Benchmark of the minimizer on one MI355X.
 
 Default workload: the FP64 hysteresis sweep on the 80 nm cube (40^3 Kuhn
-cells: 68,921 magnet nodes, 274,625 potential nodes), field +8 -> -8 -> +8 T
+cells: 68,921 magnet nodes, 250,047 potential nodes), field +8 -> -8 -> +8 T
 in 0.1 T steps along z tilted by 1 degree, each point warm-started from the
 previous minimum.  A "step" is one field point of the sweep (a full
 minimization: trial steps, potential solves, field, step logic, stopping
@@ -362,8 +362,8 @@ def main():
         "metric": METRIC, "value": value, "unit": "node-iterations/s", "n_gpus": 1,
         "steps": K, "warmup": args.warmup, "ms_per_step": wall / K * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "FP64 hysteresis sweep, 80 nm cube, 40^3 Kuhn cells (68,921 magnet / "
-                               "274,625 potential nodes), +8 -> -8 -> +8 T in 0.1 T steps at 1 deg",
+        "config": {"workload": f"FP64 hysteresis sweep, 80 nm cube, 40^3 Kuhn cells ({p.N:,} magnet / "
+                               f"{p.Nt:,} potential nodes), +8 -> -8 -> +8 T in 0.1 T steps at 1 deg",
                    "field_points": K, "magnet_nodes": p.N, "potential_nodes": p.Nt,
                    "potential_preconditioner": args.precond},
         "roofline": roof,
