@@ -37,7 +37,7 @@ size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 // Layout of one problem's device arena.
 struct Layout {
   size_t mrp, mci, K, D1[3], D2[3], Q[6], V, m[2][3], H[2][3], h[3];
-  size_t lrp, lci, L, u, p, rec[2];
+  size_t lso, lsc, lsv, u, p, rec[2];
   size_t part, ctrl, prob, blk, btab;
   size_t snap[2][2];
   size_t total;
@@ -50,7 +50,7 @@ int blocks_for(int64_t rows, int lpr, int max_blocks) {
   return (int)((g + 7) / 8 * 8);
 }
 
-Layout make_layout(int64_t N, int64_t nnzM, int64_t Nt, int64_t nnzL, int G, size_t s) {
+Layout make_layout(int64_t N, int64_t nnzM, int64_t Nt, int64_t nnzLs, int G, size_t s) {
   Layout L{};
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -70,9 +70,9 @@ Layout make_layout(int64_t N, int64_t nnzM, int64_t Nt, int64_t nnzL, int G, siz
   for (int k = 0; k < 2; ++k)
     for (int c = 0; c < 3; ++c) L.H[k][c] = take(s * N);
   for (int c = 0; c < 3; ++c) L.h[c] = take(s * N);
-  L.lrp = take(4 * (Nt + 1));
-  L.lci = take(4 * nnzL);
-  L.L = take(s * nnzL);
+  L.lso = take(4 * ((Nt + 63) / 64 + 1));
+  L.lsc = take(4 * nnzLs);
+  L.lsv = take(s * nnzLs);
   L.u = take(s * Nt);
   L.p = take(s * Nt);
   for (int k = 0; k < 2; ++k) L.rec[k] = take(4 * s * Nt);
@@ -251,9 +251,10 @@ int build_amg(mmsd_problem p) {
     d.wide_a = L.A.ci.size() > kWideRow * (size_t)L.A.nrows;
     d.wide_p = L.P.ci.size() > kWideRow * (size_t)L.P.nrows;
     d.wide_r = L.R.ci.size() > kWideRow * (size_t)L.R.nrows;
-    d.arp = l == 0 ? P.lrp : (const int*)(base + lo[l].arp);
-    d.aci = l == 0 ? P.lci : (const int*)(base + lo[l].aci);
-    d.av = l == 0 ? P.L : (const real*)(base + lo[l].av);
+    // level 0's operator is the potential matrix, read in its sliced layout
+    d.arp = l == 0 ? nullptr : (const int*)(base + lo[l].arp);
+    d.aci = l == 0 ? nullptr : (const int*)(base + lo[l].aci);
+    d.av = l == 0 ? nullptr : (const real*)(base + lo[l].av);
     d.wd = (const real*)(base + lo[l].wd);
     d.prp = (const int*)(base + lo[l].prp);
     d.pci = (const int*)(base + lo[l].pci);
@@ -291,11 +292,13 @@ template <typename real>
 int build_device(mmsd_problem p) {
   mmsd_ctx c = p->ctx;
   const Assembly& A = p->A;
-  const int64_t N = A.N, Nt = A.Nt, nnzM = (int64_t)A.mci.size(), nnzL = (int64_t)A.lci.size();
+  const int64_t N = A.N, Nt = A.Nt, nnzM = (int64_t)A.mci.size();
+  const int64_t nnzLs = Nt ? sliced_entries(A.lrp) : 0;
+  if (nnzLs >= (int64_t)1 << 31) return invalid("potential matrix too large for 32-bit slice offsets");
   p->lpr = c->lpr;
   p->G = blocks_for(std::max<int64_t>(N, Nt), p->lpr, c->max_blocks);
   const int G = p->G;
-  Layout L = make_layout(N, nnzM, Nt, nnzL, G, sizeof(real));
+  Layout L = make_layout(N, nnzM, Nt, nnzLs, G, sizeof(real));
   p->arena = (char*)c->dalloc(L.total);
   if (!p->arena) {
     set_error("device allocation of " + std::to_string(L.total) + " bytes failed");
@@ -315,8 +318,32 @@ int build_device(mmsd_problem p) {
   for (int k = 0; k < 6; ++k)
     if ((rc = upload_vec<real>(st, base + L.Q[k], A.Q[k]))) return rc;
   if (Nt > 0) {
-    if ((rc = upload_int(st, base + L.lrp, A.lrp)) || (rc = upload_int(st, base + L.lci, A.lci)) ||
-        (rc = upload_vec<real>(st, base + L.L, A.L)))
+    // sliced copy of L: slice s holds rows 64s..64s+63, entry k of row i at
+    // so[s] + 64 k + (i mod 64); short rows are padded with their own column
+    // and a zero value
+    const int64_t ns = (Nt + 63) / 64;
+    std::vector<int> so(ns + 1, 0), sc(nnzLs);
+    std::vector<double> sv(nnzLs, 0.0);
+    for (int64_t sl = 0; sl < ns; ++sl) {
+      int w = 0;
+      for (int64_t i = 64 * sl; i < std::min<int64_t>(Nt, 64 * sl + 64); ++i) w = std::max(w, A.lrp[i + 1] - A.lrp[i]);
+      so[sl + 1] = so[sl] + 64 * w;
+      for (int r = 0; r < 64; ++r) {
+        const int64_t i = 64 * sl + r;
+        const int len = i < Nt ? A.lrp[i + 1] - A.lrp[i] : 0;
+        for (int k = 0; k < w; ++k) {
+          const int64_t q = so[sl] + 64LL * k + r;
+          if (k < len) {
+            sc[q] = A.lci[A.lrp[i] + k];
+            sv[q] = A.L[A.lrp[i] + k];
+          } else {
+            sc[q] = (int)std::min<int64_t>(i, Nt - 1);
+          }
+        }
+      }
+    }
+    if ((rc = upload_int(st, base + L.lso, so)) || (rc = upload_int(st, base + L.lsc, sc)) ||
+        (rc = upload_vec<real>(st, base + L.lsv, sv)))
       return rc;
     // Jacobi factors live in the d field of both CG record buffers
     std::vector<double> rec(4 * (size_t)Nt, 0.0);
@@ -349,9 +376,9 @@ int build_device(mmsd_problem p) {
   }
   for (int k = 0; k < 6; ++k) P.Q[k] = (const real*)(base + L.Q[k]);
   P.V = (const real*)(base + L.V);
-  P.lrp = (const int*)(base + L.lrp);
-  P.lci = (const int*)(base + L.lci);
-  P.L = (const real*)(base + L.L);
+  P.lso = (const int*)(base + L.lso);
+  P.lsc = (const int*)(base + L.lsc);
+  P.lsv = (const real*)(base + L.lsv);
   P.u = (real*)(base + L.u);
   P.p = (real*)(base + L.p);
   for (int k = 0; k < 2; ++k) P.rec[k] = (Rec<real>*)(base + L.rec[k]);
@@ -822,7 +849,7 @@ int mmsd_footprint(const mmsd_mesh* mesh, int precision, size_t* bytes_out) {
     return rc;
   }
   const int G = blocks_for(std::max(ps.N, ps.Nt), 4, 512);
-  *bytes_out = make_layout(ps.N, ps.nnzM, ps.Nt, ps.nnzL, G, precision == MMSD_MIXED ? 4 : 8).total;
+  *bytes_out = make_layout(ps.N, ps.nnzM, ps.Nt, ps.nnzLs, G, precision == MMSD_MIXED ? 4 : 8).total;
   return MMSD_OK;
 }
 

@@ -251,7 +251,19 @@ int pattern_sizes(const mmsd_mesh* mesh, PatternSizes* out, std::string* err) {
     build_pattern(mesh->tets, nb.pot_global, tptr, tlst, nb.pot_of, rp, ci);
     out->nnzL = (int64_t)ci.size();
   }
+  out->nnzLs = out->Nt ? sliced_entries(rp) : 0;
   return MMSD_OK;
+}
+
+int64_t sliced_entries(const std::vector<int>& rp) {
+  const int64_t n = (int64_t)rp.size() - 1;
+  int64_t total = 0;
+  for (int64_t s0 = 0; s0 < n; s0 += 64) {
+    int w = 0;
+    for (int64_t i = s0; i < std::min<int64_t>(n, s0 + 64); ++i) w = std::max(w, rp[i + 1] - rp[i]);
+    total += 64LL * w;
+  }
+  return total;
 }
 
 int assemble_material_values(Assembly* A, std::string* err) {

@@ -45,7 +45,12 @@ struct Assembly {
 
 struct PatternSizes {
   int64_t N, nnzM, Nt, nnzL;
+  int64_t nnzLs;   // entries of the sliced (64-row) copy of the potential matrix, padding included
 };
+
+// Entries of the 64-row sliced layout of a CSR pattern: each slice of 64
+// consecutive rows is padded to its longest row.
+int64_t sliced_entries(const std::vector<int>& rp);
 
 // Validate the mesh and count rows and nonzeros (no values).
 int pattern_sizes(const mmsd_mesh* mesh, PatternSizes* out, std::string* err);

@@ -161,10 +161,12 @@ struct ProbT {
   Ptr<real> m[2][3];          // accepted / trial slots, SoA
   Ptr<real> H[2][3];          // torque m x h per slot
   Ptr<real> h[3];             // effective field (written when store_h)
-  // potential rows (magnet rows first): transformed Laplacian
-  Ptr<const int> lrp;
-  Ptr<const int> lci;
-  Ptr<const real> L;
+  // potential rows (magnet rows first): transformed Laplacian in 64-row
+  // slices (entry k of row i at lso[i/64] + 64 k + i mod 64, short rows
+  // padded with their own column and a zero value)
+  Ptr<const int> lso;
+  Ptr<const int> lsc;
+  Ptr<const real> lsv;
   Ptr<real> u;                // potential (the CG iterate), warm start across solves
   Ptr<real> p;                // search direction (row-local)
   Ptr<Rec<real>> rec[2];      // CG state by buffer parity (pcur)

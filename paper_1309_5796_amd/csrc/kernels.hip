@@ -119,12 +119,46 @@ __device__ __forceinline__ void chunk_rows(int R, int G, int t, int rpp, int& r0
   r1 = (int)(b < R ? b : R);
 }
 
+// Rows of the potential matrix are swept one per thread from its 64-row
+// sliced layout: a wavefront owns one slice, so every index and value load
+// is one contiguous 64-wide access, and a whole block-pass covers 512 rows.
+constexpr int kSellU = 4;   // entries per thread loaded before their gathers
+
+// sum_k v[k] * g(column k) over row i of the sliced potential matrix.  The
+// calling wavefront's active lanes all lie in one slice.
+template <typename real, typename G>
+__device__ __forceinline__ real sell_sum(const ProbDev<real>& P, int i, G&& g) {
+  const int sl = __builtin_amdgcn_readfirstlane(i >> 6);
+  const int o0 = P.lso[sl];
+  const int w = (P.lso[sl + 1] - o0) >> 6;
+  const int o = o0 + (i & 63);
+  real acc = 0;
+  for (int k0 = 0; k0 < w; k0 += kSellU) {
+    int j[kSellU];
+    real v[kSellU];
+#pragma unroll
+    for (int u = 0; u < kSellU; ++u) {
+      const bool ok = k0 + u < w;
+      const int q = o + 64 * (ok ? k0 + u : 0);
+      j[u] = P.lsc[q];
+      v[u] = ok ? P.lsv[q] : real(0);
+    }
+    real x[kSellU];
+#pragma unroll
+    for (int u = 0; u < kSellU; ++u) x[u] = g(j[u]);
+#pragma unroll
+    for (int u = 0; u < kSellU; ++u) acc += v[u] * x[u];
+  }
+  return acc;
+}
+
 // ---- PREP: trial magnetization, Poisson right-hand side, initial residual ----
+// One thread per row: magnet rows also form the trial m_t (and recompute it
+// at their magnet neighbours for b = D1 m_t); every potential row forms
+// r = b - L u.
 template <typename real, int LPR>
 __device__ void phase_prep(const ProbDev<real>& P, const Ctrl* C, int t, double* acc) {
-  constexpr int RPP = kBlock / LPR;
-  const int lane = threadIdx.x & (LPR - 1);
-  const int slot = threadIdx.x / LPR;
+  constexpr int RPP = kBlock;
   const bool demag = C->demag != 0;
   const int R = demag ? P.Nt : P.N;
   int r0, r1;
@@ -137,118 +171,69 @@ __device__ void phase_prep(const ProbDev<real>& P, const Ctrl* C, int t, double*
   DevPtr<const real> __restrict__ Hax = P.H[a][0];
   DevPtr<const real> __restrict__ Hay = P.H[a][1];
   DevPtr<const real> __restrict__ Haz = P.H[a][2];
+  DevPtr<const real> __restrict__ u = P.u;
   for (int base = r0; base < r1; base += RPP) {
-    const int i = base + slot;
-    const bool valid = i < r1;
-    real bi = 0, lu = 0;
-    if (valid && i < P.N) {
-      if (lane == 0) {
-        real ox, oy, oz;
-        cayley<real>(max_[i], may[i], maz[i], Hax[i], Hay[i], Haz[i], ht, ox, oy, oz);
-        P.m[tr][0][i] = ox;
-        P.m[tr][1][i] = oy;
-        P.m[tr][2][i] = oz;
-      }
+    const int i = base + threadIdx.x;
+    if (i >= r1) continue;
+    real bi = 0;
+    if (i < P.N) {
+      real ox, oy, oz;
+      cayley<real>(max_[i], may[i], maz[i], Hax[i], Hay[i], Haz[i], ht, ox, oy, oz);
+      P.m[tr][0][i] = ox;
+      P.m[tr][1][i] = oy;
+      P.m[tr][2][i] = oz;
       if (demag) {
         const int k1 = P.mrp[i + 1];
-        for (int k = P.mrp[i] + lane; k < k1; k += LPR) {
+        for (int k = P.mrp[i]; k < k1; ++k) {
           const int j = P.mci[k];
-          real ox, oy, oz;
           cayley<real>(max_[j], may[j], maz[j], Hax[j], Hay[j], Haz[j], ht, ox, oy, oz);
           bi += P.D1[0][k] * ox + P.D1[1][k] * oy + P.D1[2][k] * oz;
         }
       }
     }
     if (demag) {
-      if (valid) {
-        const int ke = P.lrp[i + 1];
-        for (int k0 = P.lrp[i] + lane; k0 < ke; k0 += kUnroll * LPR) {
-          int j[kUnroll];
-          real lv[kUnroll];
-#pragma unroll
-          for (int u = 0; u < kUnroll; ++u) {
-            const int k = k0 + u * LPR;
-            const int ks = k < ke ? k : k0;
-            j[u] = P.lci[ks];
-            lv[u] = k < ke ? P.L[ks] : real(0);
-          }
-          real uj[kUnroll];
-#pragma unroll
-          for (int u = 0; u < kUnroll; ++u) uj[u] = P.u[j[u]];
-#pragma unroll
-          for (int u = 0; u < kUnroll; ++u) lu += lv[u] * uj[u];
-        }
-      }
-      bi = group_sum<real, LPR>(bi);
-      lu = group_sum<real, LPR>(lu);
-      if (valid && lane == 0) {
-        const real ri = bi - lu;
-        if (C->precond == PC_AMG) P.r2[C->rcur][i] = ri;
-        else P.rec[C->pcur][i].r = ri;
-        acc[0] += (double)bi * (double)bi;
-        acc[1] += (double)ri * (double)ri;
-        acc[2] += (double)ri * (double)P.u[i];
-      }
+      const real ui = u[i];
+      const real lu = sell_sum(P, i, [&](int j) { return u[j]; });
+      const real ri = bi - lu;
+      if (C->precond == PC_AMG) P.r2[C->rcur][i] = ri;
+      else P.rec[C->pcur][i].r = ri;
+      acc[0] += (double)bi * (double)bi;
+      acc[1] += (double)ri * (double)ri;
+      acc[2] += (double)ri * (double)ui;
     }
   }
 }
 
-// ---- CG0: w = L D^-1 r for the starting residual ----
+// ---- CG0: w = L D^-1 r for the starting residual (one thread per row) ----
 template <typename real, int LPR>
 __device__ void phase_cg0(const ProbDev<real>& P, const Ctrl* C, int t, double* acc) {
-  constexpr int RPP = kBlock / LPR;
-  constexpr int kU = kUnrollWide<real>;
-  const int lane = threadIdx.x & (LPR - 1);
-  const int slot = threadIdx.x / LPR;
+  constexpr int RPP = kBlock;
   int r0, r1;
   chunk_rows(P.Nt, P.G, t, RPP, r0, r1);
   DevPtr<Rec<real>> __restrict__ rec = P.rec[C->pcur];
   for (int base = r0; base < r1; base += RPP) {
-    const int i = base + slot;
-    const bool valid = i < r1;
-    real sw = 0;
-    Rec<real> own{};
-    if (valid) {
-      own = ld<real>(rec, i);
-      const int ke = P.lrp[i + 1];
-      for (int k0 = P.lrp[i] + lane; k0 < ke; k0 += kU * LPR) {
-        int j[kU];
-        real lv[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          const int k = k0 + u * LPR;
-          const int ks = k < ke ? k : k0;
-          j[u] = P.lci[ks];
-          lv[u] = k < ke ? P.L[ks] : real(0);
-        }
-        Rec<real> nb[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) nb[u] = ld<real>(rec, j[u]);
-#pragma unroll
-        for (int u = 0; u < kU; ++u) sw += lv[u] * (nb[u].d * nb[u].r);
-      }
-    }
-    sw = group_sum<real, LPR>(sw);
-    if (valid && lane == 0) {
-      const real ui = own.d * own.r;
-      rec[i].w = sw;
-      acc[0] += (double)own.r * (double)ui;
-      acc[1] += (double)sw * (double)ui;
-    }
+    const int i = base + threadIdx.x;
+    if (i >= r1) continue;
+    const Rec<real> own = ld<real>(rec, i);
+    const real sw = sell_sum(P, i, [&](int j) {
+      const Rec<real> nb = ld<real>(rec, j);
+      return nb.d * nb.r;
+    });
+    const real ui = own.d * own.r;
+    rec[i].w = sw;
+    acc[0] += (double)own.r * (double)ui;
+    acc[1] += (double)sw * (double)ui;
   }
 }
 
-// ---- CG: one single-reduction PCG iteration ----
+// ---- CG: one single-reduction PCG iteration (one thread per row) ----
 // Reads records of buffer c = pcur (r_i, s_{i-1}, w_i) and writes buffer
 // 1 - c.  A gathered neighbour's new residual is recomputed as
 // r_j - alpha (w_j + beta s_j), so the sweep needs no grid-wide barrier
 // between the vector updates and w = L D^-1 r.
 template <typename real, int LPR>
 __device__ void phase_cg(const ProbDev<real>& P, const Ctrl* C, int t, double* acc) {
-  constexpr int RPP = kBlock / LPR;
-  constexpr int kU = kUnrollWide<real>;
-  const int lane = threadIdx.x & (LPR - 1);
-  const int slot = threadIdx.x / LPR;
+  constexpr int RPP = kBlock;
   int r0, r1;
   chunk_rows(P.Nt, P.G, t, RPP, r0, r1);
   const int c = C->pcur;
@@ -256,53 +241,32 @@ __device__ void phase_cg(const ProbDev<real>& P, const Ctrl* C, int t, double* a
   DevPtr<const Rec<real>> __restrict__ ro = P.rec[c];
   DevPtr<Rec<real>> __restrict__ rn = P.rec[1 - c];
   for (int base = r0; base < r1; base += RPP) {
-    const int i = base + slot;
-    const bool valid = i < r1;
-    real sw = 0;
-    Rec<real> own{};
-    real pi = 0, ui = 0;
-    if (valid) {
-      own = ld<real>(ro, i);
-      pi = P.p[i];
-      ui = P.u[i];
-      const int ke = P.lrp[i + 1];
-      for (int k0 = P.lrp[i] + lane; k0 < ke; k0 += kU * LPR) {
-        int j[kU];
-        real lv[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          const int k = k0 + u * LPR;
-          const int ks = k < ke ? k : k0;
-          j[u] = P.lci[ks];
-          lv[u] = k < ke ? P.L[ks] : real(0);
-        }
-        Rec<real> nb[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) nb[u] = ld<real>(ro, j[u]);
-#pragma unroll
-        for (int u = 0; u < kU; ++u) sw += lv[u] * (nb[u].d * (nb[u].r - alpha * (nb[u].w + beta * nb[u].s)));
-      }
-    }
-    sw = group_sum<real, LPR>(sw);
-    if (valid && lane == 0) {
-      pi = own.d * own.r + beta * pi;
-      const real si = own.w + beta * own.s;
-      ui = ui + alpha * pi;
-      const real ri = own.r - alpha * si;
-      const real zi = own.d * ri;
-      P.p[i] = pi;
-      P.u[i] = ui;
-      Rec<real> out;
-      out.r = ri;
-      out.s = si;
-      out.w = sw;
-      out.d = own.d;
-      st<real>(rn, i, out);
-      acc[0] += (double)ri * (double)zi;
-      acc[1] += (double)sw * (double)zi;
-      acc[2] += (double)ri * (double)ri;
-      acc[3] += (double)ri * (double)ui;
-    }
+    const int i = base + threadIdx.x;
+    if (i >= r1) continue;
+    const Rec<real> own = ld<real>(ro, i);
+    real pi = P.p[i];
+    real ui = P.u[i];
+    const real sw = sell_sum(P, i, [&](int j) {
+      const Rec<real> nb = ld<real>(ro, j);
+      return nb.d * (nb.r - alpha * (nb.w + beta * nb.s));
+    });
+    pi = own.d * own.r + beta * pi;
+    const real si = own.w + beta * own.s;
+    ui = ui + alpha * pi;
+    const real ri = own.r - alpha * si;
+    const real zi = own.d * ri;
+    P.p[i] = pi;
+    P.u[i] = ui;
+    Rec<real> out;
+    out.r = ri;
+    out.s = si;
+    out.w = sw;
+    out.d = own.d;
+    st<real>(rn, i, out);
+    acc[0] += (double)ri * (double)zi;
+    acc[1] += (double)sw * (double)zi;
+    acc[2] += (double)ri * (double)ri;
+    acc[3] += (double)ri * (double)ui;
   }
 }
 
@@ -347,8 +311,17 @@ __device__ __forceinline__ real row_sum(DevPtr<const int> __restrict__ rp, DevPt
 // skipped: the operation that produces x_{l+1} (POST(l + 1), or SOLVE) also
 // writes xa_l = wd b + P x_{l+1} for the members of each aggregate it owns
 // (row I of R_l lists them), so no index is gathered twice.
-// W lanes share a row: the kernel's LPR, or 16 on levels whose rows are long.
-template <typename real, int W>
+// W lanes share a row: the kernel's LPR, or 16 on levels whose rows are long;
+// DOWN and POST on level 0 (the potential matrix) take one thread per row
+// over its sliced layout (W = 1, A0 = true).
+template <typename real, int W, bool A0, typename G>
+__device__ __forceinline__ real a_row(const ProbDev<real>& P, DevRef<const MgLevelDev<real>> L, int i, int lane,
+                                      G&& g) {
+  if constexpr (A0) return sell_sum(P, i, g);
+  else return row_sum<real, W>(L.arp, L.aci, L.av, i, lane, g);
+}
+
+template <typename real, int W, bool A0 = false>
 __device__ void mg_rows(const ProbDev<real>& P, const Ctrl* C, DevRef<const MgLevelDev<real>> L, int op, int l, int t,
                         double* acc) {
   constexpr int RPP = kBlock / W;
@@ -384,8 +357,7 @@ __device__ void mg_rows(const ProbDev<real>& P, const Ctrl* C, DevRef<const MgLe
       const int i = base + slot;
       const bool valid = i < r1;
       const real bi = (valid && lane == 0) ? b[i] : real(0);
-      real sum = valid ? row_sum<real, W>(L.arp, L.aci, L.av, i, lane,
-                                          [&](int j) { return l == 0 ? wd[j] * b[j] : wb[j]; })
+      real sum = valid ? a_row<real, W, A0>(P, L, i, lane, [&](int j) { return l == 0 ? wd[j] * b[j] : wb[j]; })
                        : real(0);
       sum = group_sum<real, W>(sum);
       if (valid && lane == 0) L.res[i] = bi - sum;
@@ -415,7 +387,7 @@ __device__ void mg_rows(const ProbDev<real>& P, const Ctrl* C, DevRef<const MgLe
         xai = xa[i];
         if (l == 0) pold = P.zp[i].b;
       }
-      real sum = valid ? row_sum<real, W>(L.arp, L.aci, L.av, i, lane, [&](int j) { return xa[j]; }) : real(0);
+      real sum = valid ? a_row<real, W, A0>(P, L, i, lane, [&](int j) { return xa[j]; }) : real(0);
       sum = group_sum<real, W>(sum);
       real zi = 0;
       if (valid && lane == 0) {
@@ -475,7 +447,9 @@ __device__ void phase_mg(const ProbDev<real>& P, const Ctrl* C, int t, double* a
   }
   DevRef<const MgLevelDev<real>> L = P.lev[l];
   const int wide = op == MG_REST ? L.wide_r : op == MG_PROL ? L.wide_p : L.wide_a;
-  if (wide && LPR < 16)
+  if (l == 0 && (op == MG_DOWN || op == MG_POST))
+    mg_rows<real, 1, true>(P, C, L, op, l, t, acc);
+  else if (wide && LPR < 16)
     mg_rows<real, 16>(P, C, L, op, l, t, acc);
   else
     mg_rows<real, LPR>(P, C, L, op, l, t, acc);
@@ -483,12 +457,11 @@ __device__ void phase_mg(const ProbDev<real>& P, const Ctrl* C, int t, double* a
 
 // PCG_A: p = z + beta p_old (recomputed at gathered neighbours from the
 // {z, p} records), q = L p, p.q; also the {wd r, wd q} records PCG_B gathers.
-// p itself is stored by PCG_B, which gathers no {z, p} record.
+// p itself is stored by PCG_B, which gathers no {z, p} record.  One thread
+// per row.
 template <typename real, int LPR>
 __device__ void phase_pcg_a(const ProbDev<real>& P, const Ctrl* C, int t, double* acc) {
-  constexpr int RPP = kBlock / LPR;
-  const int lane = threadIdx.x & (LPR - 1);
-  const int slot = threadIdx.x / LPR;
+  constexpr int RPP = kBlock;
   int r0, r1;
   chunk_rows(P.Nt, P.G, t, RPP, r0, r1);
   const real beta = real(C->beta);
@@ -497,41 +470,30 @@ __device__ void phase_pcg_a(const ProbDev<real>& P, const Ctrl* C, int t, double
   DevPtr<const real> __restrict__ r = P.r2[C->rcur];
   DevPtr<const real> __restrict__ wd = P.lev[0].wd;
   for (int base = r0; base < r1; base += RPP) {
-    const int i = base + slot;
-    const bool valid = i < r1;
-    Pair<real> own{};
-    real ri = 0, wi = 0;
-    if (valid && lane == 0) {
-      own = ld<real>(zp, i);
-      ri = r[i];
-      wi = wd[i];
-    }
+    const int i = base + threadIdx.x;
+    if (i >= r1) continue;
+    const Pair<real> own = ld<real>(zp, i);
+    const real ri = r[i], wi = wd[i];
     // beta = 0 starts a solve: the p half then holds the previous solve's
     // direction and is not read
-    real sum = valid ? row_sum<real, LPR>(P.lrp, P.lci, P.L, i, lane, [&](int j) {
+    const real sum = sell_sum(P, i, [&](int j) {
       const Pair<real> e = ld<real>(zp, j);
       return first ? e.a : e.a + beta * e.b;
-    })
-                     : real(0);
-    sum = group_sum<real, LPR>(sum);
-    if (valid && lane == 0) {
-      const real pi = first ? own.a : own.a + beta * own.b;
-      P.q[i] = sum;
-      st<real>(P.rq, i, Pair<real>{wi * ri, wi * sum});
-      acc[0] += (double)pi * (double)sum;
-    }
+    });
+    const real pi = first ? own.a : own.a + beta * own.b;
+    P.q[i] = sum;
+    st<real>(P.rq, i, Pair<real>{wi * ri, wi * sum});
+    acc[0] += (double)pi * (double)sum;
   }
 }
 
 // PCG_B: p = z + beta p_old (stored), r -= alpha q, u += alpha p, then the
-// finest pre-smoothing residual
-// of the next V-cycle, res = r - L (wd r), with neighbours' wd r_new
-// recomputed from their {wd r, wd q} records.  Partials: r.r, r.u.
+// finest pre-smoothing residual of the next V-cycle, res = r - L (wd r),
+// with neighbours' wd r_new recomputed from their {wd r, wd q} records.
+// Partials: r.r, r.u.  One thread per row.
 template <typename real, int LPR>
 __device__ void phase_pcg_b(const ProbDev<real>& P, const Ctrl* C, int t, double* acc) {
-  constexpr int RPP = kBlock / LPR;
-  const int lane = threadIdx.x & (LPR - 1);
-  const int slot = threadIdx.x / LPR;
+  constexpr int RPP = kBlock;
   int r0, r1;
   chunk_rows(P.Nt, P.G, t, RPP, r0, r1);
   const real alpha = real(C->alpha), beta = real(C->beta);
@@ -542,33 +504,23 @@ __device__ void phase_pcg_b(const ProbDev<real>& P, const Ctrl* C, int t, double
   DevPtr<const real> __restrict__ q = P.q;
   DevPtr<const Pair<real>> __restrict__ rq = P.rq;
   for (int base = r0; base < r1; base += RPP) {
-    const int i = base + slot;
-    const bool valid = i < r1;
-    real roi = 0, qi = 0, uo = 0;
-    Pair<real> own{};
-    if (valid && lane == 0) {
-      roi = ro[i];
-      qi = q[i];
-      uo = P.u[i];
-      own = ld<real>(zp, i);
-    }
-    real sum = valid ? row_sum<real, LPR>(P.lrp, P.lci, P.L, i, lane, [&](int j) {
+    const int i = base + threadIdx.x;
+    if (i >= r1) continue;
+    const real roi = ro[i], qi = q[i], uo = P.u[i];
+    const Pair<real> own = ld<real>(zp, i);
+    const real sum = sell_sum(P, i, [&](int j) {
       const Pair<real> e = ld<real>(rq, j);
       return e.a - alpha * e.b;
-    })
-                     : real(0);
-    sum = group_sum<real, LPR>(sum);
-    if (valid && lane == 0) {
-      const real pi = first ? own.a : own.a + beta * own.b;
-      st<real>(zp, i, Pair<real>{own.a, pi});
-      const real ri = roi - alpha * qi;
-      const real ui = uo + alpha * pi;
-      rn[i] = ri;
-      P.u[i] = ui;
-      P.lev[0].res[i] = ri - sum;
-      acc[0] += (double)ri * (double)ri;
-      acc[1] += (double)ri * (double)ui;
-    }
+    });
+    const real pi = first ? own.a : own.a + beta * own.b;
+    st<real>(zp, i, Pair<real>{own.a, pi});
+    const real ri = roi - alpha * qi;
+    const real ui = uo + alpha * pi;
+    rn[i] = ri;
+    P.u[i] = ui;
+    P.lev[0].res[i] = ri - sum;
+    acc[0] += (double)ri * (double)ri;
+    acc[1] += (double)ri * (double)ui;
   }
 }
 
