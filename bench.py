@@ -108,7 +108,10 @@ def run_poly(args):
     print(f"[bench] mesh {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     ctx = binding.Context(0)
     out = {}
-    for name, prec in (("mixed", binding.MIXED), ("fp64", binding.FP64)):
+    forms = [("mixed", binding.MIXED), ("fp64", binding.FP64)]
+    if args.poly_prec != "both":
+        forms = [f for f in forms if f[0] == args.poly_prec]
+    for name, prec in forms:
         t0 = time.perf_counter()
         p = binding.Problem(ctx, cfg["mesh"], precision=prec)
         print(f"[bench] {name} setup {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
@@ -127,6 +130,15 @@ def run_poly(args):
         print(f"[bench] {name}: status {r.status} evals {r.evals} pcg {r.pcg_iters} {wall:.1f} s "
               f"E={r.energy_J:.12e} torque {r.max_torque:.2e}", file=sys.stderr, flush=True)
         p.close()
+    if len(out) < 2:
+        ctx.close()
+        (name, o), = out.items()
+        line = base_line(o["N"] * o["r"].evals / o["wall"], 1, 0, o["wall"], "f64" if name == "fp64" else
+                         "f32+f64-reductions", {"workload": f"{name} polycrystal, 200x200x100 nm box, one minimization",
+                                                "magnet_nodes": o["N"], "potential_nodes": o["Nt"]})
+        line["roofline"] = roofline_of(o["tm"], 4)
+        print(json.dumps(line), flush=True)
+        return
     mx, fp = out["mixed"], out["fp64"]
     scale = sum(abs(getattr(fp["r"], k)) for k in ("e_exch_J", "e_anis_J", "e_zeem_J", "e_demag_J"))
     line = base_line(mx["N"] * mx["r"].evals / mx["wall"], 1, 0, mx["wall"], "f32+f64-reductions",
@@ -298,6 +310,7 @@ def main():
     ap.add_argument("--hbm-gb", type=float, default=64.0)
     ap.add_argument("--slots", type=int, default=32)
     ap.add_argument("--serve-timeout", type=float, default=900.0)
+    ap.add_argument("--poly-prec", default="both", choices=["both", "mixed", "fp64"])
     ap.add_argument("--precond", default="auto", choices=["auto", "jacobi", "amg"],
                     help="preconditioner of the potential solve")
     args = ap.parse_args()

@@ -4,6 +4,7 @@
 // only arms a run and polls a small control block (one batch of launches of
 // lookahead), so no host round trip sits between phases.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -118,6 +119,49 @@ Prob<real>& desc_of(mmsd_problem p) {
 // Average row length above which a multigrid operator is swept with 16
 // lanes per row.
 constexpr size_t kWideRow = 24;
+// Rows from which a multigrid matrix with short rows (at most kWideRow on
+// average) also gets a sliced copy and is swept one row per thread (enough
+// wavefronts to fill the GPU; long rows keep 16 lanes per row, which
+// measured faster).
+constexpr int kSlicedRows = 65536;
+
+// 64-row sliced layout of a CSR matrix: slice s holds rows 64s..64s+63,
+// entry k of row i at so[s] + 64 k + (i mod 64); short rows are padded with
+// their own column (clamped to the column range) and a zero value.
+struct Sliced {
+  std::vector<int> so, sc;
+  std::vector<double> sv;
+};
+Sliced make_sliced(const std::vector<int>& rp, const std::vector<int>& ci, const std::vector<double>& v,
+                   int ncols) {
+  const int64_t n = (int64_t)rp.size() - 1, ns = (n + 63) / 64;
+  Sliced S;
+  S.so.assign(ns + 1, 0);
+  for (int64_t sl = 0; sl < ns; ++sl) {
+    int w = 0;
+    for (int64_t i = 64 * sl; i < std::min<int64_t>(n, 64 * sl + 64); ++i) w = std::max(w, rp[i + 1] - rp[i]);
+    S.so[sl + 1] = S.so[sl] + 64 * w;
+  }
+  S.sc.assign(S.so[ns], 0);
+  S.sv.assign(S.so[ns], 0.0);
+  for (int64_t sl = 0; sl < ns; ++sl) {
+    const int w = (S.so[sl + 1] - S.so[sl]) / 64;
+    for (int r = 0; r < 64; ++r) {
+      const int64_t i = 64 * sl + r;
+      const int len = i < n ? rp[i + 1] - rp[i] : 0;
+      for (int k = 0; k < w; ++k) {
+        const int64_t q = S.so[sl] + 64LL * k + r;
+        if (k < len) {
+          S.sc[q] = ci[rp[i] + k];
+          S.sv[q] = v[rp[i] + k];
+        } else {
+          S.sc[q] = (int)std::min<int64_t>(i, ncols - 1);
+        }
+      }
+    }
+  }
+  return S;
+}
 
 // P is plain aggregation: every row holds a single entry 1 (the post-smoothing
 // of such a level recomputes the prolongation where it gathers).
@@ -190,11 +234,30 @@ int build_amg(mmsd_problem p) {
     off.push_back(at);
     return at;
   };
-  struct LvOff { size_t arp, aci, av, wd, prp, pci, pv, rrp, rci, rv, b, wb, res, xa, xb; };
+  struct LvOff { size_t arp, aci, av, wd, prp, pci, pv, rrp, rci, rv, b, wb, res, xa, xb, sl[3][3]; };
   std::vector<LvOff> lo(nl);
+  // sliced copies (A of levels >= 1, P, R) of the matrices with many rows
+  std::vector<std::array<Sliced, 3>> sl(nl);
+  for (int l = 0; l < nl; ++l) {
+    const AmgLevel& L = H.lv[l];
+    const Csr* M[3] = {&L.A, &L.P, &L.R};
+    for (int k = 0; k < 3; ++k) {
+      if ((k == 0 && l == 0) || M[k]->nrows < kSlicedRows || M[k]->ci.size() > kWideRow * (size_t)M[k]->nrows)
+        continue;
+      sl[l][k] = make_sliced(M[k]->rp, M[k]->ci, M[k]->v, M[k]->ncols);
+      if ((int64_t)sl[l][k].so.back() >= (int64_t)1 << 30) return invalid("multigrid matrix too large to slice");
+    }
+  }
   for (int l = 0; l < nl; ++l) {
     const AmgLevel& L = H.lv[l];
     const size_t n = L.A.nrows, nn = L.P.ncols;
+    for (int k = 0; k < 3; ++k) {
+      const Sliced& S = sl[l][k];
+      if (S.so.empty()) continue;
+      lo[l].sl[k][0] = take(4 * S.so.size());
+      lo[l].sl[k][1] = take(4 * S.sc.size());
+      lo[l].sl[k][2] = take(s * S.sv.size());
+    }
     if (l > 0) {
       lo[l].arp = take(4 * (n + 1));
       lo[l].aci = take(4 * L.A.ci.size());
@@ -244,14 +307,40 @@ int build_amg(mmsd_problem p) {
         (rc = upload_int(st, base + lo[l].rrp, L.R.rp)) || (rc = upload_int(st, base + lo[l].rci, L.R.ci)) ||
         (rc = upload_vec<real>(st, base + lo[l].rv, L.R.v)))
       return rc;
+    const int* so[3] = {nullptr, nullptr, nullptr};
+    const int* sc[3] = {nullptr, nullptr, nullptr};
+    const real* sv[3] = {nullptr, nullptr, nullptr};
+    for (int k = 0; k < 3; ++k) {
+      const Sliced& S = sl[l][k];
+      if (S.so.empty()) continue;
+      if ((rc = upload_int(st, base + lo[l].sl[k][0], S.so)) || (rc = upload_int(st, base + lo[l].sl[k][1], S.sc)) ||
+          (rc = upload_vec<real>(st, base + lo[l].sl[k][2], S.sv)))
+        return rc;
+      so[k] = (const int*)(base + lo[l].sl[k][0]);
+      sc[k] = (const int*)(base + lo[l].sl[k][1]);
+      sv[k] = (const real*)(base + lo[l].sl[k][2]);
+    }
+    if (l == 0) {   // level 0's operator is the potential matrix
+      so[0] = P.lso;
+      sc[0] = P.lsc;
+      sv[0] = P.lsv;
+    }
     MgLevel<real>& d = lv[l];
+    d.aso = so[0];
+    d.asc = sc[0];
+    d.asv = sv[0];
+    d.pso = so[1];
+    d.psc = sc[1];
+    d.psv = sv[1];
+    d.rso = so[2];
+    d.rsc = sc[2];
+    d.rsv = sv[2];
     d.n = L.A.nrows;
     d.n_next = L.P.ncols;
     d.plain = plain_prolongation(L.P) ? 1 : 0;
     d.wide_a = L.A.ci.size() > kWideRow * (size_t)L.A.nrows;
     d.wide_p = L.P.ci.size() > kWideRow * (size_t)L.P.nrows;
     d.wide_r = L.R.ci.size() > kWideRow * (size_t)L.R.nrows;
-    // level 0's operator is the potential matrix, read in its sliced layout
     d.arp = l == 0 ? nullptr : (const int*)(base + lo[l].arp);
     d.aci = l == 0 ? nullptr : (const int*)(base + lo[l].aci);
     d.av = l == 0 ? nullptr : (const real*)(base + lo[l].av);
@@ -318,32 +407,10 @@ int build_device(mmsd_problem p) {
   for (int k = 0; k < 6; ++k)
     if ((rc = upload_vec<real>(st, base + L.Q[k], A.Q[k]))) return rc;
   if (Nt > 0) {
-    // sliced copy of L: slice s holds rows 64s..64s+63, entry k of row i at
-    // so[s] + 64 k + (i mod 64); short rows are padded with their own column
-    // and a zero value
-    const int64_t ns = (Nt + 63) / 64;
-    std::vector<int> so(ns + 1, 0), sc(nnzLs);
-    std::vector<double> sv(nnzLs, 0.0);
-    for (int64_t sl = 0; sl < ns; ++sl) {
-      int w = 0;
-      for (int64_t i = 64 * sl; i < std::min<int64_t>(Nt, 64 * sl + 64); ++i) w = std::max(w, A.lrp[i + 1] - A.lrp[i]);
-      so[sl + 1] = so[sl] + 64 * w;
-      for (int r = 0; r < 64; ++r) {
-        const int64_t i = 64 * sl + r;
-        const int len = i < Nt ? A.lrp[i + 1] - A.lrp[i] : 0;
-        for (int k = 0; k < w; ++k) {
-          const int64_t q = so[sl] + 64LL * k + r;
-          if (k < len) {
-            sc[q] = A.lci[A.lrp[i] + k];
-            sv[q] = A.L[A.lrp[i] + k];
-          } else {
-            sc[q] = (int)std::min<int64_t>(i, Nt - 1);
-          }
-        }
-      }
-    }
-    if ((rc = upload_int(st, base + L.lso, so)) || (rc = upload_int(st, base + L.lsc, sc)) ||
-        (rc = upload_vec<real>(st, base + L.lsv, sv)))
+    // the potential matrix lives on the device only in its sliced layout
+    const Sliced S = make_sliced(A.lrp, A.lci, A.L, (int)Nt);
+    if ((rc = upload_int(st, base + L.lso, S.so)) || (rc = upload_int(st, base + L.lsc, S.sc)) ||
+        (rc = upload_vec<real>(st, base + L.lsv, S.sv)))
       return rc;
     // Jacobi factors live in the d field of both CG record buffers
     std::vector<double> rec(4 * (size_t)Nt, 0.0);

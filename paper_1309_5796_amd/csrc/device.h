@@ -125,6 +125,17 @@ struct MgLevelT {
   Ptr<const int> rrp;          // R = P^T: n_next x n
   Ptr<const int> rci;
   Ptr<const real> rv;
+  // sliced copies (64-row slices, as the potential matrix) of A, P and R;
+  // null when the matrix has too few rows to fill the GPU one row per thread
+  Ptr<const int> aso;
+  Ptr<const int> asc;
+  Ptr<const real> asv;
+  Ptr<const int> pso;
+  Ptr<const int> psc;
+  Ptr<const real> psv;
+  Ptr<const int> rso;
+  Ptr<const int> rsc;
+  Ptr<const real> rsv;
   Ptr<real> b;                 // right-hand side (level 0 uses the CG residual)
   Ptr<real> wb;                // wd b (levels >= 1), written with b
   Ptr<real> res;               // residual after pre-smoothing

@@ -124,13 +124,15 @@ __device__ __forceinline__ void chunk_rows(int R, int G, int t, int rpp, int& r0
 // is one contiguous 64-wide access, and a whole block-pass covers 512 rows.
 constexpr int kSellU = 4;   // entries per thread loaded before their gathers
 
-// sum_k v[k] * g(column k) over row i of the sliced potential matrix.  The
-// calling wavefront's active lanes all lie in one slice.
+// sum_k v[k] * g(column k) over row i of a matrix in the sliced layout
+// (slice offsets so, columns sc, values sv).  The calling wavefront's active
+// lanes all lie in one slice.
 template <typename real, typename G>
-__device__ __forceinline__ real sell_sum(const ProbDev<real>& P, int i, G&& g) {
+__device__ __forceinline__ real sell_row(DevPtr<const int> so, DevPtr<const int> sc, DevPtr<const real> sv, int i,
+                                         G&& g) {
   const int sl = __builtin_amdgcn_readfirstlane(i >> 6);
-  const int o0 = P.lso[sl];
-  const int w = (P.lso[sl + 1] - o0) >> 6;
+  const int o0 = so[sl];
+  const int w = (so[sl + 1] - o0) >> 6;
   const int o = o0 + (i & 63);
   real acc = 0;
   for (int k0 = 0; k0 < w; k0 += kSellU) {
@@ -140,8 +142,8 @@ __device__ __forceinline__ real sell_sum(const ProbDev<real>& P, int i, G&& g) {
     for (int u = 0; u < kSellU; ++u) {
       const bool ok = k0 + u < w;
       const int q = o + 64 * (ok ? k0 + u : 0);
-      j[u] = P.lsc[q];
-      v[u] = ok ? P.lsv[q] : real(0);
+      j[u] = sc[q];
+      v[u] = ok ? sv[q] : real(0);
     }
     real x[kSellU];
 #pragma unroll
@@ -150,6 +152,12 @@ __device__ __forceinline__ real sell_sum(const ProbDev<real>& P, int i, G&& g) {
     for (int u = 0; u < kSellU; ++u) acc += v[u] * x[u];
   }
   return acc;
+}
+
+// ... over row i of the potential matrix
+template <typename real, typename G>
+__device__ __forceinline__ real sell_sum(const ProbDev<real>& P, int i, G&& g) {
+  return sell_row<real>(P.lso, P.lsc, P.lsv, i, g);
 }
 
 // ---- PREP: trial magnetization, Poisson right-hand side, initial residual ----
@@ -311,17 +319,27 @@ __device__ __forceinline__ real row_sum(DevPtr<const int> __restrict__ rp, DevPt
 // skipped: the operation that produces x_{l+1} (POST(l + 1), or SOLVE) also
 // writes xa_l = wd b + P x_{l+1} for the members of each aggregate it owns
 // (row I of R_l lists them), so no index is gathered twice.
-// W lanes share a row: the kernel's LPR, or 16 on levels whose rows are long;
-// DOWN and POST on level 0 (the potential matrix) take one thread per row
-// over its sliced layout (W = 1, A0 = true).
-template <typename real, int W, bool A0, typename G>
-__device__ __forceinline__ real a_row(const ProbDev<real>& P, DevRef<const MgLevelDev<real>> L, int i, int lane,
-                                      G&& g) {
-  if constexpr (A0) return sell_sum(P, i, g);
+// W lanes share a row: the kernel's LPR, or 16 on levels whose rows are
+// long; W = 1 (one thread per row) reads the operation's matrix from its
+// sliced copy, which matrices with many rows have (the level-0 operator is
+// the potential matrix).
+template <typename real, int W, typename G>
+__device__ __forceinline__ real a_row(DevRef<const MgLevelDev<real>> L, int i, int lane, G&& g) {
+  if constexpr (W == 1) return sell_row<real>(L.aso, L.asc, L.asv, i, g);
   else return row_sum<real, W>(L.arp, L.aci, L.av, i, lane, g);
 }
+template <typename real, int W, typename G>
+__device__ __forceinline__ real p_row(DevRef<const MgLevelDev<real>> L, int i, int lane, G&& g) {
+  if constexpr (W == 1) return sell_row<real>(L.pso, L.psc, L.psv, i, g);
+  else return row_sum<real, W>(L.prp, L.pci, L.pv, i, lane, g);
+}
+template <typename real, int W, typename G>
+__device__ __forceinline__ real r_row(DevRef<const MgLevelDev<real>> L, int i, int lane, G&& g) {
+  if constexpr (W == 1) return sell_row<real>(L.rso, L.rsc, L.rsv, i, g);
+  else return row_sum<real, W>(L.rrp, L.rci, L.rv, i, lane, g);
+}
 
-template <typename real, int W, bool A0 = false>
+template <typename real, int W>
 __device__ void mg_rows(const ProbDev<real>& P, const Ctrl* C, DevRef<const MgLevelDev<real>> L, int op, int l, int t,
                         double* acc) {
   constexpr int RPP = kBlock / W;
@@ -342,7 +360,7 @@ __device__ void mg_rows(const ProbDev<real>& P, const Ctrl* C, DevRef<const MgLe
       const int i = base + slot;
       const bool valid = i < r1;
       const real wi = (valid && lane == 0 && !last) ? wdn[i] : real(0);
-      real sum = valid ? row_sum<real, W>(L.rrp, L.rci, L.rv, i, lane, [&](int j) { return res[j]; }) : real(0);
+      real sum = valid ? r_row<real, W>(L, i, lane, [&](int j) { return res[j]; }) : real(0);
       sum = group_sum<real, W>(sum);
       if (valid && lane == 0) {
         bn[i] = sum;
@@ -357,7 +375,7 @@ __device__ void mg_rows(const ProbDev<real>& P, const Ctrl* C, DevRef<const MgLe
       const int i = base + slot;
       const bool valid = i < r1;
       const real bi = (valid && lane == 0) ? b[i] : real(0);
-      real sum = valid ? a_row<real, W, A0>(P, L, i, lane, [&](int j) { return l == 0 ? wd[j] * b[j] : wb[j]; })
+      real sum = valid ? a_row<real, W>(L, i, lane, [&](int j) { return l == 0 ? wd[j] * b[j] : wb[j]; })
                        : real(0);
       sum = group_sum<real, W>(sum);
       if (valid && lane == 0) L.res[i] = bi - sum;
@@ -368,7 +386,7 @@ __device__ void mg_rows(const ProbDev<real>& P, const Ctrl* C, DevRef<const MgLe
       const int i = base + slot;
       const bool valid = i < r1;
       const real wbi = (valid && lane == 0) ? wd[i] * b[i] : real(0);
-      real sum = valid ? row_sum<real, W>(L.prp, L.pci, L.pv, i, lane, [&](int j) { return xn[j]; }) : real(0);
+      real sum = valid ? p_row<real, W>(L, i, lane, [&](int j) { return xn[j]; }) : real(0);
       sum = group_sum<real, W>(sum);
       if (valid && lane == 0) L.xa[i] = wbi + sum;
     }
@@ -387,7 +405,7 @@ __device__ void mg_rows(const ProbDev<real>& P, const Ctrl* C, DevRef<const MgLe
         xai = xa[i];
         if (l == 0) pold = P.zp[i].b;
       }
-      real sum = valid ? a_row<real, W, A0>(P, L, i, lane, [&](int j) { return xa[j]; }) : real(0);
+      real sum = valid ? a_row<real, W>(L, i, lane, [&](int j) { return xa[j]; }) : real(0);
       sum = group_sum<real, W>(sum);
       real zi = 0;
       if (valid && lane == 0) {
@@ -447,8 +465,9 @@ __device__ void phase_mg(const ProbDev<real>& P, const Ctrl* C, int t, double* a
   }
   DevRef<const MgLevelDev<real>> L = P.lev[l];
   const int wide = op == MG_REST ? L.wide_r : op == MG_PROL ? L.wide_p : L.wide_a;
-  if (l == 0 && (op == MG_DOWN || op == MG_POST))
-    mg_rows<real, 1, true>(P, C, L, op, l, t, acc);
+  const bool sliced = op == MG_REST ? L.rso != nullptr : op == MG_PROL ? L.pso != nullptr : L.aso != nullptr;
+  if (sliced)
+    mg_rows<real, 1>(P, C, L, op, l, t, acc);
   else if (wide && LPR < 16)
     mg_rows<real, 16>(P, C, L, op, l, t, acc);
   else
