@@ -107,6 +107,8 @@ def run_poly(args):
     cfg = meshgen.config3()
     print(f"[bench] mesh {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     ctx = binding.Context(0)
+    if args.lanes or args.blocks:
+        ctx.set_launch_config(lanes_per_row=args.lanes, max_blocks=args.blocks)
     out = {}
     forms = [("mixed", binding.MIXED), ("fp64", binding.FP64)]
     if args.poly_prec != "both":

@@ -525,8 +525,12 @@ int resolve(mmsd_problem p, const mmsd_options* o, Resolved* r) {
 
 int arm(mmsd_problem p, const Resolved& r, int stage, int store_h) {
   const Assembly& A = p->A;
-  const double dp[14] = {r.tol, r.rtol * r.rtol, 1e-4, 0.5, 0.5, 0.1, 1e-10, 1e10, 1e-14,
-                         p->b_ext[0] / A.Js, p->b_ext[1] / A.Js, p->b_ext[2] / A.Js, A.c_an, A.vol};
+  // energy resolution: FP64 runs keep the plain floor on tau; in the mixed
+  // form the energy carries FP32 rounding of the fields (about 2^-20 of the
+  // sum of the term magnitudes), below which backtracking cannot decide
+  const double e_res = p->precision == MMSD_MIXED ? std::ldexp(1.0, -20) : 0.0;
+  const double dp[15] = {r.tol, r.rtol * r.rtol, 1e-4, 0.5, 0.5, 0.1, 1e-10, 1e10, 1e-14,
+                         p->b_ext[0] / A.Js, p->b_ext[1] / A.Js, p->b_ext[2] / A.Js, A.c_an, A.vol, e_res};
   MMSD_HIP(launch_ctrl_init(p->dctrl, kArmSlot, stage, r.terms, r.M, r.rule, r.maxit, store_h,
                             (r.terms & MMSD_DEMAG) ? 1 : 0, p->acc, r.precond, (long long)r.max_evals, dp,
                             p->ctx->stream));

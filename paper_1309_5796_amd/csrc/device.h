@@ -74,6 +74,7 @@ struct Ctrl {
   double alg_bytes;              // algorithmic bytes of the executed phases (roofline accounting)
   // options and constants
   double tol, pcg_rtol2, c1, rho, kappa0, theta0, tau_min, tau_max, tau_floor;
+  double e_res;            // relative resolution of the energy (0: exact arithmetic assumed)
   double bz[3];                  // applied field / Js
   double c_an;                   // sum_e V_e K1_e / (mu0 Ms^2)
   double vol;                    // sum_i V_i

@@ -281,26 +281,26 @@ __device__ void phase_cg(const ProbDev<real>& P, const Ctrl* C, int t, double* a
 // ---- multigrid-preconditioned CG ----
 // Lane-partial sum over row i of a CSR matrix of v[k] * g(column): column
 // indices and values first, then all the gathers, then the products.
-template <typename real, int LPR, typename G>
+template <typename real, int LPR, int U = kUnroll, typename G>
 __device__ __forceinline__ real row_sum(DevPtr<const int> __restrict__ rp, DevPtr<const int> __restrict__ ci,
                                         DevPtr<const real> __restrict__ v, int i, int lane, G&& g) {
   real acc = 0;
   const int ke = rp[i + 1];
-  for (int k0 = rp[i] + lane; k0 < ke; k0 += kUnroll * LPR) {
-    int j[kUnroll];
-    real lv[kUnroll];
+  for (int k0 = rp[i] + lane; k0 < ke; k0 += U * LPR) {
+    int j[U];
+    real lv[U];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int k = k0 + u * LPR;
       const int ks = k < ke ? k : k0;
       j[u] = ci[ks];
       lv[u] = k < ke ? v[ks] : real(0);
     }
-    real x[kUnroll];
+    real x[U];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) x[u] = g(j[u]);
+    for (int u = 0; u < U; ++u) x[u] = g(j[u]);
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) acc += lv[u] * x[u];
+    for (int u = 0; u < U; ++u) acc += lv[u] * x[u];
   }
   return acc;
 }
@@ -323,20 +323,25 @@ __device__ __forceinline__ real row_sum(DevPtr<const int> __restrict__ rp, DevPt
 // long; W = 1 (one thread per row) reads the operation's matrix from its
 // sliced copy, which matrices with many rows have (the level-0 operator is
 // the potential matrix).
+// entries per lane per batch: 16-lane rows are the long ones (40-75 entries),
+// which one batch of 8 covers
+template <int W>
+constexpr int kRowU = W >= 16 ? 8 : kUnroll;
+
 template <typename real, int W, typename G>
 __device__ __forceinline__ real a_row(DevRef<const MgLevelDev<real>> L, int i, int lane, G&& g) {
   if constexpr (W == 1) return sell_row<real>(L.aso, L.asc, L.asv, i, g);
-  else return row_sum<real, W>(L.arp, L.aci, L.av, i, lane, g);
+  else return row_sum<real, W, kRowU<W>>(L.arp, L.aci, L.av, i, lane, g);
 }
 template <typename real, int W, typename G>
 __device__ __forceinline__ real p_row(DevRef<const MgLevelDev<real>> L, int i, int lane, G&& g) {
   if constexpr (W == 1) return sell_row<real>(L.pso, L.psc, L.psv, i, g);
-  else return row_sum<real, W>(L.prp, L.pci, L.pv, i, lane, g);
+  else return row_sum<real, W, kRowU<W>>(L.prp, L.pci, L.pv, i, lane, g);
 }
 template <typename real, int W, typename G>
 __device__ __forceinline__ real r_row(DevRef<const MgLevelDev<real>> L, int i, int lane, G&& g) {
   if constexpr (W == 1) return sell_row<real>(L.rso, L.rsc, L.rsv, i, g);
-  else return row_sum<real, W>(L.rrp, L.rci, L.rv, i, lane, g);
+  else return row_sum<real, W, kRowU<W>>(L.rrp, L.rci, L.rv, i, lane, g);
 }
 
 template <typename real, int W>
@@ -773,7 +778,10 @@ __device__ void step_logic(Ctrl* C, const double* v) {
     }
     C->tau *= C->rho;
     C->backtrack = 1;
-    if (C->tau < C->tau_floor) {
+    // stop also when the energy change the next trial can make (~ tau d) is
+    // below the energy's resolution in this precision
+    const double e_scale = fabs(eterm[0]) + fabs(eterm[1]) + fabs(eterm[2]) + fabs(eterm[3]);
+    if (C->tau < C->tau_floor || C->tau * C->d_acc < C->e_res * e_scale) {
       finish_done(C, MMSD_W_FLOOR);
       return;
     }
@@ -1017,7 +1025,7 @@ __device__ __forceinline__ void run_phase(const ProbDev<real>& P, const Ctrl* C,
 }
 
 template <typename real, int LPR>
-__global__ void __launch_bounds__(kBlock, 4) k_step(const ProbDev<real>* __restrict__ probs, int nprob,
+__global__ void __launch_bounds__(kBlock, 6) k_step(const ProbDev<real>* __restrict__ probs, int nprob,
                                                     const int* __restrict__ blk_start, int parity) {
   __shared__ Ctrl s_c;
   __shared__ double s_red[kBlock / 64][kNPart];
@@ -1104,7 +1112,7 @@ __global__ void __launch_bounds__(kBlock, 4) k_step(const ProbDev<real>* __restr
 struct CtrlInit {
   int stage, terms, nonmono_M, step_rule, pcg_maxit, store_h, demag, acc, precond, pad;
   long long max_evals;
-  double tol, pcg_rtol2, c1, rho, kappa0, theta0, tau_min, tau_max, tau_floor;
+  double tol, pcg_rtol2, c1, rho, kappa0, theta0, tau_min, tau_max, tau_floor, e_res;
   double bz[3], c_an, vol;
 };
 
@@ -1153,6 +1161,7 @@ __global__ void k_ctrl_init(Ctrl* ctrl, int slot, CtrlInit a) {
   C->tau_min = a.tau_min;
   C->tau_max = a.tau_max;
   C->tau_floor = a.tau_floor;
+  C->e_res = a.e_res;
   for (int k = 0; k < 3; ++k) C->bz[k] = a.bz[k];
   C->c_an = a.c_an;
   C->vol = a.vol;
@@ -1227,6 +1236,7 @@ hipError_t launch_ctrl_init(Ctrl* ctrl, int slot, int stage, int terms, int nonm
   a.bz[2] = dparams[11];
   a.c_an = dparams[12];
   a.vol = dparams[13];
+  a.e_res = dparams[14];
   hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, s, ctrl, slot, a);
   return hipGetLastError();
 }
