@@ -323,10 +323,9 @@ __device__ __forceinline__ real row_sum(DevPtr<const int> __restrict__ rp, DevPt
 // long; W = 1 (one thread per row) reads the operation's matrix from its
 // sliced copy, which matrices with many rows have (the level-0 operator is
 // the potential matrix).
-// entries per lane per batch: 16-lane rows are the long ones (40-75 entries),
-// which one batch of 8 covers
+// entries per lane per batch (16-lane rows, 25-64 entries, take one batch)
 template <int W>
-constexpr int kRowU = W >= 16 ? 8 : kUnroll;
+constexpr int kRowU = kUnroll;
 
 template <typename real, int W, typename G>
 __device__ __forceinline__ real a_row(DevRef<const MgLevelDev<real>> L, int i, int lane, G&& g) {
