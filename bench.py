@@ -139,6 +139,8 @@ def run_poly(args):
                          "f32+f64-reductions", {"workload": f"{name} polycrystal, 200x200x100 nm box, one minimization",
                                                 "magnet_nodes": o["N"], "potential_nodes": o["Nt"]})
         line["roofline"] = roofline_of(o["tm"], 4)
+        if name == "fp64" and line["roofline"]:
+            line["roofline"]["traffic"] = measured_traffic("k_step_fp64_poly")
         print(json.dumps(line), flush=True)
         return
     mx, fp = out["mixed"], out["fp64"]

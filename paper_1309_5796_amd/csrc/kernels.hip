@@ -161,16 +161,21 @@ __device__ __forceinline__ real sell_sum(const ProbDev<real>& P, int i, G&& g) {
 }
 
 // ---- PREP: trial magnetization, Poisson right-hand side, initial residual ----
-// One thread per row: magnet rows also form the trial m_t (and recompute it
-// at their magnet neighbours for b = D1 m_t); every potential row forms
-// r = b - L u.
+// Over the block's chunk of rows, first the magnet rows with LPR lanes per
+// row: the trial m_t (Cayley step, also recomputed at magnet neighbours) and
+// b = D1 m_t, stored in the residual slot; then every potential row, one
+// thread per row over the sliced matrix: r = b - L u.  The block barrier
+// between the two orders each row's b before its reuse (same block).
 template <typename real, int LPR>
 __device__ void phase_prep(const ProbDev<real>& P, const Ctrl* C, int t, double* acc) {
-  constexpr int RPP = kBlock;
+  constexpr int RPP = kBlock / LPR;
+  const int lane = threadIdx.x & (LPR - 1);
+  const int slot = threadIdx.x / LPR;
   const bool demag = C->demag != 0;
+  const bool amg = C->precond == PC_AMG;
   const int R = demag ? P.Nt : P.N;
   int r0, r1;
-  chunk_rows(R, P.G, t, RPP, r0, r1);
+  chunk_rows(R, P.G, t, kBlock, r0, r1);
   const int a = C->acc, tr = 1 - a;
   const real ht = real(0.5 * C->tau);
   DevPtr<const real> __restrict__ max_ = P.m[a][0];
@@ -179,36 +184,54 @@ __device__ void phase_prep(const ProbDev<real>& P, const Ctrl* C, int t, double*
   DevPtr<const real> __restrict__ Hax = P.H[a][0];
   DevPtr<const real> __restrict__ Hay = P.H[a][1];
   DevPtr<const real> __restrict__ Haz = P.H[a][2];
-  DevPtr<const real> __restrict__ u = P.u;
-  for (int base = r0; base < r1; base += RPP) {
-    const int i = base + threadIdx.x;
-    if (i >= r1) continue;
+  DevPtr<real> __restrict__ r2 = P.r2[C->rcur];
+  DevPtr<Rec<real>> __restrict__ rec = P.rec[C->pcur];
+  const int m1 = r1 < P.N ? r1 : P.N;
+  for (int base = r0; base < m1; base += RPP) {
+    const int i = base + slot;
+    const bool valid = i < m1;
     real bi = 0;
-    if (i < P.N) {
-      real ox, oy, oz;
-      cayley<real>(max_[i], may[i], maz[i], Hax[i], Hay[i], Haz[i], ht, ox, oy, oz);
-      P.m[tr][0][i] = ox;
-      P.m[tr][1][i] = oy;
-      P.m[tr][2][i] = oz;
+    if (valid) {
+      if (lane == 0) {
+        real ox, oy, oz;
+        cayley<real>(max_[i], may[i], maz[i], Hax[i], Hay[i], Haz[i], ht, ox, oy, oz);
+        P.m[tr][0][i] = ox;
+        P.m[tr][1][i] = oy;
+        P.m[tr][2][i] = oz;
+      }
       if (demag) {
         const int k1 = P.mrp[i + 1];
-        for (int k = P.mrp[i]; k < k1; ++k) {
+        for (int k = P.mrp[i] + lane; k < k1; k += LPR) {
           const int j = P.mci[k];
+          real ox, oy, oz;
           cayley<real>(max_[j], may[j], maz[j], Hax[j], Hay[j], Haz[j], ht, ox, oy, oz);
           bi += P.D1[0][k] * ox + P.D1[1][k] * oy + P.D1[2][k] * oz;
         }
       }
     }
     if (demag) {
-      const real ui = u[i];
-      const real lu = sell_sum(P, i, [&](int j) { return u[j]; });
-      const real ri = bi - lu;
-      if (C->precond == PC_AMG) P.r2[C->rcur][i] = ri;
-      else P.rec[C->pcur][i].r = ri;
-      acc[0] += (double)bi * (double)bi;
-      acc[1] += (double)ri * (double)ri;
-      acc[2] += (double)ri * (double)ui;
+      bi = group_sum<real, LPR>(bi);
+      if (valid && lane == 0) {
+        if (amg) r2[i] = bi;
+        else rec[i].r = bi;
+      }
     }
+  }
+  if (!demag) return;
+  __syncthreads();
+  DevPtr<const real> __restrict__ u = P.u;
+  for (int base = r0; base < r1; base += kBlock) {
+    const int i = base + threadIdx.x;
+    if (i >= r1) continue;
+    const real bi = i < P.N ? (amg ? r2[i] : rec[i].r) : real(0);
+    const real ui = u[i];
+    const real lu = sell_sum(P, i, [&](int j) { return u[j]; });
+    const real ri = bi - lu;
+    if (amg) r2[i] = ri;
+    else rec[i].r = ri;
+    acc[0] += (double)bi * (double)bi;
+    acc[1] += (double)ri * (double)ri;
+    acc[2] += (double)ri * (double)ui;
   }
 }
 
