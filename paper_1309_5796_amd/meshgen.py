@@ -249,6 +249,30 @@ def config1(air: bool = True) -> dict:
     return dict(mesh=mesh, m0=noisy_plus_z(n, rm), b_ext=-2.0 * U_H_1DEG, tol=1e-6)
 
 
+def delaunay_box(seed: int, outer: float = 30e-9, inner: float = 12e-9, n: int = 16) -> Mesh:
+    """Irregular test mesh: Delaunay tetrahedra of a jittered (n+1)^3 point
+    grid over [-outer, outer]^3 (interior points moved by up to 0.3 of the
+    spacing, boundary points kept on their faces); tets whose centroid lies in
+    [-inner, inner]^3 are magnetic (region 1); the outer faces are Dirichlet;
+    no transformation shell.  Node degrees vary (about 8 to 30)."""
+    from scipy.spatial import Delaunay
+    rng = np.random.default_rng(seed)
+    t = np.linspace(-outer, outer, n + 1)
+    g = np.stack(np.meshgrid(t, t, t, indexing="ij"), axis=-1).reshape(-1, 3)
+    on_face = np.abs(np.abs(g) - outer) < 1e-6 * (t[1] - t[0])
+    jit = rng.uniform(-0.3, 0.3, size=g.shape) * (t[1] - t[0])
+    xyz = np.where(on_face, g, g + jit)
+    tets = Delaunay(xyz).simplices.astype(np.int32)
+    d = xyz[tets[:, 1:]] - xyz[tets[:, :1]]
+    vol = np.abs(np.linalg.det(d)) / 6.0
+    tets = tets[vol > 1e-6 * (t[1] - t[0]) ** 3]          # drop flat boundary slivers
+    cen = xyz[tets].mean(axis=1)
+    region = np.all(np.abs(cen) < inner, axis=1).astype(np.int32)
+    dirichlet = np.any(on_face, axis=1).astype(np.uint8)
+    return Mesh(xyz=xyz, tets=tets, region=region, dirichlet=dirichlet,
+                materials=[Material(1, JS_T, K1_JM3, A_JM, np.array([0.0, 0.0, 1.0]))])
+
+
 def sweep_fields(bmax: float = 8.0, step: float = 0.1) -> np.ndarray:
     """+bmax -> -bmax -> +bmax in `step` T steps along the 1-degree direction."""
     k = int(round(bmax / step))

@@ -12,17 +12,21 @@ from paper_1309_5796_amd import binding, meshgen
 NM = 1e-9
 
 
-@pytest.fixture(scope="module")
-def both():
-    cfg = meshgen.config1()
-    mesh = cfg["mesh"]
-    # a second material region so per-region values are exercised
-    region = mesh.region.copy()
-    mag = np.nonzero(region)[0]
-    region[mag[::3]] = 2
-    mesh = meshgen.Mesh(xyz=mesh.xyz, tets=mesh.tets, region=region, dirichlet=mesh.dirichlet,
-                        shell=mesh.shell, materials=mesh.materials + [
-                            meshgen.Material(2, meshgen.JS_T, 1.3e6, 3e-12, np.array([0.3, -0.2, 0.9]))])
+@pytest.fixture(scope="module", params=["kuhn_two_regions", "delaunay"])
+def both(request):
+    if request.param == "delaunay":
+        # irregular connectivity: potential rows of 4 to ~25 entries
+        mesh = meshgen.delaunay_box(5)
+    else:
+        cfg = meshgen.config1()
+        mesh = cfg["mesh"]
+        # a second material region so per-region values are exercised
+        region = mesh.region.copy()
+        mag = np.nonzero(region)[0]
+        region[mag[::3]] = 2
+        mesh = meshgen.Mesh(xyz=mesh.xyz, tets=mesh.tets, region=region, dirichlet=mesh.dirichlet,
+                            shell=mesh.shell, materials=mesh.materials + [
+                                meshgen.Material(2, meshgen.JS_T, 1.3e6, 3e-12, np.array([0.3, -0.2, 0.9]))])
     return mesh, oracle.System(mesh), binding.assembly_export(mesh)
 
 

@@ -253,3 +253,39 @@ def test_step_rules_match_oracle(ctx, cfg1, cfg1_system, rule, name):
     assert rel_energy_err(r.energy_J, s.evaluate(ro.m, cfg1["b_ext"])) < 1e-10
     assert abs(r.iterations - ro.iterations) <= 3
     p.close()
+
+
+@pytest.mark.parametrize("precond", ["jacobi", "amg"])
+def test_irregular_mesh_matches_oracle(ctx, precond):
+    """Delaunay mesh with potential rows of 4 to ~25 entries (padded slices,
+    uneven slice widths): evaluation in FP64 and the mixed form, and a FP64
+    minimization, against the oracle."""
+    from paper_1309_5796_amd import binding
+    say(f"irregular mesh {precond}")
+    mesh = meshgen.delaunay_box(7)
+    s = oracle.System(mesh)
+    pc = binding.PRECOND_JACOBI if precond == "jacobi" else binding.PRECOND_AMG
+    rng = np.random.default_rng(31)
+    m = np.tile([0.0, 0.0, 1.0], (s.N, 1)) + 0.4 * rng.normal(size=(s.N, 3))
+    m /= np.linalg.norm(m, axis=1, keepdims=True)
+    B = -1.5 * meshgen.U_H_1DEG
+    ev = s.evaluate(m, B)
+    for prec, tol_e, tol_h in ((binding.FP64, 1e-12, 1e-10), (binding.MIXED, 1e-6, 1e-5)):
+        p = binding.Problem(ctx, mesh, precision=prec)
+        p.set_m(m)
+        p.set_field(B)
+        r = p.evaluate(pcg_rtol=1e-14 if prec == binding.FP64 else 1e-7, precond=pc)
+        assert rel_energy_err(r.energy_J, ev) < tol_e, prec
+        h = p.get_field()
+        assert np.abs(h - ev["h"]).max() < tol_h * np.abs(ev["h"]).max(), prec
+        p.close()
+    ro = oracle.minimize(s, m, B, Options())
+    p = binding.Problem(ctx, mesh)
+    p.set_m(m)
+    p.set_field(B)
+    r = p.minimize(precond=pc)
+    assert r.status == 0 and ro.status == 0
+    scale = abs(ro.terms["E_ex"]) + abs(ro.terms["E_an"]) + abs(ro.terms["E_Z"]) + abs(ro.terms["E_d"])
+    assert abs(r.energy_J - ro.E) < 1e-10 * scale
+    np.testing.assert_allclose(r.m_avg, s.mean_m(ro.m), atol=1e-7)
+    p.close()
