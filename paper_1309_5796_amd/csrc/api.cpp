@@ -116,8 +116,15 @@ Prob<real>& desc_of(mmsd_problem p) {
   return *reinterpret_cast<Prob<real>*>(p->desc);
 }
 
-// Average row length above which a multigrid operator is swept with 16
-// lanes per row.
+// Lanes per row for a multigrid matrix swept in CSR: rows of more than 16
+// entries on average take 8 lanes loading 8 entries each (one batch up to 64
+// entries and 64 rows per block pass), more than 64 take 16 lanes; shorter
+// rows use the kernel's lanes per row.
+int row_lanes(const Csr& M) {
+  const double avg = M.nrows ? (double)M.ci.size() / M.nrows : 0.0;
+  return avg > 64 ? 16 : avg > 16 ? 8 : 0;
+}
+// Average row length up to which a matrix with many rows is sliced.
 constexpr size_t kWideRow = 24;
 // Rows from which a multigrid matrix with short rows (at most kWideRow on
 // average) also gets a sliced copy and is swept one row per thread (enough
@@ -338,9 +345,9 @@ int build_amg(mmsd_problem p) {
     d.n = L.A.nrows;
     d.n_next = L.P.ncols;
     d.plain = plain_prolongation(L.P) ? 1 : 0;
-    d.wide_a = L.A.ci.size() > kWideRow * (size_t)L.A.nrows;
-    d.wide_p = L.P.ci.size() > kWideRow * (size_t)L.P.nrows;
-    d.wide_r = L.R.ci.size() > kWideRow * (size_t)L.R.nrows;
+    d.lanes_a = row_lanes(L.A);
+    d.lanes_p = row_lanes(L.P);
+    d.lanes_r = row_lanes(L.R);
     d.arp = l == 0 ? nullptr : (const int*)(base + lo[l].arp);
     d.aci = l == 0 ? nullptr : (const int*)(base + lo[l].aci);
     d.av = l == 0 ? nullptr : (const real*)(base + lo[l].av);

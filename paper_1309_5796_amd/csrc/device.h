@@ -115,7 +115,7 @@ template <typename real, template <typename> class Ptr>
 struct MgLevelT {
   int n, n_next;
   int plain;               // P is plain aggregation: row i holds a single 1 in column pci[i]
-  int wide_a, wide_p, wide_r;   // rows of A, P, R long enough for 16 lanes per row
+  int lanes_a, lanes_p, lanes_r;   // lanes per row for A, P, R: 0 (the kernel's), 8 or 16
   Ptr<const int> arp;
   Ptr<const int> aci;
   Ptr<const real> av;

@@ -346,9 +346,10 @@ __device__ __forceinline__ real row_sum(DevPtr<const int> __restrict__ rp, DevPt
 // long; W = 1 (one thread per row) reads the operation's matrix from its
 // sliced copy, which matrices with many rows have (the level-0 operator is
 // the potential matrix).
-// entries per lane per batch (16-lane rows, 25-64 entries, take one batch)
+// entries per lane per batch: 8 for the 8- and 16-lane rows of long-row
+// matrices (one batch covers 64 or 128 entries)
 template <int W>
-constexpr int kRowU = kUnroll;
+constexpr int kRowU = W >= 8 ? 8 : kUnroll;
 
 template <typename real, int W, typename G>
 __device__ __forceinline__ real a_row(DevRef<const MgLevelDev<real>> L, int i, int lane, G&& g) {
@@ -491,12 +492,14 @@ __device__ void phase_mg(const ProbDev<real>& P, const Ctrl* C, int t, double* a
     return;
   }
   DevRef<const MgLevelDev<real>> L = P.lev[l];
-  const int wide = op == MG_REST ? L.wide_r : op == MG_PROL ? L.wide_p : L.wide_a;
+  const int lanes = op == MG_REST ? L.lanes_r : op == MG_PROL ? L.lanes_p : L.lanes_a;
   const bool sliced = op == MG_REST ? L.rso != nullptr : op == MG_PROL ? L.pso != nullptr : L.aso != nullptr;
   if (sliced)
     mg_rows<real, 1>(P, C, L, op, l, t, acc);
-  else if (wide && LPR < 16)
+  else if (lanes == 16)
     mg_rows<real, 16>(P, C, L, op, l, t, acc);
+  else if (lanes == 8)
+    mg_rows<real, 8>(P, C, L, op, l, t, acc);
   else
     mg_rows<real, LPR>(P, C, L, op, l, t, acc);
 }
@@ -1047,7 +1050,7 @@ __device__ __forceinline__ void run_phase(const ProbDev<real>& P, const Ctrl* C,
 }
 
 template <typename real, int LPR>
-__global__ void __launch_bounds__(kBlock, 6) k_step(const ProbDev<real>* __restrict__ probs, int nprob,
+__global__ void __launch_bounds__(kBlock, 5) k_step(const ProbDev<real>* __restrict__ probs, int nprob,
                                                     const int* __restrict__ blk_start, int parity) {
   __shared__ Ctrl s_c;
   __shared__ double s_red[kBlock / 64][kNPart];
