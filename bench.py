@@ -6,8 +6,8 @@ cells: 68,921 magnet nodes, 250,047 potential nodes), field +8 -> -8 -> +8 T
 in 0.1 T steps along z tilted by 1 degree, each point warm-started from the
 previous minimum.  A "step" is one field point of the sweep (a full
 minimization: trial steps, potential solves, field, step logic, stopping
-test, continuation); --steps K times the first K points (default 161, the
-descending branch +8 -> -8 T with its switching field; 321 = whole loop).
+test, continuation); --steps K times the first K points (default 321, the
+whole loop with both switching fields; 161 = the descending branch).
 
 Prints one JSON line with node-iterations/s (magnet nodes x energy-gradient
 evaluations, line-search trials included, per second of wall time), the
@@ -290,7 +290,7 @@ def run_copy(args):
     from paper_1309_5796_amd import binding
     ctx = binding.Context(0)
     nbytes = 256 << 20
-    ms = ctx.copy_probe(nbytes, reps=args.steps if args.steps != 161 else 10)
+    ms = ctx.copy_probe(nbytes, reps=10)
     print(json.dumps({"workload": "copy probe", "bytes_read": nbytes, "bytes_written": nbytes,
                       "ms": ms, "GBps": 2 * nbytes / ms / 1e6}), flush=True)
     ctx.close()
@@ -299,8 +299,8 @@ def run_copy(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=161,
-                    help="field points timed from +8 T (161 = descending branch, 321 = whole loop)")
+    ap.add_argument("--steps", type=int, default=321,
+                    help="field points timed from +8 T (321 = whole loop, 161 = descending branch)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")

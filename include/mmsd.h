@@ -12,7 +12,9 @@
  * 20-energy nonmonotone line search, and the stopping test on the torque.
  * The stray field comes from a magnetic scalar potential with an open
  * boundary handled by a space transformation (Results, comparison section);
- * the potential is solved by Jacobi-preconditioned CG on the device.
+ * the potential is solved on the device by CG preconditioned with an
+ * algebraic multigrid V-cycle (built on the host at problem creation) or by
+ * Jacobi.
  *
  * Conventions
  *  - Every function returns int: 0 = OK, > 0 = warning (result valid),
@@ -42,7 +44,9 @@ extern "C" {
 /* ---- status codes ------------------------------------------------------ */
 #define MMSD_OK 0
 #define MMSD_W_MAXEVALS 1     /* evaluation budget reached before the stopping test */
-#define MMSD_W_FLOOR 2        /* backtracking step fell below the floor; torque reported */
+#define MMSD_W_FLOOR 2        /* backtracking step fell below the floor (in the mixed form
+                                 also: the next trial's energy change is below the FP32
+                                 resolution of the energy); torque reported */
 #define MMSD_E_INVALID (-1)   /* bad argument */
 #define MMSD_E_MESH (-2)      /* degenerate/inverted tetrahedron, bad index, bad Dirichlet set */
 #define MMSD_E_NOMEM (-3)     /* device or host allocation failed */
