@@ -195,7 +195,8 @@ int mmsd_get_potential(mmsd_problem p, double* u_out);    /* [n_nodes] input nod
 /* Hysteresis (Introduction: continuation of local minima): for each field
  * b_T[k] (n x 3, T) minimize starting from the previous minimum, with a fresh
  * step-length state.  per_step[k] receives each result.  Switching is a sign
- * change of <m>.u between consecutive steps, u = b_T[0]/|b_T[0]|.  If
+ * change of <m>.u between consecutive steps, u = b_T[k]/|b_T[k]| for the
+ * first nonzero field (a sweep may start at zero field).  If
  * o->refine_tol_T > 0 each switching field is bisected from the last
  * unswitched minimum.  b_switch_out (nullable, capacity n) receives the
  * switching fields projected on u (T); *n_switch_out (nullable) their count. */

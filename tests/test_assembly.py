@@ -104,3 +104,17 @@ def test_bad_meshes_are_rejected_on_the_host():
     with pytest.raises(binding.MMSDError) as e:
         binding.assembly_export(touching)
     assert e.value.code == binding.E_MESH
+
+
+def test_sphere_experiment_mesh():
+    """Staircase ball standing in for the paper's 20 nm sphere (80,000 tets,
+    edge 0.76 nm): magnetic volume within 0.5% of the sphere's, about as many
+    magnetic tets, and every magnetic tet inside the sphere's bounding box."""
+    mesh = meshgen.kuhn_ball()
+    mag = mesh.region > 0
+    d = mesh.xyz[mesh.tets[mag][:, 1:]] - mesh.xyz[mesh.tets[mag][:, :1]]
+    vol = np.abs(np.linalg.det(d)).sum() / 6.0
+    r = 10e-9
+    assert abs(vol - 4.0 / 3.0 * np.pi * r ** 3) < 5e-3 * 4.0 / 3.0 * np.pi * r ** 3
+    assert 75_000 < int(mag.sum()) < 95_000
+    assert np.abs(mesh.xyz[np.unique(mesh.tets[mag])]).max() <= r * (1 + 1e-12)

@@ -220,3 +220,25 @@ def test_server_results_equal_alone_and_in_the_mix(ctx):
     st = srv.stats()
     assert st["completed"] == len(reqs) and st["resident"] == 0
     srv.close()
+
+
+def test_sphere_short_sweep_matches_oracle(ctx):
+    """Coarse staircase ball (the paper's sphere experiment at 8 cells per
+    diameter): field points 0, -1.5, -3 T at 45 degrees, warm-started, against
+    the oracle's continuation."""
+    from paper_1309_5796_amd import binding
+    say("sphere short sweep")
+    mesh = meshgen.kuhn_ball(cells=8)
+    s = oracle.System(mesh)
+    m0 = np.tile([0.0, 0.0, 1.0], (s.N, 1))
+    fields = -np.array([0.0, 1.5, 3.0])[:, None] * meshgen.U_H_45DEG[None, :]
+    recs, _ = oracle.hysteresis(s, m0, fields, Options())
+    p = binding.Problem(ctx, mesh)
+    p.set_m(m0)
+    res, _ = p.hysteresis(fields)
+    for r_gpu, r_or in zip(res, recs):
+        scale = abs(r_gpu.e_exch_J) + abs(r_gpu.e_anis_J) + abs(r_gpu.e_zeem_J) + abs(r_gpu.e_demag_J)
+        assert r_gpu.status == 0 and r_or.status == 0
+        assert abs(r_gpu.energy_J - r_or.E) < 1e-10 * scale
+        np.testing.assert_allclose(r_gpu.m_avg, r_or.m_avg, atol=1e-7)
+    p.close()
