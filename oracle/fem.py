@@ -239,3 +239,79 @@ class System:
 
     def mean_m(self, m: np.ndarray) -> np.ndarray:
         return (self.V[:, None] * m).sum(axis=0) / self.V.sum()
+
+
+# -- element-wise evaluation at full size (no assembled matrices) -----------
+
+def local_terms(mesh, m: np.ndarray, sample: np.ndarray, b_ext, terms: int = EXCH | ANIS | ZEEM) -> dict:
+    """Exchange, anisotropy and Zeeman parts of the energy (J), summed tet by
+    tet, and of the effective field (units of Ms) at the sampled magnetic
+    nodes, each from the tets around that node only: the same energy and
+    field as System.evaluate (module docstring) without assembling K, Q or
+    the potential matrix, so meshes of millions of nodes fit.
+
+    m: (N, 3) at the magnetic nodes (ascending global index); sample:
+    magnetic-node indices.  Returns E_ex, E_an, E_Z and h (len(sample), 3).
+    """
+    xyz, tets = np.asarray(mesh.xyz, float), np.asarray(mesh.tets, np.int64)
+    region = np.asarray(mesh.region)
+    mats = {int(mt.region): mt for mt in mesh.materials}
+    mag = np.nonzero(region > 0)[0]
+    mt = tets[mag]
+    nodes = np.unique(mt)
+    gmap = -np.ones(xyz.shape[0], dtype=np.int64)
+    gmap[nodes] = np.arange(nodes.size)
+    loc = gmap[mt]                                               # (Em, 4)
+    Js = mats[int(region[mag[0]])].Js
+    Ms = Js / MU0
+    mu0Ms2 = MU0 * Ms * Ms
+    b_ext = np.asarray(b_ext, float)
+    out = dict(E_ex=0.0, E_an=0.0, E_Z=0.0)
+    # energies, in chunks of tets
+    V_all = np.zeros(nodes.size)
+    for s0 in range(0, mag.size, 1 << 20):
+        sl = slice(s0, min(mag.size, s0 + (1 << 20)))
+        V_e, grad = tet_geometry(xyz, mt[sl])
+        reg = region[mag[sl]]
+        A_e = np.array([mats[int(r)].A for r in reg])
+        K1_e = np.array([mats[int(r)].K1 for r in reg])
+        ax = np.array([np.asarray(mats[int(r)].axis, float) / np.linalg.norm(mats[int(r)].axis) for r in reg])
+        me = m[loc[sl]]                                          # (e, 4, 3)
+        np.add.at(V_all, loc[sl].ravel(), np.repeat(V_e / 4.0, 4))
+        if terms & EXCH:
+            G = np.einsum("eac,ebc->eab", grad, grad)             # grad_a . grad_b
+            MM = np.einsum("eac,ebc->eab", me, me)                # m_a . m_b
+            out["E_ex"] += float(np.sum(A_e * V_e * np.einsum("eab,eab->e", G, MM)))
+        if terms & ANIS:
+            um = np.einsum("ec,eac->ea", ax, me)                  # u . m_a
+            out["E_an"] += float(np.sum(V_e * K1_e * (1.0 - 0.25 * np.sum(um * um, axis=1))))
+        if terms & ZEEM:
+            out["E_Z"] -= Ms * float(np.sum(V_e / 4.0 * np.einsum("eac,c->e", me, b_ext)))
+    # fields at the sampled nodes from their own tets
+    sample = np.asarray(sample, np.int64)
+    order = np.argsort(loc.ravel(), kind="stable")
+    first = np.searchsorted(loc.ravel()[order], sample, side="left")
+    last = np.searchsorted(loc.ravel()[order], sample, side="right")
+    h = np.zeros((sample.size, 3))
+    for k, i in enumerate(sample):
+        slots = order[first[k]:last[k]]
+        et, vert = slots // 4, slots % 4                          # incident tets, i's vertex in each
+        V_e, grad = tet_geometry(xyz, mt[et])
+        reg = region[mag[et]]
+        Vi = float(np.sum(V_e / 4.0))
+        c = 1.0 / (mu0Ms2 * Vi)
+        me = m[loc[et]]
+        if terms & EXCH:
+            A_e = np.array([mats[int(r)].A for r in reg])
+            gi = grad[np.arange(et.size), vert]                   # grad(phi_i) in each tet
+            Km = np.einsum("e,ec,ebc,ebd->d", A_e * V_e, gi, grad, me)
+            h[k] += -2.0 * c * Km
+        if terms & ANIS:
+            K1_e = np.array([mats[int(r)].K1 for r in reg])
+            ax = np.array([np.asarray(mats[int(r)].axis, float) / np.linalg.norm(mats[int(r)].axis) for r in reg])
+            Qm = np.einsum("e,ec,ed,d->c", V_e / 4.0 * K1_e, ax, ax, m[i])
+            h[k] += 2.0 * c * Qm
+        if terms & ZEEM:
+            h[k] += b_ext / Js
+    out["h"] = h
+    return out

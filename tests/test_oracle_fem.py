@@ -170,3 +170,28 @@ def test_flat_prism_demag_factor_extrapolates_to_aharoni():
     limit = Nz[2] + d2 / (2 ** p - 1)
     assert 0.8 < p < 2.2
     assert abs(limit - aharoni_z(2, 2, 1)) < 5e-3 * aharoni_z(2, 2, 1)
+
+
+def test_elementwise_terms_equal_the_assembled_ones():
+    """The element-wise evaluation used at full size (no assembled matrices)
+    gives the same exchange, anisotropy and Zeeman energies and fields as the
+    assembled operators, on a two-material mesh."""
+    from oracle.fem import local_terms
+    cfg = meshgen.config1()
+    mesh = cfg["mesh"]
+    region = mesh.region.copy()
+    region[np.nonzero(region)[0][::4]] = 2
+    mesh = meshgen.Mesh(xyz=mesh.xyz, tets=mesh.tets, region=region, dirichlet=mesh.dirichlet, shell=mesh.shell,
+                        materials=mesh.materials + [meshgen.Material(2, meshgen.JS_T, 2.1e6, 5e-12,
+                                                                     np.array([0.2, 0.5, 0.8]))])
+    s = oracle.System(mesh)
+    rng = np.random.default_rng(4)
+    m = rng.normal(size=(s.N, 3))
+    m /= np.linalg.norm(m, axis=1, keepdims=True)
+    terms = oracle.fem.EXCH | oracle.fem.ANIS | oracle.fem.ZEEM
+    ev = s.evaluate(m, cfg["b_ext"], terms)
+    smp = rng.choice(s.N, 60, replace=False)
+    lt = local_terms(mesh, m, smp, cfg["b_ext"], terms)
+    for k in ("E_ex", "E_an", "E_Z"):
+        assert abs(lt[k] - ev[k]) <= 1e-13 * abs(ev[k])
+    assert np.abs(lt["h"] - ev["h"][smp]).max() <= 1e-13 * np.abs(ev["h"]).max()
