@@ -2,10 +2,14 @@
 //
 // One launch advances every unfinished problem of a table by one phase (see
 // device.h for the phases and the parity protocol).  Work layout:
-//  * CSR rows are split over `LPR` lanes (4, 8 or 16) of a 64-wide wavefront;
-//    a block of 512 threads walks a contiguous chunk of rows in passes of
-//    512/LPR rows.  Column indices and values stream coalesced; node vectors
-//    are gathered (they stay in L2: every entry is reused by ~15 rows).
+//  * Rows of the potential matrix (and of multigrid matrices with many short
+//    rows) are swept one per thread from a 64-row sliced layout: a wavefront
+//    owns a slice, so index and value loads are contiguous 64-wide accesses.
+//  * Other CSR rows (magnet matrices, coarse multigrid levels) are split over
+//    `LPR` lanes (4, 8 or 16) of a 64-wide wavefront.  A block of 512 threads
+//    walks a contiguous chunk of rows in passes.  Node vectors are gathered
+//    (they stay in L2: every entry is reused by ~15 rows); values gathered
+//    together are packed into records.
 //  * Block b of a problem takes chunk (b % 8) * (G / 8) + b / 8: blocks are
 //    dealt to the 8 XCDs round-robin, so this gives each XCD one contiguous
 //    eighth of the rows and keeps neighbour gathers inside its own L2.
