@@ -280,7 +280,8 @@ def run_serve(args):
     line["detail"] = {"p50_s": float(np.percentile(lat, 50)) if len(lat) else None,
                       "p99_s": float(np.percentile(lat, 99)) if len(lat) else None,
                       "completed": int(len(lat)), "statuses": sorted(set(statuses)),
-                      "device_launches": st["launches"], "offered_rate_req_s": 200.0,
+                      "device_launches": st["launches"], "setup_seconds_summed": st["setup_seconds"],
+                      "device_loop_busy_s": st["loop_seconds"], "offered_rate_req_s": 200.0,
                       "served_rate_req_s": len(lat) / wall}
     print(json.dumps(line), flush=True)
 

@@ -276,8 +276,10 @@ int mmsd_submit(mmsd_server s, const mmsd_mesh* mesh, const mmsd_material* mats,
 int mmsd_poll(mmsd_server s, uint64_t ticket, mmsd_result* out, double* m_out);
 int mmsd_cancel(mmsd_server s, uint64_t ticket);
 /* stats: [0] submitted, [1] completed, [2] resident, [3] queued, [4] bytes resident,
- * [5] device launches, [6] node-evaluations completed */
-int mmsd_server_stats(mmsd_server s, double stats[7]);
+ * [5] device launches, [6] node-evaluations completed, [7] seconds spent in request
+ * setup (assembly, multigrid setup, upload; summed over the setup workers),
+ * [8] seconds the device loop spent in launch batches */
+int mmsd_server_stats(mmsd_server s, double stats[9]);
 int mmsd_server_destroy(mmsd_server s);
 
 const char* mmsd_last_error(void);

@@ -458,9 +458,10 @@ class Server:
         _check(self.lib.mmsd_cancel(self.handle, ticket))
 
     def stats(self) -> dict:
-        s = (C.c_double * 7)()
+        s = (C.c_double * 9)()
         _check(self.lib.mmsd_server_stats(self.handle, s))
-        keys = ["submitted", "completed", "resident", "queued", "bytes_resident", "launches", "node_evals"]
+        keys = ["submitted", "completed", "resident", "queued", "bytes_resident", "launches", "node_evals",
+                "setup_seconds", "loop_seconds"]
         return dict(zip(keys, s[:]))
 
     def close(self):

@@ -30,6 +30,10 @@ using Clock = std::chrono::steady_clock;
 
 size_t align_up_bytes(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Setup workers: host assembly and multigrid setup of several requests overlap
+// (only their uploads serialize on the upload context).
+constexpr int kSetupThreads = 3;
+
 enum ReqState { RQ_QUEUED, RQ_SETUP, RQ_READY, RQ_RESIDENT, RQ_DONE, RQ_FAILED, RQ_CANCELLED };
 
 struct Request {
@@ -85,7 +89,9 @@ struct mmsd_server_s {
   int slots_used = 0;
   bool stop = false;
   double n_submitted = 0, n_completed = 0, launches = 0, node_evals = 0;
-  std::thread setup_thr, loop_thr;
+  double setup_seconds = 0, loop_seconds = 0;   // summed over setups; device loop busy time
+  std::vector<std::thread> setup_thr;   // host assembly, multigrid setup and upload overlap across threads
+  std::thread loop_thr;
   // device-side tables (owned by the loop thread)
   char* dtab = nullptr;
   size_t dtab_bytes = 0;
@@ -140,6 +146,7 @@ void mmsd_server_s::setup_loop() {
     }
     lk.unlock();
     // assemble + upload outside the lock
+    const auto t_setup = Clock::now();
     mmsd_mesh m = r->mesh();
     mmsd_problem p = nullptr;
     int rc = mmsd_problem_create(upload_ctx, &m, r->mats.data(), (int)r->mats.size(), r->precision, &p);
@@ -156,6 +163,7 @@ void mmsd_server_s::setup_loop() {
     }
     if (rc) r->error = mmsd_last_error();
     lk.lock();
+    setup_seconds += std::chrono::duration<double>(Clock::now() - t_setup).count();
     if (rc) {
       if (p) mmsd_problem_destroy(p);
       bytes_reserved -= r->footprint;
@@ -274,6 +282,7 @@ void mmsd_server_s::device_loop() {
     }
     // a batch of launches, then read the done list
     const int B = 16;
+    const auto t_batch = Clock::now();
     if (!rc) rc = issue(loop_ctx, tabs, B, nullptr);
     if (!rc && hipMemcpyAsync(hdone, dtab, sizeof(unsigned), hipMemcpyDeviceToHost, st) != hipSuccess) rc = MMSD_E_HIP;
     if (!rc && hipMemcpyAsync(hdone + 2, dtab + 256, sizeof(int) * resident.size(), hipMemcpyDeviceToHost, st) !=
@@ -281,6 +290,7 @@ void mmsd_server_s::device_loop() {
       rc = MMSD_E_HIP;
     if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = MMSD_E_HIP;
     lk.lock();
+    loop_seconds += std::chrono::duration<double>(Clock::now() - t_batch).count();
     launches += B * tabs.size();
     if (rc) {
       // a device failure poisons every resident request
@@ -355,7 +365,7 @@ int mmsd_server_create(mmsd_ctx ctx, size_t hbm_budget, int max_slots, mmsd_serv
     delete s;
     return rc;
   }
-  s->setup_thr = std::thread(&mmsd_server_s::setup_loop, s);
+  for (int k = 0; k < kSetupThreads; ++k) s->setup_thr.emplace_back(&mmsd_server_s::setup_loop, s);
   s->loop_thr = std::thread(&mmsd_server_s::device_loop, s);
   *out = s;
   return MMSD_OK;
@@ -439,7 +449,7 @@ int mmsd_cancel(mmsd_server s, uint64_t ticket) {
   return MMSD_OK;
 }
 
-int mmsd_server_stats(mmsd_server s, double st[7]) {
+int mmsd_server_stats(mmsd_server s, double st[9]) {
   if (!s || !st) return MMSD_E_INVALID;
   std::lock_guard<std::mutex> lk(s->mu);
   double resident = 0;
@@ -452,6 +462,8 @@ int mmsd_server_stats(mmsd_server s, double st[7]) {
   st[4] = (double)s->bytes_reserved;
   st[5] = s->launches;
   st[6] = s->node_evals;
+  st[7] = s->setup_seconds;
+  st[8] = s->loop_seconds;
   return MMSD_OK;
 }
 
@@ -463,7 +475,7 @@ int mmsd_server_destroy(mmsd_server s) {
   }
   s->cv_setup.notify_all();
   s->cv_loop.notify_all();
-  s->setup_thr.join();
+  for (std::thread& t : s->setup_thr) t.join();
   s->loop_thr.join();
   hipSetDevice(s->loop_ctx->device);
   hipStreamSynchronize(s->loop_ctx->stream);
