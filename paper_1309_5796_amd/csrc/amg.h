@@ -29,7 +29,7 @@ struct AmgHierarchy {
 
 struct AmgParams {
   double theta = 0.04;           // strength of connection |a_ij| >= theta sqrt(a_ii a_jj)
-  int smooth_levels = 1;         // levels whose prolongation is Jacobi-smoothed
+  int smooth_levels = 10;        // levels whose prolongation is Jacobi-smoothed (all, with p_drop)
   int coarse_max = 600;          // stop coarsening at or below this size
   int max_levels = 10;
   double p_drop = 0.2;           // drop smoothed-P entries below this fraction of the row's largest
