@@ -9,11 +9,11 @@
 //   smoothing:  P = (I - omega D^-1 A) T on the first `smooth_levels` levels
 //               (all by default), P = T below; entries of a smoothed row
 //               below p_drop x its largest are dropped and the rest rescaled
-//               to the row's sum.  On the 80 nm cube: P from 7 to 2.8 and the
-//               next operator from 75 to 36 entries per row at the same
-//               iteration count; with the drop, smoothing every level keeps
-//               the operator complexity at 1.42 and takes 55 -> 35 PCG
-//               iterations from zero (polycrystal: 86 -> 40)
+//               to the row's sum.  On the 80 nm cube (p_drop 0.1): P from 7
+//               to 3.0 and the next operator from 75 to 39 entries per row;
+//               with the drop, smoothing every level keeps the operator
+//               complexity at 1.45 and takes 56 -> 34 PCG iterations from
+//               zero (polycrystal: 84 -> 34, complexity 1.46)
 //   Galerkin:   A_{l+1} = P^T A P
 // The coarsest operator is inverted densely (Cholesky, then the inverse).
 #include "amg.h"

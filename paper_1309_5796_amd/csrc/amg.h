@@ -32,7 +32,7 @@ struct AmgParams {
   int smooth_levels = 10;        // levels whose prolongation is Jacobi-smoothed (all, with p_drop)
   int coarse_max = 600;          // stop coarsening at or below this size
   int max_levels = 10;
-  double p_drop = 0.2;           // drop smoothed-P entries below this fraction of the row's largest
+  double p_drop = 0.1;           // drop smoothed-P entries below this fraction of the row's largest
 };
 
 // Build the hierarchy for the symmetric positive definite CSR matrix A.
