@@ -323,3 +323,43 @@ def test_polycrystal_full_size_local_terms_match_oracle(ctx):
             assert abs(getattr(r, k_gpu) - lt[k_or]) <= tol_e * abs(lt[k_or]), (prec, k_gpu)
         assert np.abs(h[smp] - lt["h"]).max() <= tol_h * np.abs(lt["h"]).max(), prec
         p.close()
+
+
+def test_degenerate_sizes_and_states(ctx):
+    """Edge cases: the smallest mesh (one Kuhn cell, 6 tets, 8 nodes, no air:
+    fewer rows than one wavefront), a start already at the minimum (zero
+    torque: no step is taken), and a field-free, anisotropy-free problem
+    (exchange only: any uniform state is a minimum)."""
+    from paper_1309_5796_amd import binding
+    say("degenerate sizes and states")
+    mesh = meshgen.kuhn_box((1e-9, 1e-9, 1e-9), (1, 1, 1), air=False)
+    s = oracle.System(mesh)
+    assert s.N == 8
+    rng = np.random.default_rng(51)
+    m = rng.normal(size=(8, 3))
+    m /= np.linalg.norm(m, axis=1, keepdims=True)
+    B = np.array([0.3, -0.2, 1.1])
+    terms = EXCH | ANIS | ZEEM
+    p = binding.Problem(ctx, mesh)
+    p.set_m(m)
+    p.set_field(B)
+    r = p.evaluate(terms=terms)
+    ev = s.evaluate(m, B, terms)
+    assert abs(r.energy_J - ev["E"]) <= 1e-12 * sum(abs(ev[k]) for k in ("E_ex", "E_an", "E_Z"))
+    assert np.abs(p.get_field() - ev["h"]).max() <= 1e-12 * np.abs(ev["h"]).max()
+    r = p.minimize(terms=terms)
+    ro = oracle.minimize(s, m, B, Options(terms=terms))
+    assert r.status == 0 and ro.status == 0
+    assert abs(r.energy_J - ro.E) <= 1e-10 * (abs(ro.terms["E_ex"]) + abs(ro.terms["E_an"]) + abs(ro.terms["E_Z"]))
+    # already at the minimum: uniform along the easy axis and the field
+    p.set_m(np.tile([0.0, 0.0, 1.0], (8, 1)))
+    p.set_field(np.array([0.0, 0.0, 0.5]))
+    r = p.minimize(terms=terms)
+    assert r.status == 0 and r.iterations == 0 and r.evals == 1 and r.max_torque == 0.0
+    # exchange only: a uniform tilted state stays put
+    u = np.tile([0.6, 0.0, 0.8], (8, 1))
+    p.set_m(u)
+    r = p.minimize(terms=EXCH)
+    assert r.status == 0 and r.iterations == 0
+    assert np.abs(p.get_m() - u).max() < 1e-15
+    p.close()
