@@ -78,9 +78,9 @@ __device__ __forceinline__ void cayley(real mx, real my, real mz, real Hx, real 
 // gathers, then accumulate: two dependent memory round trips per row batch
 // instead of two per nonzero.
 constexpr int kUnroll = 4;
-// Phases that gather several values per neighbour (CG records, the field's
-// m and u) take half the batch in FP64 to stay within 64 VGPRs, which lets
-// 8 wavefronts share a SIMD.
+// The FIELD phase gathers four values per neighbour (m and u) and takes half
+// the batch in FP64 to bound its register use (the kernel's VGPR count is
+// the largest phase's).
 template <typename real>
 constexpr int kUnrollWide = sizeof(real) == 8 ? 2 : 4;
 
@@ -1053,6 +1053,8 @@ __device__ __forceinline__ void run_phase(const ProbDev<real>& P, const Ctrl* C,
   }
 }
 
+// At most 96 VGPRs (5 wavefronts per SIMD): two 512-thread blocks per CU stay
+// resident, the shape that measured fastest, with no register spills.
 template <typename real, int LPR>
 __global__ void __launch_bounds__(kBlock, 5) k_step(const ProbDev<real>* __restrict__ probs, int nprob,
                                                     const int* __restrict__ blk_start, int parity) {
