@@ -54,10 +54,17 @@ print(json.dumps(dict(evals=r.evals, seconds=dt, N=s.N)))
     if out.returncode != 0:
         return {"error": out.stderr[-500:]}
     d = json.loads(out.stdout.strip().splitlines()[-1])
+    cpu = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {"value": d["N"] * d["evals"] / d["seconds"], "unit": "node-iterations/s", "cores": 1,
             "kind": "oracle",
             "sample": f"first {d['evals']} energy-gradient evaluations of the +8 T point of the same sweep "
-                      f"(FP64 NumPy/SciPy, potential by Jacobi-CG to 1e-13), {d['seconds']:.1f} s on one core"}
+                      f"(FP64 NumPy/SciPy, potential by Jacobi-CG to 1e-13), {d['seconds']:.1f} s on one core "
+                      f"of {os.cpu_count()} ({cpu})"}
 
 
 def kernel_source_hash() -> str:
