@@ -116,13 +116,19 @@ Prob<real>& desc_of(mmsd_problem p) {
   return *reinterpret_cast<Prob<real>*>(p->desc);
 }
 
-// Lanes per row for a multigrid matrix swept in CSR: rows of more than 16
-// entries on average take 8 lanes loading 8 entries each (one batch up to 64
-// entries and 64 rows per block pass), more than 64 take 16 lanes; shorter
-// rows use the kernel's lanes per row.
+// Lanes per row W (4, 8 or 16) for a multigrid matrix swept in CSR.  A
+// block pass covers 512 / W rows.  Rows of more than 16 entries on average
+// take 8 lanes loading 8 entries each (64 entries per batch), more than 64
+// take 16; shorter rows take 4 lanes loading 4 each.  A small matrix whose
+// rows all fit one pass of the 512 blocks of a full-GPU launch at 16 lanes
+// takes 16 lanes when its rows are long: that spreads its few rows over 4x
+// more blocks than 4 lanes would (measured 1-1.5 us faster per sweep on the
+// coarse levels, where each sweep is a chain of dependent loads).
+constexpr int64_t kSmallRows = 512 * (kBlock / 16);
 int row_lanes(const Csr& M) {
   const double avg = M.nrows ? (double)M.ci.size() / M.nrows : 0.0;
-  return avg > 64 ? 16 : avg > 16 ? 8 : 0;
+  if (avg > 16 && M.nrows <= kSmallRows) return 16;
+  return avg > 64 ? 16 : avg > 16 ? 8 : 4;
 }
 // Average row length up to which a matrix with many rows is sliced.
 constexpr size_t kWideRow = 24;

@@ -118,7 +118,7 @@ template <typename real, template <typename> class Ptr>
 struct MgLevelT {
   int n, n_next;
   int plain;               // P is plain aggregation: row i holds a single 1 in column pci[i]
-  int lanes_a, lanes_p, lanes_r;   // lanes per row for A, P, R: 0 (the kernel's), 8 or 16
+  int lanes_a, lanes_p, lanes_r;   // lanes per row for A, P, R in CSR: 4, 8 or 16
   Ptr<const int> arp;
   Ptr<const int> aci;
   Ptr<const real> av;

@@ -10,9 +10,10 @@
 //    walks a contiguous chunk of rows in passes.  Node vectors are gathered
 //    (they stay in L2: every entry is reused by ~15 rows); values gathered
 //    together are packed into records.
-//  * Block b of a problem takes chunk (b % 8) * (G / 8) + b / 8: blocks are
-//    dealt to the 8 XCDs round-robin, so this gives each XCD one contiguous
-//    eighth of the rows and keeps neighbour gathers inside its own L2.
+//  * Blocks are dealt to the 8 XCDs round-robin (block b runs on XCD b % 8);
+//    the row chunks are cut into 8 contiguous runs, one per XCD, so that
+//    neighbour gathers stay inside an XCD's own L2 and every XCD gets an
+//    equal share also of a coarse level's few chunks.
 //  * Reductions are deterministic and need no atomics: wavefront butterfly,
 //    then the 8 waves in order, one partial per block; the next launch's
 //    blocks each combine those G partials in the same fixed order.
@@ -113,14 +114,24 @@ __device__ __forceinline__ void st(DevPtr<Rec<real>> p, int i, const Rec<real>& 
   reinterpret_cast<DevPtr<vec4<real>>>(p)[i] = vec4<real>{x.r, x.s, x.w, x.d};
 }
 
-// Rows [r0, r1) of chunk t out of G for R rows, chunk rounded to `rpp`.
-__device__ __forceinline__ void chunk_rows(int R, int G, int t, int rpp, int& r0, int& r1) {
+// Rows [r0, r1) of block `blk` (of G, a multiple of 8) for R rows.  The rows
+// are cut into chunks of ceil(R / G) rounded up to `rpp`, and the chunks are
+// dealt to the 8 XCDs (block b runs on XCD b % 8) as 8 contiguous runs of
+// almost equal length: each XCD sweeps neighbouring rows, which keeps their
+// gathers in its own L2, and all 8 XCDs share the work also when there are
+// fewer chunks than blocks (the coarse multigrid levels).
+__device__ __forceinline__ void chunk_rows(int R, int G, int blk, int rpp, int& r0, int& r1) {
+  r0 = r1 = R;
+  if (R <= 0) return;
   long long c = ((long long)R + G - 1) / G;
   c = (c + rpp - 1) / rpp * rpp;
-  long long a = c * t;
-  r0 = (int)(a < R ? a : R);
-  long long b = a + c;
-  r1 = (int)(b < R ? b : R);
+  const int nch = (int)((R + c - 1) / c);          // <= G
+  const int x = blk & 7, k = blk >> 3;
+  const int s = x * nch / 8, e = (x + 1) * nch / 8;
+  if (k >= e - s) return;
+  const long long a = (long long)(s + k) * c;
+  r0 = (int)a;
+  r1 = (int)(a + c < R ? a + c : R);
 }
 
 // Rows of the potential matrix are swept one per thread from its 64-row
@@ -171,7 +182,7 @@ __device__ __forceinline__ real sell_sum(const ProbDev<real>& P, int i, G&& g) {
 // thread per row over the sliced matrix: r = b - L u.  The block barrier
 // between the two orders each row's b before its reuse (same block).
 template <typename real, int LPR>
-__device__ void phase_prep(const ProbDev<real>& P, const Ctrl* C, int t, double* acc) {
+__device__ void phase_prep(const ProbDev<real>& P, const Ctrl* C, int blk, double* acc) {
   constexpr int RPP = kBlock / LPR;
   const int lane = threadIdx.x & (LPR - 1);
   const int slot = threadIdx.x / LPR;
@@ -179,7 +190,7 @@ __device__ void phase_prep(const ProbDev<real>& P, const Ctrl* C, int t, double*
   const bool amg = C->precond == PC_AMG;
   const int R = demag ? P.Nt : P.N;
   int r0, r1;
-  chunk_rows(R, P.G, t, kBlock, r0, r1);
+  chunk_rows(R, P.G, blk, kBlock, r0, r1);
   const int a = C->acc, tr = 1 - a;
   const real ht = real(0.5 * C->tau);
   DevPtr<const real> __restrict__ max_ = P.m[a][0];
@@ -241,10 +252,10 @@ __device__ void phase_prep(const ProbDev<real>& P, const Ctrl* C, int t, double*
 
 // ---- CG0: w = L D^-1 r for the starting residual (one thread per row) ----
 template <typename real, int LPR>
-__device__ void phase_cg0(const ProbDev<real>& P, const Ctrl* C, int t, double* acc) {
+__device__ void phase_cg0(const ProbDev<real>& P, const Ctrl* C, int blk, double* acc) {
   constexpr int RPP = kBlock;
   int r0, r1;
-  chunk_rows(P.Nt, P.G, t, RPP, r0, r1);
+  chunk_rows(P.Nt, P.G, blk, RPP, r0, r1);
   DevPtr<Rec<real>> __restrict__ rec = P.rec[C->pcur];
   for (int base = r0; base < r1; base += RPP) {
     const int i = base + threadIdx.x;
@@ -267,10 +278,10 @@ __device__ void phase_cg0(const ProbDev<real>& P, const Ctrl* C, int t, double* 
 // r_j - alpha (w_j + beta s_j), so the sweep needs no grid-wide barrier
 // between the vector updates and w = L D^-1 r.
 template <typename real, int LPR>
-__device__ void phase_cg(const ProbDev<real>& P, const Ctrl* C, int t, double* acc) {
+__device__ void phase_cg(const ProbDev<real>& P, const Ctrl* C, int blk, double* acc) {
   constexpr int RPP = kBlock;
   int r0, r1;
-  chunk_rows(P.Nt, P.G, t, RPP, r0, r1);
+  chunk_rows(P.Nt, P.G, blk, RPP, r0, r1);
   const int c = C->pcur;
   const real alpha = real(C->alpha), beta = real(C->beta);
   DevPtr<const Rec<real>> __restrict__ ro = P.rec[c];
@@ -346,12 +357,11 @@ __device__ __forceinline__ real row_sum(DevPtr<const int> __restrict__ rp, DevPt
 // skipped: the operation that produces x_{l+1} (POST(l + 1), or SOLVE) also
 // writes xa_l = wd b + P x_{l+1} for the members of each aggregate it owns
 // (row I of R_l lists them), so no index is gathered twice.
-// W lanes share a row: the kernel's LPR, or 16 on levels whose rows are
-// long; W = 1 (one thread per row) reads the operation's matrix from its
-// sliced copy, which matrices with many rows have (the level-0 operator is
-// the potential matrix).
-// entries per lane per batch: 8 for the 8- and 16-lane rows of long-row
-// matrices (one batch covers 64 or 128 entries)
+// W lanes share a row (4, 8 or 16, chosen per matrix by the host); W = 1
+// (one thread per row) reads the operation's matrix from its sliced copy,
+// which matrices with many rows have (the level-0 operator is the potential
+// matrix).  A lane loads 8 entries per batch with 8 or 16 lanes (matrices
+// with long rows), kUnroll with 4.
 template <int W>
 constexpr int kRowU = W >= 8 ? 8 : kUnroll;
 
@@ -372,7 +382,7 @@ __device__ __forceinline__ real r_row(DevRef<const MgLevelDev<real>> L, int i, i
 }
 
 template <typename real, int W>
-__device__ void mg_rows(const ProbDev<real>& P, const Ctrl* C, DevRef<const MgLevelDev<real>> L, int op, int l, int t,
+__device__ void mg_rows(const ProbDev<real>& P, const Ctrl* C, DevRef<const MgLevelDev<real>> L, int op, int l, int blk,
                         double* acc) {
   constexpr int RPP = kBlock / W;
   const int lane = threadIdx.x & (W - 1);
@@ -387,7 +397,7 @@ __device__ void mg_rows(const ProbDev<real>& P, const Ctrl* C, DevRef<const MgLe
     DevPtr<real> __restrict__ wbn = last ? nullptr : P.lev[l + 1].wb;
     DevPtr<const real> __restrict__ wdn = last ? nullptr : P.lev[l + 1].wd;
     DevPtr<const real> __restrict__ res = L.res;
-    chunk_rows(L.n_next, P.G, t, RPP, r0, r1);
+    chunk_rows(L.n_next, P.G, blk, RPP, r0, r1);
     for (int base = r0; base < r1; base += RPP) {
       const int i = base + slot;
       const bool valid = i < r1;
@@ -401,7 +411,7 @@ __device__ void mg_rows(const ProbDev<real>& P, const Ctrl* C, DevRef<const MgLe
     }
     return;
   }
-  chunk_rows(L.n, P.G, t, RPP, r0, r1);
+  chunk_rows(L.n, P.G, blk, RPP, r0, r1);
   if (op == MG_DOWN) {
     for (int base = r0; base < r1; base += RPP) {
       const int i = base + slot;
@@ -464,7 +474,7 @@ __device__ void mg_rows(const ProbDev<real>& P, const Ctrl* C, DevRef<const MgLe
 }
 
 template <typename real, int LPR>
-__device__ void phase_mg(const ProbDev<real>& P, const Ctrl* C, int t, double* acc) {
+__device__ void phase_mg(const ProbDev<real>& P, const Ctrl* C, int blk, double* acc) {
   const int op = C->mg_op, l = C->mg_lev;
   if (op == MG_SOLVE) {
     // dense coarsest solve: one row per block at a time, the whole block
@@ -473,7 +483,7 @@ __device__ void phase_mg(const ProbDev<real>& P, const Ctrl* C, int t, double* a
     const int nc = P.nc;
     DevRef<const MgLevelDev<real>> F = P.lev[P.n_lev - 1];
     const int wid = threadIdx.x >> 6, lid = threadIdx.x & 63;
-    for (int i = t; i < nc; i += P.G) {
+    for (int i = blk; i < nc; i += P.G) {
       DevPtr<const real> __restrict__ row = P.Ainv + (size_t)i * nc;
       double sum = 0;
       for (int j = threadIdx.x; j < nc; j += kBlock) sum += (double)(row[j] * P.bc[j]);
@@ -499,13 +509,13 @@ __device__ void phase_mg(const ProbDev<real>& P, const Ctrl* C, int t, double* a
   const int lanes = op == MG_REST ? L.lanes_r : op == MG_PROL ? L.lanes_p : L.lanes_a;
   const bool sliced = op == MG_REST ? L.rso != nullptr : op == MG_PROL ? L.pso != nullptr : L.aso != nullptr;
   if (sliced)
-    mg_rows<real, 1>(P, C, L, op, l, t, acc);
+    mg_rows<real, 1>(P, C, L, op, l, blk, acc);
   else if (lanes == 16)
-    mg_rows<real, 16>(P, C, L, op, l, t, acc);
+    mg_rows<real, 16>(P, C, L, op, l, blk, acc);
   else if (lanes == 8)
-    mg_rows<real, 8>(P, C, L, op, l, t, acc);
+    mg_rows<real, 8>(P, C, L, op, l, blk, acc);
   else
-    mg_rows<real, LPR>(P, C, L, op, l, t, acc);
+    mg_rows<real, 4>(P, C, L, op, l, blk, acc);
 }
 
 // PCG_A: p = z + beta p_old (recomputed at gathered neighbours from the
@@ -513,10 +523,10 @@ __device__ void phase_mg(const ProbDev<real>& P, const Ctrl* C, int t, double* a
 // p itself is stored by PCG_B, which gathers no {z, p} record.  One thread
 // per row.
 template <typename real, int LPR>
-__device__ void phase_pcg_a(const ProbDev<real>& P, const Ctrl* C, int t, double* acc) {
+__device__ void phase_pcg_a(const ProbDev<real>& P, const Ctrl* C, int blk, double* acc) {
   constexpr int RPP = kBlock;
   int r0, r1;
-  chunk_rows(P.Nt, P.G, t, RPP, r0, r1);
+  chunk_rows(P.Nt, P.G, blk, RPP, r0, r1);
   const real beta = real(C->beta);
   const bool first = C->beta == 0.0;
   DevPtr<const Pair<real>> __restrict__ zp = P.zp;
@@ -545,10 +555,10 @@ __device__ void phase_pcg_a(const ProbDev<real>& P, const Ctrl* C, int t, double
 // with neighbours' wd r_new recomputed from their {wd r, wd q} records.
 // Partials: r.r, r.u.  One thread per row.
 template <typename real, int LPR>
-__device__ void phase_pcg_b(const ProbDev<real>& P, const Ctrl* C, int t, double* acc) {
+__device__ void phase_pcg_b(const ProbDev<real>& P, const Ctrl* C, int blk, double* acc) {
   constexpr int RPP = kBlock;
   int r0, r1;
-  chunk_rows(P.Nt, P.G, t, RPP, r0, r1);
+  chunk_rows(P.Nt, P.G, blk, RPP, r0, r1);
   const real alpha = real(C->alpha), beta = real(C->beta);
   const bool first = C->beta == 0.0;
   DevPtr<Pair<real>> __restrict__ zp = P.zp;
@@ -579,13 +589,13 @@ __device__ void phase_pcg_b(const ProbDev<real>& P, const Ctrl* C, int t, double
 
 // ---- FIELD: effective field, torque, fused reductions ----
 template <typename real, int LPR>
-__device__ void phase_field(const ProbDev<real>& P, const Ctrl* C, int t, double* acc) {
+__device__ void phase_field(const ProbDev<real>& P, const Ctrl* C, int blk, double* acc) {
   constexpr int RPP = kBlock / LPR;
   constexpr int kU = kUnrollWide<real>;
   const int lane = threadIdx.x & (LPR - 1);
   const int slot = threadIdx.x / LPR;
   int r0, r1;
-  chunk_rows(P.N, P.G, t, RPP, r0, r1);
+  chunk_rows(P.N, P.G, blk, RPP, r0, r1);
   const int a = C->acc, tr = 1 - a;
   const int terms = C->terms;
   const bool exch = terms & MMSD_EXCH, anis = terms & MMSD_ANIS, zeem = terms & MMSD_ZEEM;
@@ -1019,19 +1029,19 @@ __device__ void reduce_partials(DevPtr<const double> src, int G, int np, int pha
 // by the kernel boundary.  The accumulators live only inside one phase, so
 // each phase is register-allocated on its own.
 template <typename real, int LPR, int PHASE>
-__device__ __forceinline__ void run_phase(const ProbDev<real>& P, const Ctrl* C, int t, int lb, int parity,
+__device__ __forceinline__ void run_phase(const ProbDev<real>& P, const Ctrl* C, int lb, int parity,
                                           double (*s_red)[kNPart]) {
   constexpr int NA = PHASE == PH_FIELD ? kNPart : PHASE == PH_PREP ? 3 : PHASE == PH_MG ? 1 : 4;
   double acc[NA];
 #pragma unroll
   for (int k = 0; k < NA; ++k) acc[k] = 0.0;
-  if constexpr (PHASE == PH_PREP) phase_prep<real, LPR>(P, C, t, acc);
-  else if constexpr (PHASE == PH_CG0) phase_cg0<real, LPR>(P, C, t, acc);
-  else if constexpr (PHASE == PH_CG) phase_cg<real, LPR>(P, C, t, acc);
-  else if constexpr (PHASE == PH_FIELD) phase_field<real, LPR>(P, C, t, acc);
-  else if constexpr (PHASE == PH_MG) phase_mg<real, LPR>(P, C, t, acc);
-  else if constexpr (PHASE == PH_PCG_A) phase_pcg_a<real, LPR>(P, C, t, acc);
-  else phase_pcg_b<real, LPR>(P, C, t, acc);
+  if constexpr (PHASE == PH_PREP) phase_prep<real, LPR>(P, C, lb, acc);
+  else if constexpr (PHASE == PH_CG0) phase_cg0<real, LPR>(P, C, lb, acc);
+  else if constexpr (PHASE == PH_CG) phase_cg<real, LPR>(P, C, lb, acc);
+  else if constexpr (PHASE == PH_FIELD) phase_field<real, LPR>(P, C, lb, acc);
+  else if constexpr (PHASE == PH_MG) phase_mg<real, LPR>(P, C, lb, acc);
+  else if constexpr (PHASE == PH_PCG_A) phase_pcg_a<real, LPR>(P, C, lb, acc);
+  else phase_pcg_b<real, LPR>(P, C, lb, acc);
 
   const int np = n_parts(PHASE, C->mg_op, C->mg_lev);
   if (np == 0) return;
@@ -1110,29 +1120,28 @@ __global__ void __launch_bounds__(kBlock, 5) k_step(const ProbDev<real>* __restr
   }
   const int phase = s_c.phase;
   if (!is_work(phase)) return;
-  const int t = (lb & 7) * (P.G >> 3) + (lb >> 3);
 
   switch (phase) {
     case PH_PREP:
-      run_phase<real, LPR, PH_PREP>(P, &s_c, t, lb, parity, s_red);
+      run_phase<real, LPR, PH_PREP>(P, &s_c, lb, parity, s_red);
       break;
     case PH_CG0:
-      run_phase<real, LPR, PH_CG0>(P, &s_c, t, lb, parity, s_red);
+      run_phase<real, LPR, PH_CG0>(P, &s_c, lb, parity, s_red);
       break;
     case PH_CG:
-      run_phase<real, LPR, PH_CG>(P, &s_c, t, lb, parity, s_red);
+      run_phase<real, LPR, PH_CG>(P, &s_c, lb, parity, s_red);
       break;
     case PH_FIELD:
-      run_phase<real, LPR, PH_FIELD>(P, &s_c, t, lb, parity, s_red);
+      run_phase<real, LPR, PH_FIELD>(P, &s_c, lb, parity, s_red);
       break;
     case PH_MG:
-      run_phase<real, LPR, PH_MG>(P, &s_c, t, lb, parity, s_red);
+      run_phase<real, LPR, PH_MG>(P, &s_c, lb, parity, s_red);
       break;
     case PH_PCG_A:
-      run_phase<real, LPR, PH_PCG_A>(P, &s_c, t, lb, parity, s_red);
+      run_phase<real, LPR, PH_PCG_A>(P, &s_c, lb, parity, s_red);
       break;
     case PH_PCG_B:
-      run_phase<real, LPR, PH_PCG_B>(P, &s_c, t, lb, parity, s_red);
+      run_phase<real, LPR, PH_PCG_B>(P, &s_c, lb, parity, s_red);
       break;
   }
 }
