@@ -316,8 +316,8 @@ bool amg_setup(const Csr& A0, const AmgParams& prm, AmgHierarchy* h) {
       L.P = std::move(T);
     }
     L.R = transpose(L.P);
-    Csr AP = spgemm(A, L.P);
-    Csr Ac = spgemm(L.R, AP);
+    L.AP = spgemm(A, L.P);
+    Csr Ac = spgemm(L.R, L.AP);
     L.A = std::move(A);
     h->lv.push_back(std::move(L));
     A = std::move(Ac);

@@ -1,6 +1,7 @@
 // Host setup of the algebraic multigrid preconditioner for the scalar-potential
-// solve: smoothed aggregation on the finest level, plain aggregation below,
-// Galerkin coarse operators, dense inverse on the coarsest level.
+// solve: smoothed aggregation (Jacobi-smoothed prolongation on the first
+// `smooth_levels` levels, plain aggregation below), Galerkin coarse
+// operators, dense inverse on the coarsest level.
 #pragma once
 #include <vector>
 
@@ -18,6 +19,7 @@ struct AmgLevel {
   double omega = 0;        // Jacobi smoothing weight 4 / (3 rho(D^-1 A))
   Csr P;                   // prolongation to this level from the next coarser one
   Csr R;                   // restriction, the transpose of P
+  Csr AP;                  // A P (formed for the Galerkin product; post-smoothing sweeps it)
 };
 
 struct AmgHierarchy {

@@ -140,13 +140,14 @@ constexpr int kSlicedRows = 65536;
 
 // 64-row sliced layout of a CSR matrix: slice s holds rows 64s..64s+63,
 // entry k of row i at so[s] + 64 k + (i mod 64); short rows are padded with
-// their own column (clamped to the column range) and a zero value.
+// their own column (clamped to the column range) and zero values.  Entries
+// carry vw values each (v and sv hold vw consecutive values per entry).
 struct Sliced {
   std::vector<int> so, sc;
   std::vector<double> sv;
 };
 Sliced make_sliced(const std::vector<int>& rp, const std::vector<int>& ci, const std::vector<double>& v,
-                   int ncols) {
+                   int ncols, int vw = 1) {
   const int64_t n = (int64_t)rp.size() - 1, ns = (n + 63) / 64;
   Sliced S;
   S.so.assign(ns + 1, 0);
@@ -156,7 +157,7 @@ Sliced make_sliced(const std::vector<int>& rp, const std::vector<int>& ci, const
     S.so[sl + 1] = S.so[sl] + 64 * w;
   }
   S.sc.assign(S.so[ns], 0);
-  S.sv.assign(S.so[ns], 0.0);
+  S.sv.assign((size_t)vw * S.so[ns], 0.0);
   for (int64_t sl = 0; sl < ns; ++sl) {
     const int w = (S.so[sl + 1] - S.so[sl]) / 64;
     for (int r = 0; r < 64; ++r) {
@@ -166,7 +167,7 @@ Sliced make_sliced(const std::vector<int>& rp, const std::vector<int>& ci, const
         const int64_t q = S.so[sl] + 64LL * k + r;
         if (k < len) {
           S.sc[q] = ci[rp[i] + k];
-          S.sv[q] = v[rp[i] + k];
+          for (int t = 0; t < vw; ++t) S.sv[vw * q + t] = v[(size_t)vw * (rp[i] + k) + t];
         } else {
           S.sc[q] = (int)std::min<int64_t>(i, ncols - 1);
         }
@@ -176,12 +177,33 @@ Sliced make_sliced(const std::vector<int>& rp, const std::vector<int>& ci, const
   return S;
 }
 
-// P is plain aggregation: every row holds a single entry 1 (the post-smoothing
-// of such a level recomputes the prolongation where it gathers).
-static bool plain_prolongation(const Csr& P) {
-  for (int i = 0; i < P.nrows; ++i)
-    if (P.rp[i + 1] - P.rp[i] != 1 || P.v[P.rp[i]] != 1.0) return false;
-  return true;
+// The matrix the fused prolongation and post-smoothing sweeps: the union of
+// the patterns of A P and P (P's lies inside A P's when A's diagonal is
+// stored) with the value pairs {(A P)_ik, P_ik}, two values per entry in v.
+Csr fused_q(const Csr& AP, const Csr& P) {
+  Csr Q;
+  Q.nrows = AP.nrows;
+  Q.ncols = AP.ncols;
+  Q.rp.assign(Q.nrows + 1, 0);
+  std::vector<int> ci;
+  std::vector<double> v;
+  ci.reserve(AP.ci.size());
+  v.reserve(2 * AP.ci.size());
+  for (int i = 0; i < Q.nrows; ++i) {
+    int a = AP.rp[i], b = P.rp[i];
+    const int ae = AP.rp[i + 1], be = P.rp[i + 1];
+    while (a < ae || b < be) {   // both rows sorted by column
+      const int ca = a < ae ? AP.ci[a] : INT32_MAX, cb = b < be ? P.ci[b] : INT32_MAX;
+      const int c = std::min(ca, cb);
+      ci.push_back(c);
+      v.push_back(ca == c ? AP.v[a++] : 0.0);
+      v.push_back(cb == c ? P.v[b++] : 0.0);
+    }
+    Q.rp[i + 1] = (int)ci.size();
+  }
+  Q.ci = std::move(ci);
+  Q.v = std::move(v);
+  return Q;
 }
 
 // Algorithmic bytes per executed phase: every matrix entry, index and
@@ -205,25 +227,16 @@ void bytes_model(mmsd_problem p) {
     for (size_t l = 0; l < H.lv.size(); ++l) {
       const AmgLevel& L = H.lv[l];
       const double n = L.A.nrows, nn = L.P.ncols;
-      const double zA = (double)L.A.ci.size(), zP = (double)L.P.ci.size();
-      const double spA = 4 * (n + 1) + (4 + s) * zA, spP = 4 * (n + 1) + (4 + s) * zP, spR = 4 * (nn + 1) + (4 + s) * zP;
+      const double zA = (double)L.A.ci.size(), zP = (double)L.P.ci.size(), zQ = (double)p->amg_q_nnz[l];
+      const double spA = 4 * (n + 1) + (4 + s) * zA, spR = 4 * (nn + 1) + (4 + s) * zP;
+      const double spQ = 4 * (n + 1) + (4 + 2 * s) * zQ;
       b[byte_slot(PH_MG, MG_DOWN, (int)l)] = spA + 3 * s * n;     // b, wd in; res out
       b[byte_slot(PH_MG, MG_REST, (int)l)] = spR + s * n + s * nn;   // res in; b out
       if (l + 1 < H.lv.size()) b[byte_slot(PH_MG, MG_REST, (int)l)] += 2 * s * nn;   // wd in; wd b out
-      b[byte_slot(PH_MG, MG_PROL, (int)l)] = spP + 3 * s * n + s * nn;
-      b[byte_slot(PH_MG, MG_POST, (int)l)] = spA + 4 * s * n;     // xa, b, wd in; xb out
+      b[byte_slot(PH_MG, MG_POST, (int)l)] = spQ + s * nn + 4 * s * n;   // x_{l+1}, b, wd, res in; xb out
       if (l == 0) b[byte_slot(PH_MG, MG_POST, 0)] += 2 * s * n;     // p carried over into the {z, p} records
     }
     b[byte_slot(PH_MG, MG_SOLVE, 0)] = s * (double)H.nc * (H.nc + 2);
-    // a plain level's xa is written by the operation that produces the
-    // coarser solution (POST of the level below, or SOLVE)
-    for (size_t l = 0; l < H.lv.size(); ++l) {
-      const AmgLevel& L = H.lv[l];
-      if (!plain_prolongation(L.P)) continue;
-      const double n = L.A.nrows, nn = L.P.ncols;
-      const double sc = 4 * (nn + 1) + (4 + s) * (double)L.P.ci.size() + 2 * s * n;   // R rows, wd b in; xa out
-      b[l + 1 < H.lv.size() ? byte_slot(PH_MG, MG_POST, (int)l + 1) : byte_slot(PH_MG, MG_SOLVE, 0)] += sc;
-    }
   }
   p->phase_bytes_h = 3 * s * N;
   p->prep_bytes_nodemag = 9 * s * N;
@@ -247,17 +260,24 @@ int build_amg(mmsd_problem p) {
     off.push_back(at);
     return at;
   };
-  struct LvOff { size_t arp, aci, av, wd, prp, pci, pv, rrp, rci, rv, b, wb, res, xa, xb, sl[3][3]; };
+  struct LvOff { size_t arp, aci, av, wd, qrp, qci, qv, rrp, rci, rv, b, wb, res, xb, sl[3][3]; };
   std::vector<LvOff> lo(nl);
-  // sliced copies (A of levels >= 1, P, R) of the matrices with many rows
+  // the fused prolongation / post-smoothing matrices (two values per entry)
+  std::vector<Csr> Q(nl);
+  p->amg_q_nnz.assign(nl, 0);
+  for (int l = 0; l < nl; ++l) {
+    Q[l] = fused_q(H.lv[l].AP, H.lv[l].P);
+    p->amg_q_nnz[l] = (int64_t)Q[l].ci.size();
+  }
+  // sliced copies (A of levels >= 1, Q, R) of the matrices with many rows
   std::vector<std::array<Sliced, 3>> sl(nl);
   for (int l = 0; l < nl; ++l) {
     const AmgLevel& L = H.lv[l];
-    const Csr* M[3] = {&L.A, &L.P, &L.R};
+    const Csr* M[3] = {&L.A, &Q[l], &L.R};
     for (int k = 0; k < 3; ++k) {
       if ((k == 0 && l == 0) || M[k]->nrows < kSlicedRows || M[k]->ci.size() > kWideRow * (size_t)M[k]->nrows)
         continue;
-      sl[l][k] = make_sliced(M[k]->rp, M[k]->ci, M[k]->v, M[k]->ncols);
+      sl[l][k] = make_sliced(M[k]->rp, M[k]->ci, M[k]->v, M[k]->ncols, k == 1 ? 2 : 1);
       if ((int64_t)sl[l][k].so.back() >= (int64_t)1 << 30) return invalid("multigrid matrix too large to slice");
     }
   }
@@ -271,22 +291,26 @@ int build_amg(mmsd_problem p) {
       lo[l].sl[k][1] = take(4 * S.sc.size());
       lo[l].sl[k][2] = take(s * S.sv.size());
     }
-    if (l > 0) {
+    // CSR copies only of the matrices without a sliced one
+    if (l > 0 && sl[l][0].so.empty()) {
       lo[l].arp = take(4 * (n + 1));
       lo[l].aci = take(4 * L.A.ci.size());
       lo[l].av = take(s * L.A.ci.size());
     }
+    if (sl[l][1].so.empty()) {
+      lo[l].qrp = take(4 * (n + 1));
+      lo[l].qci = take(4 * Q[l].ci.size());
+      lo[l].qv = take(2 * s * Q[l].ci.size());
+    }
+    if (sl[l][2].so.empty()) {
+      lo[l].rrp = take(4 * (nn + 1));
+      lo[l].rci = take(4 * L.R.ci.size());
+      lo[l].rv = take(s * L.R.ci.size());
+    }
     lo[l].wd = take(s * n);
-    lo[l].prp = take(4 * (n + 1));
-    lo[l].pci = take(4 * L.P.ci.size());
-    lo[l].pv = take(s * L.P.ci.size());
-    lo[l].rrp = take(4 * (nn + 1));
-    lo[l].rci = take(4 * L.R.ci.size());
-    lo[l].rv = take(s * L.R.ci.size());
     lo[l].b = take(s * n);
     lo[l].wb = take(s * n);
     lo[l].res = take(s * n);
-    lo[l].xa = take(s * n);
     lo[l].xb = take(s * n);
   }
   const size_t o_ainv = take(s * (size_t)H.nc * H.nc), o_bc = take(s * H.nc), o_xc = take(s * H.nc);
@@ -310,16 +334,17 @@ int build_amg(mmsd_problem p) {
     const AmgLevel& L = H.lv[l];
     std::vector<double> wd(L.dinv.size());
     for (size_t i = 0; i < wd.size(); ++i) wd[i] = L.omega * L.dinv[i];
-    if (l > 0) {
-      if ((rc = upload_int(st, base + lo[l].arp, L.A.rp)) || (rc = upload_int(st, base + lo[l].aci, L.A.ci)) ||
-          (rc = upload_vec<real>(st, base + lo[l].av, L.A.v)))
-        return rc;
-    }
-    if ((rc = upload_vec<real>(st, base + lo[l].wd, wd)) || (rc = upload_int(st, base + lo[l].prp, L.P.rp)) ||
-        (rc = upload_int(st, base + lo[l].pci, L.P.ci)) || (rc = upload_vec<real>(st, base + lo[l].pv, L.P.v)) ||
-        (rc = upload_int(st, base + lo[l].rrp, L.R.rp)) || (rc = upload_int(st, base + lo[l].rci, L.R.ci)) ||
-        (rc = upload_vec<real>(st, base + lo[l].rv, L.R.v)))
+    const bool csr[3] = {l > 0 && sl[l][0].so.empty(), sl[l][1].so.empty(), sl[l][2].so.empty()};
+    if (csr[0] && ((rc = upload_int(st, base + lo[l].arp, L.A.rp)) || (rc = upload_int(st, base + lo[l].aci, L.A.ci)) ||
+                   (rc = upload_vec<real>(st, base + lo[l].av, L.A.v))))
       return rc;
+    if (csr[1] && ((rc = upload_int(st, base + lo[l].qrp, Q[l].rp)) || (rc = upload_int(st, base + lo[l].qci, Q[l].ci)) ||
+                   (rc = upload_vec<real>(st, base + lo[l].qv, Q[l].v))))
+      return rc;
+    if (csr[2] && ((rc = upload_int(st, base + lo[l].rrp, L.R.rp)) || (rc = upload_int(st, base + lo[l].rci, L.R.ci)) ||
+                   (rc = upload_vec<real>(st, base + lo[l].rv, L.R.v))))
+      return rc;
+    if ((rc = upload_vec<real>(st, base + lo[l].wd, wd))) return rc;
     const int* so[3] = {nullptr, nullptr, nullptr};
     const int* sc[3] = {nullptr, nullptr, nullptr};
     const real* sv[3] = {nullptr, nullptr, nullptr};
@@ -342,40 +367,36 @@ int build_amg(mmsd_problem p) {
     d.aso = so[0];
     d.asc = sc[0];
     d.asv = sv[0];
-    d.pso = so[1];
-    d.psc = sc[1];
-    d.psv = sv[1];
+    d.qso = so[1];
+    d.qsc = sc[1];
+    d.qsv = reinterpret_cast<const Pair<real>*>(sv[1]);
     d.rso = so[2];
     d.rsc = sc[2];
     d.rsv = sv[2];
     d.n = L.A.nrows;
     d.n_next = L.P.ncols;
-    d.plain = plain_prolongation(L.P) ? 1 : 0;
     d.lanes_a = row_lanes(L.A);
-    d.lanes_p = row_lanes(L.P);
+    d.lanes_q = row_lanes(Q[l]);
     d.lanes_r = row_lanes(L.R);
-    d.arp = l == 0 ? nullptr : (const int*)(base + lo[l].arp);
-    d.aci = l == 0 ? nullptr : (const int*)(base + lo[l].aci);
-    d.av = l == 0 ? nullptr : (const real*)(base + lo[l].av);
+    d.arp = csr[0] ? (const int*)(base + lo[l].arp) : nullptr;
+    d.aci = csr[0] ? (const int*)(base + lo[l].aci) : nullptr;
+    d.av = csr[0] ? (const real*)(base + lo[l].av) : nullptr;
+    d.qrp = csr[1] ? (const int*)(base + lo[l].qrp) : nullptr;
+    d.qci = csr[1] ? (const int*)(base + lo[l].qci) : nullptr;
+    d.qv = csr[1] ? (const Pair<real>*)(base + lo[l].qv) : nullptr;
+    d.rrp = csr[2] ? (const int*)(base + lo[l].rrp) : nullptr;
+    d.rci = csr[2] ? (const int*)(base + lo[l].rci) : nullptr;
+    d.rv = csr[2] ? (const real*)(base + lo[l].rv) : nullptr;
     d.wd = (const real*)(base + lo[l].wd);
-    d.prp = (const int*)(base + lo[l].prp);
-    d.pci = (const int*)(base + lo[l].pci);
-    d.pv = (const real*)(base + lo[l].pv);
-    d.rrp = (const int*)(base + lo[l].rrp);
-    d.rci = (const int*)(base + lo[l].rci);
-    d.rv = (const real*)(base + lo[l].rv);
     d.b = (real*)(base + lo[l].b);
     d.wb = (real*)(base + lo[l].wb);
     d.res = (real*)(base + lo[l].res);
-    d.xa = (real*)(base + lo[l].xa);
     d.xb = (real*)(base + lo[l].xb);
   }
   if ((rc = upload_vec<real>(st, base + o_ainv, H.Ainv))) return rc;
   MMSD_HIP(hipMemcpyAsync(base + o_lev, lv.data(), sizeof(MgLevel<real>) * nl, hipMemcpyHostToDevice, st));
   MMSD_HIP(hipStreamSynchronize(st));
   P.n_lev = nl;
-  P.mg_plain = 0;
-  for (int l = 0; l < nl; ++l) P.mg_plain |= lv[l].plain << l;
   P.nc = H.nc;
   P.lev = (const MgLevel<real>*)(base + o_lev);
   P.Ainv = (const real*)(base + o_ainv);

@@ -43,7 +43,7 @@ enum Phase : int {
   PH_PCG_A = 8,  // AMG-preconditioned CG: p = z + beta p, q = L p, p.q
   PH_PCG_B = 9   // u += alpha p, r -= alpha q, and the finest pre-smoothing residual
 };
-enum MgOp : int { MG_DOWN = 0, MG_REST = 1, MG_SOLVE = 2, MG_PROL = 3, MG_POST = 4 };
+enum MgOp : int { MG_DOWN = 0, MG_REST = 1, MG_SOLVE = 2, MG_POST = 3 };
 enum Precond : int { PC_AUTO = 0, PC_JACOBI = 1, PC_AMG = 2 };
 constexpr int kMaxLevels = 12;
 enum Stage : int { ST_INIT = 0, ST_RUN = 1, ST_EVAL = 2 };
@@ -117,33 +117,32 @@ using DevRef = __attribute__((address_space(1))) T&;
 template <typename real, template <typename> class Ptr>
 struct MgLevelT {
   int n, n_next;
-  int plain;               // P is plain aggregation: row i holds a single 1 in column pci[i]
-  int lanes_a, lanes_p, lanes_r;   // lanes per row for A, P, R in CSR: 4, 8 or 16
+  int lanes_a, lanes_q, lanes_r;   // lanes per row for A, Q, R in CSR: 4, 8 or 16
+  int pad;
   Ptr<const int> arp;
   Ptr<const int> aci;
   Ptr<const real> av;
   Ptr<const real> wd;
-  Ptr<const int> prp;          // P: n x n_next
-  Ptr<const int> pci;
-  Ptr<const real> pv;
+  Ptr<const int> qrp;          // Q: n x n_next, the pattern of A P with value pairs {(A P)_ik, P_ik}
+  Ptr<const int> qci;
+  Ptr<const Pair<real>> qv;
   Ptr<const int> rrp;          // R = P^T: n_next x n
   Ptr<const int> rci;
   Ptr<const real> rv;
-  // sliced copies (64-row slices, as the potential matrix) of A, P and R;
+  // sliced copies (64-row slices, as the potential matrix) of A, Q and R;
   // null when the matrix has too few rows to fill the GPU one row per thread
   Ptr<const int> aso;
   Ptr<const int> asc;
   Ptr<const real> asv;
-  Ptr<const int> pso;
-  Ptr<const int> psc;
-  Ptr<const real> psv;
+  Ptr<const int> qso;
+  Ptr<const int> qsc;
+  Ptr<const Pair<real>> qsv;
   Ptr<const int> rso;
   Ptr<const int> rsc;
   Ptr<const real> rsv;
   Ptr<real> b;                 // right-hand side (level 0 uses the CG residual)
   Ptr<real> wb;                // wd b (levels >= 1), written with b
   Ptr<real> res;               // residual after pre-smoothing
-  Ptr<real> xa;                // after prolongation of the coarse correction
   Ptr<real> xb;                // after post-smoothing (level 0: the preconditioned residual z)
 };
 
@@ -157,7 +156,7 @@ struct __align__(4 * sizeof(real)) Rec {
 
 // Index of a phase in the per-problem byte table: plain phases by number,
 // V-cycle operations by (op, level).
-constexpr int kByteSlots = 16 + 5 * kMaxLevels;
+constexpr int kByteSlots = 16 + 4 * kMaxLevels;
 __host__ __device__ inline int byte_slot(int phase, int op, int lev) {
   return phase == PH_MG ? 16 + op * kMaxLevels + lev : phase;
 }
@@ -187,7 +186,6 @@ struct ProbT {
   Ptr<Rec<real>> rec[2];      // CG state by buffer parity (pcur)
   // multigrid-preconditioned CG (absent when n_lev == 0)
   int n_lev;              // levels with a coarser level below them
-  int mg_plain;           // bit l: level l's P is plain aggregation (see MgLevel::plain)
   int nc;                 // size of the coarsest level
   Ptr<const MgLevelT<real, Ptr>> lev;
   Ptr<const real> Ainv;       // dense inverse of the coarsest operator, row-major nc x nc

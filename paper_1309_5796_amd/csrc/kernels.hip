@@ -169,6 +169,38 @@ __device__ __forceinline__ real sell_row(DevPtr<const int> so, DevPtr<const int>
   return acc;
 }
 
+// The same over a sliced matrix with two values per entry {a, b}: returns
+// {sum a * g, sum b * g} from one gather per entry.
+template <typename real, typename G>
+__device__ __forceinline__ Pair<real> sell_row2(DevPtr<const int> so, DevPtr<const int> sc,
+                                                DevPtr<const Pair<real>> sv, int i, G&& g) {
+  const int sl = __builtin_amdgcn_readfirstlane(i >> 6);
+  const int o0 = so[sl];
+  const int w = (so[sl + 1] - o0) >> 6;
+  const int o = o0 + (i & 63);
+  real sa = 0, sb = 0;
+  for (int k0 = 0; k0 < w; k0 += kSellU) {
+    int j[kSellU];
+    Pair<real> v[kSellU];
+#pragma unroll
+    for (int u = 0; u < kSellU; ++u) {
+      const bool ok = k0 + u < w;
+      const int q = o + 64 * (ok ? k0 + u : 0);
+      j[u] = sc[q];
+      v[u] = ok ? ld<real>(sv, q) : Pair<real>{0, 0};
+    }
+    real x[kSellU];
+#pragma unroll
+    for (int u = 0; u < kSellU; ++u) x[u] = g(j[u]);
+#pragma unroll
+    for (int u = 0; u < kSellU; ++u) {
+      sa += v[u].a * x[u];
+      sb += v[u].b * x[u];
+    }
+  }
+  return Pair<real>{sa, sb};
+}
+
 // ... over row i of the potential matrix
 template <typename real, typename G>
 __device__ __forceinline__ real sell_sum(const ProbDev<real>& P, int i, G&& g) {
@@ -343,20 +375,49 @@ __device__ __forceinline__ real row_sum(DevPtr<const int> __restrict__ rp, DevPt
   return acc;
 }
 
+// The same over a matrix with two values per entry {a, b}: returns
+// {sum a * g, sum b * g} from one gather per entry.
+template <typename real, int LPR, int U, typename G>
+__device__ __forceinline__ Pair<real> row_sum2(DevPtr<const int> __restrict__ rp, DevPtr<const int> __restrict__ ci,
+                                               DevPtr<const Pair<real>> __restrict__ v, int i, int lane, G&& g) {
+  real sa = 0, sb = 0;
+  const int ke = rp[i + 1];
+  for (int k0 = rp[i] + lane; k0 < ke; k0 += U * LPR) {
+    int j[U];
+    Pair<real> lv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u * LPR;
+      const int ks = k < ke ? k : k0;
+      j[u] = ci[ks];
+      lv[u] = k < ke ? ld<real>(v, ks) : Pair<real>{0, 0};
+    }
+    real x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) x[u] = g(j[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      sa += lv[u].a * x[u];
+      sb += lv[u].b * x[u];
+    }
+  }
+  return Pair<real>{sa, sb};
+}
+
 // One operation of the symmetric V(1,1) cycle with damped-Jacobi smoothing
 // (x = wd b before the coarse correction, one sweep after it):
 //   DOWN(l)  res = b - A (wd b)
 //   REST(l)  b_{l+1} = R res (and wb_{l+1} = wd_{l+1} b_{l+1}, what DOWN and
 //            POST of level l + 1 gather)
 //   SOLVE    x_c = A_c^-1 b_c (dense)
-//   PROL(l)  xa = wd b + P x_{l+1}
-//   POST(l)  xb = xa + wd (b - A xa); at level 0 the result is z, stored in
-//            the {z, p} records (whole records are written: p is carried
-//            over), and b.z is reduced
-// On a level l whose P is plain aggregation (each row one entry), PROL(l) is
-// skipped: the operation that produces x_{l+1} (POST(l + 1), or SOLVE) also
-// writes xa_l = wd b + P x_{l+1} for the members of each aggregate it owns
-// (row I of R_l lists them), so no index is gathered twice.
+//   POST(l)  coarse correction and post-smoothing in one sweep:
+//            xa = wd b + P x_{l+1}, xb = xa + wd (b - A xa).  Since
+//            A xa = A (wd b) + (A P) x_{l+1} and DOWN left res = b - A (wd b),
+//            xb = xa + wd (res - (A P) x_{l+1}): one sweep of the matrix with
+//            the pattern of A P and the value pairs {(A P)_ik, P_ik} (P's
+//            pattern lies inside A P's) over x_{l+1}.  At level 0 the result
+//            is z, stored in the {z, p} records (whole records are written:
+//            p is carried over), and b.z is reduced.
 // W lanes share a row (4, 8 or 16, chosen per matrix by the host); W = 1
 // (one thread per row) reads the operation's matrix from its sliced copy,
 // which matrices with many rows have (the level-0 operator is the potential
@@ -371,9 +432,9 @@ __device__ __forceinline__ real a_row(DevRef<const MgLevelDev<real>> L, int i, i
   else return row_sum<real, W, kRowU<W>>(L.arp, L.aci, L.av, i, lane, g);
 }
 template <typename real, int W, typename G>
-__device__ __forceinline__ real p_row(DevRef<const MgLevelDev<real>> L, int i, int lane, G&& g) {
-  if constexpr (W == 1) return sell_row<real>(L.pso, L.psc, L.psv, i, g);
-  else return row_sum<real, W, kRowU<W>>(L.prp, L.pci, L.pv, i, lane, g);
+__device__ __forceinline__ Pair<real> q_row(DevRef<const MgLevelDev<real>> L, int i, int lane, G&& g) {
+  if constexpr (W == 1) return sell_row2<real>(L.qso, L.qsc, L.qsv, i, g);
+  else return row_sum2<real, W, kUnroll>(L.qrp, L.qci, L.qv, i, lane, g);   // two values: half the batch
 }
 template <typename real, int W, typename G>
 __device__ __forceinline__ real r_row(DevRef<const MgLevelDev<real>> L, int i, int lane, G&& g) {
@@ -422,51 +483,30 @@ __device__ void mg_rows(const ProbDev<real>& P, const Ctrl* C, DevRef<const MgLe
       sum = group_sum<real, W>(sum);
       if (valid && lane == 0) L.res[i] = bi - sum;
     }
-  } else if (op == MG_PROL) {
-    DevPtr<const real> __restrict__ xn = last ? P.xc : P.lev[l + 1].xb;
-    for (int base = r0; base < r1; base += RPP) {
-      const int i = base + slot;
-      const bool valid = i < r1;
-      const real wbi = (valid && lane == 0) ? wd[i] * b[i] : real(0);
-      real sum = valid ? p_row<real, W>(L, i, lane, [&](int j) { return xn[j]; }) : real(0);
-      sum = group_sum<real, W>(sum);
-      if (valid && lane == 0) L.xa[i] = wbi + sum;
-    }
   } else {   // MG_POST
-    DevPtr<const real> __restrict__ xa = L.xa;
-    // level l - 1 plain: scatter its xa over the members of aggregate i
-    const bool scatter = l > 0 && P.lev[l - 1].plain;
-    DevRef<const MgLevelDev<real>> F = P.lev[l > 0 ? l - 1 : 0];
+    DevPtr<const real> __restrict__ xn = last ? P.xc : P.lev[l + 1].xb;
+    DevPtr<const real> __restrict__ res = L.res;
     for (int base = r0; base < r1; base += RPP) {
       const int i = base + slot;
       const bool valid = i < r1;
-      real bi = 0, wi = 0, xai = 0, pold = 0;
+      real bi = 0, wi = 0, ri = 0, pold = 0;
       if (valid && lane == 0) {
         bi = b[i];
         wi = wd[i];
-        xai = xa[i];
+        ri = res[i];
         if (l == 0) pold = P.zp[i].b;
       }
-      real sum = valid ? a_row<real, W>(L, i, lane, [&](int j) { return xa[j]; }) : real(0);
-      sum = group_sum<real, W>(sum);
-      real zi = 0;
+      Pair<real> sum = valid ? q_row<real, W>(L, i, lane, [&](int j) { return xn[j]; }) : Pair<real>{0, 0};
+      sum.a = group_sum<real, W>(sum.a);
+      sum.b = group_sum<real, W>(sum.b);
       if (valid && lane == 0) {
-        zi = xai + wi * (bi - sum);
+        const real xai = wi * bi + sum.b;
+        const real zi = xai + wi * (ri - sum.a);
         if (l == 0) {
           st<real>(P.zp, i, Pair<real>{zi, pold});
           acc[0] += (double)bi * (double)zi;
         } else {
           L.xb[i] = zi;
-        }
-      }
-      if (scatter) {
-        zi = __shfl(zi, 0, W);
-        if (valid) {
-          for (int k = F.rrp[i] + lane; k < F.rrp[i + 1]; k += W) {
-            const int j = F.rci[k];
-            const real wbj = l == 1 ? F.wd[j] * P.r2[C->rcur][j] : F.wb[j];
-            F.xa[j] = wbj + F.rv[k] * zi;
-          }
         }
       }
     }
@@ -481,7 +521,6 @@ __device__ void phase_mg(const ProbDev<real>& P, const Ctrl* C, int blk, double*
     // streams the row coalesced, then wavefront sums and the waves in order
     __shared__ double s_row[kBlock / 64];
     const int nc = P.nc;
-    DevRef<const MgLevelDev<real>> F = P.lev[P.n_lev - 1];
     const int wid = threadIdx.x >> 6, lid = threadIdx.x & 63;
     for (int i = blk; i < nc; i += P.G) {
       DevPtr<const real> __restrict__ row = P.Ainv + (size_t)i * nc;
@@ -493,21 +532,13 @@ __device__ void phase_mg(const ProbDev<real>& P, const Ctrl* C, int blk, double*
       double v = s_row[0];
       for (int w = 1; w < kBlock / 64; ++w) v += s_row[w];
       if (threadIdx.x == 0) P.xc[i] = real(v);
-      if (F.plain) {   // xa of the last level over the members of aggregate i
-        const real xi = real(v);
-        for (int k = F.rrp[i] + threadIdx.x; k < F.rrp[i + 1]; k += kBlock) {
-          const int j = F.rci[k];
-          const real wbj = P.n_lev == 1 ? F.wd[j] * P.r2[C->rcur][j] : F.wb[j];
-          F.xa[j] = wbj + F.rv[k] * xi;
-        }
-      }
       __syncthreads();
     }
     return;
   }
   DevRef<const MgLevelDev<real>> L = P.lev[l];
-  const int lanes = op == MG_REST ? L.lanes_r : op == MG_PROL ? L.lanes_p : L.lanes_a;
-  const bool sliced = op == MG_REST ? L.rso != nullptr : op == MG_PROL ? L.pso != nullptr : L.aso != nullptr;
+  const int lanes = op == MG_REST ? L.lanes_r : op == MG_POST ? L.lanes_q : L.lanes_a;
+  const bool sliced = op == MG_REST ? L.rso != nullptr : op == MG_POST ? L.qso != nullptr : L.aso != nullptr;
   if (sliced)
     mg_rows<real, 1>(P, C, L, op, l, blk, acc);
   else if (lanes == 16)
@@ -881,7 +912,7 @@ __device__ void step_logic(Ctrl* C, const double* v) {
 
 // Advance the state by the outcome of the phase it records (v: the finished
 // reductions of that phase's partials).
-__device__ void transition(Ctrl* C, const double* v, const double* btab, int n_lev, int plain) {
+__device__ void transition(Ctrl* C, const double* v, const double* btab, int n_lev) {
   C->seq++;
   const int phase = C->phase;
   if (phase == PH_IDLE || phase == PH_DONE) return;
@@ -930,15 +961,11 @@ __device__ void transition(Ctrl* C, const double* v, const double* btab, int n_l
           return;
         case MG_SOLVE:
           C->mg_lev = n_lev - 1;
-          C->mg_op = ((plain >> C->mg_lev) & 1) ? MG_POST : MG_PROL;
-          return;
-        case MG_PROL:
           C->mg_op = MG_POST;
           return;
         default:   // MG_POST
           if (C->mg_lev > 0) {
             C->mg_lev--;
-            C->mg_op = ((plain >> C->mg_lev) & 1) ? MG_POST : MG_PROL;
             return;
           }
           // z = M r is complete: next search direction
@@ -1108,7 +1135,7 @@ __global__ void __launch_bounds__(kBlock, 5) k_step(const ProbDev<real>* __restr
   if (np_prev > 0) reduce_partials(part_prev, P.G, np_prev, ran, pre, s_tot);
   __syncthreads();
   if (threadIdx.x == 0) {
-    transition(&s_c, s_tot, lb == 0 ? s_btab : nullptr, P.n_lev, P.mg_plain);
+    transition(&s_c, s_tot, lb == 0 ? s_btab : nullptr, P.n_lev);
     s_newly_done = (ran != PH_DONE && s_c.phase == PH_DONE);
   }
   __syncthreads();

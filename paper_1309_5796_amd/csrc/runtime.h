@@ -121,6 +121,7 @@ struct mmsd_problem_s {
   // multigrid preconditioner of the potential solve
   bool has_amg = false;
   mmsd::AmgHierarchy amg;                 // host copy (sizes; values uploaded)
+  std::vector<int64_t> amg_q_nnz;         // entries of each level's fused prolongation/smoothing matrix
   char* amg_arena = nullptr;
   size_t amg_bytes = 0;
   mmsd::Ctrl* hctrl = nullptr;            // pinned mirrors [2 polls][2 slots]
