@@ -19,6 +19,7 @@
 #include "amg.h"
 
 #include <algorithm>
+#include <cstdint>
 #include <cmath>
 #include <functional>
 #include <random>
@@ -231,6 +232,32 @@ bool dense_inverse(const Csr& A, std::vector<double>& inv) {
 }
 
 }  // namespace
+
+Csr residual_restriction(const AmgLevel& L) {
+  const Csr T = transpose(L.AP);   // (A P)^T: n_next x n
+  const Csr& R = L.R;
+  Csr M;
+  M.nrows = T.nrows;
+  M.ncols = T.ncols;
+  M.rp.assign(M.nrows + 1, 0);
+  M.ci.reserve(T.ci.size());
+  M.v.reserve(T.ci.size());
+  for (int I = 0; I < M.nrows; ++I) {
+    int a = T.rp[I], b = R.rp[I];
+    const int ae = T.rp[I + 1], be = R.rp[I + 1];
+    while (a < ae || b < be) {   // both rows sorted by column
+      const int ca = a < ae ? T.ci[a] : INT32_MAX, cb = b < be ? R.ci[b] : INT32_MAX;
+      const int c = std::min(ca, cb);
+      double v = 0;
+      if (cb == c) v += R.v[b++];
+      if (ca == c) v -= T.v[a++] * L.omega * L.dinv[c];
+      M.ci.push_back(c);
+      M.v.push_back(v);
+    }
+    M.rp[I + 1] = (int)M.ci.size();
+  }
+  return M;
+}
 
 bool amg_setup(const Csr& A0, const AmgParams& prm, AmgHierarchy* h) {
   h->lv.clear();

@@ -37,6 +37,12 @@ struct AmgParams {
   double p_drop = 0.1;           // drop smoothed-P entries below this fraction of the row's largest
 };
 
+// M = R (I - A W) with W = omega D^-1: the restriction of the residual left
+// by one damped-Jacobi sweep from zero, b_{l+1} = M b_l.  For symmetric A,
+// R A = (A P)^T, so M = R - (A P)^T W, with the pattern of (A P)^T (which
+// holds R's, A's diagonal being stored); rows with ascending columns.
+Csr residual_restriction(const AmgLevel& L);
+
 // Build the hierarchy for the symmetric positive definite CSR matrix A.
 // Returns false (and leaves h empty) when the matrix does not coarsen.
 bool amg_setup(const Csr& A, const AmgParams& prm, AmgHierarchy* h);

@@ -116,20 +116,71 @@ Prob<real>& desc_of(mmsd_problem p) {
   return *reinterpret_cast<Prob<real>*>(p->desc);
 }
 
-// Lanes per row W (4, 8 or 16) for a multigrid matrix swept in CSR.  A
-// block pass covers 512 / W rows.  Rows of more than 16 entries on average
-// take 8 lanes loading 8 entries each (64 entries per batch), more than 64
-// take 16; shorter rows take 4 lanes loading 4 each.  A small matrix whose
-// rows all fit one pass of the 512 blocks of a full-GPU launch at 16 lanes
-// takes 16 lanes when its rows are long: that spreads its few rows over 4x
-// more blocks than 4 lanes would (measured 1-1.5 us faster per sweep on the
-// coarse levels, where each sweep is a chain of dependent loads).
-constexpr int64_t kSmallRows = 512 * (kBlock / 16);
+// Lanes per row W (4, 8, 16 or 32) for a multigrid matrix swept in CSR.  A
+// block pass covers 512 / W rows; a lane loads 8 entries per batch (4 with
+// 4 lanes).  Rows of more than 16 entries on average take 8 lanes (64
+// entries per batch), more than 64 take 16, shorter ones 4.  A small matrix
+// whose rows all fit one pass of the 512 blocks of a full-GPU launch at 32
+// lanes (at most 8192 rows) takes 32 lanes when its rows are long: that
+// spreads its few rows over many more blocks, and a row of up to 256
+// entries is one batch.  The coarse levels are latency-bound (each sweep a
+// chain of dependent loads): measured 1-1.5 us faster per sweep than 8
+// lanes.
+constexpr int64_t kSmallRows = 512 * (kBlock / 32);
 int row_lanes(const Csr& M) {
   const double avg = M.nrows ? (double)M.ci.size() / M.nrows : 0.0;
-  if (avg > 16 && M.nrows <= kSmallRows) return 16;
+  if (avg > 16 && M.nrows <= kSmallRows) return 32;
   return avg > 64 ? 16 : avg > 16 ? 8 : 4;
 }
+// Block passes of a CSR sweep of n rows at W lanes per row over g blocks.
+static int64_t sweep_passes(int64_t n, int64_t g, int W) {
+  const int64_t rpp = kBlock / W, c = (n + g - 1) / g;
+  return (c + rpp - 1) / rpp;
+}
+
+// Latency cost of a sweep of matrix M (rows of avg entries) at W lanes per
+// row (W = 1: sliced, one thread per row) over g blocks, in units of one
+// dependent round trip: each block pass loads the row start, then per batch
+// the entries and their gathers (8 entries per lane per batch at 8 or more
+// lanes, 4 otherwise), then stores.
+static int64_t sweep_cost(int64_t n, double avg, int64_t g, int W) {
+  const double per_batch = W == 1 ? 4.0 : W == 4 ? 16.0 : 8.0 * W;
+  const int64_t batches = std::max<int64_t>(1, (int64_t)std::ceil(avg / per_batch));
+  return sweep_passes(n, g, W) * (batches + 1);
+}
+
+// Shape of a DOWN launch that also restricts (levels >= 1), for the 512
+// blocks of a full-GPU launch: the split of the blocks between A's rows (nA
+// rows of avgA entries at wa lanes) and M's, and M's lanes per row, that
+// minimize the slower part's cost (on ties: the most blocks for M, then
+// the cheapest M sweep; measured 1-1.5 us faster on the coarse levels than
+// the fewest).  The fusion is kept (m_blocks > 0) when
+// that cost is below the two separate sweeps' plus one launch (counted as
+// 2 round trips): on coarse, latency-bound levels it removes a launch; on a
+// large level, M (about 5x R's entries) would cost more than it saves.
+static void fused_shape(int64_t nA, double avgA, int wa, int64_t nR, double avgR, int wr, const Csr& M, int& wm,
+                        int& m_blocks) {
+  const double avgM = M.nrows ? (double)M.ci.size() / M.nrows : 0.0;
+  const int64_t separate = sweep_cost(nA, avgA, 512, wa) + sweep_cost(nR, avgR, 512, wr) + 2;
+  int64_t best = INT64_MAX;
+  wm = 4;
+  m_blocks = 0;
+  int64_t best_m = INT64_MAX;
+  for (int64_t gd = 8; gd <= 504; gd += 8) {   // ties: the largest share for M, then M's cheapest lanes
+    const int64_t ca = sweep_cost(nA, avgA, gd, wa);
+    for (int W : {4, 8, 16, 32}) {
+      const int64_t cm = sweep_cost(M.nrows, avgM, 512 - gd, W), c = std::max(ca, cm);
+      if (c < best || (c == best && 512 - gd > m_blocks) || (c == best && 512 - gd == m_blocks && cm < best_m)) {
+        best = c;
+        best_m = cm;
+        wm = W;
+        m_blocks = (int)(512 - gd);
+      }
+    }
+  }
+  if (best >= separate) m_blocks = 0;
+}
+
 // Average row length up to which a matrix with many rows is sliced.
 constexpr size_t kWideRow = 24;
 // Rows from which a multigrid matrix with short rows (at most kWideRow on
@@ -180,30 +231,77 @@ Sliced make_sliced(const std::vector<int>& rp, const std::vector<int>& ci, const
 // The matrix the fused prolongation and post-smoothing sweeps: the union of
 // the patterns of A P and P (P's lies inside A P's when A's diagonal is
 // stored) with the value pairs {(A P)_ik, P_ik}, two values per entry in v.
-Csr fused_q(const Csr& AP, const Csr& P) {
+// Each row lists P's columns first (front[i] of them), then the others, each
+// part by ascending column.
+Csr fused_q(const Csr& AP, const Csr& P, std::vector<int>& front) {
   Csr Q;
   Q.nrows = AP.nrows;
   Q.ncols = AP.ncols;
   Q.rp.assign(Q.nrows + 1, 0);
+  front.assign(Q.nrows, 0);
   std::vector<int> ci;
   std::vector<double> v;
   ci.reserve(AP.ci.size());
   v.reserve(2 * AP.ci.size());
+  std::vector<int> rest_c;
+  std::vector<double> rest_v;
   for (int i = 0; i < Q.nrows; ++i) {
     int a = AP.rp[i], b = P.rp[i];
     const int ae = AP.rp[i + 1], be = P.rp[i + 1];
+    rest_c.clear();
+    rest_v.clear();
     while (a < ae || b < be) {   // both rows sorted by column
       const int ca = a < ae ? AP.ci[a] : INT32_MAX, cb = b < be ? P.ci[b] : INT32_MAX;
       const int c = std::min(ca, cb);
-      ci.push_back(c);
-      v.push_back(ca == c ? AP.v[a++] : 0.0);
-      v.push_back(cb == c ? P.v[b++] : 0.0);
+      const double va = ca == c ? AP.v[a++] : 0.0;
+      if (cb == c) {
+        ci.push_back(c);
+        v.push_back(va);
+        v.push_back(P.v[b++]);
+        front[i]++;
+      } else {
+        rest_c.push_back(c);
+        rest_v.push_back(va);
+      }
+    }
+    for (size_t k = 0; k < rest_c.size(); ++k) {
+      ci.push_back(rest_c[k]);
+      v.push_back(rest_v[k]);
+      v.push_back(0.0);
     }
     Q.rp[i + 1] = (int)ci.size();
   }
   Q.ci = std::move(ci);
   Q.v = std::move(v);
   return Q;
+}
+
+// The sliced form of Q: the (A P) values over Q's pattern, and the P values
+// of the row fronts as a sliced matrix of their own (same 64-row slices,
+// entry k of row i at po[s] + 64 k + i mod 64, zero-padded).
+struct SlicedQ {
+  Sliced ap;
+  std::vector<int> po;
+  std::vector<double> pv;
+};
+SlicedQ make_sliced_q(const Csr& Q, const std::vector<int>& front) {
+  SlicedQ S;
+  std::vector<double> apv(Q.ci.size());
+  for (size_t k = 0; k < Q.ci.size(); ++k) apv[k] = Q.v[2 * k];
+  S.ap = make_sliced(Q.rp, Q.ci, apv, Q.ncols);
+  std::vector<int> frp(Q.nrows + 1, 0), fci;
+  std::vector<double> fv;
+  for (int i = 0; i < Q.nrows; ++i) {
+    for (int k = 0; k < front[i]; ++k) {
+      fci.push_back(Q.ci[Q.rp[i] + k]);
+      fv.push_back(Q.v[2 * (size_t)(Q.rp[i] + k) + 1]);
+    }
+    frp[i + 1] = (int)fci.size();
+  }
+  Sliced F = make_sliced(frp, fci, fv, Q.ncols);
+  S.po = std::move(F.so);
+  S.pv = std::move(F.sv);
+  return S;
 }
 
 // Algorithmic bytes per executed phase: every matrix entry, index and
@@ -229,10 +327,16 @@ void bytes_model(mmsd_problem p) {
       const double n = L.A.nrows, nn = L.P.ncols;
       const double zA = (double)L.A.ci.size(), zP = (double)L.P.ci.size(), zQ = (double)p->amg_q_nnz[l];
       const double spA = 4 * (n + 1) + (4 + s) * zA, spR = 4 * (nn + 1) + (4 + s) * zP;
-      const double spQ = 4 * (n + 1) + (4 + 2 * s) * zQ;
+      // Q: CSR with value pairs, or sliced with the (A P) values and P's
+      // values of the row fronts
+      const double spQ = p->amg_q_sliced[l] ? 4 * (n + 1) + (4 + s) * zQ + s * (double)L.P.ci.size()
+                                            : 4 * (n + 1) + (4 + 2 * s) * zQ;
       b[byte_slot(PH_MG, MG_DOWN, (int)l)] = spA + 3 * s * n;     // b, wd in; res out
       b[byte_slot(PH_MG, MG_REST, (int)l)] = spR + s * n + s * nn;   // res in; b out
       if (l + 1 < H.lv.size()) b[byte_slot(PH_MG, MG_REST, (int)l)] += 2 * s * nn;   // wd in; wd b out
+      if (p->amg_m_nnz[l] > 0)   // DOWN also restricts: M rows, b_{l+1} out (and wd in, wd b out)
+        b[byte_slot(PH_MG, MG_DOWN, (int)l)] += 4 * (nn + 1) + (4 + s) * (double)p->amg_m_nnz[l] + s * nn +
+                                               (l + 1 < H.lv.size() ? 2 * s * nn : 0.0);
       b[byte_slot(PH_MG, MG_POST, (int)l)] = spQ + s * nn + 4 * s * n;   // x_{l+1}, b, wd, res in; xb out
       if (l == 0) b[byte_slot(PH_MG, MG_POST, 0)] += 2 * s * n;     // p carried over into the {z, p} records
     }
@@ -260,14 +364,20 @@ int build_amg(mmsd_problem p) {
     off.push_back(at);
     return at;
   };
-  struct LvOff { size_t arp, aci, av, wd, qrp, qci, qv, rrp, rci, rv, b, wb, res, xb, sl[3][3]; };
+  struct LvOff { size_t arp, aci, av, wd, qrp, qci, qv, qpo, qpv, rrp, rci, rv, mrp, mci, mv, b, wb, res, xb, sl[3][3]; };
   std::vector<LvOff> lo(nl);
-  // the fused prolongation / post-smoothing matrices (two values per entry)
-  std::vector<Csr> Q(nl);
+  // the fused prolongation / post-smoothing matrices (two values per entry),
+  // and on levels >= 1 the restriction M = R (I - A wd) that DOWN sweeps too
+  std::vector<Csr> Q(nl), M(nl);
+  std::vector<std::vector<int>> qfront(nl);
+  std::vector<SlicedQ> sq(nl);
   p->amg_q_nnz.assign(nl, 0);
+  p->amg_m_nnz.assign(nl, 0);
+  p->amg_q_sliced.assign(nl, 0);
   for (int l = 0; l < nl; ++l) {
-    Q[l] = fused_q(H.lv[l].AP, H.lv[l].P);
+    Q[l] = fused_q(H.lv[l].AP, H.lv[l].P, qfront[l]);
     p->amg_q_nnz[l] = (int64_t)Q[l].ci.size();
+    if (l >= 1) M[l] = residual_restriction(H.lv[l]);
   }
   // sliced copies (A of levels >= 1, Q, R) of the matrices with many rows
   std::vector<std::array<Sliced, 3>> sl(nl);
@@ -277,9 +387,27 @@ int build_amg(mmsd_problem p) {
     for (int k = 0; k < 3; ++k) {
       if ((k == 0 && l == 0) || M[k]->nrows < kSlicedRows || M[k]->ci.size() > kWideRow * (size_t)M[k]->nrows)
         continue;
-      sl[l][k] = make_sliced(M[k]->rp, M[k]->ci, M[k]->v, M[k]->ncols, k == 1 ? 2 : 1);
+      if (k == 1) {
+        sq[l] = make_sliced_q(Q[l], qfront[l]);
+        sl[l][k] = std::move(sq[l].ap);
+        p->amg_q_sliced[l] = 1;
+      } else {
+        sl[l][k] = make_sliced(M[k]->rp, M[k]->ci, M[k]->v, M[k]->ncols);
+      }
       if ((int64_t)sl[l][k].so.back() >= (int64_t)1 << 30) return invalid("multigrid matrix too large to slice");
     }
+  }
+  // which levels' DOWN also restricts, and how
+  std::vector<int> wm(nl, 4), mblk(nl, 0);
+  for (int l = 1; l < nl; ++l) {
+    const AmgLevel& L = H.lv[l];
+    fused_shape(L.A.nrows, (double)L.A.ci.size() / L.A.nrows, sl[l][0].so.empty() ? row_lanes(L.A) : 1, L.R.nrows,
+                (double)L.R.ci.size() / std::max(1, L.R.nrows), sl[l][2].so.empty() ? row_lanes(L.R) : 1, M[l], wm[l],
+                mblk[l]);
+  }
+  for (int l = 1; l < nl; ++l) {
+    if (mblk[l] > 0) p->amg_m_nnz[l] = (int64_t)M[l].ci.size();
+    else M[l] = Csr{};
   }
   for (int l = 0; l < nl; ++l) {
     const AmgLevel& L = H.lv[l];
@@ -301,11 +429,19 @@ int build_amg(mmsd_problem p) {
       lo[l].qrp = take(4 * (n + 1));
       lo[l].qci = take(4 * Q[l].ci.size());
       lo[l].qv = take(2 * s * Q[l].ci.size());
+    } else {
+      lo[l].qpo = take(4 * sq[l].po.size());
+      lo[l].qpv = take(s * sq[l].pv.size());
     }
     if (sl[l][2].so.empty()) {
       lo[l].rrp = take(4 * (nn + 1));
       lo[l].rci = take(4 * L.R.ci.size());
       lo[l].rv = take(s * L.R.ci.size());
+    }
+    if (mblk[l] > 0) {
+      lo[l].mrp = take(4 * (nn + 1));
+      lo[l].mci = take(4 * M[l].ci.size());
+      lo[l].mv = take(s * M[l].ci.size());
     }
     lo[l].wd = take(s * n);
     lo[l].b = take(s * n);
@@ -341,8 +477,14 @@ int build_amg(mmsd_problem p) {
     if (csr[1] && ((rc = upload_int(st, base + lo[l].qrp, Q[l].rp)) || (rc = upload_int(st, base + lo[l].qci, Q[l].ci)) ||
                    (rc = upload_vec<real>(st, base + lo[l].qv, Q[l].v))))
       return rc;
+    if (!csr[1] &&
+        ((rc = upload_int(st, base + lo[l].qpo, sq[l].po)) || (rc = upload_vec<real>(st, base + lo[l].qpv, sq[l].pv))))
+      return rc;
     if (csr[2] && ((rc = upload_int(st, base + lo[l].rrp, L.R.rp)) || (rc = upload_int(st, base + lo[l].rci, L.R.ci)) ||
                    (rc = upload_vec<real>(st, base + lo[l].rv, L.R.v))))
+      return rc;
+    if (mblk[l] > 0 && ((rc = upload_int(st, base + lo[l].mrp, M[l].rp)) || (rc = upload_int(st, base + lo[l].mci, M[l].ci)) ||
+                   (rc = upload_vec<real>(st, base + lo[l].mv, M[l].v))))
       return rc;
     if ((rc = upload_vec<real>(st, base + lo[l].wd, wd))) return rc;
     const int* so[3] = {nullptr, nullptr, nullptr};
@@ -369,7 +511,9 @@ int build_amg(mmsd_problem p) {
     d.asv = sv[0];
     d.qso = so[1];
     d.qsc = sc[1];
-    d.qsv = reinterpret_cast<const Pair<real>*>(sv[1]);
+    d.qsv = sv[1];
+    d.qpo = csr[1] ? nullptr : (const int*)(base + lo[l].qpo);
+    d.qpv = csr[1] ? nullptr : (const real*)(base + lo[l].qpv);
     d.rso = so[2];
     d.rsc = sc[2];
     d.rsv = sv[2];
@@ -378,6 +522,11 @@ int build_amg(mmsd_problem p) {
     d.lanes_a = row_lanes(L.A);
     d.lanes_q = row_lanes(Q[l]);
     d.lanes_r = row_lanes(L.R);
+    d.lanes_m = wm[l];
+    d.m_blocks = mblk[l];
+    d.mrp = mblk[l] > 0 ? (const int*)(base + lo[l].mrp) : nullptr;
+    d.mci = mblk[l] > 0 ? (const int*)(base + lo[l].mci) : nullptr;
+    d.mv = mblk[l] > 0 ? (const real*)(base + lo[l].mv) : nullptr;
     d.arp = csr[0] ? (const int*)(base + lo[l].arp) : nullptr;
     d.aci = csr[0] ? (const int*)(base + lo[l].aci) : nullptr;
     d.av = csr[0] ? (const real*)(base + lo[l].av) : nullptr;
@@ -397,6 +546,8 @@ int build_amg(mmsd_problem p) {
   MMSD_HIP(hipMemcpyAsync(base + o_lev, lv.data(), sizeof(MgLevel<real>) * nl, hipMemcpyHostToDevice, st));
   MMSD_HIP(hipStreamSynchronize(st));
   P.n_lev = nl;
+  P.mg_fused = 0;
+  for (int l = 0; l < nl; ++l) P.mg_fused |= (lv[l].m_blocks > 0) << l;
   P.nc = H.nc;
   P.lev = (const MgLevel<real>*)(base + o_lev);
   P.Ainv = (const real*)(base + o_ainv);

@@ -43,7 +43,8 @@ enum Phase : int {
   PH_PCG_A = 8,  // AMG-preconditioned CG: p = z + beta p, q = L p, p.q
   PH_PCG_B = 9   // u += alpha p, r -= alpha q, and the finest pre-smoothing residual
 };
-enum MgOp : int { MG_DOWN = 0, MG_REST = 1, MG_SOLVE = 2, MG_POST = 3 };
+enum MgOp : int { MG_DOWN = 0, MG_REST = 1, MG_SOLVE = 2, MG_POST = 3,
+                  MG_RESTM = 4 };   // inside a DOWN launch: the blocks that sweep M
 enum Precond : int { PC_AUTO = 0, PC_JACOBI = 1, PC_AMG = 2 };
 constexpr int kMaxLevels = 12;
 enum Stage : int { ST_INIT = 0, ST_RUN = 1, ST_EVAL = 2 };
@@ -117,7 +118,9 @@ using DevRef = __attribute__((address_space(1))) T&;
 template <typename real, template <typename> class Ptr>
 struct MgLevelT {
   int n, n_next;
-  int lanes_a, lanes_q, lanes_r;   // lanes per row for A, Q, R in CSR: 4, 8 or 16
+  int lanes_a, lanes_q, lanes_r, lanes_m;   // lanes per row for A, Q, R, M in CSR: 4, 8, 16 or 32
+  int m_blocks;            // blocks of 512 (scaled to the launch's) that sweep M in DOWN; 0: no M,
+                           // the level restricts in a REST operation of its own
   int pad;
   Ptr<const int> arp;
   Ptr<const int> aci;
@@ -129,14 +132,19 @@ struct MgLevelT {
   Ptr<const int> rrp;          // R = P^T: n_next x n
   Ptr<const int> rci;
   Ptr<const real> rv;
+  Ptr<const int> mrp;          // M = R (I - A wd): n_next x n, b_{l+1} = M b
+  Ptr<const int> mci;
+  Ptr<const real> mv;
   // sliced copies (64-row slices, as the potential matrix) of A, Q and R;
   // null when the matrix has too few rows to fill the GPU one row per thread
   Ptr<const int> aso;
   Ptr<const int> asc;
   Ptr<const real> asv;
-  Ptr<const int> qso;
-  Ptr<const int> qsc;
-  Ptr<const Pair<real>> qsv;
+  Ptr<const int> qso;          // Q sliced: the (A P) values; P's values of the row
+  Ptr<const int> qsc;          // fronts (each row lists P's columns first) in
+  Ptr<const real> qsv;         // slices of their own (offsets qpo)
+  Ptr<const int> qpo;
+  Ptr<const real> qpv;
   Ptr<const int> rso;
   Ptr<const int> rsc;
   Ptr<const real> rsv;
@@ -186,6 +194,7 @@ struct ProbT {
   Ptr<Rec<real>> rec[2];      // CG state by buffer parity (pcur)
   // multigrid-preconditioned CG (absent when n_lev == 0)
   int n_lev;              // levels with a coarser level below them
+  int mg_fused;           // bit l: level l's DOWN also restricts (MgLevel::m_blocks > 0)
   int nc;                 // size of the coarsest level
   Ptr<const MgLevelT<real, Ptr>> lev;
   Ptr<const real> Ainv;       // dense inverse of the coarsest operator, row-major nc x nc

@@ -115,16 +115,19 @@ __device__ __forceinline__ void st(DevPtr<Rec<real>> p, int i, const Rec<real>& 
 }
 
 // Rows [r0, r1) of block `blk` (of G, a multiple of 8) for R rows.  The rows
-// are cut into chunks of ceil(R / G) rounded up to `rpp`, and the chunks are
-// dealt to the 8 XCDs (block b runs on XCD b % 8) as 8 contiguous runs of
-// almost equal length: each XCD sweeps neighbouring rows, which keeps their
-// gathers in its own L2, and all 8 XCDs share the work also when there are
-// fewer chunks than blocks (the coarse multigrid levels).
-__device__ __forceinline__ void chunk_rows(int R, int G, int blk, int rpp, int& r0, int& r1) {
+// are cut into chunks of ceil(R / G) rounded up to `align` (64 for the
+// sliced layout, whose wavefronts each own one slice), and to whole block
+// passes of `rpp` rows when a chunk takes more than one, so a small level
+// spreads over up to G blocks.  The chunks are dealt to the 8 XCDs (block b
+// runs on XCD b % 8) as 8 contiguous runs of almost equal length: each XCD
+// sweeps neighbouring rows, which keeps their gathers in its own L2, and all
+// 8 XCDs share the work also when there are fewer chunks than blocks.
+__device__ __forceinline__ void chunk_rows(int R, int G, int blk, int rpp, int align, int& r0, int& r1) {
   r0 = r1 = R;
   if (R <= 0) return;
   long long c = ((long long)R + G - 1) / G;
-  c = (c + rpp - 1) / rpp * rpp;
+  c = (c + align - 1) / align * align;
+  if (c > rpp) c = (c + rpp - 1) / rpp * rpp;
   const int nch = (int)((R + c - 1) / c);          // <= G
   const int x = blk & 7, k = blk >> 3;
   const int s = x * nch / 8, e = (x + 1) * nch / 8;
@@ -169,33 +172,36 @@ __device__ __forceinline__ real sell_row(DevPtr<const int> so, DevPtr<const int>
   return acc;
 }
 
-// The same over a sliced matrix with two values per entry {a, b}: returns
-// {sum a * g, sum b * g} from one gather per entry.
+// Row i of the sliced fused matrix Q: {sum (A P)_ik g(k), sum P_ik g(k)}
+// from one gather per entry; P's values cover the first wp entries of the
+// row (sliced with offsets po), the (A P) values all of them.
 template <typename real, typename G>
-__device__ __forceinline__ Pair<real> sell_row2(DevPtr<const int> so, DevPtr<const int> sc,
-                                                DevPtr<const Pair<real>> sv, int i, G&& g) {
+__device__ __forceinline__ Pair<real> sell_row_q(DevPtr<const int> so, DevPtr<const int> sc, DevPtr<const real> sv,
+                                                 DevPtr<const int> po, DevPtr<const real> pv, int i, G&& g) {
   const int sl = __builtin_amdgcn_readfirstlane(i >> 6);
-  const int o0 = so[sl];
-  const int w = (so[sl + 1] - o0) >> 6;
-  const int o = o0 + (i & 63);
+  const int o0 = so[sl], p0 = po[sl];
+  const int w = (so[sl + 1] - o0) >> 6, wp = (po[sl + 1] - p0) >> 6;
+  const int o = o0 + (i & 63), op = p0 + (i & 63);
   real sa = 0, sb = 0;
   for (int k0 = 0; k0 < w; k0 += kSellU) {
     int j[kSellU];
-    Pair<real> v[kSellU];
+    real va[kSellU], vb[kSellU];
 #pragma unroll
     for (int u = 0; u < kSellU; ++u) {
-      const bool ok = k0 + u < w;
-      const int q = o + 64 * (ok ? k0 + u : 0);
+      const int k = k0 + u;
+      const bool ok = k < w;
+      const int q = o + 64 * (ok ? k : 0);
       j[u] = sc[q];
-      v[u] = ok ? ld<real>(sv, q) : Pair<real>{0, 0};
+      va[u] = ok ? sv[q] : real(0);
+      vb[u] = k < wp ? pv[op + 64 * k] : real(0);
     }
     real x[kSellU];
 #pragma unroll
     for (int u = 0; u < kSellU; ++u) x[u] = g(j[u]);
 #pragma unroll
     for (int u = 0; u < kSellU; ++u) {
-      sa += v[u].a * x[u];
-      sb += v[u].b * x[u];
+      sa += va[u] * x[u];
+      sb += vb[u] * x[u];
     }
   }
   return Pair<real>{sa, sb};
@@ -222,7 +228,7 @@ __device__ void phase_prep(const ProbDev<real>& P, const Ctrl* C, int blk, doubl
   const bool amg = C->precond == PC_AMG;
   const int R = demag ? P.Nt : P.N;
   int r0, r1;
-  chunk_rows(R, P.G, blk, kBlock, r0, r1);
+  chunk_rows(R, P.G, blk, kBlock, 64, r0, r1);
   const int a = C->acc, tr = 1 - a;
   const real ht = real(0.5 * C->tau);
   DevPtr<const real> __restrict__ max_ = P.m[a][0];
@@ -287,7 +293,7 @@ template <typename real, int LPR>
 __device__ void phase_cg0(const ProbDev<real>& P, const Ctrl* C, int blk, double* acc) {
   constexpr int RPP = kBlock;
   int r0, r1;
-  chunk_rows(P.Nt, P.G, blk, RPP, r0, r1);
+  chunk_rows(P.Nt, P.G, blk, RPP, 64, r0, r1);
   DevPtr<Rec<real>> __restrict__ rec = P.rec[C->pcur];
   for (int base = r0; base < r1; base += RPP) {
     const int i = base + threadIdx.x;
@@ -313,7 +319,7 @@ template <typename real, int LPR>
 __device__ void phase_cg(const ProbDev<real>& P, const Ctrl* C, int blk, double* acc) {
   constexpr int RPP = kBlock;
   int r0, r1;
-  chunk_rows(P.Nt, P.G, blk, RPP, r0, r1);
+  chunk_rows(P.Nt, P.G, blk, RPP, 64, r0, r1);
   const int c = C->pcur;
   const real alpha = real(C->alpha), beta = real(C->beta);
   DevPtr<const Rec<real>> __restrict__ ro = P.rec[c];
@@ -406,7 +412,9 @@ __device__ __forceinline__ Pair<real> row_sum2(DevPtr<const int> __restrict__ rp
 
 // One operation of the symmetric V(1,1) cycle with damped-Jacobi smoothing
 // (x = wd b before the coarse correction, one sweep after it):
-//   DOWN(l)  res = b - A (wd b)
+//   DOWN(l)  res = b - A (wd b); on levels l >= 1 the same launch also
+//            restricts, b_{l+1} = M b with M = R (I - A wd) (a share of the
+//            blocks sweeps M's rows), and REST(l) is skipped
 //   REST(l)  b_{l+1} = R res (and wb_{l+1} = wd_{l+1} b_{l+1}, what DOWN and
 //            POST of level l + 1 gather)
 //   SOLVE    x_c = A_c^-1 b_c (dense)
@@ -418,10 +426,10 @@ __device__ __forceinline__ Pair<real> row_sum2(DevPtr<const int> __restrict__ rp
 //            pattern lies inside A P's) over x_{l+1}.  At level 0 the result
 //            is z, stored in the {z, p} records (whole records are written:
 //            p is carried over), and b.z is reduced.
-// W lanes share a row (4, 8 or 16, chosen per matrix by the host); W = 1
+// W lanes share a row (4, 8, 16 or 32, chosen per matrix by the host); W = 1
 // (one thread per row) reads the operation's matrix from its sliced copy,
 // which matrices with many rows have (the level-0 operator is the potential
-// matrix).  A lane loads 8 entries per batch with 8 or 16 lanes (matrices
+// matrix).  A lane loads 8 entries per batch with 8 or more lanes (matrices
 // with long rows), kUnroll with 4.
 template <int W>
 constexpr int kRowU = W >= 8 ? 8 : kUnroll;
@@ -433,7 +441,7 @@ __device__ __forceinline__ real a_row(DevRef<const MgLevelDev<real>> L, int i, i
 }
 template <typename real, int W, typename G>
 __device__ __forceinline__ Pair<real> q_row(DevRef<const MgLevelDev<real>> L, int i, int lane, G&& g) {
-  if constexpr (W == 1) return sell_row2<real>(L.qso, L.qsc, L.qsv, i, g);
+  if constexpr (W == 1) return sell_row_q<real>(L.qso, L.qsc, L.qsv, L.qpo, L.qpv, i, g);
   else return row_sum2<real, W, kUnroll>(L.qrp, L.qci, L.qv, i, lane, g);   // two values: half the batch
 }
 template <typename real, int W, typename G>
@@ -442,9 +450,16 @@ __device__ __forceinline__ real r_row(DevRef<const MgLevelDev<real>> L, int i, i
   else return row_sum<real, W, kRowU<W>>(L.rrp, L.rci, L.rv, i, lane, g);
 }
 
+template <typename real, int W, typename G>
+__device__ __forceinline__ real m_row(DevRef<const MgLevelDev<real>> L, int i, int lane, G&& g) {
+  return row_sum<real, W, kRowU<W>>(L.mrp, L.mci, L.mv, i, lane, g);
+}
+
+// Rows of operation `op` on level l, block blk of the G blocks that share
+// them.
 template <typename real, int W>
 __device__ void mg_rows(const ProbDev<real>& P, const Ctrl* C, DevRef<const MgLevelDev<real>> L, int op, int l, int blk,
-                        double* acc) {
+                        int G, double* acc) {
   constexpr int RPP = kBlock / W;
   const int lane = threadIdx.x & (W - 1);
   const int slot = threadIdx.x / W;
@@ -453,17 +468,21 @@ __device__ void mg_rows(const ProbDev<real>& P, const Ctrl* C, DevRef<const MgLe
   DevPtr<const real> __restrict__ wb = L.wb;
   const bool last = l + 1 == P.n_lev;
   int r0, r1;
-  if (op == MG_REST) {
+  if (op == MG_REST || op == MG_RESTM) {
     DevPtr<real> __restrict__ bn = last ? P.bc : P.lev[l + 1].b;
     DevPtr<real> __restrict__ wbn = last ? nullptr : P.lev[l + 1].wb;
     DevPtr<const real> __restrict__ wdn = last ? nullptr : P.lev[l + 1].wd;
     DevPtr<const real> __restrict__ res = L.res;
-    chunk_rows(L.n_next, P.G, blk, RPP, r0, r1);
+    const bool m = op == MG_RESTM;   // b_{l+1} = M b, else R res
+    chunk_rows(L.n_next, G, blk, RPP, W == 1 ? 64 : 1, r0, r1);
     for (int base = r0; base < r1; base += RPP) {
       const int i = base + slot;
       const bool valid = i < r1;
       const real wi = (valid && lane == 0 && !last) ? wdn[i] : real(0);
-      real sum = valid ? r_row<real, W>(L, i, lane, [&](int j) { return res[j]; }) : real(0);
+      real sum = 0;
+      if (valid)
+        sum = m ? m_row<real, W>(L, i, lane, [&](int j) { return b[j]; })
+                : r_row<real, W>(L, i, lane, [&](int j) { return res[j]; });
       sum = group_sum<real, W>(sum);
       if (valid && lane == 0) {
         bn[i] = sum;
@@ -472,7 +491,7 @@ __device__ void mg_rows(const ProbDev<real>& P, const Ctrl* C, DevRef<const MgLe
     }
     return;
   }
-  chunk_rows(L.n, P.G, blk, RPP, r0, r1);
+  chunk_rows(L.n, G, blk, RPP, W == 1 ? 64 : 1, r0, r1);
   if (op == MG_DOWN) {
     for (int base = r0; base < r1; base += RPP) {
       const int i = base + slot;
@@ -513,6 +532,30 @@ __device__ void mg_rows(const ProbDev<real>& P, const Ctrl* C, DevRef<const MgLe
   }
 }
 
+// The row layout of an operation's matrix picks the kernel variant.
+template <typename real>
+__device__ __forceinline__ void mg_dispatch(const ProbDev<real>& P, const Ctrl* C, DevRef<const MgLevelDev<real>> L, int op, int l,
+                            int blk, int G, double* acc) {
+  const int lanes = op == MG_REST    ? L.lanes_r
+                    : op == MG_RESTM ? L.lanes_m
+                    : op == MG_POST  ? L.lanes_q
+                                     : L.lanes_a;
+  const bool sliced = op == MG_REST    ? L.rso != nullptr
+                      : op == MG_RESTM ? false
+                      : op == MG_POST  ? L.qso != nullptr
+                                       : L.aso != nullptr;
+  if (sliced)
+    mg_rows<real, 1>(P, C, L, op, l, blk, G, acc);
+  else if (lanes == 32)
+    mg_rows<real, 32>(P, C, L, op, l, blk, G, acc);
+  else if (lanes == 16)
+    mg_rows<real, 16>(P, C, L, op, l, blk, G, acc);
+  else if (lanes == 8)
+    mg_rows<real, 8>(P, C, L, op, l, blk, G, acc);
+  else
+    mg_rows<real, 4>(P, C, L, op, l, blk, G, acc);
+}
+
 template <typename real, int LPR>
 __device__ void phase_mg(const ProbDev<real>& P, const Ctrl* C, int blk, double* acc) {
   const int op = C->mg_op, l = C->mg_lev;
@@ -537,16 +580,25 @@ __device__ void phase_mg(const ProbDev<real>& P, const Ctrl* C, int blk, double*
     return;
   }
   DevRef<const MgLevelDev<real>> L = P.lev[l];
-  const int lanes = op == MG_REST ? L.lanes_r : op == MG_POST ? L.lanes_q : L.lanes_a;
-  const bool sliced = op == MG_REST ? L.rso != nullptr : op == MG_POST ? L.qso != nullptr : L.aso != nullptr;
-  if (sliced)
-    mg_rows<real, 1>(P, C, L, op, l, blk, acc);
-  else if (lanes == 16)
-    mg_rows<real, 16>(P, C, L, op, l, blk, acc);
-  else if (lanes == 8)
-    mg_rows<real, 8>(P, C, L, op, l, blk, acc);
-  else
-    mg_rows<real, 4>(P, C, L, op, l, blk, acc);
+  int o = op, b = blk, g = P.G, passes = 1;
+  if (op == MG_DOWN && L.m_blocks > 0) {
+    // fused restriction: the last gm blocks sweep M, the others A; with
+    // too few blocks to split, every block does both, one after the other
+    if (g >= 16) {
+      int gm = (g * L.m_blocks / 512 + 7) / 8 * 8;
+      gm = gm < 8 ? 8 : gm > g - 8 ? g - 8 : gm;
+      if (blk >= g - gm) {
+        o = MG_RESTM;
+        b = blk - (g - gm);
+        g = gm;
+      } else {
+        g -= gm;
+      }
+    } else {
+      passes = 2;
+    }
+  }
+  for (int k = 0; k < passes; ++k) mg_dispatch<real>(P, C, L, k == 0 ? o : MG_RESTM, l, b, g, acc);
 }
 
 // PCG_A: p = z + beta p_old (recomputed at gathered neighbours from the
@@ -557,7 +609,7 @@ template <typename real, int LPR>
 __device__ void phase_pcg_a(const ProbDev<real>& P, const Ctrl* C, int blk, double* acc) {
   constexpr int RPP = kBlock;
   int r0, r1;
-  chunk_rows(P.Nt, P.G, blk, RPP, r0, r1);
+  chunk_rows(P.Nt, P.G, blk, RPP, 64, r0, r1);
   const real beta = real(C->beta);
   const bool first = C->beta == 0.0;
   DevPtr<const Pair<real>> __restrict__ zp = P.zp;
@@ -589,7 +641,7 @@ template <typename real, int LPR>
 __device__ void phase_pcg_b(const ProbDev<real>& P, const Ctrl* C, int blk, double* acc) {
   constexpr int RPP = kBlock;
   int r0, r1;
-  chunk_rows(P.Nt, P.G, blk, RPP, r0, r1);
+  chunk_rows(P.Nt, P.G, blk, RPP, 64, r0, r1);
   const real alpha = real(C->alpha), beta = real(C->beta);
   const bool first = C->beta == 0.0;
   DevPtr<Pair<real>> __restrict__ zp = P.zp;
@@ -626,7 +678,7 @@ __device__ void phase_field(const ProbDev<real>& P, const Ctrl* C, int blk, doub
   const int lane = threadIdx.x & (LPR - 1);
   const int slot = threadIdx.x / LPR;
   int r0, r1;
-  chunk_rows(P.N, P.G, blk, RPP, r0, r1);
+  chunk_rows(P.N, P.G, blk, RPP, RPP, r0, r1);
   const int a = C->acc, tr = 1 - a;
   const int terms = C->terms;
   const bool exch = terms & MMSD_EXCH, anis = terms & MMSD_ANIS, zeem = terms & MMSD_ZEEM;
@@ -912,7 +964,7 @@ __device__ void step_logic(Ctrl* C, const double* v) {
 
 // Advance the state by the outcome of the phase it records (v: the finished
 // reductions of that phase's partials).
-__device__ void transition(Ctrl* C, const double* v, const double* btab, int n_lev) {
+__device__ void transition(Ctrl* C, const double* v, const double* btab, int n_lev, int fused) {
   C->seq++;
   const int phase = C->phase;
   if (phase == PH_IDLE || phase == PH_DONE) return;
@@ -948,8 +1000,11 @@ __device__ void transition(Ctrl* C, const double* v, const double* btab, int n_l
     case PH_MG:
       switch (C->mg_op) {
         case MG_DOWN:
-          C->mg_op = MG_REST;
-          return;
+          if (!((fused >> C->mg_lev) & 1)) {
+            C->mg_op = MG_REST;
+            return;
+          }
+          [[fallthrough]];   // this DOWN also restricted
         case MG_REST:
           if (C->mg_lev + 1 < n_lev) {
             C->mg_lev++;
@@ -1093,7 +1148,7 @@ __device__ __forceinline__ void run_phase(const ProbDev<real>& P, const Ctrl* C,
 // At most 96 VGPRs (5 wavefronts per SIMD): two 512-thread blocks per CU stay
 // resident, the shape that measured fastest, with no register spills.
 template <typename real, int LPR>
-__global__ void __launch_bounds__(kBlock, 5) k_step(const ProbDev<real>* __restrict__ probs, int nprob,
+__global__ void __launch_bounds__(kBlock, 4) k_step(const ProbDev<real>* __restrict__ probs, int nprob,
                                                     const int* __restrict__ blk_start, int parity) {
   __shared__ Ctrl s_c;
   __shared__ double s_red[kBlock / 64][kNPart];
@@ -1135,7 +1190,7 @@ __global__ void __launch_bounds__(kBlock, 5) k_step(const ProbDev<real>* __restr
   if (np_prev > 0) reduce_partials(part_prev, P.G, np_prev, ran, pre, s_tot);
   __syncthreads();
   if (threadIdx.x == 0) {
-    transition(&s_c, s_tot, lb == 0 ? s_btab : nullptr, P.n_lev);
+    transition(&s_c, s_tot, lb == 0 ? s_btab : nullptr, P.n_lev, P.mg_fused);
     s_newly_done = (ran != PH_DONE && s_c.phase == PH_DONE);
   }
   __syncthreads();
