@@ -181,6 +181,10 @@ static void fused_shape(int64_t nA, double avgA, int wa, int64_t nR, double avgR
   if (best >= separate) m_blocks = 0;
 }
 
+// Largest dense Ainv M (coarsest size x last level's rows) folded into the
+// last DOWN.
+constexpr double kMaxFoldedBytes = 64.0 * (1 << 20);
+
 // Average row length up to which a matrix with many rows is sliced.
 constexpr size_t kWideRow = 24;
 // Rows from which a multigrid matrix with short rows (at most kWideRow on
@@ -334,7 +338,9 @@ void bytes_model(mmsd_problem p) {
       b[byte_slot(PH_MG, MG_DOWN, (int)l)] = spA + 3 * s * n;     // b, wd in; res out
       b[byte_slot(PH_MG, MG_REST, (int)l)] = spR + s * n + s * nn;   // res in; b out
       if (l + 1 < H.lv.size()) b[byte_slot(PH_MG, MG_REST, (int)l)] += 2 * s * nn;   // wd in; wd b out
-      if (p->amg_m_nnz[l] > 0)   // DOWN also restricts: M rows, b_{l+1} out (and wd in, wd b out)
+      if (p->amg_folded && l + 1 == H.lv.size())   // DOWN also solves: dense Ainv M rows, x_c out
+        b[byte_slot(PH_MG, MG_DOWN, (int)l)] += s * nn * n + s * nn;
+      else if (p->amg_m_nnz[l] > 0)   // DOWN also restricts: M rows, b_{l+1} out (and wd in, wd b out)
         b[byte_slot(PH_MG, MG_DOWN, (int)l)] += 4 * (nn + 1) + (4 + s) * (double)p->amg_m_nnz[l] + s * nn +
                                                (l + 1 < H.lv.size() ? 2 * s * nn : 0.0);
       b[byte_slot(PH_MG, MG_POST, (int)l)] = spQ + s * nn + 4 * s * n;   // x_{l+1}, b, wd, res in; xb out
@@ -405,9 +411,26 @@ int build_amg(mmsd_problem p) {
                 (double)L.R.ci.size() / std::max(1, L.R.nrows), sl[l][2].so.empty() ? row_lanes(L.R) : 1, M[l], wm[l],
                 mblk[l]);
   }
+  // the last level's DOWN also solves the coarsest level when it restricts
+  // and the dense product Ainv M is small: x_c = (Ainv M) b
+  std::vector<double> ainv_m;
+  p->amg_folded = false;
+  if (nl >= 2 && mblk[nl - 1] > 0 && (double)H.nc * H.lv[nl - 1].A.nrows * s <= kMaxFoldedBytes) {
+    const Csr& Ml = M[nl - 1];
+    const int64_t nlast = H.lv[nl - 1].A.nrows;
+    ainv_m.assign((size_t)H.nc * nlast, 0.0);
+    for (int64_t I = 0; I < H.nc; ++I) {
+      double* out = &ainv_m[(size_t)I * nlast];
+      for (int64_t K = 0; K < H.nc; ++K) {
+        const double a = H.Ainv[(size_t)I * H.nc + K];
+        for (int k = Ml.rp[K]; k < Ml.rp[K + 1]; ++k) out[Ml.ci[k]] += a * Ml.v[k];
+      }
+    }
+    p->amg_folded = true;
+  }
   for (int l = 1; l < nl; ++l) {
-    if (mblk[l] > 0) p->amg_m_nnz[l] = (int64_t)M[l].ci.size();
-    else M[l] = Csr{};
+    if (mblk[l] > 0 && !(p->amg_folded && l == nl - 1)) p->amg_m_nnz[l] = (int64_t)M[l].ci.size();
+    else if (mblk[l] == 0) M[l] = Csr{};
   }
   for (int l = 0; l < nl; ++l) {
     const AmgLevel& L = H.lv[l];
@@ -450,6 +473,7 @@ int build_amg(mmsd_problem p) {
     lo[l].xb = take(s * n);
   }
   const size_t o_ainv = take(s * (size_t)H.nc * H.nc), o_bc = take(s * H.nc), o_xc = take(s * H.nc);
+  const size_t o_ainvm = take(s * ainv_m.size());
   size_t o_r2[2];
   for (int k = 0; k < 2; ++k) o_r2[k] = take(s * Nt);
   const size_t o_zp = take(2 * s * Nt);
@@ -543,6 +567,7 @@ int build_amg(mmsd_problem p) {
     d.xb = (real*)(base + lo[l].xb);
   }
   if ((rc = upload_vec<real>(st, base + o_ainv, H.Ainv))) return rc;
+  if ((rc = upload_vec<real>(st, base + o_ainvm, ainv_m))) return rc;
   MMSD_HIP(hipMemcpyAsync(base + o_lev, lv.data(), sizeof(MgLevel<real>) * nl, hipMemcpyHostToDevice, st));
   MMSD_HIP(hipStreamSynchronize(st));
   P.n_lev = nl;
@@ -551,6 +576,7 @@ int build_amg(mmsd_problem p) {
   P.nc = H.nc;
   P.lev = (const MgLevel<real>*)(base + o_lev);
   P.Ainv = (const real*)(base + o_ainv);
+  P.AinvM = p->amg_folded ? (const real*)(base + o_ainvm) : nullptr;
   P.bc = (real*)(base + o_bc);
   P.xc = (real*)(base + o_xc);
   for (int k = 0; k < 2; ++k) {

@@ -198,6 +198,8 @@ struct ProbT {
   int nc;                 // size of the coarsest level
   Ptr<const MgLevelT<real, Ptr>> lev;
   Ptr<const real> Ainv;       // dense inverse of the coarsest operator, row-major nc x nc
+  Ptr<const real> AinvM;      // nullable: Ainv M of the last level, row-major nc x n_last; the
+                              // last DOWN then forms x_c = Ainv M b itself and SOLVE is skipped
   Ptr<real> bc;               // coarsest right-hand side and solution
   Ptr<real> xc;
   Ptr<real> r2[2];            // residual by parity (rcur)

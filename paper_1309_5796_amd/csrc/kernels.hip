@@ -556,6 +556,29 @@ __device__ __forceinline__ void mg_dispatch(const ProbDev<real>& P, const Ctrl* 
     mg_rows<real, 4>(P, C, L, op, l, blk, G, acc);
 }
 
+// x_c = (Ainv M) b_l on the last level: one dense row per block at a time,
+// streamed coalesced by the whole block, wavefront sums, then the waves in
+// order.
+template <typename real>
+__device__ void coarse_rows(const ProbDev<real>& P, DevRef<const MgLevelDev<real>> L, int blk, int G) {
+  __shared__ double s_row[kBlock / 64];
+  const int nc = P.nc, n = L.n;
+  DevPtr<const real> __restrict__ b = L.b;
+  const int wid = threadIdx.x >> 6, lid = threadIdx.x & 63;
+  for (int i = blk; i < nc; i += G) {
+    DevPtr<const real> __restrict__ row = P.AinvM + (size_t)i * n;
+    double sum = 0;
+    for (int j = threadIdx.x; j < n; j += kBlock) sum += (double)(row[j] * b[j]);
+    sum = wave_sum(sum);
+    if (lid == 0) s_row[wid] = sum;
+    __syncthreads();
+    double v = s_row[0];
+    for (int w = 1; w < kBlock / 64; ++w) v += s_row[w];
+    if (threadIdx.x == 0) P.xc[i] = real(v);
+    __syncthreads();
+  }
+}
+
 template <typename real, int LPR>
 __device__ void phase_mg(const ProbDev<real>& P, const Ctrl* C, int blk, double* acc) {
   const int op = C->mg_op, l = C->mg_lev;
@@ -598,7 +621,13 @@ __device__ void phase_mg(const ProbDev<real>& P, const Ctrl* C, int blk, double*
       passes = 2;
     }
   }
-  for (int k = 0; k < passes; ++k) mg_dispatch<real>(P, C, L, k == 0 ? o : MG_RESTM, l, b, g, acc);
+  for (int k = 0; k < passes; ++k) {
+    const int ok = k == 0 ? o : MG_RESTM;
+    if (ok == MG_RESTM && P.AinvM && l + 1 == P.n_lev)
+      coarse_rows<real>(P, L, b, g);   // x_c = (Ainv M) b
+    else
+      mg_dispatch<real>(P, C, L, ok, l, b, g, acc);
+  }
 }
 
 // PCG_A: p = z + beta p_old (recomputed at gathered neighbours from the
@@ -964,7 +993,7 @@ __device__ void step_logic(Ctrl* C, const double* v) {
 
 // Advance the state by the outcome of the phase it records (v: the finished
 // reductions of that phase's partials).
-__device__ void transition(Ctrl* C, const double* v, const double* btab, int n_lev, int fused) {
+__device__ void transition(Ctrl* C, const double* v, const double* btab, int n_lev, int fused, bool folded) {
   C->seq++;
   const int phase = C->phase;
   if (phase == PH_IDLE || phase == PH_DONE) return;
@@ -1009,6 +1038,8 @@ __device__ void transition(Ctrl* C, const double* v, const double* btab, int n_l
           if (C->mg_lev + 1 < n_lev) {
             C->mg_lev++;
             C->mg_op = MG_DOWN;
+          } else if (folded) {   // the last DOWN also solved the coarsest level
+            C->mg_op = MG_POST;
           } else {
             C->mg_op = MG_SOLVE;
             C->mg_lev = 0;
@@ -1190,7 +1221,7 @@ __global__ void __launch_bounds__(kBlock, 4) k_step(const ProbDev<real>* __restr
   if (np_prev > 0) reduce_partials(part_prev, P.G, np_prev, ran, pre, s_tot);
   __syncthreads();
   if (threadIdx.x == 0) {
-    transition(&s_c, s_tot, lb == 0 ? s_btab : nullptr, P.n_lev, P.mg_fused);
+    transition(&s_c, s_tot, lb == 0 ? s_btab : nullptr, P.n_lev, P.mg_fused, P.AinvM != nullptr);
     s_newly_done = (ran != PH_DONE && s_c.phase == PH_DONE);
   }
   __syncthreads();

@@ -124,6 +124,7 @@ struct mmsd_problem_s {
   std::vector<int64_t> amg_q_nnz;         // entries of each level's fused prolongation/smoothing matrix
   std::vector<int64_t> amg_m_nnz;         // entries of each level's residual restriction (levels >= 1)
   std::vector<int> amg_q_sliced;          // 1: the level's Q is swept from its sliced form
+  bool amg_folded = false;                // the last DOWN forms the coarsest solution (Ainv M)
   char* amg_arena = nullptr;
   size_t amg_bytes = 0;
   mmsd::Ctrl* hctrl = nullptr;            // pinned mirrors [2 polls][2 slots]
