@@ -26,9 +26,8 @@
 #include <thread>
 
 namespace mmsd {
-namespace {
 
-void pfor(int64_t n, const std::function<void(int64_t, int64_t)>& f) {
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& f) {
   unsigned hw = std::thread::hardware_concurrency();
   int nt = (int)std::max<unsigned>(1, std::min<unsigned>(hw ? hw : 4, 16));
   if (n < 2048) nt = 1;
@@ -44,6 +43,8 @@ void pfor(int64_t n, const std::function<void(int64_t, int64_t)>& f) {
   }
   for (auto& x : th) x.join();
 }
+
+namespace {
 
 std::vector<double> diagonal(const Csr& A) {
   std::vector<double> d(A.nrows, 0.0);
@@ -62,7 +63,7 @@ double spectral_radius(const Csr& A, const std::vector<double>& dinv) {
   for (auto& v : x) v = U(rng);
   double lam = 1.0;
   for (int it = 0; it < 20; ++it) {
-    pfor(n, [&](int64_t a, int64_t b) {
+    parallel_for(n, [&](int64_t a, int64_t b) {
       for (int64_t i = a; i < b; ++i) {
         double s = 0;
         for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) s += A.v[k] * x[A.ci[k]];
@@ -151,7 +152,7 @@ Csr spgemm(const Csr& A, const Csr& B) {
   C.ncols = B.ncols;
   std::vector<std::vector<int>> cols(A.nrows);
   std::vector<std::vector<double>> vals(A.nrows);
-  pfor(A.nrows, [&](int64_t a, int64_t b) {
+  parallel_for(A.nrows, [&](int64_t a, int64_t b) {
     std::vector<double> acc(B.ncols, 0.0);
     std::vector<int> mark(B.ncols, -1), list;
     for (int64_t i = a; i < b; ++i) {
@@ -179,7 +180,7 @@ Csr spgemm(const Csr& A, const Csr& B) {
   for (int i = 0; i < C.nrows; ++i) C.rp[i + 1] = C.rp[i] + (int)cols[i].size();
   C.ci.resize(C.rp.back());
   C.v.resize(C.rp.back());
-  pfor(C.nrows, [&](int64_t a, int64_t b) {
+  parallel_for(C.nrows, [&](int64_t a, int64_t b) {
     for (int64_t i = a; i < b; ++i) {
       std::copy(cols[i].begin(), cols[i].end(), C.ci.begin() + C.rp[i]);
       std::copy(vals[i].begin(), vals[i].end(), C.v.begin() + C.rp[i]);
@@ -240,22 +241,33 @@ Csr residual_restriction(const AmgLevel& L) {
   M.nrows = T.nrows;
   M.ncols = T.ncols;
   M.rp.assign(M.nrows + 1, 0);
-  M.ci.reserve(T.ci.size());
-  M.v.reserve(T.ci.size());
-  for (int I = 0; I < M.nrows; ++I) {
-    int a = T.rp[I], b = R.rp[I];
+  // rows are the sorted unions of T's and R's rows: count, then fill
+  auto merge = [&](int I, int* ci, double* v) {
+    int a = T.rp[I], b = R.rp[I], o = 0;
     const int ae = T.rp[I + 1], be = R.rp[I + 1];
-    while (a < ae || b < be) {   // both rows sorted by column
+    while (a < ae || b < be) {
       const int ca = a < ae ? T.ci[a] : INT32_MAX, cb = b < be ? R.ci[b] : INT32_MAX;
       const int c = std::min(ca, cb);
-      double v = 0;
-      if (cb == c) v += R.v[b++];
-      if (ca == c) v -= T.v[a++] * L.omega * L.dinv[c];
-      M.ci.push_back(c);
-      M.v.push_back(v);
+      double x = 0;
+      if (cb == c) x += R.v[b++];
+      if (ca == c) x -= T.v[a++] * L.omega * L.dinv[c];
+      if (ci) {
+        ci[o] = c;
+        v[o] = x;
+      }
+      ++o;
     }
-    M.rp[I + 1] = (int)M.ci.size();
-  }
+    return o;
+  };
+  parallel_for(M.nrows, [&](int64_t a, int64_t b) {
+    for (int64_t I = a; I < b; ++I) M.rp[I + 1] = merge((int)I, nullptr, nullptr);
+  });
+  for (int I = 0; I < M.nrows; ++I) M.rp[I + 1] += M.rp[I];
+  M.ci.resize(M.rp[M.nrows]);
+  M.v.resize(M.rp[M.nrows]);
+  parallel_for(M.nrows, [&](int64_t a, int64_t b) {
+    for (int64_t I = a; I < b; ++I) merge((int)I, &M.ci[M.rp[I]], &M.v[M.rp[I]]);
+  });
   return M;
 }
 
@@ -292,7 +304,7 @@ bool amg_setup(const Csr& A0, const AmgParams& prm, AmgHierarchy* h) {
       P.ncols = na;
       P.rp.assign(A.nrows + 1, 0);
       std::vector<std::vector<std::pair<int, double>>> rows(A.nrows);
-      pfor(A.nrows, [&](int64_t a, int64_t b) {
+      parallel_for(A.nrows, [&](int64_t a, int64_t b) {
         for (int64_t i = a; i < b; ++i) {
           auto& r = rows[i];
           bool found = false;

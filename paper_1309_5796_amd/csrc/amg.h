@@ -3,6 +3,8 @@
 // `smooth_levels` levels, plain aggregation below), Galerkin coarse
 // operators, dense inverse on the coarsest level.
 #pragma once
+#include <cstdint>
+#include <functional>
 #include <vector>
 
 namespace mmsd {
@@ -36,6 +38,10 @@ struct AmgParams {
   int max_levels = 10;
   double p_drop = 0.1;           // drop smoothed-P entries below this fraction of the row's largest
 };
+
+// Runs f(a, b) over [0, n) cut into contiguous ranges, on up to 16 threads
+// (one for n < 2048).
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& f);
 
 // M = R (I - A W) with W = omega D^-1: the restriction of the residual left
 // by one damped-Jacobi sweep from zero, b_{l+1} = M b_l.  For symmetric A,

@@ -195,116 +195,177 @@ constexpr int kSlicedRows = 65536;
 
 // 64-row sliced layout of a CSR matrix: slice s holds rows 64s..64s+63,
 // entry k of row i at so[s] + 64 k + (i mod 64); short rows are padded with
-// their own column (clamped to the column range) and zero values.  Entries
-// carry vw values each (v and sv hold vw consecutive values per entry).
+// their own column (clamped to the column range) and a zero value.  Entry
+// k's value is v[stride k + off] (one value of an interleaved array).
+// Slices are built in parallel.
 struct Sliced {
   std::vector<int> so, sc;
   std::vector<double> sv;
 };
 Sliced make_sliced(const std::vector<int>& rp, const std::vector<int>& ci, const std::vector<double>& v,
-                   int ncols, int vw = 1) {
+                   int ncols, int stride = 1, int off = 0) {
   const int64_t n = (int64_t)rp.size() - 1, ns = (n + 63) / 64;
   Sliced S;
   S.so.assign(ns + 1, 0);
-  for (int64_t sl = 0; sl < ns; ++sl) {
-    int w = 0;
-    for (int64_t i = 64 * sl; i < std::min<int64_t>(n, 64 * sl + 64); ++i) w = std::max(w, rp[i + 1] - rp[i]);
-    S.so[sl + 1] = S.so[sl] + 64 * w;
-  }
+  parallel_for(ns, [&](int64_t a, int64_t b) {
+    for (int64_t sl = a; sl < b; ++sl) {
+      int w = 0;
+      for (int64_t i = 64 * sl; i < std::min<int64_t>(n, 64 * sl + 64); ++i) w = std::max(w, rp[i + 1] - rp[i]);
+      S.so[sl + 1] = 64 * w;
+    }
+  });
+  for (int64_t sl = 0; sl < ns; ++sl) S.so[sl + 1] += S.so[sl];
   S.sc.assign(S.so[ns], 0);
-  S.sv.assign((size_t)vw * S.so[ns], 0.0);
-  for (int64_t sl = 0; sl < ns; ++sl) {
-    const int w = (S.so[sl + 1] - S.so[sl]) / 64;
-    for (int r = 0; r < 64; ++r) {
-      const int64_t i = 64 * sl + r;
-      const int len = i < n ? rp[i + 1] - rp[i] : 0;
-      for (int k = 0; k < w; ++k) {
-        const int64_t q = S.so[sl] + 64LL * k + r;
-        if (k < len) {
-          S.sc[q] = ci[rp[i] + k];
-          for (int t = 0; t < vw; ++t) S.sv[vw * q + t] = v[(size_t)vw * (rp[i] + k) + t];
-        } else {
-          S.sc[q] = (int)std::min<int64_t>(i, ncols - 1);
+  S.sv.assign(S.so[ns], 0.0);
+  parallel_for(ns, [&](int64_t a, int64_t b) {
+    for (int64_t sl = a; sl < b; ++sl) {
+      const int w = (S.so[sl + 1] - S.so[sl]) / 64;
+      for (int r = 0; r < 64; ++r) {
+        const int64_t i = 64 * sl + r;
+        const int len = i < n ? rp[i + 1] - rp[i] : 0;
+        for (int k = 0; k < w; ++k) {
+          const int64_t q = S.so[sl] + 64LL * k + r;
+          if (k < len) {
+            S.sc[q] = ci[rp[i] + k];
+            S.sv[q] = v[(size_t)stride * (rp[i] + k) + off];
+          } else {
+            S.sc[q] = (int)std::min<int64_t>(i, ncols - 1);
+          }
         }
       }
     }
-  }
+  });
   return S;
 }
 
 // The matrix the fused prolongation and post-smoothing sweeps: the union of
 // the patterns of A P and P (P's lies inside A P's when A's diagonal is
 // stored) with the value pairs {(A P)_ik, P_ik}, two values per entry in v.
-// Each row lists P's columns first (front[i] of them), then the others, each
-// part by ascending column.
+// Each row lists P's columns first (front[i] of them, P's whole row), then
+// the others, each part by ascending column.  Rows are built in parallel.
 Csr fused_q(const Csr& AP, const Csr& P, std::vector<int>& front) {
   Csr Q;
-  Q.nrows = AP.nrows;
+  const int n = AP.nrows;
+  Q.nrows = n;
   Q.ncols = AP.ncols;
-  Q.rp.assign(Q.nrows + 1, 0);
-  front.assign(Q.nrows, 0);
-  std::vector<int> ci;
-  std::vector<double> v;
-  ci.reserve(AP.ci.size());
-  v.reserve(2 * AP.ci.size());
-  std::vector<int> rest_c;
-  std::vector<double> rest_v;
-  for (int i = 0; i < Q.nrows; ++i) {
-    int a = AP.rp[i], b = P.rp[i];
-    const int ae = AP.rp[i + 1], be = P.rp[i + 1];
-    rest_c.clear();
-    rest_v.clear();
-    while (a < ae || b < be) {   // both rows sorted by column
-      const int ca = a < ae ? AP.ci[a] : INT32_MAX, cb = b < be ? P.ci[b] : INT32_MAX;
-      const int c = std::min(ca, cb);
-      const double va = ca == c ? AP.v[a++] : 0.0;
-      if (cb == c) {
-        ci.push_back(c);
-        v.push_back(va);
-        v.push_back(P.v[b++]);
-        front[i]++;
-      } else {
-        rest_c.push_back(c);
-        rest_v.push_back(va);
+  Q.rp.assign(n + 1, 0);
+  front.assign(n, 0);
+  // row lengths: |AP row| + P columns missing from it (rows sorted by column)
+  parallel_for(n, [&](int64_t a0, int64_t b0) {
+    for (int64_t i = a0; i < b0; ++i) {
+      int a = AP.rp[i], extra = 0;
+      for (int b = P.rp[i]; b < P.rp[i + 1]; ++b) {
+        while (a < AP.rp[i + 1] && AP.ci[a] < P.ci[b]) ++a;
+        if (a == AP.rp[i + 1] || AP.ci[a] != P.ci[b]) ++extra;
+      }
+      Q.rp[i + 1] = AP.rp[i + 1] - AP.rp[i] + extra;
+      front[i] = P.rp[i + 1] - P.rp[i];
+    }
+  });
+  for (int i = 0; i < n; ++i) Q.rp[i + 1] += Q.rp[i];
+  Q.ci.resize(Q.rp[n]);
+  Q.v.resize(2 * (size_t)Q.rp[n]);
+  parallel_for(n, [&](int64_t a0, int64_t b0) {
+    for (int64_t i = a0; i < b0; ++i) {
+      int o = Q.rp[i];
+      // P's columns, with the (A P) value where A P has the column
+      int a = AP.rp[i];
+      for (int b = P.rp[i]; b < P.rp[i + 1]; ++b, ++o) {
+        while (a < AP.rp[i + 1] && AP.ci[a] < P.ci[b]) ++a;
+        Q.ci[o] = P.ci[b];
+        Q.v[2 * (size_t)o] = (a < AP.rp[i + 1] && AP.ci[a] == P.ci[b]) ? AP.v[a] : 0.0;
+        Q.v[2 * (size_t)o + 1] = P.v[b];
+      }
+      // then A P's other columns
+      int b = P.rp[i];
+      for (a = AP.rp[i]; a < AP.rp[i + 1]; ++a) {
+        while (b < P.rp[i + 1] && P.ci[b] < AP.ci[a]) ++b;
+        if (b < P.rp[i + 1] && P.ci[b] == AP.ci[a]) continue;
+        Q.ci[o] = AP.ci[a];
+        Q.v[2 * (size_t)o] = AP.v[a];
+        Q.v[2 * (size_t)o + 1] = 0.0;
+        ++o;
       }
     }
-    for (size_t k = 0; k < rest_c.size(); ++k) {
-      ci.push_back(rest_c[k]);
-      v.push_back(rest_v[k]);
-      v.push_back(0.0);
-    }
-    Q.rp[i + 1] = (int)ci.size();
-  }
-  Q.ci = std::move(ci);
-  Q.v = std::move(v);
+  });
   return Q;
 }
 
-// The sliced form of Q: the (A P) values over Q's pattern, and the P values
-// of the row fronts as a sliced matrix of their own (same 64-row slices,
-// entry k of row i at po[s] + 64 k + i mod 64, zero-padded).
+// The sliced form of Q, built from A P and P directly: the (A P) values over
+// Q's pattern (rows ordered as in fused_q: P's columns first), and the P
+// values of the row fronts as a sliced matrix of their own (same 64-row
+// slices, entry k of row i at po[s] + 64 k + i mod 64, zero-padded).
+// nnz receives Q's entry count.  Slices are built in parallel.
 struct SlicedQ {
   Sliced ap;
   std::vector<int> po;
   std::vector<double> pv;
 };
-SlicedQ make_sliced_q(const Csr& Q, const std::vector<int>& front) {
-  SlicedQ S;
-  std::vector<double> apv(Q.ci.size());
-  for (size_t k = 0; k < Q.ci.size(); ++k) apv[k] = Q.v[2 * k];
-  S.ap = make_sliced(Q.rp, Q.ci, apv, Q.ncols);
-  std::vector<int> frp(Q.nrows + 1, 0), fci;
-  std::vector<double> fv;
-  for (int i = 0; i < Q.nrows; ++i) {
-    for (int k = 0; k < front[i]; ++k) {
-      fci.push_back(Q.ci[Q.rp[i] + k]);
-      fv.push_back(Q.v[2 * (size_t)(Q.rp[i] + k) + 1]);
+SlicedQ make_sliced_q(const Csr& AP, const Csr& P, int64_t& nnz) {
+  const int64_t n = AP.nrows, ns = (n + 63) / 64;
+  std::vector<int> len(n), front(n);
+  parallel_for(n, [&](int64_t a0, int64_t b0) {
+    for (int64_t i = a0; i < b0; ++i) {
+      int a = AP.rp[i], extra = 0;
+      for (int b = P.rp[i]; b < P.rp[i + 1]; ++b) {
+        while (a < AP.rp[i + 1] && AP.ci[a] < P.ci[b]) ++a;
+        if (a == AP.rp[i + 1] || AP.ci[a] != P.ci[b]) ++extra;
+      }
+      len[i] = AP.rp[i + 1] - AP.rp[i] + extra;
+      front[i] = P.rp[i + 1] - P.rp[i];
     }
-    frp[i + 1] = (int)fci.size();
+  });
+  nnz = 0;
+  for (int64_t i = 0; i < n; ++i) nnz += len[i];
+  SlicedQ S;
+  S.ap.so.assign(ns + 1, 0);
+  S.po.assign(ns + 1, 0);
+  parallel_for(ns, [&](int64_t a, int64_t b) {
+    for (int64_t sl = a; sl < b; ++sl) {
+      int w = 0, wp = 0;
+      for (int64_t i = 64 * sl; i < std::min<int64_t>(n, 64 * sl + 64); ++i) {
+        w = std::max(w, len[i]);
+        wp = std::max(wp, front[i]);
+      }
+      S.ap.so[sl + 1] = 64 * w;
+      S.po[sl + 1] = 64 * wp;
+    }
+  });
+  for (int64_t sl = 0; sl < ns; ++sl) {
+    S.ap.so[sl + 1] += S.ap.so[sl];
+    S.po[sl + 1] += S.po[sl];
   }
-  Sliced F = make_sliced(frp, fci, fv, Q.ncols);
-  S.po = std::move(F.so);
-  S.pv = std::move(F.sv);
+  S.ap.sc.assign(S.ap.so[ns], 0);
+  S.ap.sv.assign(S.ap.so[ns], 0.0);
+  S.pv.assign(S.po[ns], 0.0);
+  parallel_for(ns, [&](int64_t a0, int64_t b0) {
+    for (int64_t sl = a0; sl < b0; ++sl) {
+      const int w = (S.ap.so[sl + 1] - S.ap.so[sl]) / 64;
+      for (int r = 0; r < 64; ++r) {
+        const int64_t i = 64 * sl + r;
+        auto at = [&](int k) { return S.ap.so[sl] + 64LL * k + r; };
+        int k = 0;
+        if (i < n) {
+          int a = AP.rp[i];
+          for (int b = P.rp[i]; b < P.rp[i + 1]; ++b, ++k) {   // P's columns
+            while (a < AP.rp[i + 1] && AP.ci[a] < P.ci[b]) ++a;
+            S.ap.sc[at(k)] = P.ci[b];
+            S.ap.sv[at(k)] = (a < AP.rp[i + 1] && AP.ci[a] == P.ci[b]) ? AP.v[a] : 0.0;
+            S.pv[S.po[sl] + 64LL * k + r] = P.v[b];
+          }
+          int b = P.rp[i];
+          for (a = AP.rp[i]; a < AP.rp[i + 1]; ++a) {   // A P's other columns
+            while (b < P.rp[i + 1] && P.ci[b] < AP.ci[a]) ++b;
+            if (b < P.rp[i + 1] && P.ci[b] == AP.ci[a]) continue;
+            S.ap.sc[at(k)] = AP.ci[a];
+            S.ap.sv[at(k)] = AP.v[a];
+            ++k;
+          }
+        }
+        for (; k < w; ++k) S.ap.sc[at(k)] = (int)std::min<int64_t>(i, AP.ncols - 1);   // padding
+      }
+    }
+  });
   return S;
 }
 
@@ -381,23 +442,30 @@ int build_amg(mmsd_problem p) {
   p->amg_m_nnz.assign(nl, 0);
   p->amg_q_sliced.assign(nl, 0);
   for (int l = 0; l < nl; ++l) {
-    Q[l] = fused_q(H.lv[l].AP, H.lv[l].P, qfront[l]);
-    p->amg_q_nnz[l] = (int64_t)Q[l].ci.size();
-    if (l >= 1) M[l] = residual_restriction(H.lv[l]);
+    const AmgLevel& L = H.lv[l];
+    // Q's rows average about A P's entries: sliced by the same rule as A, R
+    const bool q_sliced = L.AP.nrows >= kSlicedRows && L.AP.ci.size() <= kWideRow * (size_t)L.AP.nrows;
+    if (q_sliced) {
+      sq[l] = make_sliced_q(L.AP, L.P, p->amg_q_nnz[l]);
+      p->amg_q_sliced[l] = 1;
+    } else {
+      Q[l] = fused_q(L.AP, L.P, qfront[l]);
+      p->amg_q_nnz[l] = (int64_t)Q[l].ci.size();
+    }
+    if (l >= 1) M[l] = residual_restriction(L);
   }
   // sliced copies (A of levels >= 1, Q, R) of the matrices with many rows
   std::vector<std::array<Sliced, 3>> sl(nl);
   for (int l = 0; l < nl; ++l) {
     const AmgLevel& L = H.lv[l];
-    const Csr* M[3] = {&L.A, &Q[l], &L.R};
+    const Csr* M[3] = {&L.A, nullptr, &L.R};
     for (int k = 0; k < 3; ++k) {
-      if ((k == 0 && l == 0) || M[k]->nrows < kSlicedRows || M[k]->ci.size() > kWideRow * (size_t)M[k]->nrows)
-        continue;
-      if (k == 1) {
-        sq[l] = make_sliced_q(Q[l], qfront[l]);
-        sl[l][k] = std::move(sq[l].ap);
-        p->amg_q_sliced[l] = 1;
+      if (k == 1) {   // Q: sliced above when its level qualifies
+        if (!p->amg_q_sliced[l]) continue;
+        sl[l][1] = std::move(sq[l].ap);
       } else {
+        if ((k == 0 && l == 0) || M[k]->nrows < kSlicedRows || M[k]->ci.size() > kWideRow * (size_t)M[k]->nrows)
+          continue;
         sl[l][k] = make_sliced(M[k]->rp, M[k]->ci, M[k]->v, M[k]->ncols);
       }
       if ((int64_t)sl[l][k].so.back() >= (int64_t)1 << 30) return invalid("multigrid matrix too large to slice");
@@ -419,13 +487,15 @@ int build_amg(mmsd_problem p) {
     const Csr& Ml = M[nl - 1];
     const int64_t nlast = H.lv[nl - 1].A.nrows;
     ainv_m.assign((size_t)H.nc * nlast, 0.0);
-    for (int64_t I = 0; I < H.nc; ++I) {
-      double* out = &ainv_m[(size_t)I * nlast];
-      for (int64_t K = 0; K < H.nc; ++K) {
-        const double a = H.Ainv[(size_t)I * H.nc + K];
-        for (int k = Ml.rp[K]; k < Ml.rp[K + 1]; ++k) out[Ml.ci[k]] += a * Ml.v[k];
+    parallel_for(H.nc, [&](int64_t I0, int64_t I1) {
+      for (int64_t I = I0; I < I1; ++I) {
+        double* out = &ainv_m[(size_t)I * nlast];
+        for (int64_t K = 0; K < H.nc; ++K) {
+          const double a = H.Ainv[(size_t)I * H.nc + K];
+          for (int k = Ml.rp[K]; k < Ml.rp[K + 1]; ++k) out[Ml.ci[k]] += a * Ml.v[k];
+        }
       }
-    }
+    });
     p->amg_folded = true;
   }
   for (int l = 1; l < nl; ++l) {
