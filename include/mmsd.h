@@ -118,7 +118,11 @@ typedef struct {
   double easy_axis[3];
 } mmsd_material;
 
-/* Bytes of device memory a problem on this mesh will hold (admission). */
+/* Bytes of device memory a problem on this mesh will hold, for admission:
+ * exact for the first arena (operators, node state, control), plus an
+ * allowance for the multigrid hierarchy, whose size is known only after its
+ * setup ((24 + 2 s) bytes per potential-matrix entry and 8 s per potential
+ * node, s = 8 for FP64, 4 for mixed). */
 int mmsd_footprint(const mmsd_mesh* mesh, int precision, size_t* bytes_out);
 
 /* Validate the mesh, assemble the FE operators on the host and upload them.

@@ -1201,7 +1201,13 @@ int mmsd_footprint(const mmsd_mesh* mesh, int precision, size_t* bytes_out) {
     return rc;
   }
   const int G = blocks_for(std::max(ps.N, ps.Nt), 4, 512);
-  *bytes_out = make_layout(ps.N, ps.nnzM, ps.Nt, ps.nnzLs, G, precision == MMSD_MIXED ? 4 : 8).total;
+  const size_t sv = precision == MMSD_MIXED ? 4 : 8;
+  // the multigrid hierarchy's arena, known only after its setup: an
+  // allowance of (24 + 2 s) bytes per potential-matrix entry and 8 s per
+  // potential node (the 80 nm cube's FP64 hierarchy, counted from its
+  // layout: ~155 MB against 166 MB allowed)
+  const size_t amg = ps.Nt > 0 ? (24 + 2 * sv) * (size_t)ps.nnzLs + 8 * sv * (size_t)ps.Nt : 0;
+  *bytes_out = make_layout(ps.N, ps.nnzM, ps.Nt, ps.nnzLs, G, sv).total + amg;
   return MMSD_OK;
 }
 

@@ -172,6 +172,10 @@ void mmsd_server_s::setup_loop() {
       finish_request(this, r, rc);
       continue;
     }
+    // exact device bytes from here on (admission used the estimate)
+    bytes_reserved += p->arena_bytes + p->amg_bytes;
+    bytes_reserved -= r->footprint;
+    r->footprint = p->arena_bytes + p->amg_bytes;
     r->prob = p;
     r->state = RQ_READY;
     ready.push_back(r);

@@ -242,3 +242,22 @@ def test_sphere_short_sweep_matches_oracle(ctx):
         assert abs(r_gpu.energy_J - r_or.E) < 1e-10 * scale
         np.testing.assert_allclose(r_gpu.m_avg, r_or.m_avg, atol=1e-7)
     p.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_footprint_covers_the_device_memory_a_problem_holds(ctx, precision):
+    """The admission estimate (first arena exact, multigrid hierarchy by an
+    allowance) is at least what problem creation allocates through the
+    context's allocator, on the 80 nm cube and on an irregular mesh."""
+    from paper_1309_5796_amd import binding
+    prec = binding.FP64 if precision == "fp64" else binding.MIXED
+    for name, mesh in (("80 nm cube", meshgen.config2()["mesh"]), ("irregular", meshgen.delaunay_box(3))):
+        say(f"footprint {name} {precision}")
+        live = ctx._alloc.live
+        before = sum(t.numel() for t in live.values())
+        p = binding.Problem(ctx, mesh, precision=prec)
+        used = sum(t.numel() for t in live.values()) - before
+        est = binding.footprint(mesh, prec)
+        say(f"  allocated {used / 1e6:.1f} MB, footprint {est / 1e6:.1f} MB")
+        assert used > 0 and est >= used
+        p.close()
