@@ -236,6 +236,19 @@ int mmsd_timing_read(mmsd_ctx ctx, double stats[3], int reset);
  * value.  Applies to problems created afterwards. */
 int mmsd_set_launch_config(mmsd_ctx ctx, int lanes_per_row, int max_blocks);
 
+/* Forms of the multigrid V(1,1) cycle for problems created afterwards on
+ * this context (rearrangements of the same cycle, equal up to rounding):
+ *   MMSD_VC_FUSE_REST   on coarse levels where the library's cost model
+ *                       finds it pays, the restriction runs inside the
+ *                       down-sweep's launch, b_{l+1} = R (I - A wd) b;
+ *   MMSD_VC_FOLD_SOLVE  with the last level fused, the coarsest solve too,
+ *                       x_c = Ainv R (I - A wd) b.
+ * Default: both.  0 gives the plain order (REST and SOLVE launches of their
+ * own).  Returns MMSD_E_INVALID for other bits. */
+#define MMSD_VC_FUSE_REST 1
+#define MMSD_VC_FOLD_SOLVE 2
+int mmsd_set_vcycle(mmsd_ctx ctx, int flags);
+
 /* Measurement aid: `reps` launches of a plain device-to-device copy kernel
  * (k_copy_probe) of `bytes` bytes each; *ms_out (nullable) gets the mean
  * time per launch.  Used to calibrate hardware traffic counters against a

@@ -26,6 +26,7 @@ FP64, MIXED = 0, 1
 EXCH, ANIS, ZEEM, DEMAG, ALL = 1, 2, 4, 8, 15
 STEP_ADAPTIVE, STEP_ALTERNATE, STEP_BB1, STEP_BB2 = 0, 1, 2, 3
 PRECOND_AUTO, PRECOND_JACOBI, PRECOND_AMG = 0, 1, 2
+VC_FUSE_REST, VC_FOLD_SOLVE = 1, 2
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -63,6 +64,7 @@ SIGNATURES = [
     ("mmsd_ctx_create", C.c_int, [C.c_int, C.c_void_p, ALLOC_FN, FREE_FN, C.c_void_p, C.POINTER(C.c_void_p)]),
     ("mmsd_ctx_destroy", C.c_int, [C.c_void_p]),
     ("mmsd_footprint", C.c_int, [C.POINTER(MeshC), C.c_int, C.POINTER(C.c_size_t)]),
+    ("mmsd_set_vcycle", C.c_int, [C.c_void_p, C.c_int]),
     ("mmsd_problem_create", C.c_int, [C.c_void_p, C.POINTER(MeshC), C.POINTER(MaterialC), C.c_int, C.c_int,
                                       C.POINTER(C.c_void_p)]),
     ("mmsd_problem_destroy", C.c_int, [C.c_void_p]),
@@ -229,6 +231,10 @@ class Context:
 
     def set_launch_config(self, lanes_per_row: int = 0, max_blocks: int = 0):
         _check(self.lib.mmsd_set_launch_config(self.handle, lanes_per_row, max_blocks))
+
+    def set_vcycle(self, flags: int):
+        """V-cycle forms for problems created afterwards (VC_FUSE_REST, VC_FOLD_SOLVE)."""
+        _check(self.lib.mmsd_set_vcycle(self.handle, flags))
 
     def timing(self, on: bool):
         _check(self.lib.mmsd_timing_enable(self.handle, 1 if on else 0))

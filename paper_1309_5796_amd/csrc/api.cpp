@@ -473,7 +473,7 @@ int build_amg(mmsd_problem p) {
   }
   // which levels' DOWN also restricts, and how
   std::vector<int> wm(nl, 4), mblk(nl, 0);
-  for (int l = 1; l < nl; ++l) {
+  for (int l = 1; l < nl && (c->vcycle & MMSD_VC_FUSE_REST); ++l) {
     const AmgLevel& L = H.lv[l];
     fused_shape(L.A.nrows, (double)L.A.ci.size() / L.A.nrows, sl[l][0].so.empty() ? row_lanes(L.A) : 1, L.R.nrows,
                 (double)L.R.ci.size() / std::max(1, L.R.nrows), sl[l][2].so.empty() ? row_lanes(L.R) : 1, M[l], wm[l],
@@ -483,7 +483,8 @@ int build_amg(mmsd_problem p) {
   // and the dense product Ainv M is small: x_c = (Ainv M) b
   std::vector<double> ainv_m;
   p->amg_folded = false;
-  if (nl >= 2 && mblk[nl - 1] > 0 && (double)H.nc * H.lv[nl - 1].A.nrows * s <= kMaxFoldedBytes) {
+  if ((c->vcycle & MMSD_VC_FOLD_SOLVE) && nl >= 2 && mblk[nl - 1] > 0 &&
+      (double)H.nc * H.lv[nl - 1].A.nrows * s <= kMaxFoldedBytes) {
     const Csr& Ml = M[nl - 1];
     const int64_t nlast = H.lv[nl - 1].A.nrows;
     ainv_m.assign((size_t)H.nc * nlast, 0.0);
@@ -1173,6 +1174,13 @@ int mmsd_set_launch_config(mmsd_ctx c, int lanes_per_row, int max_blocks) {
     return invalid("max_blocks must be a multiple of 8 in [8, 2048]");
   if (lanes_per_row) c->lpr = lanes_per_row;
   if (max_blocks) c->max_blocks = max_blocks;
+  return MMSD_OK;
+}
+
+int mmsd_set_vcycle(mmsd_ctx c, int flags) {
+  if (!c) return invalid("null context");
+  if (flags & ~(MMSD_VC_FUSE_REST | MMSD_VC_FOLD_SOLVE)) return invalid("unknown V-cycle flags");
+  c->vcycle = flags;
   return MMSD_OK;
 }
 

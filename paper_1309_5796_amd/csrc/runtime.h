@@ -90,6 +90,7 @@ struct mmsd_ctx_s {
   void* user = nullptr;
   int lpr = 4;
   int max_blocks = 512;
+  int vcycle = MMSD_VC_FUSE_REST | MMSD_VC_FOLD_SOLVE;   // V-cycle forms for new problems
   bool use_graph = true;
   mmsd::TimingState timing;
   std::map<int64_t, std::pair<int, int>> tuned;   // autotuner results by problem class

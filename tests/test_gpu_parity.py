@@ -363,3 +363,33 @@ def test_degenerate_sizes_and_states(ctx):
     assert r.status == 0 and r.iterations == 0
     assert np.abs(p.get_m() - u).max() < 1e-15
     p.close()
+
+
+@pytest.mark.parametrize("flags,blocks", [(0, 0), (1, 0), (3, 0), (3, 8)],
+                         ids=["plain", "fused-rest", "fused-rest+solve", "fused-one-block-pass"])
+def test_vcycle_forms_match_oracle(cfg1, cfg1_system, flags, blocks):
+    """Every form of the V-cycle reaches the oracle's minimum: the plain order
+    (REST on the coarse level and a SOLVE launch), the restriction inside
+    DOWN, the coarsest solve folded into it, and the fused DOWN at 8 blocks
+    (every block sweeps A's rows and then M's)."""
+    from paper_1309_5796_amd import binding
+    say(f"vcycle flags={flags} max_blocks={blocks}")
+    c = binding.Context(0)
+    try:
+        c.set_vcycle(flags)
+        if blocks:
+            c.set_launch_config(4, blocks)
+        s = cfg1_system
+        ro = oracle.minimize(s, cfg1["m0"], cfg1["b_ext"], Options())
+        p = binding.Problem(c, cfg1["mesh"])
+        p.set_m(cfg1["m0"])
+        p.set_field(cfg1["b_ext"])
+        r = p.minimize()
+        assert r.status == 0 and r.max_torque < 1e-6
+        ev = s.evaluate(ro.m, cfg1["b_ext"])
+        assert rel_energy_err(r.energy_J, ev) < 1e-10
+        assert np.abs(p.get_m() - ro.m).max() < 1e-5
+        say(f"  iters={r.iterations} pcg={r.pcg_iters}")
+        p.close()
+    finally:
+        c.close()
