@@ -188,9 +188,9 @@ constexpr double kMaxFoldedBytes = 64.0 * (1 << 20);
 // Average row length up to which a matrix with many rows is sliced.
 constexpr size_t kWideRow = 24;
 // Rows from which a multigrid matrix with short rows (at most kWideRow on
-// average) also gets a sliced copy and is swept one row per thread (enough
-// wavefronts to fill the GPU; long rows keep 16 lanes per row, which
-// measured faster).
+// average) is held in the sliced layout (no CSR copy) and swept one row per
+// thread (enough wavefronts to fill the GPU); long rows keep their lanes per
+// row (row_lanes), which measured faster.
 constexpr int kSlicedRows = 65536;
 
 // 64-row sliced layout of a CSR matrix: slice s holds rows 64s..64s+63,
