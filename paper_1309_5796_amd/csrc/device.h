@@ -17,8 +17,9 @@
 //          the energy, max|H|, sum V|H|^2 and the BB dots s.s, s.y, y.y
 //          (eq. (9)).
 // With the multigrid preconditioner the potential solve runs PH_MG
-// operations (one V-cycle operation on one level per launch), PH_PCG_A and
-// PH_PCG_B instead of CG0 / CG.
+// operations (one V-cycle operation on one level per launch; a DOWN may
+// also restrict, and on the last level also solve the coarsest level),
+// PH_PCG_A and PH_PCG_B instead of CG0 / CG.
 //
 // Launches alternate a parity bit.  A launch of parity p reads the control
 // state and the per-block partial sums that the previous launch (parity

@@ -412,9 +412,11 @@ __device__ __forceinline__ Pair<real> row_sum2(DevPtr<const int> __restrict__ rp
 
 // One operation of the symmetric V(1,1) cycle with damped-Jacobi smoothing
 // (x = wd b before the coarse correction, one sweep after it):
-//   DOWN(l)  res = b - A (wd b); on levels l >= 1 the same launch also
-//            restricts, b_{l+1} = M b with M = R (I - A wd) (a share of the
-//            blocks sweeps M's rows), and REST(l) is skipped
+//   DOWN(l)  res = b - A (wd b); on the levels l >= 1 where the host finds
+//            it pays, the same launch also restricts, b_{l+1} = M b with
+//            M = R (I - A wd) (a share of the blocks sweeps M's rows), and
+//            REST(l) is skipped; on the last level, with the host's dense
+//            Ainv M, those blocks form x_c = (Ainv M) b and SOLVE is skipped
 //   REST(l)  b_{l+1} = R res (and wb_{l+1} = wd_{l+1} b_{l+1}, what DOWN and
 //            POST of level l + 1 gather)
 //   SOLVE    x_c = A_c^-1 b_c (dense)
@@ -427,9 +429,9 @@ __device__ __forceinline__ Pair<real> row_sum2(DevPtr<const int> __restrict__ rp
 //            is z, stored in the {z, p} records (whole records are written:
 //            p is carried over), and b.z is reduced.
 // W lanes share a row (4, 8, 16 or 32, chosen per matrix by the host); W = 1
-// (one thread per row) reads the operation's matrix from its sliced copy,
-// which matrices with many rows have (the level-0 operator is the potential
-// matrix).  A lane loads 8 entries per batch with 8 or more lanes (matrices
+// (one thread per row) reads the operation's matrix in the sliced layout,
+// in which matrices with many short rows are held (the level-0 operator is
+// the potential matrix).  A lane loads 8 entries per batch with 8 or more lanes (matrices
 // with long rows), kUnroll with 4.
 template <int W>
 constexpr int kRowU = W >= 8 ? 8 : kUnroll;
