@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <memory>
 #include <numeric>
 #include <thread>
 
@@ -283,14 +284,21 @@ int64_t sliced_entries(const std::vector<int>& rp) {
 int assemble_material_values(Assembly* A, std::string* err) {
   const int N = A->N;
   const int64_t Em = (int64_t)A->mregion.size();
-  // every region used needs a material with a common Js
+  // every region used needs a material with a common Js; the regions'
+  // lines are looked up once, into a table by region id
   double Js = -1;
+  int max_region = 0;
+  for (int64_t e = 0; e < Em; ++e) max_region = std::max(max_region, (int)A->mregion[e]);
+  std::vector<const MatLine*> line(max_region + 1, nullptr);
   for (int64_t e = 0; e < Em; ++e) {
-    auto it = A->mats.find(A->mregion[e]);
+    const int r = A->mregion[e];
+    if (line[r]) continue;
+    auto it = A->mats.find(r);
     if (it == A->mats.end()) {
-      *err = "no material for region " + std::to_string(A->mregion[e]);
+      *err = "no material for region " + std::to_string(r);
       return MMSD_E_INVALID;
     }
+    line[r] = &it->second;
     if (Js < 0) Js = it->second.Js;
     if (it->second.Js != Js) {
       *err = "all magnetic regions must share one Js";
@@ -309,7 +317,7 @@ int assemble_material_values(Assembly* A, std::string* err) {
   std::vector<double> kex(Em), kan(Em), uu(Em * 6);
   CompensatedSum c_an;
   for (int64_t e = 0; e < Em; ++e) {
-    const MatLine& M = A->mats[A->mregion[e]];
+    const MatLine& M = *line[A->mregion[e]];
     double Ve = A->mgeo[13 * e];
     kex[e] = M.A / (mu0Ms2 * kNm * kNm) * Ve;
     double un = std::sqrt(M.u[0] * M.u[0] + M.u[1] * M.u[1] + M.u[2] * M.u[2]);
@@ -375,7 +383,7 @@ int assemble(const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats, Assem
   }
 
   // geometry of every tet (needed for L) -- validated here
-  std::vector<double> geo(13 * E);
+  std::unique_ptr<double[]> geo(new double[13 * E]);   // every entry written below (or the mesh rejected)
   std::vector<char> bad(E, 0);
   parallel_for(E, [&](int64_t a, int64_t b) {
     for (int64_t e = a; e < b; ++e) {
@@ -404,13 +412,15 @@ int assemble(const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats, Assem
   A->mregion.resize(Em);
   std::vector<int> mag_tet_ids(Em);
   for (int64_t e = 0, k = 0; e < E; ++e)
-    if (keep[e]) {
-      mag_tet_ids[k] = (int)e;
+    if (keep[e]) mag_tet_ids[k++] = (int)e;
+  parallel_for(Em, [&](int64_t k0, int64_t k1) {
+    for (int64_t k = k0; k < k1; ++k) {
+      const int64_t e = mag_tet_ids[k];
       for (int a = 0; a < 4; ++a) A->mtet[4 * k + a] = nb.mag_of[tets[4 * e + a]];
       std::copy(&geo[13 * e], &geo[13 * e] + 13, &A->mgeo[13 * k]);
       A->mregion[k] = mesh->tet_region[e];
-      ++k;
     }
+  });
   // magnetic node -> (magnetic tet, vertex)
   {
     std::vector<int> lt(4 * Em);
