@@ -22,6 +22,8 @@
 #include <cstdint>
 #include <cmath>
 #include <functional>
+#include <map>
+#include <mutex>
 #include <random>
 #include <thread>
 
@@ -145,14 +147,22 @@ Csr transpose(const Csr& M) {
   return T;   // rows come out with ascending columns
 }
 
-// C = A B (Gustavson, rows in parallel, sorted columns).
+// C = A B (Gustavson, rows in parallel, sorted columns).  Each thread fills
+// flat buffers for its contiguous range of rows; the ranges are then laid
+// end to end.
 Csr spgemm(const Csr& A, const Csr& B) {
   Csr C;
   C.nrows = A.nrows;
   C.ncols = B.ncols;
-  std::vector<std::vector<int>> cols(A.nrows);
-  std::vector<std::vector<double>> vals(A.nrows);
+  C.rp.assign(C.nrows + 1, 0);
+  struct Part {
+    std::vector<int> ci;
+    std::vector<double> v;
+  };
+  std::mutex mu;
+  std::map<int64_t, Part> parts;   // by first row of the range
   parallel_for(A.nrows, [&](int64_t a, int64_t b) {
+    Part part;
     std::vector<double> acc(B.ncols, 0.0);
     std::vector<int> mark(B.ncols, -1), list;
     for (int64_t i = a; i < b; ++i) {
@@ -171,21 +181,25 @@ Csr spgemm(const Csr& A, const Csr& B) {
         }
       }
       std::sort(list.begin(), list.end());
-      cols[i] = list;
-      vals[i].resize(list.size());
-      for (size_t q = 0; q < list.size(); ++q) vals[i][q] = acc[list[q]];
+      for (int j : list) {
+        part.ci.push_back(j);
+        part.v.push_back(acc[j]);
+      }
+      C.rp[i + 1] = (int)list.size();
     }
+    std::lock_guard<std::mutex> g(mu);
+    parts[a] = std::move(part);
   });
-  C.rp.assign(C.nrows + 1, 0);
-  for (int i = 0; i < C.nrows; ++i) C.rp[i + 1] = C.rp[i] + (int)cols[i].size();
+  for (int i = 0; i < C.nrows; ++i) C.rp[i + 1] += C.rp[i];
   C.ci.resize(C.rp.back());
   C.v.resize(C.rp.back());
-  parallel_for(C.nrows, [&](int64_t a, int64_t b) {
-    for (int64_t i = a; i < b; ++i) {
-      std::copy(cols[i].begin(), cols[i].end(), C.ci.begin() + C.rp[i]);
-      std::copy(vals[i].begin(), vals[i].end(), C.v.begin() + C.rp[i]);
-    }
-  });
+  std::vector<std::thread> th;   // one copy per range (at most 16)
+  for (auto& kv : parts)
+    th.emplace_back([&C, &kv] {
+      std::copy(kv.second.ci.begin(), kv.second.ci.end(), C.ci.begin() + C.rp[kv.first]);
+      std::copy(kv.second.v.begin(), kv.second.v.end(), C.v.begin() + C.rp[kv.first]);
+    });
+  for (auto& t : th) t.join();
   return C;
 }
 
@@ -271,10 +285,11 @@ Csr residual_restriction(const AmgLevel& L) {
   return M;
 }
 
-bool amg_setup(const Csr& A0, const AmgParams& prm, AmgHierarchy* h) {
+bool amg_setup(Csr A0, const AmgParams& prm, AmgHierarchy* h) {
   h->lv.clear();
-  Csr A = A0;
-  double nnz_total = (double)A0.ci.size();
+  const double nnz0 = (double)A0.ci.size();
+  Csr A = std::move(A0);
+  double nnz_total = nnz0;
   while (A.nrows > prm.coarse_max && (int)h->lv.size() < prm.max_levels) {
     AmgLevel L;
     std::vector<double> d = diagonal(A);
@@ -298,15 +313,23 @@ bool amg_setup(const Csr& A0, const AmgParams& prm, AmgHierarchy* h) {
       Csr AT = spgemm(A, T);
       for (int i = 0; i < AT.nrows; ++i)
         for (int k = AT.rp[i]; k < AT.rp[i + 1]; ++k) AT.v[k] *= -L.omega * L.dinv[i];
-      // add T (one entry per row, column agg[i])
+      // add T (one entry per row, column agg[i]); each thread fills flat
+      // buffers for its contiguous range of rows, laid end to end after
       Csr P;
       P.nrows = A.nrows;
       P.ncols = na;
       P.rp.assign(A.nrows + 1, 0);
-      std::vector<std::vector<std::pair<int, double>>> rows(A.nrows);
+      struct Part {
+        std::vector<int> ci;
+        std::vector<double> v;
+      };
+      std::mutex mu;
+      std::map<int64_t, Part> parts;
       parallel_for(A.nrows, [&](int64_t a, int64_t b) {
+        Part part;
+        std::vector<std::pair<int, double>> r, kept;
         for (int64_t i = a; i < b; ++i) {
-          auto& r = rows[i];
+          r.clear();
           bool found = false;
           for (int k = AT.rp[i]; k < AT.rp[i + 1]; ++k) {
             double v = AT.v[k];
@@ -328,7 +351,7 @@ bool amg_setup(const Csr& A0, const AmgParams& prm, AmgHierarchy* h) {
               mx = std::max(mx, std::fabs(e.second));
               sum += e.second;
             }
-            std::vector<std::pair<int, double>> kept;
+            kept.clear();
             double ksum = 0;
             for (auto& e : r)
               if (std::fabs(e.second) >= prm.p_drop * mx) {
@@ -340,16 +363,22 @@ bool amg_setup(const Csr& A0, const AmgParams& prm, AmgHierarchy* h) {
               r.swap(kept);
             }
           }
+          for (auto& e : r) {
+            part.ci.push_back(e.first);
+            part.v.push_back(e.second);
+          }
+          P.rp[i + 1] = (int)r.size();
         }
+        std::lock_guard<std::mutex> g(mu);
+        parts[a] = std::move(part);
       });
-      for (int i = 0; i < A.nrows; ++i) P.rp[i + 1] = P.rp[i] + (int)rows[i].size();
+      for (int i = 0; i < A.nrows; ++i) P.rp[i + 1] += P.rp[i];
       P.ci.resize(P.rp.back());
       P.v.resize(P.rp.back());
-      for (int i = 0; i < A.nrows; ++i)
-        for (size_t q = 0; q < rows[i].size(); ++q) {
-          P.ci[P.rp[i] + q] = rows[i][q].first;
-          P.v[P.rp[i] + q] = rows[i][q].second;
-        }
+      for (auto& kv : parts) {
+        std::copy(kv.second.ci.begin(), kv.second.ci.end(), P.ci.begin() + P.rp[kv.first]);
+        std::copy(kv.second.v.begin(), kv.second.v.end(), P.v.begin() + P.rp[kv.first]);
+      }
       L.P = std::move(P);
     } else {
       L.P = std::move(T);
@@ -371,7 +400,7 @@ bool amg_setup(const Csr& A0, const AmgParams& prm, AmgHierarchy* h) {
     h->lv.clear();
     return false;
   }
-  h->complexity = nnz_total / (double)A0.ci.size();
+  h->complexity = nnz_total / nnz0;
   return true;
 }
 

@@ -49,8 +49,9 @@ void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& f);
 // holds R's, A's diagonal being stored); rows with ascending columns.
 Csr residual_restriction(const AmgLevel& L);
 
-// Build the hierarchy for the symmetric positive definite CSR matrix A.
-// Returns false (and leaves h empty) when the matrix does not coarsen.
-bool amg_setup(const Csr& A, const AmgParams& prm, AmgHierarchy* h);
+// Build the hierarchy for the symmetric positive definite CSR matrix A
+// (taken by value: pass a moved copy to spare one).  Returns false (and
+// leaves h empty) when the matrix does not coarsen.
+bool amg_setup(Csr A, const AmgParams& prm, AmgHierarchy* h);
 
 }  // namespace mmsd

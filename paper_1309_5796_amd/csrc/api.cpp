@@ -1240,7 +1240,7 @@ int mmsd_problem_create(mmsd_ctx c, const mmsd_mesh* mesh, const mmsd_material* 
     L0.rp = p->A.lrp;
     L0.ci = p->A.lci;
     L0.v = p->A.L;
-    p->has_amg = amg_setup(L0, AmgParams{}, &p->amg) && (int)p->amg.lv.size() <= kMaxLevels;
+    p->has_amg = amg_setup(std::move(L0), AmgParams{}, &p->amg) && (int)p->amg.lv.size() <= kMaxLevels;
     // the level operators are kept only for sizes and byte counts
   }
   std::lock_guard<std::mutex> lk(c->mu);
