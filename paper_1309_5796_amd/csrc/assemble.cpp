@@ -13,7 +13,9 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <numeric>
 #include <thread>
 
@@ -71,14 +73,17 @@ void node_tets(int64_t n_nodes, const int32_t* tets, int64_t n_tets, const std::
 
 // Sorted unique neighbour columns of every row.  row_node[r] is the global
 // node of row r; col_of[g] maps a global node to its column (-1 = excluded).
+// Each thread fills a flat buffer for its contiguous range of rows; the
+// ranges are laid end to end after.
 void build_pattern(const int32_t* tets, const std::vector<int>& row_node,
                    const std::vector<int>& tptr, const std::vector<int>& tlst,
                    const std::vector<int>& col_of, std::vector<int>& rp, std::vector<int>& ci) {
   const int64_t R = (int64_t)row_node.size();
-  std::vector<int> cnt(R + 1, 0);
-  std::vector<std::vector<int>> rows(R);
+  rp.assign(R + 1, 0);
+  std::mutex mu;
+  std::map<int64_t, std::vector<int>> parts;   // by first row of the range
   parallel_for(R, [&](int64_t a, int64_t b) {
-    std::vector<int> tmp;
+    std::vector<int> part, tmp;
     for (int64_t r = a; r < b; ++r) {
       int g = row_node[r];
       tmp.clear();
@@ -91,16 +96,15 @@ void build_pattern(const int32_t* tets, const std::vector<int>& row_node,
       }
       std::sort(tmp.begin(), tmp.end());
       tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
-      rows[r] = tmp;
-      cnt[r + 1] = (int)tmp.size();
+      part.insert(part.end(), tmp.begin(), tmp.end());
+      rp[r + 1] = (int)tmp.size();
     }
+    std::lock_guard<std::mutex> g(mu);
+    parts[a] = std::move(part);
   });
-  rp.assign(R + 1, 0);
-  for (int64_t r = 0; r < R; ++r) rp[r + 1] = rp[r] + cnt[r + 1];
+  for (int64_t r = 0; r < R; ++r) rp[r + 1] += rp[r];
   ci.resize(rp[R]);
-  parallel_for(R, [&](int64_t a, int64_t b) {
-    for (int64_t r = a; r < b; ++r) std::copy(rows[r].begin(), rows[r].end(), ci.begin() + rp[r]);
-  });
+  for (auto& kv : parts) std::copy(kv.second.begin(), kv.second.end(), ci.begin() + rp[kv.first]);
 }
 
 inline int find_col(const std::vector<int>& ci, int a, int b, int c) {
