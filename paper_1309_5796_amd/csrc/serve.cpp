@@ -32,7 +32,8 @@ size_t align_up_bytes(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Setup workers: host assembly and multigrid setup of several requests overlap
 // (only their uploads serialize on the upload context).  Measured on the
-// 60-request stream: 1 worker p50 10.1 s, 3 workers 4.8 s, 6 workers 3.7 s.
+// 60-request stream: 1 worker p50 10.1 s, 3 workers 4.8 s, 6 workers 3.3 s;
+// 10 and 12 workers were slower (4.4 and 5.3 s: the host CPU is saturated).
 constexpr int kSetupThreads = 6;
 
 enum ReqState { RQ_QUEUED, RQ_SETUP, RQ_READY, RQ_RESIDENT, RQ_DONE, RQ_FAILED, RQ_CANCELLED };
