@@ -51,7 +51,7 @@ int blocks_for(int64_t rows, int lpr, int max_blocks) {
   return (int)((g + 7) / 8 * 8);
 }
 
-Layout make_layout(int64_t N, int64_t nnzM, int64_t Nt, int64_t nnzLs, int G, size_t s) {
+Layout make_layout(int64_t N, int64_t nnzM, int64_t Nt, int64_t nnzLs, size_t s) {
   Layout L{};
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -669,7 +669,7 @@ int build_device(mmsd_problem p) {
   p->lpr = c->lpr;
   p->G = blocks_for(std::max<int64_t>(N, Nt), p->lpr, c->max_blocks);
   const int G = p->G;
-  Layout L = make_layout(N, nnzM, Nt, nnzLs, G, sizeof(real));
+  Layout L = make_layout(N, nnzM, Nt, nnzLs, sizeof(real));
   p->arena = (char*)c->dalloc(L.total);
   if (!p->arena) {
     set_error("device allocation of " + std::to_string(L.total) + " bytes failed");
@@ -754,7 +754,7 @@ int build_device(mmsd_problem p) {
 int set_launch(mmsd_problem p, int lpr, int max_blocks) {
   const int G = blocks_for(std::max<int64_t>(p->A.N, p->A.Nt), lpr, max_blocks);
   if (G == p->G && lpr == p->lpr) return MMSD_OK;
-  for (auto& kv : p->graphs) hipGraphExecDestroy(kv.second);
+  for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
   p->graphs.clear();
   p->lpr = lpr;
   p->G = G;
@@ -863,7 +863,7 @@ int issue(mmsd_ctx c, const std::vector<Table>& tabs, int B, std::map<int, hipGr
       if (ec != hipSuccess) return hip_fail(ec, "hipStreamEndCapture");
       hipGraphExec_t ex;
       hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-      hipGraphDestroy(g);
+      (void)hipGraphDestroy(g);
       if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
       it = graphs->emplace(B, ex).first;
     }
@@ -999,8 +999,8 @@ int run_single(mmsd_problem p, const Resolved& r, int stage, int store_h, mmsd_r
     B = std::min(B * 2, 64);
   }
   hipError_t e = hipStreamSynchronize(st);
-  hipEventDestroy(ev[0]);
-  hipEventDestroy(ev[1]);
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
   if (rc) return rc;
   if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
   const Ctrl& C = latest(&p->hctrl[2 * cur]);
@@ -1074,7 +1074,7 @@ int snapshot(mmsd_problem p, int k, bool save) {
 
 int snap_locked(mmsd_problem p, int k, bool save) {
   std::lock_guard<std::mutex> lk(p->ctx->mu);
-  hipSetDevice(p->ctx->device);
+  (void)hipSetDevice(p->ctx->device);
   int rc = p->precision == MMSD_MIXED ? snapshot<float>(p, k, save) : snapshot<double>(p, k, save);
   if (rc) return rc;
   MMSD_HIP(hipStreamSynchronize(p->ctx->stream));
@@ -1106,7 +1106,7 @@ void* mmsd_ctx_s::dalloc(size_t bytes) {
 void mmsd_ctx_s::dfree(void* p) {
   if (!p) return;
   if (free_fn) free_fn(p, user);
-  else hipFree(p);
+  else (void)hipFree(p);
 }
 
 // ============================ C ABI =======================================
@@ -1157,11 +1157,11 @@ int mmsd_ctx_create(int device, void* hip_stream, mmsd_alloc_fn alloc, mmsd_free
 
 int mmsd_ctx_destroy(mmsd_ctx c) {
   if (!c) return invalid("null context");
-  hipSetDevice(c->device);
-  hipStreamSynchronize(c->stream);
-  for (hipEvent_t e : c->timing.pool) hipEventDestroy(e);
-  for (hipEvent_t e : c->timing.pending) hipEventDestroy(e);
-  if (c->own_stream) hipStreamDestroy(c->stream);
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->timing.pool) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->timing.pending) (void)hipEventDestroy(e);
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
   return MMSD_OK;
 }
@@ -1208,14 +1208,13 @@ int mmsd_footprint(const mmsd_mesh* mesh, int precision, size_t* bytes_out) {
     set_error(err);
     return rc;
   }
-  const int G = blocks_for(std::max(ps.N, ps.Nt), 4, 512);
   const size_t sv = precision == MMSD_MIXED ? 4 : 8;
   // the multigrid hierarchy's arena, known only after its setup: an
   // allowance of (24 + 2 s) bytes per potential-matrix entry and 8 s per
   // potential node (the 80 nm cube's FP64 hierarchy, counted from its
   // layout: ~155 MB against 166 MB allowed)
   const size_t amg = ps.Nt > 0 ? (24 + 2 * sv) * (size_t)ps.nnzLs + 8 * sv * (size_t)ps.Nt : 0;
-  *bytes_out = make_layout(ps.N, ps.nnzM, ps.Nt, ps.nnzLs, G, sv).total + amg;
+  *bytes_out = make_layout(ps.N, ps.nnzM, ps.Nt, ps.nnzLs, sv).total + amg;
   return MMSD_OK;
 }
 
@@ -1244,7 +1243,7 @@ int mmsd_problem_create(mmsd_ctx c, const mmsd_mesh* mesh, const mmsd_material* 
     // the level operators are kept only for sizes and byte counts
   }
   std::lock_guard<std::mutex> lk(c->mu);
-  hipSetDevice(c->device);
+  (void)hipSetDevice(c->device);
   rc = precision == MMSD_MIXED ? build_device<float>(p) : build_device<double>(p);
   if (rc) {
     if (p->arena) c->dfree(p->arena);
@@ -1260,10 +1259,10 @@ int mmsd_problem_destroy(mmsd_problem p) {
   if (!p) return invalid("null problem");
   mmsd_ctx c = p->ctx;
   std::lock_guard<std::mutex> lk(c->mu);
-  hipSetDevice(c->device);
-  hipStreamSynchronize(c->stream);
-  for (auto& kv : p->graphs) hipGraphExecDestroy(kv.second);
-  if (p->hctrl) hipHostFree(p->hctrl);
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+  if (p->hctrl) (void)hipHostFree(p->hctrl);
   c->dfree(p->arena);
   if (p->amg_arena) c->dfree(p->amg_arena);
   delete p;
@@ -1298,7 +1297,7 @@ int mmsd_set_material(mmsd_problem p, const mmsd_material* m) {
     return rc;
   }
   std::lock_guard<std::mutex> lk(p->ctx->mu);
-  hipSetDevice(p->ctx->device);
+  (void)hipSetDevice(p->ctx->device);
   hipStream_t st = p->ctx->stream;
   if (p->precision == MMSD_MIXED) {
     Prob<float>& P = desc_of<float>(p);
@@ -1325,14 +1324,14 @@ int mmsd_set_field(mmsd_problem p, const double b[3]) {
 int mmsd_set_m(mmsd_problem p, const double* m) {
   if (!p || !m) return invalid("null argument");
   std::lock_guard<std::mutex> lk(p->ctx->mu);
-  hipSetDevice(p->ctx->device);
+  (void)hipSetDevice(p->ctx->device);
   return p->precision == MMSD_MIXED ? copy_m_to_device<float>(p, m, true) : copy_m_to_device<double>(p, m, true);
 }
 
 int mmsd_get_m(mmsd_problem p, double* m_out) {
   if (!p || !m_out) return invalid("null argument");
   std::lock_guard<std::mutex> lk(p->ctx->mu);
-  hipSetDevice(p->ctx->device);
+  (void)hipSetDevice(p->ctx->device);
   return p->precision == MMSD_MIXED ? copy_m_to_host<float>(p, m_out) : copy_m_to_host<double>(p, m_out);
 }
 
@@ -1356,7 +1355,7 @@ int mmsd_get_field(mmsd_problem p, double* h_out) {
   if (!p || !h_out) return invalid("null argument");
   if (!p->h_valid) return invalid("no field stored: call mmsd_evaluate first");
   std::lock_guard<std::mutex> lk(p->ctx->mu);
-  hipSetDevice(p->ctx->device);
+  (void)hipSetDevice(p->ctx->device);
   const int N = p->A.N;
   hipStream_t st = p->ctx->stream;
   std::vector<double> tmp(3 * (size_t)N);
@@ -1380,7 +1379,7 @@ int mmsd_get_field(mmsd_problem p, double* h_out) {
 int mmsd_get_potential(mmsd_problem p, double* u_out) {
   if (!p || !u_out) return invalid("null argument");
   std::lock_guard<std::mutex> lk(p->ctx->mu);
-  hipSetDevice(p->ctx->device);
+  (void)hipSetDevice(p->ctx->device);
   const Assembly& A = p->A;
   std::fill(u_out, u_out + A.n_nodes, 0.0);
   if (!A.Nt) return MMSD_OK;
@@ -1554,19 +1553,21 @@ int mmsd_minimize_batch(mmsd_problem* probs, int n, const mmsd_options* o, mmsd_
     rc = arm(probs[i], rs[i], ST_INIT, 0);
   }
   std::map<int, hipGraphExec_t> graphs;
-  int64_t launched = 0;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if (!rc && (hipEventCreateWithFlags(&ev[0], hipEventDisableTiming) != hipSuccess ||
+              hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess))
+    rc = hip_fail(hipGetLastError(), "poll events");
   if (!rc) {
     int B = 8, cur = 0;
     bool have_prev = false;
     unsigned compacted_at = 0;
-    hipEvent_t ev[2];
-    hipEventCreateWithFlags(&ev[0], hipEventDisableTiming);
-    hipEventCreateWithFlags(&ev[1], hipEventDisableTiming);
     for (;;) {
       if ((rc = issue(c, tabs, B, &graphs))) break;
-      launched += B;
-      hipMemcpyAsync(&hdone[cur], dndone, sizeof(unsigned), hipMemcpyDeviceToHost, st);
-      hipEventRecord(ev[cur], st);
+      if (hipMemcpyAsync(&hdone[cur], dndone, sizeof(unsigned), hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipEventRecord(ev[cur], st) != hipSuccess) {
+        rc = hip_fail(hipGetLastError(), "batch poll");
+        break;
+      }
       if (have_prev) {
         hipError_t e = hipEventSynchronize(ev[1 - cur]);
         if (e != hipSuccess) {
@@ -1595,7 +1596,7 @@ int mmsd_minimize_batch(mmsd_problem* probs, int n, const mmsd_options* o, mmsd_
           }
           if (nd_now >= (unsigned)n) break;
           for (unsigned k = 0; k < nd_now; ++k) done[list[k]] = 1;
-          for (auto& kv : graphs) hipGraphExecDestroy(kv.second);
+          for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
           graphs.clear();
           if ((rc = build_tables(done))) break;
           compacted_at = nd_now;
@@ -1609,11 +1610,11 @@ int mmsd_minimize_batch(mmsd_problem* probs, int n, const mmsd_options* o, mmsd_
       cur ^= 1;
       B = std::min(B * 2, 64);
     }
-    hipStreamSynchronize(st);
-    hipEventDestroy(ev[0]);
-    hipEventDestroy(ev[1]);
+    (void)hipStreamSynchronize(st);
   }
-  for (auto& kv : graphs) hipGraphExecDestroy(kv.second);
+  for (hipEvent_t e : ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
   if (!rc && c->timing.stride > 0) rc = drain_timing(c);
   double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   int worst = MMSD_OK;
@@ -1631,7 +1632,7 @@ int mmsd_minimize_batch(mmsd_problem* probs, int n, const mmsd_options* o, mmsd_
     if (C.status < 0) worst = C.status;
     else if (worst == MMSD_OK && C.status > 0) worst = C.status;
   }
-  if (hdone) hipHostFree(hdone);
+  if (hdone) (void)hipHostFree(hdone);
   if (tab) c->dfree(tab);
   c->dfree(misc);
   return rc ? rc : worst;
@@ -1656,18 +1657,18 @@ int mmsd_copy_probe(mmsd_ctx c, size_t bytes, int reps, double* ms_out) {
       hipEventCreate(&e1) != hipSuccess) {
     rc = hip_fail(hipGetLastError(), "copy probe setup");
   } else {
-    hipEventRecord(e0, st);
+    if (hipEventRecord(e0, st) != hipSuccess) rc = hip_fail(hipGetLastError(), "copy probe event");
     for (int k = 0; k < reps && !rc; ++k)
       if (launch_copy_probe(a, b, bytes, st) != hipSuccess) rc = hip_fail(hipGetLastError(), "copy probe");
-    hipEventRecord(e1, st);
-    hipEventSynchronize(e1);
     float ms = 0;
-    hipEventElapsedTime(&ms, e0, e1);
-    if (ms_out) *ms_out = ms / reps;
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    if (!rc && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      rc = hip_fail(hipGetLastError(), "copy probe timing");
+    if (!rc && ms_out) *ms_out = ms / reps;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
   }
-  hipStreamSynchronize(st);
+  (void)hipStreamSynchronize(st);
   c->dfree(a);
   c->dfree(b);
   return rc;
@@ -1754,8 +1755,8 @@ int mmsd_autotune(mmsd_problem p, int* lanes_out, int* blocks_out, double* us_ou
     }
     if (rc) break;
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   c->timing.stride = saved_stride;
   if (rc) return rc;
   // leave the problem idle at the chosen shape
@@ -1861,7 +1862,7 @@ int mmsd_set_state(mmsd_problem p, const void* buf, size_t bytes) {
   int rc;
   {
     std::lock_guard<std::mutex> lk(p->ctx->mu);
-    hipSetDevice(p->ctx->device);
+    (void)hipSetDevice(p->ctx->device);
     rc = p->precision == MMSD_MIXED ? copy_m_to_device<float>(p, (const double*)(b + 64), false)
                                     : copy_m_to_device<double>(p, (const double*)(b + 64), false);
   }

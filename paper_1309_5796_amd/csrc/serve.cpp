@@ -117,7 +117,7 @@ void finish_request(mmsd_server_s* s, Request* r, int status) {
 }  // namespace
 
 void mmsd_server_s::setup_loop() {
-  hipSetDevice(upload_ctx->device);
+  (void)hipSetDevice(upload_ctx->device);   // a failure surfaces in the calls that follow
   std::unique_lock<std::mutex> lk(mu);
   while (!stop) {
     Request* r = nullptr;
@@ -185,7 +185,7 @@ void mmsd_server_s::setup_loop() {
 }
 
 void mmsd_server_s::device_loop() {
-  hipSetDevice(loop_ctx->device);
+  (void)hipSetDevice(loop_ctx->device);   // a failure surfaces in the calls that follow
   hipStream_t st = loop_ctx->stream;
   std::vector<Request*> resident;
   std::vector<Table> tabs;
@@ -206,7 +206,7 @@ void mmsd_server_s::device_loop() {
       Request* r = resident[i];
       if (r->cancel) {
         lk.unlock();
-        hipStreamSynchronize(st);
+        (void)hipStreamSynchronize(st);   // errors surface in the next batch's checks
         mmsd_problem_destroy(r->prob);
         lk.lock();
         r->prob = nullptr;
@@ -228,7 +228,7 @@ void mmsd_server_s::device_loop() {
     int rc = MMSD_OK;
     if (dirty) {
       // rebuild the descriptor tables (no launch is in flight)
-      hipStreamSynchronize(st);
+      if (hipStreamSynchronize(st) != hipSuccess) rc = MMSD_E_HIP;
       tabs.clear();
       std::vector<int> idx[2];
       for (size_t i = 0; i < resident.size(); ++i) idx[resident[i]->precision == MMSD_MIXED ? 1 : 0].push_back((int)i);
@@ -236,7 +236,7 @@ void mmsd_server_s::device_loop() {
       for (int q = 0; q < 2; ++q)
         need += 2 * 256 + sizeof(Prob<double>) * idx[q].size() + 4 * (idx[q].size() + 1);
       if (need > dtab_bytes) {
-        if (dtab) hipFree(dtab);
+        if (dtab) (void)hipFree(dtab);
         dtab = nullptr;
         dtab_bytes = 0;
         if (hipMalloc((void**)&dtab, 2 * need) == hipSuccess) dtab_bytes = 2 * need;
@@ -245,7 +245,7 @@ void mmsd_server_s::device_loop() {
       unsigned* dndone = (unsigned*)dtab;
       int* dlist = (int*)(dtab + 256);
       size_t off = 256 + align_up_bytes(4 * (size_t)(resident.size() + 2));
-      if (!rc) hipMemsetAsync(dtab, 0, 256, st);
+      if (!rc && hipMemsetAsync(dtab, 0, 256, st) != hipSuccess) rc = MMSD_E_HIP;
       for (int q = 0; q < 2 && !rc; ++q) {
         if (idx[q].empty()) continue;
         const size_t ps = q ? sizeof(Prob<float>) : sizeof(Prob<double>);
@@ -278,11 +278,12 @@ void mmsd_server_s::device_loop() {
         off += align_up_bytes(h.size());
         char* db = dtab + off;
         off += align_up_bytes(4 * blk.size());
-        hipMemcpyAsync(dp, h.data(), h.size(), hipMemcpyHostToDevice, st);
-        hipMemcpyAsync(db, blk.data(), 4 * blk.size(), hipMemcpyHostToDevice, st);
+        if (hipMemcpyAsync(dp, h.data(), h.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(db, blk.data(), 4 * blk.size(), hipMemcpyHostToDevice, st) != hipSuccess)
+          rc = MMSD_E_HIP;
         tabs.push_back(Table{q ? MMSD_MIXED : MMSD_FP64, dp, (const int*)db, (int)idx[q].size(), blk.back(), lpr});
       }
-      if (hipStreamSynchronize(st) != hipSuccess) rc = MMSD_E_HIP;
+      if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = MMSD_E_HIP;
       processed = 0;
       dirty = false;
     }
@@ -318,15 +319,23 @@ void mmsd_server_s::device_loop() {
       Request* r = resident[slot];
       mmsd_problem p = r->prob;
       Ctrl two[2];
-      hipMemcpy(two, p->dctrl, 2 * sizeof(Ctrl), hipMemcpyDeviceToHost);
+      if (hipMemcpy(two, p->dctrl, 2 * sizeof(Ctrl), hipMemcpyDeviceToHost) != hipSuccess) {
+        r->error = "device failure reading the result";
+        r->status = MMSD_E_HIP;
+        continue;
+      }
       const Ctrl& C = latest(two);
       p->acc = C.acc;
       fill_result(p, C, &r->result, 0.0, C.launches_done);
       r->m_final.resize(3 * (size_t)p->A.N);
-      mmsd_get_m(p, r->m_final.data());
+      if (mmsd_get_m(p, r->m_final.data()) != MMSD_OK) {
+        r->error = mmsd_last_error();
+        r->status = MMSD_E_HIP;
+        continue;
+      }
       r->status = C.status;
     }
-    hipStreamSynchronize(st);
+    (void)hipStreamSynchronize(st);   // errors surface in the next batch's checks
     lk.lock();
     for (int k = (int)fin.size() - 1; k >= 0; --k) {
       Request* r = resident[fin[k]];
@@ -483,14 +492,14 @@ int mmsd_server_destroy(mmsd_server s) {
   s->cv_loop.notify_all();
   for (std::thread& t : s->setup_thr) t.join();
   s->loop_thr.join();
-  hipSetDevice(s->loop_ctx->device);
-  hipStreamSynchronize(s->loop_ctx->stream);
+  (void)hipSetDevice(s->loop_ctx->device);
+  (void)hipStreamSynchronize(s->loop_ctx->stream);
   for (auto& kv : s->reqs) {
     if (kv.second->prob) mmsd_problem_destroy(kv.second->prob);
     delete kv.second;
   }
-  if (s->dtab) hipFree(s->dtab);
-  if (s->hdone) hipHostFree(s->hdone);
+  if (s->dtab) (void)hipFree(s->dtab);
+  if (s->hdone) (void)hipHostFree(s->hdone);
   mmsd_ctx_destroy(s->upload_ctx);
   mmsd_ctx_destroy(s->loop_ctx);
   delete s;
