@@ -1178,8 +1178,12 @@ __device__ __forceinline__ void run_phase(const ProbDev<real>& P, const Ctrl* C,
   }
 }
 
-// At most 96 VGPRs (5 wavefronts per SIMD): two 512-thread blocks per CU stay
-// resident, the shape that measured fastest, with no register spills.
+// At most 128 VGPRs (4 wavefronts per SIMD): two 512-thread blocks per CU
+// stay resident (as they would at 5), with no register spills.  512 blocks
+// of 512 threads measured fastest overall: 768 blocks slowed the sweep by
+// 16%; 256 blocks of 1024 threads (the same wavefronts per CU) took 1.5% off
+// a PCG iteration of the 80 nm cube but slowed the small grain problems by
+// 6-10%.
 template <typename real, int LPR>
 __global__ void __launch_bounds__(kBlock, 4) k_step(const ProbDev<real>* __restrict__ probs, int nprob,
                                                     const int* __restrict__ blk_start, int parity) {
