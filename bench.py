@@ -377,6 +377,9 @@ def main():
     ap.add_argument("--poly-prec", default="both", choices=["both", "mixed", "fp64"])
     ap.add_argument("--precond", default="auto", choices=["auto", "jacobi", "amg"],
                     help="preconditioner of the potential solve")
+    ap.add_argument("--vcycle", default="fused", choices=["fused", "plain"],
+                    help="multigrid cycle: restriction and coarse solve fused into the down-sweep "
+                         "where the library finds it pays (default), or the plain order")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is "
@@ -397,6 +400,8 @@ def main():
     ctx = binding.Context(0)
     if args.lanes or args.blocks:
         ctx.set_launch_config(lanes_per_row=args.lanes, max_blocks=args.blocks)
+    if args.vcycle == "plain":
+        ctx.set_vcycle(0)
     p = binding.Problem(ctx, cfg["mesh"], precision=binding.FP64)
     state0 = p.get_state()
     pc = {"auto": binding.PRECOND_AUTO, "jacobi": binding.PRECOND_JACOBI, "amg": binding.PRECOND_AMG}[args.precond]
@@ -443,7 +448,7 @@ def main():
         "config": {"workload": f"FP64 hysteresis sweep, 80 nm cube, 40^3 Kuhn cells ({p.N:,} magnet / "
                                f"{p.Nt:,} potential nodes), +8 -> -8 -> +8 T in 0.1 T steps at 1 deg",
                    "field_points": K, "magnet_nodes": p.N, "potential_nodes": p.Nt,
-                   "potential_preconditioner": args.precond},
+                   "potential_preconditioner": args.precond, "vcycle": args.vcycle},
         "roofline": roof,
         "detail": {"evals": evals, "iterations": iters, "pcg_iters": pcg, "launches": launches,
                    "wall_s": wall, "switching_fields_T": [float(b) for b in bsw],
