@@ -29,9 +29,16 @@
 
 namespace mmsd {
 
+namespace {
+thread_local const std::atomic<int>* t_sharing = nullptr;
+}  // namespace
+
+void share_cores(const std::atomic<int>* active) { t_sharing = active; }
+
 void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& f) {
   unsigned hw = std::thread::hardware_concurrency();
   int nt = (int)std::max<unsigned>(1, std::min<unsigned>(hw ? hw : 4, 16));
+  if (t_sharing) nt = std::max(1, std::min(nt, (int)(hw ? hw : 4) / std::max(1, t_sharing->load())));
   if (n < 2048) nt = 1;
   if (nt == 1) {
     f(0, n);

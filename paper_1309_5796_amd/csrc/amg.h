@@ -3,6 +3,7 @@
 // `smooth_levels` levels, plain aggregation below), Galerkin coarse
 // operators, dense inverse on the coarsest level.
 #pragma once
+#include <atomic>
 #include <cstdint>
 #include <functional>
 #include <vector>
@@ -40,8 +41,14 @@ struct AmgParams {
 };
 
 // Runs f(a, b) over [0, n) cut into contiguous ranges, on up to 16 threads
-// (one for n < 2048).
+// (one for n < 2048), and on the calling thread's share of the cores when a
+// sharing counter is set (below).
 void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& f);
+
+// Threads that share the cores: while `active` is set on a thread, its
+// parallel_for calls use at most cores / *active threads (the server's setup
+// workers set it to their count of busy workers).  nullptr: no sharing.
+void share_cores(const std::atomic<int>* active);
 
 // M = R (I - A W) with W = omega D^-1: the restriction of the residual left
 // by one damped-Jacobi sweep from zero, b_{l+1} = M b_l.  For symmetric A,

@@ -9,6 +9,8 @@
 // deterministic.
 #include "assemble.h"
 
+#include "amg.h"
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -37,24 +39,6 @@ struct CompensatedSum {
 
 
 constexpr double kNm = 1e-9;
-
-void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& body) {
-  unsigned hw = std::thread::hardware_concurrency();
-  int64_t nt = std::max<int64_t>(1, std::min<int64_t>(hw ? hw : 4, 16));
-  if (n < 4096) nt = 1;
-  if (nt == 1) {
-    body(0, n);
-    return;
-  }
-  std::vector<std::thread> th;
-  int64_t chunk = (n + nt - 1) / nt;
-  for (int64_t t = 0; t < nt; ++t) {
-    int64_t a = t * chunk, b = std::min(n, a + chunk);
-    if (a >= b) break;
-    th.emplace_back(body, a, b);
-  }
-  for (auto& x : th) x.join();
-}
 
 // Node -> incident (tet, vertex) lists, for the tets selected by `keep`.
 void node_tets(int64_t n_nodes, const int32_t* tets, int64_t n_tets, const std::vector<char>& keep,

@@ -14,12 +14,14 @@
 // Each problem keeps its own block decomposition, so its result does not
 // depend on what else is resident.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
 #include <thread>
 
+#include "amg.h"
 #include "runtime.h"
 
 using namespace mmsd;
@@ -34,6 +36,8 @@ size_t align_up_bytes(size_t x) { return (x + 255) & ~size_t(255); }
 // (only their uploads serialize on the upload context).  Measured on the
 // 60-request stream: 1 worker p50 10.1 s, 3 workers 4.8 s, 6 workers 3.3 s;
 // 10 and 12 workers were slower (4.4 and 5.3 s: the host CPU is saturated).
+// The busy workers split the cores between their parallel loops (6 workers:
+// p50 2.7-3.0 s).
 constexpr int kSetupThreads = 6;
 
 enum ReqState { RQ_QUEUED, RQ_SETUP, RQ_READY, RQ_RESIDENT, RQ_DONE, RQ_FAILED, RQ_CANCELLED };
@@ -93,6 +97,7 @@ struct mmsd_server_s {
   double n_submitted = 0, n_completed = 0, launches = 0, node_evals = 0;
   double setup_seconds = 0, loop_seconds = 0;   // summed over setups; device loop busy time
   std::vector<std::thread> setup_thr;   // host assembly, multigrid setup and upload overlap across threads
+  std::atomic<int> busy_setups{0};      // workers inside a setup: they share the cores
   std::thread loop_thr;
   // device-side tables (owned by the loop thread)
   char* dtab = nullptr;
@@ -118,6 +123,7 @@ void finish_request(mmsd_server_s* s, Request* r, int status) {
 
 void mmsd_server_s::setup_loop() {
   (void)hipSetDevice(upload_ctx->device);   // a failure surfaces in the calls that follow
+  mmsd::share_cores(&busy_setups);          // the setup's parallel loops split the cores among busy workers
   std::unique_lock<std::mutex> lk(mu);
   while (!stop) {
     Request* r = nullptr;
@@ -149,6 +155,7 @@ void mmsd_server_s::setup_loop() {
     lk.unlock();
     // assemble + upload outside the lock
     const auto t_setup = Clock::now();
+    busy_setups.fetch_add(1);
     mmsd_mesh m = r->mesh();
     mmsd_problem p = nullptr;
     int rc = mmsd_problem_create(upload_ctx, &m, r->mats.data(), (int)r->mats.size(), r->precision, &p);
@@ -165,6 +172,7 @@ void mmsd_server_s::setup_loop() {
     }
     if (rc) r->error = mmsd_last_error();
     lk.lock();
+    busy_setups.fetch_sub(1);
     setup_seconds += std::chrono::duration<double>(Clock::now() - t_setup).count();
     if (rc) {
       if (p) mmsd_problem_destroy(p);
