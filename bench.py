@@ -31,7 +31,7 @@ METRIC = "node-iterations/s + HBM roofline fraction; served-solve p50/p99 latenc
 HBM_PEAK_GBS = 8000.0
 
 
-def cpu_baseline(n_evals: int = 2) -> dict:
+def cpu_baseline(n_evals: int = 5) -> dict:
     """Time the oracle (one thread) on a prefix of the first field point of the
     same sweep: `n_evals` energy-gradient evaluations of its minimizer."""
     code = f"""
