@@ -284,7 +284,10 @@ int mmsd_assembly_export(const mmsd_mesh* mesh, const mmsd_material* mats, int n
  * most max_slots resident), assembles and uploads them off the critical
  * path, advances every resident problem by one phase per device launch
  * (continuous batching), and releases a slot as soon as its problem is done.
- * A request runs with the block count mmsd_minimize_batch would give it. */
+ * A request runs with the block count mmsd_minimize_batch would give it.
+ * mmsd_submit copies the request and returns at once; its footprint is sized
+ * (mmsd_footprint) by an idle setup worker, in queue order, so a mesh that
+ * fails validation is reported by mmsd_poll, not by mmsd_submit. */
 int mmsd_server_create(mmsd_ctx ctx, size_t hbm_budget, int max_slots, mmsd_server* out);
 int mmsd_submit(mmsd_server s, const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats,
                 const double b_T[3], int precision, const double* m0 /* nullable: +z */,

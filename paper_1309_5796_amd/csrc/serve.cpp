@@ -52,7 +52,10 @@ struct Request {
   int precision = MMSD_FP64;
   std::vector<double> m0;
   mmsd_options opts{};
-  size_t footprint = 0;
+  size_t footprint = 0;    // device bytes: estimate (sizing), exact once resident
+  bool sized = false;      // footprint known (sizing runs on a setup worker, not in submit)
+  bool sizing = false;     // a worker is sizing it
+  int size_rc = MMSD_OK;   // sizing failed (invalid mesh)
   ReqState state = RQ_QUEUED;
   bool cancel = false;
   mmsd_problem prob = nullptr;
@@ -127,11 +130,23 @@ void mmsd_server_s::setup_loop() {
   std::unique_lock<std::mutex> lk(mu);
   while (!stop) {
     Request* r = nullptr;
-    if (!queue.empty()) {
+    Request* tosize = nullptr;   // the first queued request nobody has sized yet
+    for (Request* q : queue)
+      if (!q->sized && !q->sizing && !q->cancel) {
+        tosize = q;
+        break;
+      }
+    // a request being sized stays queued (its worker still writes to it), cancelled or not
+    if (!queue.empty() && !queue.front()->sizing && (queue.front()->sized || queue.front()->cancel)) {
       Request* f = queue.front();
       if (f->cancel) {
         queue.pop_front();
         finish_request(this, f, MMSD_E_CANCELLED);
+        continue;
+      }
+      if (f->size_rc != MMSD_OK) {
+        queue.pop_front();
+        finish_request(this, f, f->size_rc);
         continue;
       }
       if (f->footprint > budget) {
@@ -147,6 +162,26 @@ void mmsd_server_s::setup_loop() {
         slots_used += 1;
         r->state = RQ_SETUP;
       }
+    }
+    if (!r && tosize) {
+      // size a queued request outside the lock (admission needs its bytes)
+      tosize->sizing = true;
+      const mmsd_mesh m = tosize->mesh();
+      const int precision = tosize->precision;
+      lk.unlock();
+      busy_setups.fetch_add(1);
+      size_t fp = 0;
+      const int rc = mmsd_footprint(&m, precision, &fp);
+      const std::string err = rc ? mmsd_last_error() : std::string();
+      busy_setups.fetch_sub(1);
+      lk.lock();
+      tosize->footprint = fp;
+      tosize->size_rc = rc;
+      if (rc) tosize->error = err;
+      tosize->sized = true;
+      tosize->sizing = false;
+      cv_setup.notify_all();
+      continue;
     }
     if (!r) {
       cv_setup.wait_for(lk, std::chrono::milliseconds(20));
@@ -400,9 +435,6 @@ int mmsd_submit(mmsd_server s, const mmsd_mesh* mesh, const mmsd_material* mats,
     set_error("bad submit arguments");
     return MMSD_E_INVALID;
   }
-  size_t fp = 0;
-  int rc = mmsd_footprint(mesh, precision, &fp);
-  if (rc) return rc;
   auto* r = new Request;
   r->xyz.assign(mesh->xyz, mesh->xyz + 3 * mesh->n_nodes);
   r->tets.assign(mesh->tets, mesh->tets + 4 * mesh->n_tets);
@@ -424,8 +456,7 @@ int mmsd_submit(mmsd_server s, const mmsd_mesh* mesh, const mmsd_material* mats,
   }
   if (o) r->opts = *o;
   else mmsd_options_default(&r->opts);
-  r->footprint = fp;
-  r->t_submit = Clock::now();
+  r->t_submit = Clock::now();   // sized later, on a setup worker
   std::lock_guard<std::mutex> lk(s->mu);
   r->ticket = s->next_ticket++;
   s->reqs[r->ticket] = r;

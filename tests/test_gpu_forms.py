@@ -203,6 +203,12 @@ def test_server_results_equal_alone_and_in_the_mix(ctx):
         mesh, m0 = small_grain(edge, seed)
         tickets.append((srv.submit(mesh, -1.5 * meshgen.U_H_1DEG, precision=prec, m0=m0),
                         meshgen.n_magnetic(mesh)))
+    # a broken mesh in the queue: submit accepts it (sizing runs later, on a
+    # setup worker), its poll reports the mesh error, and the others still finish
+    bad, _ = small_grain(10, 17)
+    bad.tets = bad.tets.copy()
+    bad.tets[3, 2] = bad.xyz.shape[0] + 5
+    bad_ticket = srv.submit(bad, -1.5 * meshgen.U_H_1DEG)
     got = {}
     t0 = time.time()
     while len(got) < len(tickets) and time.time() - t0 < 120:
@@ -217,8 +223,13 @@ def test_server_results_equal_alone_and_in_the_mix(ctx):
     for k in range(len(reqs)):
         r, m = got[k]
         assert (r.energy_J, r.evals, m.tobytes()) == alone[k], k
+    t0 = time.time()
+    with pytest.raises(binding.MMSDError, match="out of range") as e:
+        while srv.poll(bad_ticket) is None and time.time() - t0 < 30:
+            time.sleep(0.01)
+    assert e.value.code == binding.E_MESH
     st = srv.stats()
-    assert st["completed"] == len(reqs) and st["resident"] == 0
+    assert st["completed"] == len(reqs) + 1 and st["resident"] == 0
     srv.close()
 
 
