@@ -288,7 +288,7 @@ def run_serve(args):
     line["roofline"] = None
     lat_sub = np.array(lat_sub)
     # latency from each request's arrival time (its place in the stream), and
-    # from the return of its submit call (which sizes the request)
+    # from the return of its submit call (which only copies the request)
     line["detail"] = {"p50_s": float(np.percentile(lat, 50)) if len(lat) else None,
                       "p99_s": float(np.percentile(lat, 99)) if len(lat) else None,
                       "p50_from_submit_s": float(np.percentile(lat_sub, 50)) if len(lat_sub) else None,
@@ -351,6 +351,54 @@ def run_sphere(args):
     print(json.dumps(line), flush=True)
 
 
+def run_assemble(args):
+    """Operator assembly of one mesh, host (mmsd_assembly_export) against
+    device (mmsd_assemble_device: host patterns, device values), wall time of
+    one call each after an untimed size query and warm-up; on the largest
+    request of the served stream (520k magnet / 1.25M potential nodes) and
+    the 80 nm cube."""
+    import ctypes as C
+    import numpy as np
+    import torch
+    from paper_1309_5796_amd import binding, meshgen
+    reqs = meshgen.config5_requests()[:60]
+    meshes = [("served request (largest of the first 60)", meshgen.request_mesh(reqs[args.assemble_request])["mesh"]),
+              ("80 nm cube", meshgen.config2()["mesh"])]
+    ctx = binding.Context(0)
+    lib = ctx.lib
+    out = []
+    for name, mesh in meshes:
+        a = binding.MeshArgs(mesh)
+        sizes = (C.c_int64 * 4)()
+        binding._check(lib.mmsd_assembly_export(C.byref(a.c), a.mats, a.n_mats, sizes, *([None] * 12)))
+        N, nnzM, Nt, nnzL = (int(x) for x in sizes)
+        host = [np.empty(n) for n in (N + 1, nnzM, nnzM, 3 * nnzM, 3 * nnzM, 6 * N, N, Nt, Nt + 1, nnzL, nnzL, 4)]
+        hp = [x.ctypes.data_as(C.c_void_p) for x in host]
+        times_h, times_d = [], []
+        for rep in range(3):
+            t0 = time.perf_counter()
+            binding._check(lib.mmsd_assembly_export(C.byref(a.c), a.mats, a.n_mats, sizes, *hp))
+            times_h.append(time.perf_counter() - t0)
+        dev = torch.device("cuda", 0)
+        outs = [torch.empty(max(n, 1), dtype=torch.float64, device=dev)
+                for n in (N + 1, nnzM, nnzM, 3 * nnzM, 3 * nnzM, 6 * N, N, Nt, Nt + 1, nnzL, nnzL)]
+        dp = [C.c_void_p(t.data_ptr()) for t in outs]
+        for rep in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            binding._check(lib.mmsd_assemble_device(ctx.handle, C.byref(a.c), a.mats, a.n_mats, sizes, *dp))
+            torch.cuda.synchronize()
+            times_d.append(time.perf_counter() - t0)
+        print(f"[bench] assemble {name}: host {min(times_h):.3f} s, device {min(times_d):.3f} s",
+              file=sys.stderr, flush=True)
+        out.append({"mesh": name, "magnet_nodes": N, "potential_nodes": Nt, "tets": int(mesh.tets.shape[0]),
+                    "host_s": min(times_h), "device_s": min(times_d)})
+        del outs, host
+    ctx.close()
+    print(json.dumps({"workload": "operator assembly, host vs device values", "host_threads":
+                      min(16, os.cpu_count() or 1), "detail": out}), flush=True)
+
+
 def run_copy(args):
     """Counter calibration: a plain 256 MiB device copy (read 256 MiB, write 256 MiB)."""
     from paper_1309_5796_amd import binding
@@ -374,7 +422,9 @@ def main():
     ap.add_argument("--blocks", type=int, default=0, help="blocks per problem (multiple of 8; 0 = library default)")
     ap.add_argument("--chunk", type=int, default=20, help="field points per library call")
     ap.add_argument("--workload", default="sweep80",
-                    choices=["sweep80", "poly", "grains", "serve", "sphere", "copy"])
+                    choices=["sweep80", "poly", "grains", "serve", "sphere", "copy", "assemble"])
+    ap.add_argument("--assemble-request", type=int, default=38,
+                    help="request of the served stream whose mesh --workload assemble times")
     ap.add_argument("--max-evals", type=int, default=100000)
     ap.add_argument("--grains", type=int, default=256)
     ap.add_argument("--requests", type=int, default=60)
@@ -394,7 +444,7 @@ def main():
         sys.exit(2)
     if args.workload != "sweep80":
         {"poly": run_poly, "grains": run_grains, "serve": run_serve, "sphere": run_sphere,
-         "copy": run_copy}[args.workload](args)
+         "copy": run_copy, "assemble": run_assemble}[args.workload](args)
         return
 
     import numpy as np

@@ -278,6 +278,24 @@ int mmsd_assembly_export(const mmsd_mesh* mesh, const mmsd_material* mats, int n
                          int32_t* mrp, int32_t* mci, double* K, double* D1, double* D2, double* Q, double* V,
                          int32_t* pot_global, int32_t* lrp, int32_t* lci, double* L, double* scalars);
 
+/* Device-side assembly of the same operators (Abstract: linear tetrahedral
+ * elements; Results, comparison section: the transformed open-boundary
+ * Laplacian).  The host validates the mesh and materials and builds the
+ * numbering, adjacency and sparsity patterns; HIP kernels on ctx's stream
+ * compute the tet geometry and shell metric and every value.  Arguments and
+ * layouts are those of mmsd_assembly_export without scalars, but every array
+ * is DEVICE memory the caller owns: all eleven NULL = size query (sizes[4]
+ * only, no device work), all eleven set = assemble; a mix is MMSD_E_INVALID.
+ * With N_t = 0, lrp[1] = {0} and lci, L, pot_global are untouched.
+ * Temporaries (~150 B per tet) come from ctx's allocator and are freed before
+ * return; the call returns once the values are written.  Errors: the host
+ * checks of mmsd_assembly_export (MMSD_E_MESH / MMSD_E_INVALID), degenerate
+ * tets, tets outside the shell and non-positive diagonals found by the
+ * kernels (MMSD_E_MESH), MMSD_E_NOMEM, MMSD_E_HIP. */
+int mmsd_assemble_device(mmsd_ctx ctx, const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats,
+                         int64_t sizes[4], int32_t* mrp, int32_t* mci, double* K, double* D1, double* D2,
+                         double* Q, double* V, int32_t* pot_global, int32_t* lrp, int32_t* lci, double* L);
+
 /* ---- serving ----------------------------------------------------------- */
 /* A server owns a worker thread that admits submitted minimizations while
  * their device footprint fits in hbm_budget bytes and a slot is free (at

@@ -92,6 +92,8 @@ SIGNATURES = [
     ("mmsd_autotune", C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     ("mmsd_assembly_export", C.c_int, [C.POINTER(MeshC), C.POINTER(MaterialC), C.c_int, C.POINTER(C.c_int64)]
      + [C.c_void_p] * 12),
+    ("mmsd_assemble_device", C.c_int, [C.c_void_p, C.POINTER(MeshC), C.POINTER(MaterialC), C.c_int,
+                                       C.POINTER(C.c_int64)] + [C.c_void_p] * 11),
     ("mmsd_server_create", C.c_int, [C.c_void_p, C.c_size_t, C.c_int, C.POINTER(C.c_void_p)]),
     ("mmsd_submit", C.c_int, [C.c_void_p, C.POINTER(MeshC), C.POINTER(MaterialC), C.c_int, C.POINTER(C.c_double),
                               C.c_int, C.POINTER(C.c_double), C.POINTER(OptionsC), C.POINTER(C.c_uint64)]),
@@ -227,6 +229,7 @@ class Context:
         _check(rc)
         self.handle = h
         self.lib = lib
+        self.device = device
         self._children = weakref.WeakSet()   # problems and servers to close first
 
     def set_launch_config(self, lanes_per_row: int = 0, max_blocks: int = 0):
@@ -416,6 +419,32 @@ def assembly_export(mesh, materials=None) -> dict:
     out["D1"] = out["D1"].reshape(3, nnzM)
     out["D2"] = out["D2"].reshape(3, nnzM)
     out["Q"] = out["Q"].reshape(6, N)
+    out.update(N=N, Nt=Nt)
+    return out
+
+
+def assemble_device(ctx: Context, mesh, materials=None) -> dict:
+    """The same operators as assembly_export, assembled by the device
+    kernels into torch tensors on ctx's device (no scalars)."""
+    import torch
+    lib = ctx.lib
+    a = MeshArgs(mesh, materials)
+    sizes = (C.c_int64 * 4)()
+    _check(lib.mmsd_assemble_device(ctx.handle, C.byref(a.c), a.mats, a.n_mats, sizes, *([None] * 11)))
+    N, nnzM, Nt, nnzL = (int(x) for x in sizes)
+    dev = torch.device("cuda", ctx.device)
+    i32, f64 = torch.int32, torch.float64
+    out = dict(mrp=torch.empty(N + 1, dtype=i32, device=dev), mci=torch.empty(nnzM, dtype=i32, device=dev),
+               K=torch.empty(nnzM, dtype=f64, device=dev), D1=torch.empty(3, nnzM, dtype=f64, device=dev),
+               D2=torch.empty(3, nnzM, dtype=f64, device=dev), Q=torch.empty(6, N, dtype=f64, device=dev),
+               V=torch.empty(N, dtype=f64, device=dev), pot_global=torch.empty(Nt, dtype=i32, device=dev),
+               lrp=torch.empty(Nt + 1, dtype=i32, device=dev), lci=torch.empty(nnzL, dtype=i32, device=dev),
+               L=torch.empty(nnzL, dtype=f64, device=dev))
+    order = ["mrp", "mci", "K", "D1", "D2", "Q", "V", "pot_global", "lrp", "lci", "L"]
+    # an empty tensor has no storage: give the library a valid one-element stand-in
+    keep = [out[k] if out[k].numel() else torch.empty(1, dtype=out[k].dtype, device=dev) for k in order]
+    _check(lib.mmsd_assemble_device(ctx.handle, C.byref(a.c), a.mats, a.n_mats, sizes,
+                                    *[C.c_void_p(t.data_ptr()) for t in keep]))
     out.update(N=N, Nt=Nt)
     return out
 

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmmsd.so")
-SOURCES = ["kernels.hip", "assemble.cpp", "amg.cpp", "api.cpp", "serve.cpp"]
+SOURCES = ["kernels.hip", "assemble_dev.hip", "assemble.cpp", "amg.cpp", "api.cpp", "serve.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

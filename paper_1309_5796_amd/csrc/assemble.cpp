@@ -512,4 +512,102 @@ int assemble(const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats, Assem
   return MMSD_OK;
 }
 
+int assemble_structure(const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats, AssemblyStructure* S,
+                       std::string* err) {
+  int st = check_mesh(mesh, err);
+  if (st) return st;
+  Numbering nb;
+  if ((st = number_nodes(mesh, &nb, err))) return st;
+  const int64_t E = mesh->n_tets;
+  const int32_t* tets = mesh->tets;
+  S->E = E;
+  S->N = (int)nb.mag_global.size();
+  S->Nt = (int)nb.pot_global.size();
+  S->mag_global = std::move(nb.mag_global);
+  S->pot_global = std::move(nb.pot_global);
+  S->pot_of = std::move(nb.pot_of);
+  std::map<int, MatLine> lines;
+  for (int k = 0; k < n_mats; ++k) {
+    const mmsd_material& m = mats[k];
+    double un = std::sqrt(m.easy_axis[0] * m.easy_axis[0] + m.easy_axis[1] * m.easy_axis[1] +
+                          m.easy_axis[2] * m.easy_axis[2]);
+    if (m.region < 1 || !(un > 0) || !(m.Js_T > 0) || !(m.A_Jm >= 0) || !std::isfinite(m.K1_Jm3)) {
+      *err = "invalid material for region " + std::to_string(m.region);
+      return MMSD_E_INVALID;
+    }
+    lines[m.region] = MatLine{m.Js_T, m.K1_Jm3, m.A_Jm, {m.easy_axis[0], m.easy_axis[1], m.easy_axis[2]}};
+  }
+  // magnetic tets
+  std::vector<char> keep(E);
+  int64_t Em = 0;
+  int max_region = 0;
+  for (int64_t e = 0; e < E; ++e) {
+    Em += (keep[e] = mesh->tet_region[e] > 0);
+    max_region = std::max(max_region, (int)mesh->tet_region[e]);
+  }
+  S->mtet.resize(4 * Em);
+  S->mtet_mesh.resize(Em);
+  S->mregion.resize(Em);
+  for (int64_t e = 0, k = 0; e < E; ++e)
+    if (keep[e]) S->mtet_mesh[k++] = (int)e;
+  parallel_for(Em, [&](int64_t k0, int64_t k1) {
+    for (int64_t k = k0; k < k1; ++k) {
+      const int64_t e = S->mtet_mesh[k];
+      for (int a = 0; a < 4; ++a) S->mtet[4 * k + a] = nb.mag_of[tets[4 * e + a]];
+      S->mregion[k] = mesh->tet_region[e];
+    }
+  });
+  // materials of the regions in use: one Js, factors as assemble_material_values forms them
+  std::vector<char> used(max_region + 1, 0);
+  for (int64_t k = 0; k < Em; ++k) used[S->mregion[k]] = 1;
+  double Js = -1;
+  for (int r = 1; r <= max_region; ++r) {
+    if (!used[r]) continue;
+    auto it = lines.find(r);
+    if (it == lines.end()) {
+      *err = "no material for region " + std::to_string(r);
+      return MMSD_E_INVALID;
+    }
+    if (Js < 0) Js = it->second.Js;
+    if (it->second.Js != Js) {
+      *err = "all magnetic regions must share one Js";
+      return MMSD_E_INVALID;
+    }
+  }
+  S->Js = Js;
+  const double Ms = Js / kMu0;
+  S->mu0Ms2 = kMu0 * Ms * Ms;
+  S->reg.assign(8 * (size_t)(max_region + 1), 0.0);
+  for (int r = 1; r <= max_region; ++r) {
+    if (!used[r]) continue;
+    const MatLine& M = lines[r];
+    double* t = &S->reg[8 * (size_t)r];
+    t[0] = M.A / (S->mu0Ms2 * kNm * kNm);
+    t[1] = M.K1;
+    double un = std::sqrt(M.u[0] * M.u[0] + M.u[1] * M.u[1] + M.u[2] * M.u[2]);
+    double u[3] = {M.u[0] / un, M.u[1] / un, M.u[2] / un};
+    t[2] = u[0] * u[0];
+    t[3] = u[1] * u[1];
+    t[4] = u[2] * u[2];
+    t[5] = u[0] * u[1];
+    t[6] = u[0] * u[2];
+    t[7] = u[1] * u[2];
+  }
+  {
+    std::vector<char> all(Em, 1);
+    node_tets(S->N, S->mtet.data(), Em, all, S->mnode_tets_ptr, S->mnode_tets);
+  }
+  {
+    std::vector<int> tptr, tlst;
+    node_tets(mesh->n_nodes, tets, E, keep, tptr, tlst);
+    build_pattern(tets, S->mag_global, tptr, tlst, nb.mag_of, S->mrp, S->mci);
+  }
+  if (S->Nt > 0) {
+    std::vector<char> all(E, 1);
+    node_tets(mesh->n_nodes, tets, E, all, S->tptr, S->tlst);
+    build_pattern(tets, S->pot_global, S->tptr, S->tlst, S->pot_of, S->lrp, S->lci);
+  }
+  return MMSD_OK;
+}
+
 }  // namespace mmsd

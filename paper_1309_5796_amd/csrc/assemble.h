@@ -62,4 +62,32 @@ int assemble(const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats, Assem
 // Recompute K, Q and c_an from a.mats (after a material change).
 int assemble_material_values(Assembly* a, std::string* err);
 
+// The combinatorial half of the assembly, for the device-side assembly of
+// the values: numbering, the magnetic tets with their node adjacency, both
+// sparsity patterns, every mesh node's tet adjacency, and per-region
+// material factors.  The rows, columns and summation orders are those of
+// assemble(), so the device sums the same terms in the same order.
+struct AssemblyStructure {
+  int64_t E = 0;                 // mesh tets
+  int N = 0, Nt = 0;
+  std::vector<int> mag_global, pot_global;
+  std::vector<int> pot_of;       // [n_nodes] potential row of a mesh node, -1 if none
+  std::vector<int> mtet;         // [Em*4] magnetic-node ids of magnetic tet k
+  std::vector<int> mtet_mesh;    // [Em] mesh tet of magnetic tet k
+  std::vector<int> mregion;      // [Em]
+  std::vector<int> mnode_tets_ptr, mnode_tets;   // magnetic node -> (magnetic tet, vertex)
+  std::vector<int> mrp, mci, lrp, lci;
+  std::vector<int> tptr, tlst;   // mesh node -> (mesh tet, vertex), all tets (when Nt > 0)
+  // per region id r (dense, 0..max region): [8r] A / (mu0 Ms^2 nm^2),
+  // [8r+1] K1, [8r+2..8r+7] products of the unit easy axis (xx yy zz xy xz yz)
+  std::vector<double> reg;
+  double Js = 0, mu0Ms2 = 0;
+};
+
+// Validates the mesh and the materials (as assemble() does, except that the
+// geometry checks, degenerate tets and tets outside the shell, are left to
+// the caller) and builds the structure.  Returns an MMSD_* status.
+int assemble_structure(const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats, AssemblyStructure* out,
+                       std::string* err);
+
 }  // namespace mmsd
