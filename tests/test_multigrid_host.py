@@ -36,3 +36,54 @@ def test_vcycle_rearrangements_are_identities(tmp_path):
         assert float(e_rest) < 1e-12, out
         assert float(e_post) < 1e-12, out
         assert float(e_rap) < 1e-12, out
+
+
+def write_mesh(path, mesh):
+    with open(path, "wb") as f:
+        d = getattr(mesh, "dirichlet", None)
+        sh = getattr(mesh, "shell", None)
+        np.array([mesh.xyz.shape[0], mesh.tets.shape[0], len(mesh.materials), d is not None, sh is not None],
+                 np.int64).tofile(f)
+        np.ascontiguousarray(mesh.xyz, np.float64).tofile(f)
+        np.ascontiguousarray(mesh.tets, np.int32).tofile(f)
+        np.ascontiguousarray(mesh.region, np.int32).tofile(f)
+        (np.zeros(mesh.xyz.shape[0], np.uint8) if d is None else np.ascontiguousarray(d, np.uint8)).tofile(f)
+        (np.zeros(9) if sh is None else np.ascontiguousarray(sh, np.float64)).tofile(f)
+        for m in mesh.materials:
+            np.array([m.region, m.Js, m.K1, m.A, *np.asarray(m.axis, float)], np.float64).tofile(f)
+
+
+@pytest.mark.parametrize("name", ["two_regions", "delaunay", "no_air"])
+def test_device_assembly_structure_matches_host_assembly(tmp_path, name):
+    """The host half of the device-side assembly: the structure equals the
+    full host assembly's, and the device kernels' per-row sums, replayed
+    here on the CPU from it, give the host values (same terms, same order)."""
+    if shutil.which("g++") is None:
+        pytest.skip("g++ not available")
+    if name == "two_regions":
+        mesh = meshgen.config1()["mesh"]
+        region = mesh.region.copy()
+        region[np.nonzero(region)[0][::3]] = 2
+        mesh = meshgen.Mesh(xyz=mesh.xyz, tets=mesh.tets, region=region, dirichlet=mesh.dirichlet,
+                            shell=mesh.shell, materials=mesh.materials + [
+                                meshgen.Material(2, meshgen.JS_T, 1.3e6, 3e-12, np.array([0.3, -0.2, 0.9]))])
+    elif name == "delaunay":
+        mesh = meshgen.delaunay_box(5)
+    else:
+        mesh = meshgen.config1(air=False)["mesh"]
+    exe = str(tmp_path / "structure_check")
+    subprocess.run(["g++", "-O2", "-std=c++17", "-I", CSRC, "-I", os.path.join(ROOT, "include"),
+                    os.path.join(ROOT, "tests", "native", "structure_check.cpp"), os.path.join(CSRC, "assemble.cpp"),
+                    os.path.join(CSRC, "amg.cpp"), "-o", exe, "-lpthread"], check=True)
+    path = str(tmp_path / "mesh.bin")
+    write_mesh(path, mesh)
+    out = subprocess.run([exe, path], check=True, capture_output=True, text=True).stdout
+    assert "structure equal" in out, out
+    rel = dict(zip(["V", "K", "D1", "D2", "Q"], map(float, re.findall(
+        r"rel V (\S+) K (\S+) D1 (\S+) D2 (\S+) Q (\S+)", out)[0])))
+    for k, v in rel.items():
+        assert v <= 1e-15, (k, out)
+    if "potential columns missing" in out:
+        assert "potential columns missing 0" in out, out
+    else:
+        assert name == "no_air", out
