@@ -291,7 +291,8 @@ int mmsd_assembly_export(const mmsd_mesh* mesh, const mmsd_material* mats, int n
  * return; the call returns once the values are written.  Errors: the host
  * checks of mmsd_assembly_export (MMSD_E_MESH / MMSD_E_INVALID), degenerate
  * tets, tets outside the shell and non-positive diagonals found by the
- * kernels (MMSD_E_MESH), MMSD_E_NOMEM, MMSD_E_HIP. */
+ * kernels (MMSD_E_MESH), more than 2^26 magnetic or potential rows
+ * (MMSD_E_INVALID), MMSD_E_NOMEM, MMSD_E_HIP. */
 int mmsd_assemble_device(mmsd_ctx ctx, const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats,
                          int64_t sizes[4], int32_t* mrp, int32_t* mci, double* K, double* D1, double* D2,
                          double* Q, double* V, int32_t* pot_global, int32_t* lrp, int32_t* lci, double* L);

@@ -9,9 +9,10 @@
 // assemble_structure); three kernels compute every value:
 //   k_asm_geo        one thread per tet: volume, P1 gradients, shell metric
 //   k_asm_magnet     one wavefront per magnetic row: V, D1, D2, K, Q
-//   k_asm_potential  one thread per potential row: L and its diagonal check
-// Each row entry is summed by one lane, in the host assembly's order (the
-// adjacency lists' order), so the sums need no atomics and are
+//   k_asm_potential  one wavefront per potential row: L and its diagonal check
+// In a row kernel the lanes first load one tet each and stage its terms in
+// LDS; then each row entry is summed by one lane, in the host assembly's
+// order (the adjacency lists' order), so the sums need no atomics and are
 // deterministic.
 #include <hip/hip_runtime.h>
 
@@ -103,7 +104,6 @@ __global__ __launch_bounds__(kAsmBlock) void k_asm_geo(const double* __restrict_
 }
 
 constexpr int kWave = 64;
-constexpr int kRowsPerBlock = kAsmBlock / kWave;
 
 struct MagnetArgs {
   int N;
@@ -121,49 +121,73 @@ struct MagnetArgs {
   double *K, *D1, *D2, *Q, *V;   // D1, D2: [3][nnz]; Q: [6][N]
 };
 
-// One magnetic row per wavefront, one row entry per lane (rows longer than
-// 64 entries take several passes): every lane walks the tets around the
-// node and adds the terms whose column is its own, so each entry is summed
-// in registers in adjacency order (the host assembly's order) and written
-// once.  Lumped volume, D1/D2 (coupling to the potential's gradient), the
-// exchange stiffness and the anisotropy tensor, each scaled by the row's
-// volume as the host does.  Against a thread per row adding into the seven
-// output arrays in memory, this took the 520k-row mesh from 17.1 to 10.7 ms.
-__global__ __launch_bounds__(kAsmBlock) void k_asm_magnet(MagnetArgs a) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int i = blockIdx.x * kRowsPerBlock + (threadIdx.x / kWave);
-  if (i >= a.N) return;   // uniform across the wavefront
+// One magnetic row per block of one wavefront, in two phases per chunk of
+// up to 64 of the row's tets: lane j loads tet j (adjacency, geometry,
+// material) and writes its four (column, terms) records to LDS, so the
+// row's gathers are all in flight at once; then each lane, owning one row
+// entry (rows longer than 64 entries take several passes), adds the records
+// of its column in adjacency order (the host assembly's order).  Lumped
+// volume, D1/D2 (coupling to the potential's gradient), the exchange
+// stiffness and the anisotropy tensor, each scaled by the row's volume as
+// the host does.
+__global__ __launch_bounds__(kWave) void k_asm_magnet(MagnetArgs a) {
+  __shared__ int s_col[4 * kWave];
+  __shared__ double s_t[4][4 * kWave];   // D2 x3 and K terms per (tet, vertex)
+  __shared__ double s_d1[3][kWave];      // D1 terms per tet (the same for its four vertices)
+  __shared__ double s_ve[kWave], s_kan[kWave];
+  __shared__ int s_reg[kWave];
+  const int lane = threadIdx.x;
+  const int i = blockIdx.x;
   const int r0 = a.mrp[i], r1 = a.mrp[i + 1];
   const int k0 = a.adj_ptr[i], k1 = a.adj_ptr[i + 1];
-  double V = 0;
-  for (int k = k0; k < k1; ++k) V += 0.25 * a.geo[kGeo * (int64_t)a.mtet_mesh[a.adj[k] >> 2]];
-  const double s1 = 1.0 / V, s2 = 2.0 / V;
+  double V = 0, q[6] = {0, 0, 0, 0, 0, 0};
   for (int base = r0; base < r1; base += kWave) {
     const int p = base + lane;
     const int col = p < r1 ? a.mci[p] : -1;
-    double kk = 0, d1[3] = {0, 0, 0}, d2[3] = {0, 0, 0}, q[6] = {0, 0, 0, 0, 0, 0};
-    for (int k = k0; k < k1; ++k) {
-      const int e = a.adj[k] >> 2, va = a.adj[k] & 3;
-      const double* G = a.geo + kGeo * (int64_t)a.mtet_mesh[e];
-      const double Ve = G[0];
-      const double* g = G + 1;
-      const double* R = a.reg + 8 * (int64_t)a.mregion[e];
-      const double qv = 0.25 * Ve;
-      const double kex = R[0] * Ve;
-      for (int vb = 0; vb < 4; ++vb) {
-        if (a.mtet[4 * (int64_t)e + vb] != col) continue;
-        for (int c = 0; c < 3; ++c) {
-          d1[c] += qv * g[3 * va + c];
-          d2[c] += qv * g[3 * vb + c];
+    double kk = 0, d1[3] = {0, 0, 0}, d2[3] = {0, 0, 0};
+    for (int kb = k0; kb < k1; kb += kWave) {
+      const int n = min(kWave, k1 - kb);
+      if (lane < n) {
+        const int e = a.adj[kb + lane] >> 2, va = a.adj[kb + lane] & 3;
+        const double* G = a.geo + kGeo * (int64_t)a.mtet_mesh[e];
+        const double Ve = G[0];
+        const double* g = G + 1;
+        const int reg = a.mregion[e];
+        const double* R = a.reg + 8 * (int64_t)reg;
+        const double qv = 0.25 * Ve;
+        const double kex = R[0] * Ve;
+        s_ve[lane] = Ve;
+        s_kan[lane] = 0.25 * Ve * R[1] / a.mu0Ms2;
+        s_reg[lane] = reg;
+        for (int c = 0; c < 3; ++c) s_d1[c][lane] = qv * g[3 * va + c];
+        for (int vb = 0; vb < 4; ++vb) {
+          const int slot = 4 * lane + vb;
+          s_col[slot] = a.mtet[4 * (int64_t)e + vb];
+          for (int c = 0; c < 3; ++c) s_t[c][slot] = qv * g[3 * vb + c];
+          const double dot = g[3 * va] * g[3 * vb] + g[3 * va + 1] * g[3 * vb + 1] + g[3 * va + 2] * g[3 * vb + 2];
+          s_t[3][slot] = kex * dot;
         }
-        const double dot = g[3 * va] * g[3 * vb] + g[3 * va + 1] * g[3 * vb + 1] + g[3 * va + 2] * g[3 * vb + 2];
-        kk += kex * dot;
       }
-      if (base == r0) {
-        const double kan = 0.25 * Ve * R[1] / a.mu0Ms2;
-        for (int c = 0; c < 6; ++c) q[c] += kan * R[2 + c];
+      __syncthreads();
+      for (int j = 0; j < n; ++j) {
+        if (base == r0) {
+          V += 0.25 * s_ve[j];
+          const double* R = a.reg + 8 * (int64_t)s_reg[j];
+          for (int c = 0; c < 6; ++c) q[c] += s_kan[j] * R[2 + c];
+        }
+        for (int vb = 0; vb < 4; ++vb) {
+          const int slot = 4 * j + vb;
+          if (s_col[slot] != col) continue;
+          for (int c = 0; c < 3; ++c) {
+            d1[c] += s_d1[c][j];
+            d2[c] += s_t[c][slot];
+          }
+          kk += s_t[3][slot];
+        }
       }
+      __syncthreads();
     }
+    const double s1 = 1.0 / V, s2 = 2.0 / V;
     if (p < r1) {
       for (int c = 0; c < 3; ++c) {
         a.D1[c * a.nnz + p] = d1[c];
@@ -192,47 +216,49 @@ struct PotentialArgs {
   unsigned char* bad;      // [Nt] 1 = diagonal missing or not positive
 };
 
-// Position of column c in the sorted columns ci[r0, r1) (c is present).
-__device__ __forceinline__ int find_col(const int32_t* __restrict__ ci, int r0, int r1, int c) {
-  int lo = r0, hi = r1;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (ci[mid] < c) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
-}
-
-// One row of the transformed Laplacian per thread: the sum over the tets
-// around the node of V_e grad(phi_a) . T_e grad(phi_b), T_e the diagonal
-// shell metric, added into the row's entries in adjacency order.  A thread
-// per row keeps 64 rows' chains of dependent loads (adjacency -> tet ->
-// geometry) in flight per wavefront; one wavefront per row (as for the
-// magnetic rows, which write seven arrays per entry) measured 2.5x slower
-// here, its single chain bound by load latency.
-__global__ __launch_bounds__(kAsmBlock) void k_asm_potential(PotentialArgs a) {
-  const int r = blockIdx.x * kAsmBlock + threadIdx.x;
-  if (r >= a.Nt) return;
+// One row of the transformed Laplacian per block of one wavefront, in the
+// same two phases as the magnetic rows: lane j loads tet j of the node's
+// adjacency and writes V_e grad(phi_a) . T_e grad(phi_b) for its four
+// vertices (T_e the diagonal shell metric) with their columns to LDS; each
+// lane then adds the records of its own entry's column in adjacency order.
+__global__ __launch_bounds__(kWave) void k_asm_potential(PotentialArgs a) {
+  __shared__ int s_col[4 * kWave];
+  __shared__ double s_val[4 * kWave];
+  const int lane = threadIdx.x;
+  const int r = blockIdx.x;
   const int g = a.pot_global[r];
   const int r0 = a.lrp[r], r1 = a.lrp[r + 1];
-  for (int p = r0; p < r1; ++p) a.L[p] = 0.0;
-  for (int k = a.tptr[g]; k < a.tptr[g + 1]; ++k) {
-    const int64_t e = a.tlst[k] >> 2;
-    const int va = a.tlst[k] & 3;
-    const double* G = a.geo + kGeo * e;
-    const double Ve = G[0];
-    const double* gr = G + 1;
-    const double* T = G + 13;
-    for (int vb = 0; vb < 4; ++vb) {
-      const int col = a.pot_of[a.tets[4 * e + vb]];
-      if (col < 0) continue;
-      const int p = find_col(a.lci, r0, r1, col);
-      a.L[p] += Ve * (gr[3 * va] * T[0] * gr[3 * vb] + gr[3 * va + 1] * T[1] * gr[3 * vb + 1] +
-                      gr[3 * va + 2] * T[2] * gr[3 * vb + 2]);
+  const int t0 = a.tptr[g], t1 = a.tptr[g + 1];
+  bool diag_ok = false;
+  for (int base = r0; base < r1; base += kWave) {
+    const int p = base + lane;
+    const int mine = p < r1 ? a.lci[p] : -1;
+    double l = 0;
+    for (int tb = t0; tb < t1; tb += kWave) {
+      const int n = min(kWave, t1 - tb);
+      if (lane < n) {
+        const int64_t e = a.tlst[tb + lane] >> 2;
+        const int va = a.tlst[tb + lane] & 3;
+        const double* G = a.geo + kGeo * e;
+        const double Ve = G[0];
+        const double* gr = G + 1;
+        const double* T = G + 13;
+        for (int vb = 0; vb < 4; ++vb) {
+          const int col = a.pot_of[a.tets[4 * e + vb]];
+          s_col[4 * lane + vb] = col < 0 ? -2 : col;   // -2 matches no lane
+          s_val[4 * lane + vb] = Ve * (gr[3 * va] * T[0] * gr[3 * vb] + gr[3 * va + 1] * T[1] * gr[3 * vb + 1] +
+                                       gr[3 * va + 2] * T[2] * gr[3 * vb + 2]);
+        }
+      }
+      __syncthreads();
+      for (int j = 0; j < 4 * n; ++j)
+        if (s_col[j] == mine) l += s_val[j];
+      __syncthreads();
     }
+    if (p < r1) a.L[p] = l;
+    diag_ok = diag_ok || __ballot(p < r1 && mine == r && l > 0) != 0;
   }
-  const int pd = find_col(a.lci, r0, r1, r);
-  a.bad[r] = (pd >= r1 || a.lci[pd] != r || !(a.L[pd] > 0)) ? 1 : 0;
+  if (lane == 0) a.bad[r] = diag_ok ? 0 : 1;
 }
 
 // Device temporaries, freed (after the stream has drained) on every return.
@@ -259,7 +285,6 @@ hipError_t put(T* dst, const std::vector<T>& v, hipStream_t s) {
 }
 
 unsigned grid_of(int64_t n) { return (unsigned)((n + kAsmBlock - 1) / kAsmBlock); }
-unsigned row_grid_of(int64_t rows) { return (unsigned)((rows + kRowsPerBlock - 1) / kRowsPerBlock); }
 
 }  // namespace
 }  // namespace mmsd
@@ -297,6 +322,11 @@ extern "C" int mmsd_assemble_device(mmsd_ctx c, const mmsd_mesh* mesh, const mms
   sizes[2] = Nt;
   sizes[3] = nnzL;
   if (given == 0) return MMSD_OK;
+  // the row kernels launch one 64-lane block per row: grid threads must fit 32 bits
+  if (N > (int64_t(1) << 26) || Nt > (int64_t(1) << 26)) {
+    set_error("device assembly: more than 2^26 rows");
+    return MMSD_E_INVALID;
+  }
 
   std::lock_guard<std::mutex> lk(c->mu);
   MMSD_HIP(hipSetDevice(c->device));
@@ -356,7 +386,7 @@ extern "C" int mmsd_assemble_device(mmsd_ctx c, const mmsd_mesh* mesh, const mms
   MMSD_HIP(put(d_reg, S.reg, st));
   MagnetArgs ma{(int)N, nnzM, mrp, mci, d_madj_ptr, d_madj, d_mtet, d_mtet_mesh, d_mregion, d_reg, d_geo,
                 S.mu0Ms2, K, D1, D2, Q, V};
-  k_asm_magnet<<<row_grid_of(N), kAsmBlock, 0, st>>>(ma);
+  k_asm_magnet<<<(unsigned)N, kWave, 0, st>>>(ma);
   MMSD_HIP(hipGetLastError());
   MMSD_HIP(put(pot_global, S.pot_global, st));
   if (Nt > 0) {
@@ -374,7 +404,7 @@ extern "C" int mmsd_assemble_device(mmsd_ctx c, const mmsd_mesh* mesh, const mms
     MMSD_HIP(put(d_tptr, S.tptr, st));
     MMSD_HIP(put(d_tlst, S.tlst, st));
     PotentialArgs pa{(int)Nt, lrp, lci, pot_global, d_pot_of, d_tptr, d_tlst, d_tets, d_geo, L, d_bad};
-    k_asm_potential<<<grid_of(Nt), kAsmBlock, 0, st>>>(pa);
+    k_asm_potential<<<(unsigned)Nt, kWave, 0, st>>>(pa);
     MMSD_HIP(hipGetLastError());
     std::vector<unsigned char> bad(Nt);
     MMSD_HIP(hipMemcpyAsync(bad.data(), d_bad, Nt, hipMemcpyDeviceToHost, st));
