@@ -40,7 +40,55 @@ def two_region_config1():
                             meshgen.Material(2, meshgen.JS_T, 1.3e6, 3e-12, np.array([0.3, -0.2, 0.9]))])
 
 
+def star_ball(r_in=5e-9, r_out=10e-9, subdivisions=2):
+    """A node of high valence: the centre of a twice-subdivided icosphere
+    joined to its 320 faces (magnetic tets, 163 neighbours including
+    itself), inside an air layer of prisms up to a scaled copy of the
+    sphere (outer nodes Dirichlet).  Each prism is split by the vertices'
+    order (lowest index first), so neighbouring prisms share face
+    diagonals.  Rows over 64 entries and nodes in over 64 tets."""
+    t = (1 + 5 ** 0.5) / 2
+    v = [(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0), (0, -1, t), (0, 1, t), (0, -1, -t), (0, 1, -t),
+         (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)]
+    f = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4), (11, 10, 2),
+         (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9), (4, 9, 5), (2, 4, 11),
+         (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    verts = [np.array(p, float) / np.linalg.norm(p) for p in v]
+    for _ in range(subdivisions):
+        mid, nf = {}, []
+        def m(i, j):
+            key = (min(i, j), max(i, j))
+            if key not in mid:
+                p = verts[i] + verts[j]
+                verts.append(p / np.linalg.norm(p))
+                mid[key] = len(verts) - 1
+            return mid[key]
+        for a, b, c in f:
+            ab, bc, ca = m(a, b), m(b, c), m(c, a)
+            nf += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        f = nf
+    ns = len(verts)
+    inner = 1 + np.arange(ns)          # node ids: 0 centre, then inner, then outer
+    outer = 1 + ns + np.arange(ns)
+    xyz = np.vstack([np.zeros((1, 3)), r_in * np.array(verts), r_out * np.array(verts)])
+    tets = [(0, inner[a], inner[b], inner[c]) for a, b, c in f]
+    region = [1] * len(tets)
+    for tri in f:
+        a, b, c = sorted(tri)
+        A, B, C = inner[a], inner[b], inner[c]
+        A2, B2, C2 = outer[a], outer[b], outer[c]
+        tets += [(A, B, C, C2), (A, B, B2, C2), (A, A2, B2, C2)]
+        region += [0, 0, 0]
+    dirichlet = np.zeros(len(xyz), np.uint8)
+    dirichlet[outer] = 1
+    return meshgen.Mesh(xyz=xyz, tets=np.array(tets, np.int32), region=np.array(region, np.int32),
+                        dirichlet=dirichlet, shell=None,
+                        materials=[meshgen.Material(1, meshgen.JS_T, meshgen.K1_JM3, meshgen.A_JM,
+                                                    np.array([0.2, 0.1, 1.0]))])
+
+
 MESHES = {
+    "star_valence_320": star_ball,    # multi-pass rows in both row kernels
     "kuhn_two_regions": two_region_config1,
     "delaunay": lambda: meshgen.delaunay_box(5),     # irregular rows of 4 to ~25 entries
     "sphere_staircase": lambda: meshgen.kuhn_ball(cells=8),
@@ -130,6 +178,17 @@ def test_degenerate_tet_and_bad_arguments_are_errors(ctx):
     assert e.value.code == binding.E_MESH
     with pytest.raises(binding.MMSDError, match="degenerate tetrahedron 5"):
         binding.assembly_export(bad)
+    # the shell's outer bound pulled in: the outermost tets lie beyond it
+    shell = np.array(mesh.shell, float)
+    shell[6:9] = shell[3:6] + 0.5 * (shell[6:9] - shell[3:6])
+    short = meshgen.Mesh(xyz=mesh.xyz, tets=mesh.tets, region=mesh.region, dirichlet=mesh.dirichlet,
+                         shell=shell, materials=mesh.materials)
+    say("device assembly: tets outside the shell")
+    with pytest.raises(binding.MMSDError, match="outside the transformation shell") as e:
+        binding.assemble_device(ctx, short)
+    assert e.value.code == binding.E_MESH
+    with pytest.raises(binding.MMSDError, match="outside the transformation shell"):
+        binding.assembly_export(short)
     # some outputs set and others not
     a = binding.MeshArgs(mesh)
     sizes = (C.c_int64 * 4)()
