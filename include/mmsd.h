@@ -287,7 +287,8 @@ int mmsd_assembly_export(const mmsd_mesh* mesh, const mmsd_material* mats, int n
  * is DEVICE memory the caller owns: all eleven NULL = size query (sizes[4]
  * only, no device work), all eleven set = assemble; a mix is MMSD_E_INVALID.
  * With N_t = 0, lrp[1] = {0} and lci, L, pot_global are untouched.
- * Temporaries (~150 B per tet) come from ctx's allocator and are freed before
+ * Temporaries (~170 B per tet: a 128-B geometry record, vertex ids, the
+ * node-to-tet adjacency) come from ctx's allocator and are freed before
  * return; the call returns once the values are written.  Errors: the host
  * checks of mmsd_assembly_export (MMSD_E_MESH / MMSD_E_INVALID), degenerate
  * tets, tets outside the shell and non-positive diagonals found by the

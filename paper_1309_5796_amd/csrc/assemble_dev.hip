@@ -266,6 +266,8 @@ struct Scratch {
   mmsd_ctx_s* c;
   std::vector<void*> ptrs;
   explicit Scratch(mmsd_ctx_s* ctx) : c(ctx) {}
+  Scratch(const Scratch&) = delete;
+  Scratch& operator=(const Scratch&) = delete;
   template <typename T>
   T* get(size_t n) {
     void* p = c->dalloc(std::max<size_t>(n, 1) * sizeof(T));
