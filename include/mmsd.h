@@ -280,15 +280,19 @@ int mmsd_assembly_export(const mmsd_mesh* mesh, const mmsd_material* mats, int n
 
 /* Device-side assembly of the same operators (Abstract: linear tetrahedral
  * elements; Results, comparison section: the transformed open-boundary
- * Laplacian).  The host validates the mesh and materials and builds the
- * numbering, adjacency and sparsity patterns; HIP kernels on ctx's stream
- * compute the tet geometry and shell metric and every value.  Arguments and
- * layouts are those of mmsd_assembly_export without scalars, but every array
- * is DEVICE memory the caller owns: all eleven NULL = size query (sizes[4]
- * only, no device work), all eleven set = assemble; a mix is MMSD_E_INVALID.
+ * Laplacian).  The host validates the mesh and materials and numbers the
+ * nodes; HIP kernels on ctx's stream build the node-to-tet adjacency and
+ * the sparsity patterns and compute the tet geometry, the shell metric and
+ * every value.  Arguments and layouts are those of mmsd_assembly_export
+ * without scalars, but every array is DEVICE memory the caller owns: all
+ * eleven NULL = size query (writes sizes[4]; runs the pattern kernels), all
+ * eleven set = assemble, with sizes[4] holding what the query returned (the
+ * buffers' sizes; a mismatch is MMSD_E_INVALID before anything is written);
+ * a mix of NULL and set is MMSD_E_INVALID.  A node in more than 512 tets is
+ * MMSD_E_INVALID (the host assembly has no such limit).
  * With N_t = 0, lrp[1] = {0} and lci, L, pot_global are untouched.
- * Temporaries (~170 B per tet: a 128-B geometry record, vertex ids, the
- * node-to-tet adjacency) come from ctx's allocator and are freed before
+ * Temporaries (up to ~190 B per tet: a 128-B geometry record, vertex ids,
+ * the node-to-tet adjacencies) come from ctx's allocator and are freed before
  * return; the call returns once the values are written.  Errors: the host
  * checks of mmsd_assembly_export (MMSD_E_MESH / MMSD_E_INVALID), degenerate
  * tets, tets outside the shell and non-positive diagonals found by the

@@ -513,7 +513,7 @@ int assemble(const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats, Assem
 }
 
 int assemble_structure(const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats, AssemblyStructure* S,
-                       std::string* err) {
+                       std::string* err, bool with_patterns) {
   int st = check_mesh(mesh, err);
   if (st) return st;
   Numbering nb;
@@ -593,6 +593,7 @@ int assemble_structure(const mmsd_mesh* mesh, const mmsd_material* mats, int n_m
     t[6] = u[0] * u[2];
     t[7] = u[1] * u[2];
   }
+  if (!with_patterns) return MMSD_OK;
   {
     std::vector<char> all(Em, 1);
     node_tets(S->N, S->mtet.data(), Em, all, S->mnode_tets_ptr, S->mnode_tets);

@@ -86,8 +86,11 @@ struct AssemblyStructure {
 
 // Validates the mesh and the materials (as assemble() does, except that the
 // geometry checks, degenerate tets and tets outside the shell, are left to
-// the caller) and builds the structure.  Returns an MMSD_* status.
+// the caller) and builds the structure.  With with_patterns false it stops
+// after the numbering, the magnetic tets and the material table (the
+// adjacency and pattern vectors stay empty: the device builds them).
+// Returns an MMSD_* status.
 int assemble_structure(const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats, AssemblyStructure* out,
-                       std::string* err);
+                       std::string* err, bool with_patterns = true);
 
 }  // namespace mmsd

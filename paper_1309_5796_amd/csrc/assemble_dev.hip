@@ -5,8 +5,11 @@
 // diagonal shell metric (Results, comparison section: the open boundary is
 // handled by a space transformation).
 //
-// The host builds the combinatorial half (numbering, adjacency, patterns:
-// assemble_structure); three kernels compute every value:
+// The host validates the mesh, numbers the nodes and builds the per-region
+// material table (assemble_structure without patterns).  Kernels build the
+// node-to-tet adjacency (count, fill, sort) and both sparsity patterns
+// (k_pattern: sorted distinct columns of each row), then compute every
+// value:
 //   k_asm_geo        one thread per tet: volume, P1 gradients, shell metric
 //   k_asm_magnet     one wavefront per magnetic row: V, D1, D2, K, Q
 //   k_asm_potential  one wavefront per potential row: L and its diagonal check
@@ -261,6 +264,110 @@ __global__ __launch_bounds__(kWave) void k_asm_potential(PotentialArgs a) {
   if (lane == 0) a.bad[r] = diag_ok ? 0 : 1;
 }
 
+// ---- structure: node-to-tet adjacency and sparsity patterns ----------
+
+constexpr int kMaxCand = 2048;   // candidate columns of one row: 4 per incident tet
+
+__global__ __launch_bounds__(kAsmBlock) void k_asm_zero(int32_t* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kAsmBlock + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// Adjacency, first pass: the number of (tet, vertex) pairs at each node.
+__global__ __launch_bounds__(kAsmBlock) void k_adj_count(const int32_t* __restrict__ tets, int64_t E,
+                                                         int32_t* __restrict__ cnt) {
+  const int64_t e = (int64_t)blockIdx.x * kAsmBlock + threadIdx.x;
+  if (e >= E) return;
+  for (int v = 0; v < 4; ++v) atomicAdd(&cnt[tets[4 * e + v]], 1);
+}
+
+// Second pass, after the prefix sum of the counts: each pair into its
+// node's list (in arrival order; the third pass sorts).
+__global__ __launch_bounds__(kAsmBlock) void k_adj_fill(const int32_t* __restrict__ tets, int64_t E,
+                                                        const int32_t* __restrict__ ptr, int32_t* __restrict__ cur,
+                                                        int32_t* __restrict__ lst) {
+  const int64_t e = (int64_t)blockIdx.x * kAsmBlock + threadIdx.x;
+  if (e >= E) return;
+  for (int v = 0; v < 4; ++v) {
+    const int node = tets[4 * e + v];
+    lst[ptr[node] + atomicAdd(&cur[node], 1)] = (int)(4 * e + v);
+  }
+}
+
+// Third pass: each node's list ascending in 4 tet + vertex, the order a
+// serial pass over the tets gives (insertion sort: the lists are short).
+__global__ __launch_bounds__(kAsmBlock) void k_adj_sort(const int32_t* __restrict__ ptr, int64_t n,
+                                                        int32_t* __restrict__ lst) {
+  const int64_t i = (int64_t)blockIdx.x * kAsmBlock + threadIdx.x;
+  if (i >= n) return;
+  const int a = ptr[i], b = ptr[i + 1];
+  for (int j = a + 1; j < b; ++j) {
+    const int x = lst[j];
+    int k = j - 1;
+    while (k >= a && lst[k] > x) {
+      lst[k + 1] = lst[k];
+      --k;
+    }
+    lst[k + 1] = x;
+  }
+}
+
+struct PatternArgs {
+  int R;
+  const int32_t* row_node;   // node of row r; null: row r is node r
+  const int32_t* adj_ptr;    // node -> (tet << 2 | vertex)
+  const int32_t* adj;
+  const int32_t* tets4;      // 4 node ids per tet
+  const int32_t* col_of;     // column of a node, -1 = none; null: the node id is the column
+  int32_t* cnt;              // [R] distinct columns (count pass)
+  const int32_t* rp;         // row starts (write pass)
+  int32_t* ci;               // columns, ascending per row (write pass)
+};
+
+// The columns of row r are the distinct columns of the vertices of the
+// tets around its node.  One 64-lane block per row: the lanes stage the
+// 4 x (incident tets) candidates in LDS and mark first occurrences; the
+// count pass sums the marks, the write pass puts each distinct column at
+// its rank among them, so every row comes out sorted and unique.
+template <bool WRITE>
+__global__ __launch_bounds__(kWave) void k_pattern(PatternArgs a) {
+  __shared__ int s_c[kMaxCand];
+  __shared__ unsigned char s_first[kMaxCand];
+  const int lane = threadIdx.x;
+  const int r = blockIdx.x;
+  const int g = a.row_node ? a.row_node[r] : r;
+  const int k0 = a.adj_ptr[g];
+  const int m = 4 * (a.adj_ptr[g + 1] - k0);   // at most kMaxCand (checked on the host)
+  for (int j = lane; j < m; j += kWave) {
+    const int e = a.adj[k0 + j / 4] >> 2;
+    const int x = a.tets4[4 * (int64_t)e + (j & 3)];
+    s_c[j] = a.col_of ? a.col_of[x] : x;
+  }
+  __syncthreads();
+  for (int j = lane; j < m; j += kWave) {
+    const int c = s_c[j];
+    bool first = c >= 0;
+    for (int i = 0; i < j && first; ++i) first = s_c[i] != c;
+    s_first[j] = first ? 1 : 0;
+  }
+  __syncthreads();
+  if (!WRITE) {
+    int u = 0;
+    for (int j = lane; j < m; j += kWave) u += s_first[j];
+    for (int off = kWave / 2; off > 0; off >>= 1) u += __shfl_down(u, off);
+    if (lane == 0) a.cnt[r] = u;
+  } else {
+    const int base = a.rp[r];
+    for (int j = lane; j < m; j += kWave) {
+      if (!s_first[j]) continue;
+      const int c = s_c[j];
+      int rank = 0;
+      for (int i = 0; i < m; ++i) rank += (s_first[i] && s_c[i] < c) ? 1 : 0;
+      a.ci[base + rank] = c;
+    }
+  }
+}
+
 // Device temporaries, freed (after the stream has drained) on every return.
 struct Scratch {
   mmsd_ctx_s* c;
@@ -293,6 +400,79 @@ unsigned grid_of(int64_t n) { return (unsigned)((n + kAsmBlock - 1) / kAsmBlock)
 
 using namespace mmsd;
 
+namespace mmsd {
+namespace {
+
+// Exclusive prefix sum of n device counts into ptr[n + 1] (on the host: the
+// counts make one round trip); returns the total and the largest count.
+int scan_counts(const int32_t* d_cnt, int64_t n, int32_t* d_ptr, hipStream_t st, int64_t* total, int* largest) {
+  std::vector<int32_t> h(n + 1, 0);
+  MMSD_HIP(hipMemcpyAsync(h.data() + 1, d_cnt, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  MMSD_HIP(hipStreamSynchronize(st));
+  int64_t acc = 0;
+  int mx = 0;
+  for (int64_t i = 1; i <= n; ++i) {
+    mx = std::max(mx, h[i]);
+    acc += h[i];
+    if (acc > INT32_MAX) {
+      set_error("device assembly: more than 2^31 entries");
+      return MMSD_E_INVALID;
+    }
+    h[i] = (int32_t)acc;
+  }
+  if (d_ptr) MMSD_HIP(hipMemcpyAsync(d_ptr, h.data(), (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  MMSD_HIP(hipStreamSynchronize(st));   // h is released on return
+  *total = acc;
+  if (largest) *largest = mx;
+  return MMSD_OK;
+}
+
+// Node-to-(tet, vertex) adjacency of n nodes over E tets, into ptr[n + 1]
+// and lst[4 E] (device); cur is an n-int temporary.
+int build_adjacency(const int32_t* d_tets, int64_t E, int64_t n, int32_t* ptr, int32_t* lst, int32_t* cur,
+                    hipStream_t st) {
+  k_asm_zero<<<grid_of(n), kAsmBlock, 0, st>>>(cur, n);
+  k_adj_count<<<grid_of(E), kAsmBlock, 0, st>>>(d_tets, E, cur);
+  MMSD_HIP(hipGetLastError());
+  int64_t total = 0;
+  int largest = 0;
+  int rc = scan_counts(cur, n, ptr, st, &total, &largest);
+  if (rc) return rc;
+  if (4 * largest > kMaxCand) {
+    set_error("device assembly: a node lies in more than " + std::to_string(kMaxCand / 4) + " tets");
+    return MMSD_E_INVALID;
+  }
+  k_asm_zero<<<grid_of(n), kAsmBlock, 0, st>>>(cur, n);
+  k_adj_fill<<<grid_of(E), kAsmBlock, 0, st>>>(d_tets, E, ptr, cur, lst);
+  k_adj_sort<<<grid_of(n), kAsmBlock, 0, st>>>(ptr, n, lst);
+  MMSD_HIP(hipGetLastError());
+  return MMSD_OK;
+}
+
+// Pattern of R rows: counts, row starts into rp[R + 1], and (when ci is
+// set) the columns; returns the entry count.  Before writing columns the
+// count must equal `capacity`, the caller's buffer size.
+int build_pattern_dev(PatternArgs pa, int32_t* cnt, int32_t* rp, int32_t* ci, int64_t capacity, hipStream_t st,
+                      int64_t* nnz) {
+  pa.cnt = cnt;
+  k_pattern<false><<<(unsigned)pa.R, kWave, 0, st>>>(pa);
+  MMSD_HIP(hipGetLastError());
+  int rc = scan_counts(cnt, pa.R, rp, st, nnz, nullptr);
+  if (rc || !ci) return rc;
+  if (*nnz != capacity) {
+    set_error("device assembly: sizes[] does not hold this mesh's sizes (query them first)");
+    return MMSD_E_INVALID;
+  }
+  pa.rp = rp;
+  pa.ci = ci;
+  k_pattern<true><<<(unsigned)pa.R, kWave, 0, st>>>(pa);
+  MMSD_HIP(hipGetLastError());
+  return MMSD_OK;
+}
+
+}  // namespace
+}  // namespace mmsd
+
 extern "C" int mmsd_assemble_device(mmsd_ctx c, const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats,
                                     int64_t sizes[4], int32_t* mrp, int32_t* mci, double* K, double* D1,
                                     double* D2, double* Q, double* V, int32_t* pot_global, int32_t* lrp,
@@ -311,19 +491,22 @@ extern "C" int mmsd_assemble_device(mmsd_ctx c, const mmsd_mesh* mesh, const mms
     set_error("output pointers must be all null (size query) or all set");
     return MMSD_E_INVALID;
   }
+  const bool query = given == 0;
+  // host: validation, numbering, magnetic tets, material table
   AssemblyStructure S;
   std::string err;
-  int rc = assemble_structure(mesh, mats, n_mats, &S, &err);
+  int rc = assemble_structure(mesh, mats, n_mats, &S, &err, /*with_patterns=*/false);
   if (rc) {
     set_error(err);
     return rc;
   }
-  const int64_t N = S.N, nnzM = (int64_t)S.mci.size(), Nt = S.Nt, nnzL = (int64_t)S.lci.size();
-  sizes[0] = N;
-  sizes[1] = nnzM;
-  sizes[2] = Nt;
-  sizes[3] = nnzL;
-  if (given == 0) return MMSD_OK;
+  const int64_t N = S.N, Nt = S.Nt, E = S.E, Em = (int64_t)S.mregion.size(), n_nodes = mesh->n_nodes;
+  // the assemble call gets the query's sizes back: the output buffers' sizes
+  const int64_t cap[4] = {sizes[0], sizes[1], sizes[2], sizes[3]};
+  if (!query && (cap[0] != N || cap[2] != Nt)) {
+    set_error("device assembly: sizes[] does not hold this mesh's sizes (query them first)");
+    return MMSD_E_INVALID;
+  }
   // the row kernels launch one 64-lane block per row: grid threads must fit 32 bits
   if (N > (int64_t(1) << 26) || Nt > (int64_t(1) << 26)) {
     set_error("device assembly: more than 2^26 rows");
@@ -333,25 +516,63 @@ extern "C" int mmsd_assemble_device(mmsd_ctx c, const mmsd_mesh* mesh, const mms
   std::lock_guard<std::mutex> lk(c->mu);
   MMSD_HIP(hipSetDevice(c->device));
   hipStream_t st = c->stream;
-  const int64_t E = S.E, Em = (int64_t)S.mregion.size();
   Scratch tmp(c);
-  double* d_xyz = tmp.get<double>(3 * (size_t)mesh->n_nodes);
-  int32_t* d_tets = tmp.get<int32_t>(4 * (size_t)E);
-  double* d_geo = tmp.get<double>(kGeo * (size_t)E);
-  unsigned char* d_flag = tmp.get<unsigned char>(E);
-  int32_t* d_madj_ptr = tmp.get<int32_t>(S.mnode_tets_ptr.size());
-  int32_t* d_madj = tmp.get<int32_t>(S.mnode_tets.size());
-  int32_t* d_mtet = tmp.get<int32_t>(S.mtet.size());
-  int32_t* d_mtet_mesh = tmp.get<int32_t>(Em);
-  int32_t* d_mregion = tmp.get<int32_t>(Em);
-  double* d_reg = tmp.get<double>(S.reg.size());
-  if (!d_xyz || !d_tets || !d_geo || !d_flag || !d_madj_ptr || !d_madj || !d_mtet || !d_mtet_mesh || !d_mregion ||
-      !d_reg) {
+  // device structure: adjacency and patterns
+  int32_t* d_mtet = tmp.get<int32_t>(4 * (size_t)Em);
+  int32_t* d_madj_ptr = tmp.get<int32_t>(N + 1);
+  int32_t* d_madj = tmp.get<int32_t>(4 * (size_t)Em);
+  int32_t* d_cur = tmp.get<int32_t>(std::max(n_nodes, std::max(N, Nt)));
+  int32_t* d_rp = query ? tmp.get<int32_t>(std::max(N, Nt) + 1) : nullptr;
+  if (!d_mtet || !d_madj_ptr || !d_madj || !d_cur || (query && !d_rp)) {
     set_error("device allocation failed (assembly temporaries)");
     return MMSD_E_NOMEM;
   }
-  MMSD_HIP(hipMemcpyAsync(d_xyz, mesh->xyz, 3 * mesh->n_nodes * sizeof(double), hipMemcpyHostToDevice, st));
+  MMSD_HIP(put(d_mtet, S.mtet, st));
+  if ((rc = build_adjacency(d_mtet, Em, N, d_madj_ptr, d_madj, d_cur, st))) return rc;
+  int64_t nnzM = 0, nnzL = 0;
+  PatternArgs pm{(int)N, nullptr, d_madj_ptr, d_madj, d_mtet, nullptr, nullptr, nullptr, nullptr};
+  if ((rc = build_pattern_dev(pm, d_cur, query ? d_rp : mrp, query ? nullptr : mci, cap[1], st, &nnzM))) return rc;
+  int32_t *d_tets = nullptr, *d_tptr = nullptr, *d_tlst = nullptr, *d_pot_of = nullptr, *d_pot_global = nullptr;
+  d_tets = tmp.get<int32_t>(4 * (size_t)E);
+  if (!d_tets) {
+    set_error("device allocation failed (assembly temporaries)");
+    return MMSD_E_NOMEM;
+  }
   MMSD_HIP(hipMemcpyAsync(d_tets, mesh->tets, 4 * E * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  if (Nt > 0) {
+    d_tptr = tmp.get<int32_t>(n_nodes + 1);
+    d_tlst = tmp.get<int32_t>(4 * (size_t)E);
+    d_pot_of = tmp.get<int32_t>(n_nodes);
+    d_pot_global = query ? tmp.get<int32_t>(Nt) : pot_global;
+    if (!d_tptr || !d_tlst || !d_pot_of || !d_pot_global) {
+      set_error("device allocation failed (assembly temporaries)");
+      return MMSD_E_NOMEM;
+    }
+    MMSD_HIP(put(d_pot_of, S.pot_of, st));
+    MMSD_HIP(put(d_pot_global, S.pot_global, st));
+    if ((rc = build_adjacency(d_tets, E, n_nodes, d_tptr, d_tlst, d_cur, st))) return rc;
+    PatternArgs pp{(int)Nt, d_pot_global, d_tptr, d_tlst, d_tets, d_pot_of, nullptr, nullptr, nullptr};
+    if ((rc = build_pattern_dev(pp, d_cur, query ? d_rp : lrp, query ? nullptr : lci, cap[3], st, &nnzL)))
+      return rc;
+  }
+  sizes[0] = N;
+  sizes[1] = nnzM;
+  sizes[2] = Nt;
+  sizes[3] = nnzL;
+  if (query) return MMSD_OK;
+
+  // geometry, shell metric and validity of every tet
+  double* d_xyz = tmp.get<double>(3 * (size_t)n_nodes);
+  double* d_geo = tmp.get<double>(kGeo * (size_t)E);
+  unsigned char* d_flag = tmp.get<unsigned char>(E);
+  int32_t* d_mtet_mesh = tmp.get<int32_t>(Em);
+  int32_t* d_mregion = tmp.get<int32_t>(Em);
+  double* d_reg = tmp.get<double>(S.reg.size());
+  if (!d_xyz || !d_geo || !d_flag || !d_mtet_mesh || !d_mregion || !d_reg) {
+    set_error("device allocation failed (assembly temporaries)");
+    return MMSD_E_NOMEM;
+  }
+  MMSD_HIP(hipMemcpyAsync(d_xyz, mesh->xyz, 3 * n_nodes * sizeof(double), hipMemcpyHostToDevice, st));
   ShellDev sh{};
   sh.on = mesh->shell != nullptr;
   if (sh.on)
@@ -377,12 +598,7 @@ extern "C" int mmsd_assemble_device(mmsd_ctx c, const mmsd_mesh* mesh, const mms
         return MMSD_E_MESH;
       }
 
-  // patterns straight into the caller's buffers; the kernels read them there
-  MMSD_HIP(put(mrp, S.mrp, st));
-  MMSD_HIP(put(mci, S.mci, st));
-  MMSD_HIP(put(d_madj_ptr, S.mnode_tets_ptr, st));
-  MMSD_HIP(put(d_madj, S.mnode_tets, st));
-  MMSD_HIP(put(d_mtet, S.mtet, st));
+  // values
   MMSD_HIP(put(d_mtet_mesh, S.mtet_mesh, st));
   MMSD_HIP(put(d_mregion, S.mregion, st));
   MMSD_HIP(put(d_reg, S.reg, st));
@@ -390,21 +606,12 @@ extern "C" int mmsd_assemble_device(mmsd_ctx c, const mmsd_mesh* mesh, const mms
                 S.mu0Ms2, K, D1, D2, Q, V};
   k_asm_magnet<<<(unsigned)N, kWave, 0, st>>>(ma);
   MMSD_HIP(hipGetLastError());
-  MMSD_HIP(put(pot_global, S.pot_global, st));
   if (Nt > 0) {
-    int32_t* d_pot_of = tmp.get<int32_t>(S.pot_of.size());
-    int32_t* d_tptr = tmp.get<int32_t>(S.tptr.size());
-    int32_t* d_tlst = tmp.get<int32_t>(S.tlst.size());
     unsigned char* d_bad = tmp.get<unsigned char>(Nt);
-    if (!d_pot_of || !d_tptr || !d_tlst || !d_bad) {
+    if (!d_bad) {
       set_error("device allocation failed (assembly temporaries)");
       return MMSD_E_NOMEM;
     }
-    MMSD_HIP(put(lrp, S.lrp, st));
-    MMSD_HIP(put(lci, S.lci, st));
-    MMSD_HIP(put(d_pot_of, S.pot_of, st));
-    MMSD_HIP(put(d_tptr, S.tptr, st));
-    MMSD_HIP(put(d_tlst, S.tlst, st));
     PotentialArgs pa{(int)Nt, lrp, lci, pot_global, d_pot_of, d_tptr, d_tlst, d_tets, d_geo, L, d_bad};
     k_asm_potential<<<(unsigned)Nt, kWave, 0, st>>>(pa);
     MMSD_HIP(hipGetLastError());

@@ -196,3 +196,16 @@ def test_degenerate_tet_and_bad_arguments_are_errors(ctx):
     rc = ctx.lib.mmsd_assemble_device(ctx.handle, C.byref(a.c), a.mats, a.n_mats, sizes, C.addressof(x),
                                       *([None] * 10))
     assert rc == binding.E_INVALID
+    # buffers one entry short of the queried size: refused before any write
+    import torch
+    assert ctx.lib.mmsd_assemble_device(ctx.handle, C.byref(a.c), a.mats, a.n_mats, sizes, *([None] * 11)) == 0
+    N, nnzM, Nt, nnzL = (int(v) for v in sizes)
+    bufs = [torch.zeros(max(n, 1), dtype=torch.float64, device="cuda")
+            for n in (N + 1, nnzM, nnzM, 3 * nnzM, 3 * nnzM, 6 * N, N, Nt, Nt + 1, nnzL, nnzL)]
+    for k in (1, 3):
+        short = (C.c_int64 * 4)(*sizes)
+        short[k] -= 1
+        rc = ctx.lib.mmsd_assemble_device(ctx.handle, C.byref(a.c), a.mats, a.n_mats, short,
+                                          *[C.c_void_p(t.data_ptr()) for t in bufs])
+        assert rc == binding.E_INVALID, k
+        assert "query them first" in ctx.lib.mmsd_last_error().decode()
