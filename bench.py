@@ -353,7 +353,7 @@ def run_sphere(args):
 
 def run_assemble(args):
     """Operator assembly of one mesh, host (mmsd_assembly_export) against
-    device (mmsd_assemble_device: host patterns, device values), wall time of
+    device (mmsd_assemble_device: adjacency, patterns and values in kernels), wall time of
     one call each after an untimed size query and warm-up; on the largest
     request of the served stream (520k magnet / 1.25M potential nodes) and
     the 80 nm cube."""
@@ -395,7 +395,7 @@ def run_assemble(args):
                     "host_s": min(times_h), "device_s": min(times_d)})
         del outs, host
     ctx.close()
-    print(json.dumps({"workload": "operator assembly, host vs device values", "host_threads":
+    print(json.dumps({"workload": "operator assembly, host vs device", "host_threads":
                       min(16, os.cpu_count() or 1), "detail": out}), flush=True)
 
 
