@@ -149,11 +149,11 @@ static int64_t sweep_cost(int64_t n, double avg, int64_t g, int W) {
   return sweep_passes(n, g, W) * (batches + 1);
 }
 
-// Lanes per row of a restriction sweep: the default's (row_lanes) unless 4
-// or 8 lanes cost fewer round trips over a full launch's 512 blocks (R_0 of
-// the 80 nm cube: 39k rows of ~20 entries, one block pass at 4 lanes
+// Lanes per row of a CSR sweep: the default's (row_lanes) unless 4 or 8
+// lanes cost fewer round trips over a full launch's 512 blocks (the 39k-row
+// level of the 80 nm cube, rows of ~20 entries: one block pass at 4 lanes
 // against two at 8).
-static int restrict_lanes(const Csr& R) {
+static int model_lanes(const Csr& R) {
   const double avg = R.nrows ? (double)R.ci.size() / R.nrows : 0.0;
   int best = row_lanes(R);
   int64_t cost = sweep_cost(R.nrows, avg, 512, best);
@@ -493,8 +493,8 @@ int build_amg(mmsd_problem p) {
   std::vector<int> wm(nl, 4), mblk(nl, 0);
   for (int l = 1; l < nl && (c->vcycle & MMSD_VC_FUSE_REST); ++l) {
     const AmgLevel& L = H.lv[l];
-    fused_shape(L.A.nrows, (double)L.A.ci.size() / L.A.nrows, sl[l][0].so.empty() ? row_lanes(L.A) : 1, L.R.nrows,
-                (double)L.R.ci.size() / std::max(1, L.R.nrows), sl[l][2].so.empty() ? restrict_lanes(L.R) : 1, M[l], wm[l],
+    fused_shape(L.A.nrows, (double)L.A.ci.size() / L.A.nrows, sl[l][0].so.empty() ? model_lanes(L.A) : 1, L.R.nrows,
+                (double)L.R.ci.size() / std::max(1, L.R.nrows), sl[l][2].so.empty() ? model_lanes(L.R) : 1, M[l], wm[l],
                 mblk[l]);
   }
   // the last level's DOWN also solves the coarsest level when it restricts
@@ -632,9 +632,9 @@ int build_amg(mmsd_problem p) {
     d.rsv = sv[2];
     d.n = L.A.nrows;
     d.n_next = L.P.ncols;
-    d.lanes_a = row_lanes(L.A);
-    d.lanes_q = row_lanes(Q[l]);
-    d.lanes_r = restrict_lanes(L.R);
+    d.lanes_a = model_lanes(L.A);
+    d.lanes_q = model_lanes(Q[l]);
+    d.lanes_r = model_lanes(L.R);
     d.lanes_m = wm[l];
     d.m_blocks = mblk[l];
     d.mrp = mblk[l] > 0 ? (const int*)(base + lo[l].mrp) : nullptr;
