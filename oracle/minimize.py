@@ -21,8 +21,17 @@ is <= the maximum of the last 20 accepted energies; kappa_0 = 0.5, window of
 the last 3 tau2 values, kappa *= 0.9 / 1.1; s.y <= 0 gives tau <- 10 tau;
 tau clamped to [1e-10, 1e10]; backtracking stops below tau = 1e-14.
 Inner products are volume-weighted, <x, y>_V = sum_i V_i x_i . y_i.
-parity unpinned as a step rule; pinned through its invariants (|m| = 1,
-energy bound, stopping test) and through the physics fixtures.
+
+Pins (tests/test_oracle_minimize.py): the decisions of the step rule -- trial
+step lengths, accept/reject verdicts, tau1 and tau2, the branch of the
+adaptive switch, kappa -- equal those of an independent single-spin
+recurrence written in the rotation angle (a uniformly magnetized cube with
+only nodal terms turns as one spin); a strict Armijo constant rejects
+trials that lower the energy by less than its margin; every recorded
+verdict replays against the last M accepted energies, memory 1 gives a
+monotone search and memory 20 accepts energy increases; plus the
+invariants (|m| = 1, the energy bound, the stopping test) and the physics
+fixtures (Stoner-Wohlfarth, Bloch wall).
 """
 from __future__ import annotations
 
@@ -68,6 +77,8 @@ class Result:
     status: int
     energies: List[float] = field(default_factory=list)
     norm_drift: float = 0.0
+    trials: List[dict] = field(default_factory=list)
+    steps: List[dict] = field(default_factory=list)
 
 
 def cross(a, b):
@@ -109,12 +120,18 @@ def minimize(sys, m0: np.ndarray, b_ext, opts: Optional[Options] = None) -> Resu
     T = float(Tn.max())
     hist = [e]
     drift = 0.0
+    # with record=True: every trial (tau, its energy, the reference it was
+    # tested against, whether the Armijo form applied, the verdict) and every
+    # step-length decision after an accepted step
+    trials: List[dict] = []
+    steps: List[dict] = []
 
     def result(status, iters):
         return Result(m=m, h=h, e=e, E=ev["E"], terms={k: ev[k] for k in ("E_ex", "E_an", "E_Z", "E_d")},
                       max_torque=T, sum_V_torque2=float(np.sum(V * np.sum(H * H, axis=1))),
                       iterations=iters, evals=evals, status=status,
-                      energies=list(hist) if o.record else [], norm_drift=drift)
+                      energies=list(hist) if o.record else [], norm_drift=drift,
+                      trials=trials, steps=steps)
 
     if T < o.tol:
         return result(OK, 0)
@@ -133,10 +150,13 @@ def minimize(sys, m0: np.ndarray, b_ext, opts: Optional[Options] = None) -> Resu
             ev_t = sys.evaluate(m_t, b_ext, o.terms)
             evals += 1
             e_t = ev_t["e"]
-            if first or backtrack:
+            armijo = first or backtrack
+            if armijo:
                 ok = e_t <= e_ref - o.c1 * tau * d
             else:
                 ok = e_t <= e_ref
+            if o.record:
+                trials.append(dict(tau=tau, e=e_t, e_ref=e_ref, d=d, armijo=armijo, accepted=ok))
             if ok:
                 break
             if evals >= o.max_evals:
@@ -160,10 +180,12 @@ def minimize(sys, m0: np.ndarray, b_ext, opts: Optional[Options] = None) -> Resu
         if evals >= o.max_evals:
             return result(MAXEVALS, iters)
         first = False
+        rec = dict(ss=ss, sy=sy, yy=yy, kappa_in=kappa, branch="grow")
         if sy <= 0.0:
             tau = min(10.0 * tau, o.tau_max)
         else:
             t1, t2 = ss / sy, sy / yy
+            rec["branch"] = o.step_rule
             if o.step_rule == "bb1":
                 tau = t1
             elif o.step_rule == "bb2":
@@ -178,10 +200,16 @@ def minimize(sys, m0: np.ndarray, b_ext, opts: Optional[Options] = None) -> Resu
                 if t2 / t1 < kappa:
                     tau = min(window)
                     kappa *= 0.9
+                    rec["branch"] = "tau2min"
                 else:
                     tau = t1
                     kappa *= 1.1
+                    rec["branch"] = "tau1"
+            rec.update(t1=t1, t2=t2)
         tau = min(max(tau, o.tau_min), o.tau_max)
+        if o.record:
+            rec.update(kappa_out=kappa, tau=tau)
+            steps.append(rec)
 
 
 @dataclass

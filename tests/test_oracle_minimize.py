@@ -192,3 +192,163 @@ def test_other_step_rules_reach_the_same_minimum(cfg1, cfg1_system, rule):
     E = r.energies
     for k in range(1, len(E)):
         assert E[k] <= max(E[max(0, k - 20):k])
+
+
+# ---------------------------------------------------------------------------
+# Pins of the step-rule decisions (Method section, step length selection,
+# eq. (9) and the 20-energy nonmonotone rule).  The constants are the
+# readings the library shares with the oracle: first trial 0.1 / max|H|;
+# Armijo c1 = 1e-4 with slope -sum V |H|^2, halving; BB trials accepted
+# against the maximum of the last 20 accepted energies; adaptive switch with
+# kappa0 = 0.5, a window of the last 3 tau2 values, kappa *= 0.9 / 1.1;
+# s.y <= 0 gives 10 tau; tau clamped to [1e-10, 1e10].
+# ---------------------------------------------------------------------------
+
+def _spin_model(theta0_m, B, psi, th0=0.1, tol=1e-10, M=20, max_evals=1000, c1=1e-4):
+    """The same minimizer for one uniformly magnetized spin, written in its
+    rotation angle instead of vectors.  m = (sin t, 0, cos t), easy axis z,
+    field B (sin psi, 0, cos psi): the reduced energy per volume is
+    eps(t) = k sin^2 t - (B / Js) cos(t - psi) with k = K1 / (mu0 Ms^2); the
+    torque m x h is -eps'(t) y, the projected gradient g = eps'(t) dm/dt, and
+    the Cayley step is the rotation t -> t - 2 atan(tau eps'(t) / 2) about y.
+    Volume factors cancel from every ratio and comparison.  Returns the
+    trials (tau, accepted) and the step-length decisions."""
+    Ms = meshgen.JS_T / MU0
+    k = meshgen.K1_JM3 / (MU0 * Ms * Ms)
+    beta = B / meshgen.JS_T
+
+    def eps(t):
+        return k * math.sin(t) ** 2 - beta * math.cos(t - psi)
+
+    def deps(t):
+        return 2 * k * math.sin(t) * math.cos(t) + beta * math.sin(t - psi)
+
+    def mvec(t):
+        return np.array([math.sin(t), 0.0, math.cos(t)])
+
+    def gvec(t):
+        return deps(t) * np.array([math.cos(t), 0.0, -math.sin(t)])
+
+    t = theta0_m
+    hist = [eps(t)]
+    T = abs(deps(t))
+    trials, steps = [], []
+    if T < tol:
+        return trials, steps, 1
+    tau, kappa, window, first, evals = th0 / T, 0.5, [], True, 1
+    while True:
+        ref = max(hist[-M:])
+        d = deps(t) ** 2
+        back = False
+        while True:
+            tt = t - 2.0 * math.atan(0.5 * tau * deps(t))
+            et = eps(tt)
+            evals += 1
+            ok = et <= ref - c1 * tau * d if (first or back) else et <= ref
+            trials.append((tau, ok))
+            if ok:
+                break
+            tau *= 0.5
+            back = True
+        s = mvec(tt) - mvec(t)
+        y = gvec(tt) - gvec(t)
+        ss, sy, yy = s @ s, s @ y, y @ y
+        t = tt
+        hist.append(et)
+        if abs(deps(t)) < tol or evals >= max_evals:
+            return trials, steps, evals
+        first = False
+        if sy <= 0:
+            tau, branch, t1, t2 = min(10 * tau, 1e10), "grow", None, None
+        else:
+            t1, t2 = ss / sy, sy / yy
+            window = (window + [t2])[-3:]
+            if t2 / t1 < kappa:
+                tau, branch = min(window), "tau2min"
+                kappa *= 0.9
+            else:
+                tau, branch = t1, "tau1"
+                kappa *= 1.1
+        tau = min(max(tau, 1e-10), 1e10)
+        steps.append(dict(t1=t1, t2=t2, branch=branch, kappa_out=kappa, tau=tau))
+
+
+@pytest.mark.parametrize("th_m,B,psi_deg,th0,c1", [(0.3, -6.5, 1.0, 0.1, 1e-4), (2.5, -3.0, 10.0, 0.1, 1e-4),
+                                                    (2.5, -3.0, 10.0, 3.0, 1e-4), (1.0, 2.0, 60.0, 0.1, 1e-4),
+                                                    (2.5, -3.0, 10.0, 3.0, 0.45)],
+                         ids=["near-switching", "reversal", "first-trial-rejected", "oblique", "strict-armijo"])
+def test_step_decisions_match_single_spin_angle_model(th_m, B, psi_deg, th0, c1):
+    """On a uniformly magnetized cube with only the nodal terms (anisotropy
+    and Zeeman: no coupling between nodes) every node turns exactly alike, so
+    the oracle's vector iteration must reproduce the
+    single-spin recurrence in the rotation angle: the same trial step
+    lengths, accept/reject verdicts (first-step Armijo, nonmonotone BB
+    acceptance, halving), BB values tau1 = s.s/s.y and tau2 = s.y/y.y, the
+    branch of the adaptive switch, kappa and the next step length."""
+    s = _sw_system(psi_deg)
+    psi = math.radians(psi_deg)
+    m0 = np.tile([math.sin(th_m), 0.0, math.cos(th_m)], (s.N, 1))
+    b = B * np.array([math.sin(psi), 0.0, math.cos(psi)])
+    r = minimize(s, m0, b, Options(terms=ANIS | ZEEM, tol=1e-10, theta0=th0, c1=c1, record=True))
+    trials, steps, evals = _spin_model(th_m, B, psi, th0=th0, c1=c1)
+    assert r.evals == evals and len(r.trials) == len(trials) and len(r.steps) == len(steps)
+    for got, (tau, ok) in zip(r.trials, trials):
+        assert got["accepted"] == ok
+        assert abs(got["tau"] - tau) <= 1e-8 * tau
+    for got, want in zip(r.steps, steps):
+        assert got["branch"] == want["branch"]
+        if want["t1"] is not None:
+            assert abs(got["t1"] - want["t1"]) <= 1e-8 * abs(want["t1"])
+            assert abs(got["t2"] - want["t2"]) <= 1e-8 * abs(want["t2"])
+        assert abs(got["kappa_out"] - want["kappa_out"]) <= 1e-12
+        assert abs(got["tau"] - want["tau"]) <= 1e-8 * want["tau"]
+    branches = {x["branch"] for x in r.steps}
+    if th_m == 0.3:   # this start exercises every branch of the rule
+        assert branches == {"tau1", "tau2min", "grow"}
+    if c1 > 0.1:      # a trial that decreases the energy but not by Armijo's margin is rejected
+        assert any(not x["accepted"] and x["e"] < x["e_ref"] for x in r.trials)
+
+
+def test_first_trial_rejection_halves_tau_under_armijo():
+    """A first trial step of 3 rad overshoots: it is rejected, tau halves,
+    and the accepted trial satisfies the Armijo decrease from the initial
+    energy while its predecessor did not."""
+    s = _sw_system(10.0)
+    psi = math.radians(10.0)
+    m0 = np.tile([math.sin(2.5), 0.0, math.cos(2.5)], (s.N, 1))
+    b = -3.0 * np.array([math.sin(psi), 0.0, math.cos(psi)])
+    r = minimize(s, m0, b, Options(terms=EXCH | ANIS | ZEEM, tol=1e-10, theta0=3.0, record=True))
+    t0, t1 = r.trials[0], r.trials[1]
+    assert t0["armijo"] and not t0["accepted"]
+    assert t1["armijo"] and t1["accepted"] and t1["tau"] == 0.5 * t0["tau"]
+    assert t0["e"] > t0["e_ref"] - 1e-4 * t0["tau"] * t0["d"]
+    assert t1["e"] <= t1["e_ref"] - 1e-4 * t1["tau"] * t1["d"]
+    assert t1["e_ref"] == r.energies[0]
+
+
+@pytest.mark.parametrize("M", [1, 20])
+def test_acceptance_replays_against_the_last_M_accepted_energies(cfg1, cfg1_system, M):
+    """Replay every recorded trial of the config-1 minimization: its
+    reference is the maximum of the last M accepted energies (the current one
+    included), the Armijo form applies to the first trial and to every trial
+    after a rejection, and the verdict follows from those alone."""
+    r = minimize(cfg1_system, cfg1["m0"], cfg1["b_ext"], Options(record=True, M=M))
+    hist = [r.energies[0]]
+    armijo_next = True
+    for tr in r.trials:
+        ref = max(hist[-M:])
+        assert tr["e_ref"] == ref
+        assert tr["armijo"] == armijo_next
+        want = tr["e"] <= ref - 1e-4 * tr["tau"] * tr["d"] if tr["armijo"] else tr["e"] <= ref
+        assert tr["accepted"] == want
+        if tr["accepted"]:
+            hist.append(tr["e"])
+            armijo_next = False
+        else:
+            armijo_next = True
+    assert hist == r.energies
+    raises = sum(1 for k in range(1, len(hist)) if hist[k] > hist[k - 1])
+    if M == 1:
+        assert raises == 0                    # memory 1 is a monotone line search
+    else:
+        assert raises >= 1                    # the nonmonotone rule accepts energy increases
