@@ -4,18 +4,23 @@
 Default workload: the FP64 hysteresis sweep on the 80 nm cube (40^3 Kuhn
 cells: 68,921 magnet nodes, 250,047 potential nodes), field +8 -> -8 -> +8 T
 in 0.1 T steps along z tilted by 1 degree, each point warm-started from the
-previous minimum.  A "step" is one field point of the sweep (a full
-minimization: trial steps, potential solves, field, step logic, stopping
-test, continuation); --steps K times the first K points (default 321, the
-whole loop with both switching fields; 161 = the descending branch).
+previous minimum.  A "step" is a batch of --points-per-step (16) consecutive
+field points of the loop (each a full minimization: trial steps, potential
+solves, field, step logic, stopping test, continuation); --steps K times the
+first 16 K points (default 20: 320 of the 321 points, both branches and both
+switching fields).
 
 Prints one JSON line with node-iterations/s (magnet nodes x energy-gradient
 evaluations, line-search trials included, per second of wall time), the
-roofline of the step kernel (algorithmic bytes per launch / its average
-launch time, HIP events on the library's stream), and the CPU oracle timed on
-a bounded sample of the same workload.
+roofline of the step kernel (algorithmic bytes of the method's per-row model
+per launch over its average launch time, HIP events on the library's
+stream), and in `detail` the same for one FP64 minimization of the
+1.03M-node polycrystal (the pure-HBM case) and the p50/p99 latencies of a
+bounded run of the served request stream; and the CPU oracle timed on a
+bounded sample of the sweep.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                    [--no-poly] [--no-serve] [--workload ...]
 """
 import argparse
 import json
@@ -91,15 +96,55 @@ def measured_traffic(name: str):
     return rec["traffic_bytes_per_launch"] if rec.get("kernel_source_sha256") == kernel_source_hash() else None
 
 
-def roofline_of(tm, lanes):
+def bytes_per_evaluation_model(sz: dict, evals: int, pcg_iters: int, fp64: bool = True) -> float:
+    """Algorithmic HBM bytes of `evals` energy-gradient evaluations with
+    `pcg_iters` potential-solver iterations in all, by the per-row model of
+    the method's kernels (every matrix and vector touched once, gathered
+    neighbours cached; int32 indices; z, z_L the measured average row
+    lengths of the magnet pattern and of the potential matrix):
+      FP64: per magnet node 296 + 64 z (divergence 36 + 28 z, field
+            188 + 36 z, Cayley update 72); per potential row 44 + 12 z_L for
+            the solve's start and 108 + 12 z_L per CG iteration;
+      FP32 form: 156 + 36 z; 24 + 8 z_L; 56 + 8 z_L.
+    With z = z_L = 15 this is B = 1256 N + (224 + 288 k) N_t per FP64
+    evaluation (k CG iterations).  Preconditioner work beyond one Jacobi CG
+    iteration is not counted: the model prices the method, not this
+    implementation's multigrid."""
+    N, Nt = sz["N"], sz["Nt"]
+    z = sz["nnz_magnet"] / max(N, 1)
+    zl = sz["nnz_potential"] / Nt if Nt else 0.0
+    if fp64:
+        node, init, it = 296 + 64 * z, 44 + 12 * zl, 108 + 12 * zl
+    else:
+        node, init, it = 156 + 36 * z, 24 + 8 * zl, 56 + 8 * zl
+    return evals * (node * N + init * Nt) + pcg_iters * it * Nt
+
+
+def roofline_of(tm, kernel, sz=None, evals=0, pcg_iters=0, fp64=True, traffic=None):
+    """Roofline of the step kernel over a timed region.  `achieved` = the
+    model's algorithmic bytes (bytes_per_evaluation_model) per launch over
+    the average launch duration (HIP events bracketing every batch of step
+    launches on the library's stream); `phase_model` gives the same for the
+    library's per-phase byte table, which also counts every multigrid
+    sweep."""
     if tm["launches"] <= 0 or tm["ms"] <= 0:
         return None
-    avg_s = tm["ms"] / 1e3 / tm["launches"]
-    achieved = tm["bytes"] / tm["launches"] / avg_s / 1e9
-    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": f"k_step<double,{lanes}>",
-            "avg_launch_us": avg_s * 1e6, "alg_bytes_per_launch": tm["bytes"] / tm["launches"],
-            "launches_timed": tm["launches"]}
+    secs = tm["ms"] / 1e3
+    avg_s = secs / tm["launches"]
+    out = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
+           "traffic": traffic, "kernel": kernel, "avg_launch_us": avg_s * 1e6, "launches_timed": tm["launches"]}
+    if sz is not None:
+        B = bytes_per_evaluation_model(sz, evals, pcg_iters, fp64)
+        out.update(achieved=B / secs / 1e9, frac=B / secs / 1e9 / HBM_PEAK_GBS,
+                   alg_bytes_per_launch=B / tm["launches"],
+                   alg_bytes_per_evaluation=B / max(evals, 1),
+                   avg_row_lengths={"magnet": sz["nnz_magnet"] / max(sz["N"], 1),
+                                    "potential": sz["nnz_potential"] / max(sz["Nt"], 1)})
+    out["phase_model"] = {"achieved": tm["bytes"] / secs / 1e9, "frac": tm["bytes"] / secs / 1e9 / HBM_PEAK_GBS,
+                          "alg_bytes_per_launch": tm["bytes"] / tm["launches"]}
+    if traffic and sz is not None:
+        out["traffic_over_alg"] = traffic / out["alg_bytes_per_launch"]
+    return out
 
 
 def base_line(value, K, warmup, wall, dtype, config):
@@ -108,11 +153,46 @@ def base_line(value, K, warmup, wall, dtype, config):
             "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
 
 
+def poly_run(ctx, cfg, prec, max_evals):
+    """One minimization of the polycrystal in one precision, with the
+    library's kernel timing on."""
+    import torch
+    from paper_1309_5796_amd import binding
+    t0 = time.perf_counter()
+    p = binding.Problem(ctx, cfg["mesh"], precision=prec)
+    setup = time.perf_counter() - t0
+    sz = p.sizes()
+    p.set_m(cfg["m0"])
+    p.set_field(cfg["b_ext"])
+    ctx.timing(True)
+    ctx.timing_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = p.minimize(max_evals=max_evals)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tm = ctx.timing_read(reset=True)
+    ctx.timing(False)
+    p.close()
+    name = "fp64" if prec == binding.FP64 else "mixed"
+    print(f"[bench] polycrystal {name}: setup {setup:.1f} s, status {r.status} evals {r.evals} pcg {r.pcg_iters} "
+          f"{wall:.2f} s E={r.energy_J:.12e} torque {r.max_torque:.2e}", file=sys.stderr, flush=True)
+    return dict(r=r, wall=wall, tm=tm, sz=sz, setup=setup)
+
+
+def poly_summary(o, fp64):
+    r = o["r"]
+    kernel = "k_step<double,4>" if fp64 else "k_step<float,4>"
+    traffic = measured_traffic("k_step_fp64_poly") if fp64 else None
+    return {"evals": r.evals, "iterations": r.iterations, "pcg_iters": r.pcg_iters, "wall_s": o["wall"],
+            "setup_s": o["setup"], "status": r.status, "max_torque": r.max_torque, "energy_J": r.energy_J,
+            "node_iterations_per_s": o["sz"]["N"] * r.evals / o["wall"],
+            "roofline": roofline_of(o["tm"], kernel, o["sz"], r.evals, r.pcg_iters, fp64, traffic)}
+
+
 def run_poly(args):
     """Config 3: 1.03M-node 64-grain polycrystal, one minimization at -2 T from
     +z + noise in the mixed form and in FP64; energies compared."""
-    import numpy as np
-    import torch
     from paper_1309_5796_amd import binding, meshgen
     t0 = time.perf_counter()
     cfg = meshgen.config3()
@@ -120,58 +200,23 @@ def run_poly(args):
     ctx = binding.Context(0)
     if args.lanes or args.blocks:
         ctx.set_launch_config(lanes_per_row=args.lanes, max_blocks=args.blocks)
-    out = {}
     forms = [("mixed", binding.MIXED), ("fp64", binding.FP64)]
     if args.poly_prec != "both":
         forms = [f for f in forms if f[0] == args.poly_prec]
-    for name, prec in forms:
-        t0 = time.perf_counter()
-        p = binding.Problem(ctx, cfg["mesh"], precision=prec)
-        print(f"[bench] {name} setup {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
-        p.set_m(cfg["m0"])
-        p.set_field(cfg["b_ext"])
-        ctx.timing(True)
-        ctx.timing_read(reset=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        r = p.minimize(max_evals=args.max_evals)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        tm = ctx.timing_read(reset=True)
-        ctx.timing(False)
-        out[name] = dict(r=r, wall=wall, tm=tm, N=p.N, Nt=p.Nt)
-        print(f"[bench] {name}: status {r.status} evals {r.evals} pcg {r.pcg_iters} {wall:.1f} s "
-              f"E={r.energy_J:.12e} torque {r.max_torque:.2e}", file=sys.stderr, flush=True)
-        p.close()
-    if len(out) < 2:
-        ctx.close()
-        (name, o), = out.items()
-        line = base_line(o["N"] * o["r"].evals / o["wall"], 1, 0, o["wall"], "f64" if name == "fp64" else
-                         "f32+f64-reductions", {"workload": f"{name} polycrystal, 200x200x100 nm box, one minimization",
-                                                "magnet_nodes": o["N"], "potential_nodes": o["Nt"]})
-        line["roofline"] = roofline_of(o["tm"], 4)
-        if name == "fp64" and line["roofline"]:
-            line["roofline"]["traffic"] = measured_traffic("k_step_fp64_poly")
-        print(json.dumps(line), flush=True)
-        return
-    mx, fp = out["mixed"], out["fp64"]
-    scale = sum(abs(getattr(fp["r"], k)) for k in ("e_exch_J", "e_anis_J", "e_zeem_J", "e_demag_J"))
-    line = base_line(mx["N"] * mx["r"].evals / mx["wall"], 1, 0, mx["wall"], "f32+f64-reductions",
-                     {"workload": "mixed-precision polycrystal, 200x200x100 nm box, 126x126x63 Kuhn cells, "
-                                  "64 grains, -2 T at 1 deg, one minimization",
-                      "magnet_nodes": mx["N"], "potential_nodes": mx["Nt"]})
-    line["roofline"] = roofline_of(mx["tm"], 4)
-    line["roofline"]["kernel"] = "k_step<float,4>"
-    line["detail"] = {
-        "mixed": {"evals": mx["r"].evals, "pcg_iters": mx["r"].pcg_iters, "wall_s": mx["wall"],
-                  "status": mx["r"].status, "max_torque": mx["r"].max_torque, "energy_J": mx["r"].energy_J},
-        "fp64": {"evals": fp["r"].evals, "pcg_iters": fp["r"].pcg_iters, "wall_s": fp["wall"],
-                 "status": fp["r"].status, "max_torque": fp["r"].max_torque, "energy_J": fp["r"].energy_J,
-                 "node_iterations_per_s": fp["N"] * fp["r"].evals / fp["wall"],
-                 "roofline": roofline_of(fp["tm"], 4)},
-        "rel_energy_mixed_vs_fp64": abs(mx["r"].energy_J - fp["r"].energy_J) / scale,
-    }
+    out = {name: poly_run(ctx, cfg, prec, args.max_evals) for name, prec in forms}
     ctx.close()
+    wl = "polycrystal, 200x200x100 nm box, 126x126x63 Kuhn cells, 64 grains, -2 T at 1 deg, one minimization"
+    lead = "mixed" if "mixed" in out else "fp64"
+    o = out[lead]
+    line = base_line(o["sz"]["N"] * o["r"].evals / o["wall"], 1, 0, o["wall"],
+                     "f64" if lead == "fp64" else "f32+f64-reductions",
+                     {"workload": f"{lead} {wl}", "magnet_nodes": o["sz"]["N"], "potential_nodes": o["sz"]["Nt"]})
+    line["roofline"] = poly_summary(o, lead == "fp64")["roofline"]
+    line["detail"] = {name: poly_summary(v, name == "fp64") for name, v in out.items()}
+    if len(out) == 2:
+        fp = out["fp64"]["r"]
+        scale = sum(abs(getattr(fp, k)) for k in ("e_exch_J", "e_anis_J", "e_zeem_J", "e_demag_J"))
+        line["detail"]["rel_energy_mixed_vs_fp64"] = abs(out["mixed"]["r"].energy_J - fp.energy_J) / scale
     print(json.dumps(line), flush=True)
 
 
@@ -236,24 +281,23 @@ def run_grains(args):
     print(json.dumps(line), flush=True)
 
 
-def run_serve(args):
-    """Config 5: the first --requests of the seeded Poisson stream (200 req/s)
-    submitted at their arrival times to a server with an HBM budget; reports
-    arrival-to-result latency percentiles (and from the submit call's
-    return) and node-iterations/s."""
+def serve_stream(n_requests, hbm_gb, slots, timeout_s, log_every=15.0):
+    """Submit the first n_requests of the seeded 200 req/s Poisson stream at
+    their arrival times to a server with an HBM budget; latency from each
+    request's arrival time (its place in the stream) and from the return of
+    its submit call (which only copies the request)."""
     import numpy as np
-    import torch
     from paper_1309_5796_amd import binding, meshgen
-    reqs = meshgen.config5_requests()[: args.requests]
+    reqs = meshgen.config5_requests()[:n_requests]
     t0 = time.perf_counter()
     built = [meshgen.request_mesh(r) for r in reqs]
     print(f"[bench] {len(built)} request meshes {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     ctx = binding.Context(0)
-    srv = binding.Server(ctx, hbm_budget=int(args.hbm_gb * (1 << 30)), max_slots=args.slots)
+    srv = binding.Server(ctx, hbm_budget=int(hbm_gb * (1 << 30)), max_slots=slots)
     t_start = time.perf_counter()
     t_last = t_start
     pending = {}
-    lat, lat_sub, node_evals, statuses = [], [], 0.0, []
+    lat, lat_sub, node_evals, statuses, nodes = [], [], 0.0, [], 0
     k = 0
     while k < len(reqs) or pending:
         now = time.perf_counter() - t_start
@@ -270,37 +314,48 @@ def run_serve(args):
                 lat.append(time.perf_counter() - t_arr)
                 lat_sub.append(time.perf_counter() - t_sub)
                 node_evals += n * r.evals
+                nodes += n
                 statuses.append(r.status)
         time.sleep(0.001)
-        if time.perf_counter() - t_last > 15.0:
+        if time.perf_counter() - t_last > log_every:
             t_last = time.perf_counter()
             print(f"[bench] serve t={t_last - t_start:.0f} s submitted {k}/{len(reqs)} completed {len(lat)}",
                   file=sys.stderr, flush=True)
-        if time.perf_counter() - t_start > args.serve_timeout:
+        if time.perf_counter() - t_start > timeout_s:
             print("[bench] serve timeout", file=sys.stderr, flush=True)
             break
     wall = time.perf_counter() - t_start
     st = srv.stats()
     srv.close()
     ctx.close()
-    lat = np.array(lat)
-    line = base_line(node_evals / wall, len(lat), 0, wall, "mixed f64/f32 per request",
-                     {"workload": f"served minimizations: first {len(reqs)} requests of the seeded 200 req/s "
+    lat, lat_sub = np.array(lat), np.array(lat_sub)
+
+    def pct(a, q):
+        return float(np.percentile(a, q)) if len(a) else None
+
+    return {"requests": len(reqs), "completed": int(len(lat)), "wall_s": wall,
+            "node_iterations_per_s": node_evals / wall, "magnet_nodes_completed": nodes,
+            "p50_s": pct(lat, 50), "p99_s": pct(lat, 99),
+            "p50_from_submit_s": pct(lat_sub, 50), "p99_from_submit_s": pct(lat_sub, 99),
+            "statuses": sorted(set(statuses)), "device_launches": st["launches"],
+            "setup_seconds_summed": st["setup_seconds"], "device_loop_busy_s": st["loop_seconds"],
+            "offered_rate_req_s": 200.0, "served_rate_req_s": len(lat) / wall,
+            "hbm_budget_GB": hbm_gb, "slots": slots}
+
+
+def run_serve(args):
+    """Config 5: the first --requests of the seeded Poisson stream (200 req/s)
+    submitted at their arrival times to a server with an HBM budget; reports
+    arrival-to-result latency percentiles (and from the submit call's
+    return) and node-iterations/s."""
+    d = serve_stream(args.requests, args.hbm_gb, args.slots, args.serve_timeout)
+    line = base_line(d["node_iterations_per_s"], d["completed"], 0, d["wall_s"], "mixed f64/f32 per request",
+                     {"workload": f"served minimizations: first {d['requests']} requests of the seeded 200 req/s "
                                   f"Poisson stream, 2:2:1 boxes 1.2k-520k nodes, 64-grain density, "
                                   f"B ~ U(-4,4) T, FP64/mixed coin", "hbm_budget_GB": args.hbm_gb,
                       "slots": args.slots})
     line["roofline"] = None
-    lat_sub = np.array(lat_sub)
-    # latency from each request's arrival time (its place in the stream), and
-    # from the return of its submit call (which only copies the request)
-    line["detail"] = {"p50_s": float(np.percentile(lat, 50)) if len(lat) else None,
-                      "p99_s": float(np.percentile(lat, 99)) if len(lat) else None,
-                      "p50_from_submit_s": float(np.percentile(lat_sub, 50)) if len(lat_sub) else None,
-                      "p99_from_submit_s": float(np.percentile(lat_sub, 99)) if len(lat_sub) else None,
-                      "completed": int(len(lat)), "statuses": sorted(set(statuses)),
-                      "device_launches": st["launches"], "setup_seconds_summed": st["setup_seconds"],
-                      "device_loop_busy_s": st["loop_seconds"], "offered_rate_req_s": 200.0,
-                      "served_rate_req_s": len(lat) / wall}
+    line["detail"] = d
     print(json.dumps(line), flush=True)
 
 
@@ -414,17 +469,96 @@ def run_copy(args):
     ctx.close()
 
 
+def run_sweep(args):
+    """The FP64 hysteresis loop of the 80 nm cube, K steps of `points_per_step`
+    field points each, timed; returns the line's pieces."""
+    import numpy as np
+    import torch
+    from paper_1309_5796_amd import binding, meshgen
+
+    cfg = meshgen.config2()
+    fields = cfg["fields"]
+    P = max(1, args.points_per_step)
+    K = max(1, args.steps)
+    npts = min(K * P, len(fields))
+    ctx = binding.Context(0)
+    if args.lanes or args.blocks:
+        ctx.set_launch_config(lanes_per_row=args.lanes, max_blocks=args.blocks)
+    if args.vcycle == "plain":
+        ctx.set_vcycle(0)
+    p = binding.Problem(ctx, cfg["mesh"], precision=binding.FP64)
+    sz = p.sizes()
+    state0 = p.get_state()
+    pc = {"auto": binding.PRECOND_AUTO, "jacobi": binding.PRECOND_JACOBI, "amg": binding.PRECOND_AMG}[args.precond]
+    if args.warmup > 0:
+        for w in range(args.warmup):
+            p.hysteresis(fields[(w * P) % len(fields):(w * P) % len(fields) + P], precond=pc)
+        p.set_state(state0)
+    ctx.timing(not args.no_kernel_timing)
+    ctx.timing_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = []
+    for k in range(K):
+        lo = k * P
+        if lo >= len(fields):
+            break
+        r_chunk, _ = p.hysteresis(fields[lo:min(npts, lo + P)], precond=pc)
+        res.extend(r_chunk)
+        if (k + 1) % 4 == 0 or k + 1 == K:
+            print(f"[bench] step {k + 1}/{K}: field points {len(res)}/{npts}, {time.perf_counter() - t0:.1f} s",
+                  file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    # switching: first sign change of <m>.u_H along each branch (bracket midpoint)
+    proj = [float(np.dot(r.m_avg, meshgen.U_H_1DEG)) for r in res]
+    bu = fields[:npts] @ meshgen.U_H_1DEG
+    bsw = [0.5 * (bu[k - 1] + bu[k]) for k in range(1, npts) if np.sign(proj[k]) != np.sign(proj[k - 1])]
+    tm = ctx.timing_read(reset=True)
+    ctx.timing(False)
+    p.close()
+    ctx.close()
+    wall = t1 - t0
+    evals = sum(r.evals for r in res)
+    pcg = sum(r.pcg_iters for r in res)
+    roof = None
+    if not args.no_kernel_timing:
+        roof = roofline_of(tm, f"k_step<double,{args.lanes or 4}>", sz, evals, pcg, True,
+                           measured_traffic("k_step_fp64_sweep80"))
+        if roof:
+            roof["memory_level"] = ("hbm-or-mall: the cube's working set (~290 MB with the multigrid hierarchy) "
+                                    "is largely resident in the 256 MB Infinity Cache")
+    b0, b1 = float(bu[0]), float(bu[npts - 1])
+    desc = "whole loop" if npts == len(fields) else f"first {npts} of the {len(fields)}-point loop"
+    config = {"workload": f"FP64 hysteresis sweep, 80 nm cube, 40^3 Kuhn cells ({sz['N']:,} magnet / "
+                          f"{sz['Nt']:,} potential nodes): field {b0:+.1f} T -> ... -> {b1:+.1f} T in 0.1 T steps "
+                          f"at 1 deg ({desc} +8 -> -8 -> +8 T), {P} field points per step",
+              "field_points": npts, "points_per_step": P, "magnet_nodes": sz["N"], "potential_nodes": sz["Nt"],
+              "potential_preconditioner": args.precond, "vcycle": args.vcycle}
+    detail = {"evals": evals, "iterations": sum(r.iterations for r in res), "pcg_iters": pcg,
+              "pcg_iters_per_eval": pcg / max(evals, 1), "launches": sum(r.launches for r in res),
+              "wall_s": wall, "switching_fields_T": [float(x) for x in bsw],
+              "statuses": sorted(set(r.status for r in res))}
+    return sz["N"] * evals / wall, K, wall, config, roof, detail
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=321,
-                    help="field points timed from +8 T (321 = whole loop, 161 = descending branch)")
+    ap.add_argument("--steps", type=int, default=20,
+                    help="steps timed; a step is --points-per-step field points of the loop (20 x 16 = 320 of "
+                         "the 321 points: both branches and both switching fields)")
+    ap.add_argument("--points-per-step", type=int, default=16)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--no-poly", action="store_true", help="leave the polycrystal FP64 run out of the default line")
+    ap.add_argument("--no-serve", action="store_true", help="leave the bounded serve out of the default line")
+    ap.add_argument("--serve-requests", type=int, default=24,
+                    help="requests of the stream the default line's bounded serve runs")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--blocks", type=int, default=0, help="blocks per problem (multiple of 8; 0 = library default)")
-    ap.add_argument("--chunk", type=int, default=20, help="field points per library call")
+    ap.add_argument("--chunk", type=int, default=20, help="field points per library call (sphere)")
     ap.add_argument("--workload", default="sweep80",
                     choices=["sweep80", "poly", "grains", "serve", "sphere", "copy", "assemble"])
     ap.add_argument("--assemble-request", type=int, default=38,
@@ -451,74 +585,32 @@ def main():
          "copy": run_copy, "assemble": run_assemble}[args.workload](args)
         return
 
-    import numpy as np
-    import torch
-    from paper_1309_5796_amd import binding, meshgen
-
-    cfg = meshgen.config2()
-    fields = cfg["fields"]
-    K = max(1, min(args.steps, len(fields)))
-    ctx = binding.Context(0)
-    if args.lanes or args.blocks:
-        ctx.set_launch_config(lanes_per_row=args.lanes, max_blocks=args.blocks)
-    if args.vcycle == "plain":
-        ctx.set_vcycle(0)
-    p = binding.Problem(ctx, cfg["mesh"], precision=binding.FP64)
-    state0 = p.get_state()
-    pc = {"auto": binding.PRECOND_AUTO, "jacobi": binding.PRECOND_JACOBI, "amg": binding.PRECOND_AMG}[args.precond]
-    if args.warmup > 0:
-        p.hysteresis(fields[: args.warmup], precond=pc)
-        p.set_state(state0)
-    ctx.timing(not args.no_kernel_timing)
-    ctx.timing_read(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = []
-    for k0 in range(0, K, args.chunk):
-        r_chunk, _ = p.hysteresis(fields[k0:min(K, k0 + args.chunk)], precond=pc)
-        res.extend(r_chunk)
-        print(f"[bench] field points {len(res)}/{K}: {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    # switching: first sign change of <m>.u_H along each branch (bracket midpoint)
-    proj = [float(np.dot(r.m_avg, meshgen.U_H_1DEG)) for r in res]
-    bu = fields[:K] @ meshgen.U_H_1DEG
-    bsw = [0.5 * (bu[k - 1] + bu[k]) for k in range(1, K) if np.sign(proj[k]) != np.sign(proj[k - 1])]
-    tm = ctx.timing_read(reset=True)
-    ctx.timing(False)
-    wall = t1 - t0
-    evals = sum(r.evals for r in res)
-    iters = sum(r.iterations for r in res)
-    pcg = sum(r.pcg_iters for r in res)
-    launches = sum(r.launches for r in res)
-    value = p.N * evals / wall
-
-    roof = None
-    traffic = measured_traffic("k_step_fp64_sweep80")
-    if tm["launches"] > 0 and tm["ms"] > 0:
-        avg_s = tm["ms"] / 1e3 / tm["launches"]
-        achieved = tm["bytes"] / tm["launches"] / avg_s / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "kernel": f"k_step<double,{args.lanes or 4}>", "avg_launch_us": avg_s * 1e6,
-                "alg_bytes_per_launch": tm["bytes"] / tm["launches"], "launches_timed": tm["launches"]}
-    line = {
-        "metric": METRIC, "value": value, "unit": "node-iterations/s", "n_gpus": 1,
-        "steps": K, "warmup": args.warmup, "ms_per_step": wall / K * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"FP64 hysteresis sweep, 80 nm cube, 40^3 Kuhn cells ({p.N:,} magnet / "
-                               f"{p.Nt:,} potential nodes), +8 -> -8 -> +8 T in 0.1 T steps at 1 deg",
-                   "field_points": K, "magnet_nodes": p.N, "potential_nodes": p.Nt,
-                   "potential_preconditioner": args.precond, "vcycle": args.vcycle},
-        "roofline": roof,
-        "detail": {"evals": evals, "iterations": iters, "pcg_iters": pcg, "launches": launches,
-                   "wall_s": wall, "switching_fields_T": [float(b) for b in bsw],
-                   "statuses": sorted(set(r.status for r in res))},
-    }
+    value, K, wall, config, roof, detail = run_sweep(args)
+    line = base_line(value, K, args.warmup, wall, "f64", config)
+    line["roofline"] = roof
+    line["detail"] = detail
+    if not args.no_poly:
+        # the headline HBM case: 1.03M magnet / 2.17M potential nodes, far
+        # above the Infinity Cache; one FP64 minimization, untimed by the line
+        from paper_1309_5796_amd import binding, meshgen
+        t0 = time.perf_counter()
+        cfg3 = meshgen.config3()
+        print(f"[bench] polycrystal mesh {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        ctx = binding.Context(0)
+        o = poly_run(ctx, cfg3, binding.FP64, args.max_evals)
+        ctx.close()
+        del cfg3
+        d = poly_summary(o, True)
+        d["workload"] = ("FP64 polycrystal, 200x200x100 nm, 126x126x63 Kuhn cells, 64 grains "
+                         f"({o['sz']['N']:,} magnet / {o['sz']['Nt']:,} potential nodes), -2 T, one minimization")
+        line["detail"]["polycrystal_fp64"] = d
+    if not args.no_serve:
+        d = serve_stream(args.serve_requests, args.hbm_gb, args.slots, args.serve_timeout)
+        d["workload"] = (f"served minimizations: first {d['requests']} requests of the seeded 200 req/s Poisson "
+                         f"stream (2:2:1 boxes, FP64/mixed coin)")
+        line["detail"]["serve"] = d
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
-    p.close()
-    ctx.close()
     print(json.dumps(line), flush=True)
 
 

@@ -7,8 +7,8 @@
  * minimization" (arXiv:1309.5796).  The library minimizes the total Gibbs
  * free energy (stray field + exchange + anisotropy + Zeeman) of a P1
  * tetrahedral mesh under |m_i| = 1 (Method section, eq. (1)) by the
- * curvilinear search on the sphere (eq. (7)) with Barzilai-Borwein step
- * lengths (eq. (9)) selected by the adaptive rule the paper adopts, a
+ * curvilinear search on the sphere (eq. (8)) with Barzilai-Borwein step
+ * lengths (eq. (10)) selected by the adaptive rule the paper adopts, a
  * 20-energy nonmonotone line search, and the stopping test on the torque.
  * The stray field comes from a magnetic scalar potential with an open
  * boundary handled by a space transformation (Results, comparison section);
@@ -72,7 +72,7 @@ extern "C" {
 #define MMSD_PRECOND_JACOBI 1 /* Jacobi, single-reduction CG: one launch per iteration */
 #define MMSD_PRECOND_AMG 2    /* smoothed-aggregation multigrid V(1,1) cycle, PCG */
 
-/* step-length rules (eq. (9)); ADAPTIVE is the rule the paper uses */
+/* step-length rules (eq. (10)); ADAPTIVE is the rule the paper uses */
 #define MMSD_STEP_ADAPTIVE 0  /* adaptive tau1/tau2 switching with a min-window */
 #define MMSD_STEP_ALTERNATE 1 /* plain alternation of tau1 and tau2 */
 #define MMSD_STEP_BB1 2
@@ -125,7 +125,12 @@ typedef struct {
  * node, s = 8 for FP64, 4 for mixed). */
 int mmsd_footprint(const mmsd_mesh* mesh, int precision, size_t* bytes_out);
 
-/* Validate the mesh, assemble the FE operators on the host and upload them.
+/* The minimization problem of the Method section, eq. (1): the total Gibbs
+ * free energy (stray field + exchange + anisotropy + external) of a mesh of
+ * standard linear tetrahedral elements (Abstract), with the stray field from
+ * a magnetic scalar potential on the transformed open domain (Results,
+ * comparison with the LLG solver).
+ * Validate the mesh, assemble the FE operators on the host and upload them.
  * Magnetic nodes are the nodes of region >= 1 tetrahedra, in ascending input
  * order; every magnetic region needs a material.  Errors: MMSD_E_MESH for an
  * index out of range, a degenerate tetrahedron, no magnetic tetrahedra or a
@@ -138,13 +143,25 @@ int mmsd_problem_destroy(mmsd_problem p);
 
 int mmsd_n_magnetic(mmsd_problem p, int64_t* n);   /* N: magnetic nodes */
 int mmsd_n_potential(mmsd_problem p, int64_t* n);  /* free (non-Dirichlet) nodes, 0 if none */
+/* Operator sizes: sizes[4] = {N, entries of the magnet-row pattern (shared by
+ * the exchange and the two gradient operators), N_t, entries of the
+ * potential matrix (CSR, before any padding)}.  The measurement of the
+ * algorithmic bytes per evaluation uses the average row lengths. */
+int mmsd_problem_sizes(mmsd_problem p, int64_t sizes[4]);
 
-/* Replace the material of one region (re-assembles exchange and anisotropy). */
+/* Material constants of the exchange and anisotropy terms of eq. (1) for one
+ * region (re-assembles exchange and anisotropy).  Errors: MMSD_E_INVALID for
+ * region < 1, a zero easy axis, Js <= 0, A < 0 or a non-finite K1; the
+ * problem keeps its previous material then. */
 int mmsd_set_material(mmsd_problem p, const mmsd_material* mat);
-/* Applied field b = mu0 H_ext (T), uniform. */
+/* Applied field b = mu0 H_ext (T), uniform: the external-energy term of
+ * eq. (1).  MMSD_E_INVALID for a non-finite component. */
 int mmsd_set_field(mmsd_problem p, const double b_ext_T[3]);
-/* m: [N*3] AoS, magnetic-node order; each vector is normalized on entry; a
- * zero or non-finite vector gives MMSD_E_INVALID. */
+/* Magnetization, which eq. (1) constrains to unit length at every node.
+ * m: [N*3] AoS, magnetic-node order, host memory copied during the call;
+ * each vector is normalized on entry; a zero or non-finite vector gives
+ * MMSD_E_INVALID (m unchanged).  mmsd_get_m writes the current accepted
+ * state into the caller's [N*3] array. */
 int mmsd_set_m(mmsd_problem p, const double* m);
 int mmsd_get_m(mmsd_problem p, double* m_out);
 
@@ -181,14 +198,22 @@ typedef struct {
   double seconds;             /* wall time of the call */
 } mmsd_result;
 
-/* Minimize from the current m at the current field.  Returns the status
+/* Minimize eq. (1) from the current m at the current field by the Method
+ * section's scheme: projected gradient (eqs. (2)-(5)), curvilinear step
+ * (eqs. (7)-(8), solved in closed form), Barzilai-Borwein step lengths
+ * (eq. (10)) with the adaptive switch, first step by an inexact line search
+ * and a line search whenever the energy exceeds the last 20 (step length
+ * selection); stop when max_i |m_i x h_i| < tol (the paper's Results use
+ * the sum of the squared gradient, reported as sum_torque2).  Returns the status
  * (also in out->status): MMSD_OK, MMSD_W_MAXEVALS, MMSD_W_FLOOR, or an error
  * (MMSD_E_NONFINITE when the energy or torque became non-finite; m is then
  * the last accepted state).  The potential is warm-started from the last
  * solve. */
 int mmsd_minimize(mmsd_problem p, const mmsd_options* o, mmsd_result* out);
 
-/* One evaluation (no step) at the current m: energies and torque in *out;
+/* One evaluation of eq. (1) and its gradient (no step; the effective field
+ * h = -dphi/dm defined below eq. (9), lumped per node; the potential by the
+ * preconditioned CG solve) at the current m: energies and torque in *out;
  * the field is then available from mmsd_get_field and the potential from
  * mmsd_get_potential. */
 int mmsd_evaluate(mmsd_problem p, const mmsd_options* o, mmsd_result* out);
@@ -207,7 +232,9 @@ int mmsd_get_potential(mmsd_problem p, double* u_out);    /* [n_nodes] input nod
 int mmsd_hysteresis(mmsd_problem p, const double* b_T, int64_t n, const mmsd_options* o,
                     mmsd_result* per_step, double* b_switch_out, int64_t* n_switch_out);
 
-/* Minimize n independent problems of one context together: every device
+/* Batched form (not in the paper; each problem follows the same Method
+ * section scheme as mmsd_minimize, eqs. (1)-(10)).
+ * Minimize n independent problems of one context together: every device
  * launch advances all unfinished problems by one phase (one persistent
  * kernel over a problem table; a captured launch graph is replayed until all
  * are done, and finished problems are dropped from the table as they
@@ -217,7 +244,9 @@ int mmsd_hysteresis(mmsd_problem p, const double* b_T, int64_t n, const mmsd_opt
  * mmsd_minimize result at that block count bit for bit.  out: [n]. */
 int mmsd_minimize_batch(mmsd_problem* probs, int n, const mmsd_options* o, mmsd_result* out);
 
-/* Checkpoint: m, potential warm start and field.  bytes: in = capacity, out =
+/* Checkpoint (not in the paper): the state a hysteresis continuation
+ * carries from one field point to the next (Introduction).
+ * Checkpoint: m, potential warm start and field.  bytes: in = capacity, out =
  * size; buf NULL queries the size.  set_state restores a state taken from a
  * problem on the same mesh and precision. */
 int mmsd_get_state(mmsd_problem p, void* buf, size_t* bytes);
@@ -243,10 +272,21 @@ int mmsd_set_launch_config(mmsd_ctx ctx, int lanes_per_row, int max_blocks);
  *                       down-sweep's launch, b_{l+1} = R (I - A wd) b;
  *   MMSD_VC_FOLD_SOLVE  with the last level fused, the coarsest solve too,
  *                       x_c = Ainv R (I - A wd) b.
- * Default: both.  0 gives the plain order (REST and SOLVE launches of their
- * own).  Returns MMSD_E_INVALID for other bits. */
+ *   MMSD_VC_SLICE_ALL   hold every matrix of the hierarchy (the level
+ *                       operators, restrictions and fused prolongation
+ *                       matrices) in the 64-row sliced layout and sweep it
+ *                       one row per thread, whatever its size and row
+ *                       length.  By default only matrices of at least
+ *                       65,536 rows and at most 24 entries per row on
+ *                       average are sliced, which only meshes of about a
+ *                       million nodes reach; the option runs those code
+ *                       paths on small meshes (tests).
+ * Default: MMSD_VC_FUSE_REST | MMSD_VC_FOLD_SOLVE.  0 gives the plain order
+ * (REST and SOLVE launches of their own).  Returns MMSD_E_INVALID for other
+ * bits. */
 #define MMSD_VC_FUSE_REST 1
 #define MMSD_VC_FOLD_SOLVE 2
+#define MMSD_VC_SLICE_ALL 4
 int mmsd_set_vcycle(mmsd_ctx ctx, int flags);
 
 /* Measurement aid: `reps` launches of a plain device-to-device copy kernel
@@ -303,7 +343,9 @@ int mmsd_assemble_device(mmsd_ctx ctx, const mmsd_mesh* mesh, const mmsd_materia
                          double* Q, double* V, int32_t* pot_global, int32_t* lrp, int32_t* lci, double* L);
 
 /* ---- serving ----------------------------------------------------------- */
-/* A server owns a worker thread that admits submitted minimizations while
+/* Served form (not in the paper; every request is one mmsd_minimize of
+ * eq. (1) by the Method section's scheme).
+ * A server owns a worker thread that admits submitted minimizations while
  * their device footprint fits in hbm_budget bytes and a slot is free (at
  * most max_slots resident), assembles and uploads them off the critical
  * path, advances every resident problem by one phase per device launch

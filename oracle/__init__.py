@@ -11,8 +11,8 @@ Method: Exl et al., "LaBonte's method revisited" (arXiv:1309.5796).
                    the scalar-potential stray field with the open-boundary
                    space transformation (Method section, eq. (1); Results,
                    "Comparison with LLG solver").
-* ``minimize``  -- the Cayley curvilinear step (eq. (7)), BB step lengths
-                   (eq. (9)) with the adaptive switching rule, the 20-energy
+* ``minimize``  -- the Cayley curvilinear step (eq. (8)), BB step lengths
+                   (eq. (10)) with the adaptive switching rule, the 20-energy
                    nonmonotone globalization, the stopping test, and the
                    hysteresis continuation (Introduction, Hysteresis).
 

@@ -17,7 +17,7 @@ energy down; this module uses the reading:
   cited there): a per-axis map of the shell [a, b) onto [a, inf) and the
   metric tensor evaluated at each tetrahedron's centroid;
 * effective field (variational, lumped; the paper defines h_eff = -dphi/dm
-  below eq. (8)): h_i = -1/(mu0 Ms^2 V_i) dE/dm_i, in units of Ms.
+  below eq. (9)): h_i = -1/(mu0 Ms^2 V_i) dE/dm_i, in units of Ms.
 
 All lengths are metres and all energies joules; the reduced energy used by
 the minimizer is e = E/(mu0 Ms^2) (cubic metres).

@@ -5,9 +5,9 @@ Method section of Exl et al.:
 * projected gradient g = m x (-m x grad phi) (eq. (2)-(4)); with the effective
   field h = -grad phi (in units of Ms, variational and lumped, see ``fem``)
   this is g_i = m_i x H_i with H_i = m_i x h_i (eq. (5));
-* curvilinear step m+ = m - tau (m + m+)/2 x H(m) (eq. (7)), solved exactly
+* curvilinear step m+ = m - tau (m + m+)/2 x H(m) (eq. (8)), solved exactly
   (it is a Cayley transform, so |m+| = |m|);
-* BB step lengths tau1 = s.s / s.y, tau2 = s.y / y.y (eq. (9)) chosen by the
+* BB step lengths tau1 = s.s / s.y, tau2 = s.y / y.y (eq. (10)) chosen by the
   adaptive rule of Loris et al. 2009; the first step from an inexact line
   search; a line search whenever the new energy exceeds the previous 20
   (end of the step-length subsection);
@@ -88,7 +88,7 @@ def cross(a, b):
 def cayley(m: np.ndarray, h: np.ndarray, tau: float) -> np.ndarray:
     """Exact solution of m+ = m - tau (m + m+)/2 x H with H = m x h.
 
-    Writing a = (tau/2) H, eq. (7) reads (I - [a]x) m+ = (I + [a]x) m, whose
+    Writing a = (tau/2) H, eq. (8) reads (I - [a]x) m+ = (I + [a]x) m, whose
     solution is m+ = m + 2 (c + a x c) / (1 + a.a) with c = a x m (the
     Rodrigues form of the Cayley transform: an exact rotation of m).
     """

@@ -26,7 +26,7 @@ FP64, MIXED = 0, 1
 EXCH, ANIS, ZEEM, DEMAG, ALL = 1, 2, 4, 8, 15
 STEP_ADAPTIVE, STEP_ALTERNATE, STEP_BB1, STEP_BB2 = 0, 1, 2, 3
 PRECOND_AUTO, PRECOND_JACOBI, PRECOND_AMG = 0, 1, 2
-VC_FUSE_REST, VC_FOLD_SOLVE = 1, 2
+VC_FUSE_REST, VC_FOLD_SOLVE, VC_SLICE_ALL = 1, 2, 4
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -70,6 +70,7 @@ SIGNATURES = [
     ("mmsd_problem_destroy", C.c_int, [C.c_void_p]),
     ("mmsd_n_magnetic", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     ("mmsd_n_potential", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    ("mmsd_problem_sizes", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     ("mmsd_set_material", C.c_int, [C.c_void_p, C.POINTER(MaterialC)]),
     ("mmsd_set_field", C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     ("mmsd_set_m", C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
@@ -236,7 +237,7 @@ class Context:
         _check(self.lib.mmsd_set_launch_config(self.handle, lanes_per_row, max_blocks))
 
     def set_vcycle(self, flags: int):
-        """V-cycle forms for problems created afterwards (VC_FUSE_REST, VC_FOLD_SOLVE)."""
+        """V-cycle forms for problems created afterwards (VC_FUSE_REST, VC_FOLD_SOLVE, VC_SLICE_ALL)."""
         _check(self.lib.mmsd_set_vcycle(self.handle, flags))
 
     def timing(self, on: bool):
@@ -318,6 +319,12 @@ class Problem:
         self.N = int(n.value)
         _check(self.lib.mmsd_n_potential(h, C.byref(n)))
         self.Nt = int(n.value)
+
+    def sizes(self) -> dict:
+        """N, magnet-pattern entries, N_t and potential-matrix entries."""
+        a = (C.c_int64 * 4)()
+        _check(self.lib.mmsd_problem_sizes(self.handle, a))
+        return dict(N=int(a[0]), nnz_magnet=int(a[1]), Nt=int(a[2]), nnz_potential=int(a[3]))
 
     def close(self):
         if getattr(self, "handle", None):

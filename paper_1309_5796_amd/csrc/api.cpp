@@ -37,8 +37,8 @@ size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Layout of one problem's device arena.
 struct Layout {
-  size_t mrp, mci, K, D1[3], D2[3], Q[6], V, m[2][3], H[2][3], h[3];
-  size_t lso, lsc, lsv, u, p, rec[2];
+  size_t mrp, mci, K, D1[3], D2[3], Q[6], V, m[2][3], H[2][3], h[3], mh[2];
+  size_t lso, lsc, lsv, lsum, u, p, rec[2];
   size_t part, ctrl, prob, blk, btab;
   size_t snap[2][2];
   size_t total;
@@ -71,9 +71,11 @@ Layout make_layout(int64_t N, int64_t nnzM, int64_t Nt, int64_t nnzLs, size_t s)
   for (int k = 0; k < 2; ++k)
     for (int c = 0; c < 3; ++c) L.H[k][c] = take(s * N);
   for (int c = 0; c < 3; ++c) L.h[c] = take(s * N);
+  for (int k = 0; k < 2; ++k) L.mh[k] = take(s * N);
   L.lso = take(4 * ((Nt + 63) / 64 + 1));
   L.lsc = take(4 * nnzLs);
   L.lsv = take(s * nnzLs);
+  L.lsum = take(s * Nt);
   L.u = take(s * Nt);
   L.p = take(s * Nt);
   for (int k = 0; k < 2; ++k) L.rec[k] = take(4 * s * Nt);
@@ -398,9 +400,11 @@ void bytes_model(mmsd_problem p) {
   double* b = p->btab;
   for (int k = 0; k < kByteSlots; ++k) b[k] = 0;
   b[PH_PREP] = 4 * (N + 1) + 4 * zM + 3 * s * zM + 9 * s * N + spmvL + 2 * s * Nt;   // trial m, b = D1 m, r = b - L u
+  if (p->precision == MMSD_MIXED) b[PH_PREP] += s * Nt;   // row sums of L
   b[PH_CG0] = spmvL + 5 * s * Nt;                                                       // w = L D^-1 r
   b[PH_CG] = spmvL + 12 * s * Nt;                                                       // one CG iteration
   b[PH_FIELD] = 4 * (N + 1) + 4 * zM + 4 * s * zM + s * N * (3 + 1 + 6 + 1 + 6 + 3);
+  if (p->precision == MMSD_MIXED) b[PH_FIELD] += 2 * s * N;   // m.h of the accepted state in, the trial's out
   b[PH_PCG_A] = spmvL + 7 * s * Nt;        // {z, p}, r, wd in; q, {wd r, wd q} out
   b[PH_PCG_B] = spmvL + 13 * s * Nt;       // {wd r, wd q}, r, q, {z, p}, u in; {z, p}, r, u, res out
   if (p->has_amg) {
@@ -456,13 +460,15 @@ int build_amg(mmsd_problem p) {
   std::vector<Csr> Q(nl), M(nl);
   std::vector<std::vector<int>> qfront(nl);
   std::vector<SlicedQ> sq(nl);
+  // every matrix sliced, as on the largest meshes (a context option for tests)
+  const bool slice_all = (c->vcycle & MMSD_VC_SLICE_ALL) != 0;
   p->amg_q_nnz.assign(nl, 0);
   p->amg_m_nnz.assign(nl, 0);
   p->amg_q_sliced.assign(nl, 0);
   for (int l = 0; l < nl; ++l) {
     const AmgLevel& L = H.lv[l];
     // Q's rows average about A P's entries: sliced by the same rule as A, R
-    const bool q_sliced = L.AP.nrows >= kSlicedRows && L.AP.ci.size() <= kWideRow * (size_t)L.AP.nrows;
+    const bool q_sliced = slice_all || (L.AP.nrows >= kSlicedRows && L.AP.ci.size() <= kWideRow * (size_t)L.AP.nrows);
     if (q_sliced) {
       sq[l] = make_sliced_q(L.AP, L.P, p->amg_q_nnz[l]);
       p->amg_q_sliced[l] = 1;
@@ -482,7 +488,8 @@ int build_amg(mmsd_problem p) {
         if (!p->amg_q_sliced[l]) continue;
         sl[l][1] = std::move(sq[l].ap);
       } else {
-        if ((k == 0 && l == 0) || M[k]->nrows < kSlicedRows || M[k]->ci.size() > kWideRow * (size_t)M[k]->nrows)
+        if ((k == 0 && l == 0) ||
+            (!slice_all && (M[k]->nrows < kSlicedRows || M[k]->ci.size() > kWideRow * (size_t)M[k]->nrows)))
           continue;
         sl[l][k] = make_sliced(M[k]->rp, M[k]->ci, M[k]->v, M[k]->ncols);
       }
@@ -712,6 +719,11 @@ int build_device(mmsd_problem p) {
     if ((rc = upload_int(st, base + L.lso, S.so)) || (rc = upload_int(st, base + L.lsc, S.sc)) ||
         (rc = upload_vec<real>(st, base + L.lsv, S.sv)))
       return rc;
+    // row sums, summed in FP64 from the assembled values
+    std::vector<double> rs(Nt, 0.0);
+    for (int64_t i = 0; i < Nt; ++i)
+      for (int k = A.lrp[i]; k < A.lrp[i + 1]; ++k) rs[i] += A.L[k];
+    if ((rc = upload_vec<real>(st, base + L.lsum, rs))) return rc;
     // Jacobi factors live in the d field of both CG record buffers
     std::vector<double> rec(4 * (size_t)Nt, 0.0);
     for (int64_t i = 0; i < Nt; ++i) rec[4 * i + 3] = A.invd[i];
@@ -742,10 +754,12 @@ int build_device(mmsd_problem p) {
     }
   }
   for (int k = 0; k < 6; ++k) P.Q[k] = (const real*)(base + L.Q[k]);
+  for (int k = 0; k < 2; ++k) P.mh[k] = (real*)(base + L.mh[k]);
   P.V = (const real*)(base + L.V);
   P.lso = (const int*)(base + L.lso);
   P.lsc = (const int*)(base + L.lsc);
   P.lsv = (const real*)(base + L.lsv);
+  P.lsum = (const real*)(base + L.lsum);
   P.u = (real*)(base + L.u);
   P.p = (real*)(base + L.p);
   for (int k = 0; k < 2; ++k) P.rec[k] = (Rec<real>*)(base + L.rec[k]);
@@ -823,17 +837,28 @@ int resolve(mmsd_problem p, const mmsd_options* o, Resolved* r) {
   return MMSD_OK;
 }
 
+constexpr int kMixedHalvings = 20;   // a factor of 1e6 on the trial step
+
 int arm(mmsd_problem p, const Resolved& r, int stage, int store_h) {
   const Assembly& A = p->A;
-  // energy resolution: FP64 runs keep the plain floor on tau; in the mixed
-  // form the energy carries FP32 rounding of the fields (about 2^-20 of the
-  // sum of the term magnitudes), below which backtracking cannot decide
-  const double e_res = p->precision == MMSD_MIXED ? std::ldexp(1.0, -20) : 0.0;
+  // FP64 runs decide on the energies themselves and halve down to the tau
+  // floor, as the oracle.  The mixed form decides on the accepted energy plus
+  // each trial's change (summed from products of the step, accurate relative
+  // to the change; the difference of two FP32-field energies is not), and a
+  // line search gives up after kMixedHalvings failed trials: once the torque
+  // reaches the error of the FP32 fields, halving no longer resolves a decrease.
+  // The mixed form also stops after a run of accepted steps without
+  // progress; it counts an energy decrease as progress from 2^-20 of the sum
+  // of the term magnitudes (the resolution of an energy built from FP32
+  // fields).  Its anisotropy energy is summed per node as m.(tr(Q) I - Q) m,
+  // which already holds the constant sum_e V_e K1_e.
+  const bool mixed = p->precision == MMSD_MIXED;
   const double dp[15] = {r.tol, r.rtol * r.rtol, 1e-4, 0.5, 0.5, 0.1, 1e-10, 1e10, 1e-14,
-                         p->b_ext[0] / A.Js, p->b_ext[1] / A.Js, p->b_ext[2] / A.Js, A.c_an, A.vol, e_res};
+                         p->b_ext[0] / A.Js, p->b_ext[1] / A.Js, p->b_ext[2] / A.Js, mixed ? 0.0 : A.c_an, A.vol,
+                         mixed ? std::ldexp(1.0, -20) : 0.0};
   MMSD_HIP(launch_ctrl_init(p->dctrl, kArmSlot, stage, r.terms, r.M, r.rule, r.maxit, store_h,
-                            (r.terms & MMSD_DEMAG) ? 1 : 0, p->acc, r.precond, (long long)r.max_evals, dp,
-                            p->ctx->stream));
+                            (r.terms & MMSD_DEMAG) ? 1 : 0, p->acc, r.precond, mixed ? 1 : 0,
+                            mixed ? kMixedHalvings : 0, (long long)r.max_evals, dp, p->ctx->stream));
   return MMSD_OK;
 }
 
@@ -1197,7 +1222,7 @@ int mmsd_set_launch_config(mmsd_ctx c, int lanes_per_row, int max_blocks) {
 
 int mmsd_set_vcycle(mmsd_ctx c, int flags) {
   if (!c) return invalid("null context");
-  if (flags & ~(MMSD_VC_FUSE_REST | MMSD_VC_FOLD_SOLVE)) return invalid("unknown V-cycle flags");
+  if (flags & ~(MMSD_VC_FUSE_REST | MMSD_VC_FOLD_SOLVE | MMSD_VC_SLICE_ALL)) return invalid("unknown V-cycle flags");
   c->vcycle = flags;
   return MMSD_OK;
 }
@@ -1296,6 +1321,15 @@ int mmsd_n_magnetic(mmsd_problem p, int64_t* n) {
 int mmsd_n_potential(mmsd_problem p, int64_t* n) {
   if (!p || !n) return invalid("null argument");
   *n = p->A.Nt;
+  return MMSD_OK;
+}
+
+int mmsd_problem_sizes(mmsd_problem p, int64_t sizes[4]) {
+  if (!p || !sizes) return invalid("null argument");
+  sizes[0] = p->A.N;
+  sizes[1] = (int64_t)p->A.mci.size();
+  sizes[2] = p->A.Nt;
+  sizes[3] = (int64_t)p->A.lci.size();
   return MMSD_OK;
 }
 
@@ -1457,8 +1491,7 @@ int mmsd_hysteresis(mmsd_problem p, const double* bT, int64_t n, const mmsd_opti
           const double d[3] = {hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]};
           if (std::sqrt(dot3(d, d)) <= r.refine) break;
           double mid[3] = {0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]), 0.5 * (lo[2] + hi[2])};
-          if ((rc = snap_locked(p, 0, false))) return rc;
-          mmsd_set_field(p, mid);
+          if ((rc = snap_locked(p, 0, false)) || (rc = mmsd_set_field(p, mid))) return rc;
           mmsd_result rm;
           rc = run_single(p, r, ST_INIT, 0, &rm);
           if (rc < 0) return rc;
@@ -1472,8 +1505,7 @@ int mmsd_hysteresis(mmsd_problem p, const double* bT, int64_t n, const mmsd_opti
           }
         }
         bsw = 0.5 * (dot3(lo, uh) + dot3(hi, uh));
-        if ((rc = snap_locked(p, 1, false))) return rc;
-        mmsd_set_field(p, B1);
+        if ((rc = snap_locked(p, 1, false)) || (rc = mmsd_set_field(p, B1))) return rc;
       }
       if (b_switch_out) b_switch_out[nsw] = bsw;
       ++nsw;
@@ -1884,8 +1916,7 @@ int mmsd_set_state(mmsd_problem p, const void* buf, size_t bytes) {
     rc = p->precision == MMSD_MIXED ? copy_m_to_device<float>(p, (const double*)(b + 64), false)
                                     : copy_m_to_device<double>(p, (const double*)(b + 64), false);
   }
-  if (rc) return rc;
-  mmsd_set_field(p, bf);
+  if (rc || (rc = mmsd_set_field(p, bf))) return rc;
   if (Nt) {
     std::lock_guard<std::mutex> lk(p->ctx->mu);
     hipStream_t st = p->ctx->stream;

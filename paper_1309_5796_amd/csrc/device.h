@@ -5,7 +5,7 @@
 // lists its linear-algebra parts) is a sequence of phases, one per launch of
 // the step kernel:
 //
-//   PREP   trial m_t = Cayley(m, h, tau) (eq. (7), explicit form) on magnet
+//   PREP   trial m_t = Cayley(m, h, tau) (eq. (8), explicit form) on magnet
 //          rows; b = G m_t; r = b - L u (warm start from the last solve)
 //   CG0    w = L D^-1 r; partial r.D^-1 r and w.D^-1 r
 //   CG     one Jacobi-preconditioned CG iteration in the single-reduction
@@ -15,7 +15,7 @@
 //          values of r, s, w are recomputed where they are gathered
 //   FIELD  h = -K m - D2 u + Q m + b_ext/Js; H = m x h; fused reductions of
 //          the energy, max|H|, sum V|H|^2 and the BB dots s.s, s.y, y.y
-//          (eq. (9)).
+//          (eq. (10)).
 // With the multigrid preconditioner the potential solve runs PH_MG
 // operations (one V-cycle operation on one level per launch; a DOWN may
 // also restrict, and on the last level also solve the coarsest level),
@@ -51,14 +51,15 @@ constexpr int kMaxLevels = 12;
 enum Stage : int { ST_INIT = 0, ST_RUN = 1, ST_EVAL = 2 };
 
 constexpr int kBlock = 512;        // threads per block (8 wavefronts of 64)
-constexpr int kNPart = 13;         // partial sums per block (FIELD needs 13)
+constexpr int kNPart = 14;         // partial sums per block (FIELD needs 14)
 constexpr int kMaxHist = 64;       // nonmonotone memory capacity
 constexpr int kMaxBlocks = 2048;   // per problem (every block reads all partials)
 
 // FIELD partial slots
 enum FieldPart : int {
   FP_EEX = 0, FP_EAN = 1, FP_EZ = 2, FP_ED = 3, FP_TMAX = 4, FP_D = 5,
-  FP_SS = 6, FP_SY = 7, FP_YY = 8, FP_MX = 9, FP_MY = 10, FP_MZ = 11, FP_H2 = 12
+  FP_SS = 6, FP_SY = 7, FP_YY = 8, FP_MX = 9, FP_MY = 10, FP_MZ = 11, FP_H2 = 12,
+  FP_DE = 13   // mixed form: energy change from the accepted state, -1/2 sum V s.(h_t + h)
 };
 
 // Control state of one problem (two slots, one per launch parity).  `phase`
@@ -75,11 +76,16 @@ struct Ctrl {
   long long launches_done;       // phases executed
   long long nphase[4];           // executed PREP, CG0 / MG, CG / PCG_A + PCG_B, FIELD phases
   int precond, mg_op, mg_lev, rcur;   // preconditioner in use; V-cycle position; residual parity
-  int mg_first, pad2;
+  int mg_first, chain;           // chain: trial energies = accepted energy + the FIELD phase's change
+  int max_halvings, halvings;    // line-search halvings allowed (0: down to tau_floor) and taken
   double alg_bytes;              // algorithmic bytes of the executed phases (roofline accounting)
   // options and constants
   double tol, pcg_rtol2, c1, rho, kappa0, theta0, tau_min, tau_max, tau_floor;
-  double e_res;            // relative resolution of the energy (0: exact arithmetic assumed)
+  double e_chain;                // accepted energy of the chain (chain mode)
+  // stagnation test of the chain mode: energy and torque at the last
+  // progress, FP32 resolution of the energy, accepted steps since
+  double prog_e, prog_T, e_res;
+  int stall, pad3;
   double bz[3];                  // applied field / Js
   double c_an;                   // sum_e V_e K1_e / (mu0 Ms^2)
   double vol;                    // sum_i V_i
@@ -184,12 +190,16 @@ struct ProbT {
   Ptr<real> m[2][3];          // accepted / trial slots, SoA
   Ptr<real> H[2][3];          // torque m x h per slot
   Ptr<real> h[3];             // effective field (written when store_h)
+  Ptr<real> mh[2];            // m.h per slot (FP32 form: with H = m x h it gives h = (m.h) m + H x m)
   // potential rows (magnet rows first): transformed Laplacian in 64-row
   // slices (entry k of row i at lso[i/64] + 64 k + i mod 64, short rows
   // padded with their own column and a zero value)
   Ptr<const int> lso;
   Ptr<const int> lsc;
   Ptr<const real> lsv;
+  Ptr<const real> lsum;       // row sums of the potential matrix (zero but on rows next to the
+                              // Dirichlet boundary); the FP32 form takes L u as
+                              // sum_j L_ij (u_j - u_i) + lsum_i u_i
   Ptr<real> u;                // potential (the CG iterate), warm start across solves
   Ptr<real> p;                // search direction (row-local)
   Ptr<Rec<real>> rec[2];      // CG state by buffer parity (pcur)

@@ -48,7 +48,7 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 
 // Explicit solution of the curvilinear step m+ = m - tau (m + m+)/2 x H
-// (eq. (7)): with a = (tau/2) H and c = a x m, m+ = m + 2 (c + a x c) / (1 + a.a).
+// (eq. (8)): with a = (tau/2) H and c = a x m, m+ = m + 2 (c + a x c) / (1 + a.a).
 // ht = tau / 2.  In FP32 the result is renormalized to keep |m| = 1 at
 // single-precision rounding.
 template <typename real>
@@ -278,7 +278,15 @@ __device__ void phase_prep(const ProbDev<real>& P, const Ctrl* C, int blk, doubl
     if (i >= r1) continue;
     const real bi = i < P.N ? (amg ? r2[i] : rec[i].r) : real(0);
     const real ui = u[i];
-    const real lu = sell_sum(P, i, [&](int j) { return u[j]; });
+    // FP32: the potential is large and smooth next to its residual, and the
+    // rounding of the matrix values times u would swamp b - L u; L's rows sum
+    // to zero away from the Dirichlet boundary, so the sum is taken over
+    // differences u_j - u_i plus the (exactly assembled) row sum times u_i
+    real lu;
+    if constexpr (std::is_same<real, float>::value)
+      lu = sell_sum(P, i, [&](int j) { return u[j] - ui; }) + P.lsum[i] * ui;
+    else
+      lu = sell_sum(P, i, [&](int j) { return u[j]; });
     const real ri = bi - lu;
     if (amg) r2[i] = ri;
     else rec[i].r = ri;
@@ -708,6 +716,11 @@ __device__ void phase_field(const ProbDev<real>& P, const Ctrl* C, int blk, doub
   constexpr int kU = kUnrollWide<real>;
   const int lane = threadIdx.x & (LPR - 1);
   const int slot = threadIdx.x / LPR;
+  // FP32: the rows of K and D2 sum to zero (the P1 gradients of an element
+  // sum to zero), so the sums are taken over differences from the row's own
+  // node, sum_j K_ij (m_j - m_i) and sum_j D2_ij (u_j - u_i): the large
+  // diagonal no longer cancels against its neighbours in single precision.
+  constexpr bool kDiff = std::is_same<real, float>::value;
   int r0, r1;
   chunk_rows(P.N, P.G, blk, RPP, RPP, r0, r1);
   const int a = C->acc, tr = 1 - a;
@@ -730,6 +743,13 @@ __device__ void phase_field(const ProbDev<real>& P, const Ctrl* C, int blk, doub
     const int i = base + slot;
     const bool valid = i < r1;
     real kx = 0, ky = 0, kz = 0, dx = 0, dy = 0, dz = 0;
+    real oi0 = 0, oi1 = 0, oi2 = 0, oiu = 0;   // own values subtracted in the difference form
+    if (kDiff && valid) {
+      oi0 = mx[i];
+      oi1 = my[i];
+      oi2 = mz[i];
+      if (demag) oiu = P.u[i];
+    }
     if (valid) {
       const int ke = P.mrp[i + 1];
       for (int k0 = P.mrp[i] + lane; k0 < ke; k0 += kU * LPR) {
@@ -747,9 +767,9 @@ __device__ void phase_field(const ProbDev<real>& P, const Ctrl* C, int blk, doub
           for (int u = 0; u < kU; ++u) {
             const int k = ok[u] ? k0 + u * LPR : k0;
             kv[u] = ok[u] ? P.K[k] : real(0);
-            gx[u] = mx[j[u]];
-            gy[u] = my[j[u]];
-            gz[u] = mz[j[u]];
+            gx[u] = mx[j[u]] - oi0;
+            gy[u] = my[j[u]] - oi1;
+            gz[u] = mz[j[u]] - oi2;
           }
 #pragma unroll
           for (int u = 0; u < kU; ++u) {
@@ -767,7 +787,7 @@ __device__ void phase_field(const ProbDev<real>& P, const Ctrl* C, int blk, doub
             ex[u] = f * P.D2[0][k];
             ey[u] = f * P.D2[1][k];
             ez[u] = f * P.D2[2][k];
-            uj[u] = P.u[j[u]];
+            uj[u] = P.u[j[u]] - oiu;
           }
 #pragma unroll
           for (int u = 0; u < kU; ++u) {
@@ -806,8 +826,21 @@ __device__ void phase_field(const ProbDev<real>& P, const Ctrl* C, int blk, doub
       }
       const double V = (double)P.V[i];
       fa[FP_EEX] += 0.5 * V * (double)(m0 * kx + m1 * ky + m2 * kz);
-      fa[FP_EAN] -= 0.5 * V * (double)(m0 * ax + m1 * ay + m2 * az);
-      fa[FP_EZ] -= V * (double)(m0 * bzx + m1 * bzy + m2 * bzz);
+      if constexpr (kDiff) {
+        // FP32: the anisotropy energy sum_e V_e K1_e - m.Q m cancels for m
+        // near the easy axis; for unit m it equals m.(tr(Q) I - Q) m, whose
+        // matrix has no large entries along the axis
+        if (anis) {
+          const real t0 = P.Q[1][i] + P.Q[2][i], t1 = P.Q[0][i] + P.Q[2][i], t2 = P.Q[0][i] + P.Q[1][i];
+          const real q = t0 * m0 * m0 + t1 * m1 * m1 + t2 * m2 * m2 -
+                         real(2) * (P.Q[3][i] * m0 * m1 + P.Q[4][i] * m0 * m2 + P.Q[5][i] * m1 * m2);
+          fa[FP_EAN] += 0.5 * V * (double)q;
+        }
+      } else {
+        fa[FP_EAN] -= 0.5 * V * (double)(m0 * ax + m1 * ay + m2 * az);
+      }
+      // with the applied field in FP64 (rounding it to FP32 would bias every node alike)
+      if (zeem) fa[FP_EZ] -= V * ((double)m0 * C->bz[0] + (double)m1 * C->bz[1] + (double)m2 * C->bz[2]);
       fa[FP_ED] += 0.5 * V * (double)(m0 * dx + m1 * dy + m2 * dz);
       const double H2 = (double)Hx * Hx + (double)Hy * Hy + (double)Hz * Hz;
       fa[FP_TMAX] = fmax(fa[FP_TMAX], sqrt(H2));
@@ -826,6 +859,20 @@ __device__ void phase_field(const ProbDev<real>& P, const Ctrl* C, int blk, doub
       fa[FP_MX] += V * (double)m0;
       fa[FP_MY] += V * (double)m1;
       fa[FP_MZ] += V * (double)m2;
+      if constexpr (kDiff) {
+        // energy change from the accepted state.  Every term of the energy is
+        // quadratic or linear in m, so e(m_t) - e(m) = -1/2 sum V s.(h_t + h)
+        // exactly, with s = m_t - m: small products of s, accurate relative
+        // to the change itself, where the difference of two FP32 energies
+        // would lose it.  The accepted field is h = (m.h) m + H x m.
+        const double mha = (double)P.mh[a][i];
+        const double ha0 = mha * n0 + ((double)G1 * n2 - (double)G2 * n1);
+        const double ha1 = mha * n1 + ((double)G2 * n0 - (double)G0 * n2);
+        const double ha2 = mha * n2 + ((double)G0 * n1 - (double)G1 * n0);
+        const double sh = s0 * ((double)hx + ha0) + s1 * ((double)hy + ha1) + s2 * ((double)hz + ha2);
+        fa[FP_DE] -= 0.5 * V * sh;
+        P.mh[tr][i] = m0 * hx + m1 * hy + m2 * hz;
+      }
     }
   }
   if (lane == 0) {
@@ -861,6 +908,8 @@ __device__ void push_hist(Ctrl* C, double e) {
 __device__ void accept_trial(Ctrl* C, const double* v, double e_t, const double* eterm) {
   C->acc = 1 - C->acc;
   C->e_acc = e_t;
+  C->e_chain = e_t;
+  C->halvings = 0;
   C->T_acc = v[FP_TMAX];
   C->d_acc = v[FP_D];
   C->h2_acc = v[FP_H2];
@@ -870,6 +919,8 @@ __device__ void accept_trial(Ctrl* C, const double* v, double e_t, const double*
   C->mavg_acc[2] = v[FP_MZ] / C->vol;
   push_hist(C, e_t);
 }
+
+constexpr int kStall = 50;   // accepted steps without progress that end a mixed run
 
 __device__ void finish_done(Ctrl* C, int status) {
   C->status = status;
@@ -887,14 +938,17 @@ __device__ __forceinline__ void signal_done(const ProbDev<real>& P, const Ctrl* 
 // Step-length logic after an evaluated trial (Method section, step length
 // selection): acceptance against the nonmonotone reference, Armijo
 // backtracking for the first step and for rejected BB steps, then the BB
-// step lengths tau1 = s.s/s.y, tau2 = s.y/y.y (eq. (9)) chosen by the rule.
+// step lengths tau1 = s.s/s.y, tau2 = s.y/y.y (eq. (10)) chosen by the rule.
 __device__ void step_logic(Ctrl* C, const double* v) {
   const bool anis = C->terms & MMSD_ANIS;
   double eterm[4] = {v[FP_EEX], v[FP_EAN] + (anis ? C->c_an : 0.0), v[FP_EZ],
                      v[FP_ED] + (C->demag ? 0.5 * C->ru : 0.0)};
-  const double e_t = eterm[0] + eterm[1] + eterm[2] + eterm[3];
+  const double e_direct = eterm[0] + eterm[1] + eterm[2] + eterm[3];
+  // the energy the decisions use: direct, or (chain mode, after the first
+  // evaluation) the accepted energy plus the change the FIELD phase summed
+  const double e_t = (C->chain && C->stage == ST_RUN) ? C->e_chain + v[FP_DE] : e_direct;
   C->evals++;
-  if (!isfinite(e_t) || !isfinite(v[FP_TMAX])) {
+  if (!isfinite(e_t) || !isfinite(e_direct) || !isfinite(v[FP_TMAX])) {
     finish_done(C, MMSD_E_NONFINITE);
     return;
   }
@@ -909,6 +963,9 @@ __device__ void step_logic(Ctrl* C, const double* v) {
       finish_done(C, MMSD_OK);
       return;
     }
+    C->stall = 0;
+    C->prog_e = C->e_chain;
+    C->prog_T = C->T_acc;
     C->tau = C->theta0 / C->T_acc;
     C->first = 1;
     C->backtrack = 0;
@@ -931,10 +988,10 @@ __device__ void step_logic(Ctrl* C, const double* v) {
     }
     C->tau *= C->rho;
     C->backtrack = 1;
-    // stop also when the energy change the next trial can make (~ tau d) is
-    // below the energy's resolution in this precision
-    const double e_scale = fabs(eterm[0]) + fabs(eterm[1]) + fabs(eterm[2]) + fabs(eterm[3]);
-    if (C->tau < C->tau_floor || C->tau * C->d_acc < C->e_res * e_scale) {
+    // stop also after max_halvings failed trials of one line search (mixed
+    // form: once the torque reaches the FP32 fields' error, the trials'
+    // energy changes are no longer resolved, and halving does not help)
+    if (C->tau < C->tau_floor || (C->max_halvings > 0 && ++C->halvings > C->max_halvings)) {
       finish_done(C, MMSD_W_FLOOR);
       return;
     }
@@ -951,6 +1008,23 @@ __device__ void step_logic(Ctrl* C, const double* v) {
   if (C->evals >= C->max_evals) {
     finish_done(C, MMSD_W_MAXEVALS);
     return;
+  }
+  if (C->chain) {
+    // mixed form: once the torque reaches the error of the FP32 fields the
+    // accepted steps only shuffle noise.  Progress is a torque 10% below the
+    // best so far or an energy below the one at the last progress by more
+    // than its FP32 resolution (a reversal near a switching field lowers the
+    // energy while its torque grows); kStall accepted steps without progress
+    // end the run (FLOOR).
+    const double e_scale = fabs(eterm[0]) + fabs(eterm[1]) + fabs(eterm[2]) + fabs(eterm[3]);
+    if (C->T_acc < 0.9 * C->prog_T || C->e_chain < C->prog_e - C->e_res * e_scale) {
+      C->prog_T = fmin(C->prog_T, C->T_acc);
+      C->prog_e = fmin(C->prog_e, C->e_chain);
+      C->stall = 0;
+    } else if (++C->stall >= kStall) {
+      finish_done(C, MMSD_W_FLOOR);
+      return;
+    }
   }
   C->first = 0;
   C->backtrack = 0;
@@ -1269,7 +1343,7 @@ __global__ void __launch_bounds__(kBlock, 4) k_step(const ProbDev<real>* __restr
 // slot `slot` (the one the next step launch reads), with a sequence number
 // above both slots' so the host always picks the newest.
 struct CtrlInit {
-  int stage, terms, nonmono_M, step_rule, pcg_maxit, store_h, demag, acc, precond, pad;
+  int stage, terms, nonmono_M, step_rule, pcg_maxit, store_h, demag, acc, precond, chain, max_halvings, pad;
   long long max_evals;
   double tol, pcg_rtol2, c1, rho, kappa0, theta0, tau_min, tau_max, tau_floor, e_res;
   double bz[3], c_an, vol;
@@ -1310,6 +1384,10 @@ __global__ void k_ctrl_init(Ctrl* ctrl, int slot, CtrlInit a) {
   C->mg_lev = 0;
   C->rcur = 0;
   C->mg_first = 0;
+  C->chain = a.chain;
+  C->max_halvings = a.max_halvings;
+  C->halvings = 0;
+  C->e_chain = 0.0;
   C->alg_bytes = 0.0;
   C->tol = a.tol;
   C->pcg_rtol2 = a.pcg_rtol2;
@@ -1321,6 +1399,8 @@ __global__ void k_ctrl_init(Ctrl* ctrl, int slot, CtrlInit a) {
   C->tau_max = a.tau_max;
   C->tau_floor = a.tau_floor;
   C->e_res = a.e_res;
+  C->stall = 0;
+  C->prog_e = C->prog_T = 0.0;
   for (int k = 0; k < 3; ++k) C->bz[k] = a.bz[k];
   C->c_an = a.c_an;
   C->vol = a.vol;
@@ -1367,10 +1447,12 @@ template hipError_t launch_step<double>(int, const Prob<double>*, int, const int
 template hipError_t launch_step<float>(int, const Prob<float>*, int, const int*, int, int, hipStream_t);
 
 hipError_t launch_ctrl_init(Ctrl* ctrl, int slot, int stage, int terms, int nonmono_M, int step_rule,
-                            int pcg_maxit, int store_h, int demag, int acc, int precond, long long max_evals,
-                            const double* dparams, hipStream_t s) {
+                            int pcg_maxit, int store_h, int demag, int acc, int precond, int chain,
+                            int max_halvings, long long max_evals, const double* dparams, hipStream_t s) {
   CtrlInit a;
   a.precond = precond;
+  a.chain = chain;
+  a.max_halvings = max_halvings;
   a.pad = 0;
   a.stage = stage;
   a.terms = terms;

@@ -30,8 +30,8 @@ template <typename real>
 hipError_t launch_step(int lpr, const Prob<real>* probs, int nprob, const int* blk_start, int grid, int parity,
                        hipStream_t s);
 hipError_t launch_ctrl_init(Ctrl* ctrl, int slot, int stage, int terms, int nonmono_M, int step_rule,
-                            int pcg_maxit, int store_h, int demag, int acc, int precond, long long max_evals,
-                            const double* dparams, hipStream_t s);
+                            int pcg_maxit, int store_h, int demag, int acc, int precond, int chain,
+                            int max_halvings, long long max_evals, const double* dparams, hipStream_t s);
 
 hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream_t s);
 

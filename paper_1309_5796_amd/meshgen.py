@@ -191,11 +191,14 @@ def assign_grains(mesh: Mesh, n_grains: int, rng: np.random.Generator,
     (K1 = 0, A = 2 pJ/m).  Regions: grain g -> g+1, boundary -> n_grains+1."""
     mag = mesh.region > 0
     xyz = mesh.xyz
-    lo = xyz[mesh.tets[mag]].reshape(-1, 3).min(axis=0)
-    hi = xyz[mesh.tets[mag]].reshape(-1, 3).max(axis=0)
+    mt = mesh.tets[mag]
+    on_magnet = np.zeros(xyz.shape[0], dtype=bool)
+    on_magnet[mt.ravel()] = True
+    lo = xyz[on_magnet].min(axis=0)
+    hi = xyz[on_magnet].max(axis=0)
     centres = rng.uniform(lo, hi, size=(n_grains, 3))
     axes = [cap_axis(rng) for _ in range(n_grains)]
-    cen = tet_centroids(mesh)[mag]
+    cen = xyz[mt].mean(axis=1)
     if n_grains == 1:
         reg = np.ones(cen.shape[0], dtype=np.int32)
     else:

@@ -122,6 +122,19 @@ def test_batch_equals_one_by_one_bitwise(ctx):
     out = binding.minimize_batch(probs)
     for k, (p, r) in enumerate(zip(probs, out)):
         assert (r.energy_J, r.evals, r.iterations, p.get_m().tobytes()) == single[k], k
+    # and every result is the oracle's minimum: FP64 to 1e-10, mixed to 1e-6
+    # (relative to the sum of the term magnitudes)
+    ref = {}
+    for k, (p, r) in enumerate(zip(probs, out)):
+        edge, seed = specs[k % len(specs)]
+        if (edge, seed) not in ref:
+            mesh, m0 = small_grain(edge, seed)
+            ref[edge, seed] = oracle.minimize(oracle.System(mesh), m0, -1.0 * meshgen.U_H_1DEG, Options())
+        ro = ref[edge, seed]
+        tol = 1e-10 if p.precision == binding.FP64 else 1e-6
+        assert ro.status == 0 and r.status in ((0,) if p.precision == binding.FP64 else (0, 2)), k
+        assert abs(r.energy_J - ro.E) < tol * sum(abs(v) for v in ro.terms.values()), k
+        np.testing.assert_allclose(p.get_m(), ro.m, atol=1e-5 if p.precision == binding.FP64 else 1e-3)
     for p in probs:
         p.close()
 
@@ -223,6 +236,14 @@ def test_server_results_equal_alone_and_in_the_mix(ctx):
     for k in range(len(reqs)):
         r, m = got[k]
         assert (r.energy_J, r.evals, m.tobytes()) == alone[k], k
+    # every served result is also the oracle's minimum (FP64 1e-10, mixed 1e-6)
+    for k, (edge, seed, prec) in enumerate(reqs):
+        r, m = got[k]
+        mesh, m0 = small_grain(edge, seed)
+        ro = oracle.minimize(oracle.System(mesh), m0, -1.5 * meshgen.U_H_1DEG, Options())
+        tol = 1e-10 if prec == binding.FP64 else 1e-6
+        assert ro.status == 0 and abs(r.energy_J - ro.E) < tol * sum(abs(v) for v in ro.terms.values()), k
+        np.testing.assert_allclose(m, ro.m, atol=1e-5 if prec == binding.FP64 else 1e-3)
     t0 = time.time()
     with pytest.raises(binding.MMSDError, match="out of range") as e:
         while srv.poll(bad_ticket) is None and time.time() - t0 < 30:

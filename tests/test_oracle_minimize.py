@@ -1,5 +1,5 @@
 """Pins of the oracle's minimizer: the curvilinear step (Method section,
-eq. (7)), the gradient identities (eq. (2)-(5)), the step rule's invariants,
+eq. (8)), the gradient identities (eq. (2)-(5)), the step rule's invariants,
 and the physics it must reproduce (Stoner-Wohlfarth switching, including the
 paper's own 45-degree pin, and the Bloch wall).  No GPU."""
 import json
@@ -196,7 +196,7 @@ def test_other_step_rules_reach_the_same_minimum(cfg1, cfg1_system, rule):
 
 # ---------------------------------------------------------------------------
 # Pins of the step-rule decisions (Method section, step length selection,
-# eq. (9) and the 20-energy nonmonotone rule).  The constants are the
+# eq. (10) and the 20-energy nonmonotone rule).  The constants are the
 # readings the library shares with the oracle: first trial 0.1 / max|H|;
 # Armijo c1 = 1e-4 with slope -sum V |H|^2, halving; BB trials accepted
 # against the maximum of the last 20 accepted energies; adaptive switch with
