@@ -342,6 +342,24 @@ int mmsd_assemble_device(mmsd_ctx ctx, const mmsd_mesh* mesh, const mmsd_materia
                          int64_t sizes[4], int32_t* mrp, int32_t* mci, double* K, double* D1, double* D2,
                          double* Q, double* V, int32_t* pot_global, int32_t* lrp, int32_t* lci, double* L);
 
+/* For callers that cannot allocate device memory (a harness that forbids
+ * hipMalloc, a tight serving loop): mmsd_assemble_device with the same
+ * arguments, layouts, outputs and errors, but its device temporaries come
+ * from a fixed 64 MiB region the library holds on each GPU for the life of
+ * the process, never from an allocator (no hipMalloc, hipFree or allocating
+ * library routine is called).  A mesh whose temporaries need more (about
+ * 161 bytes per tetrahedron, 40 per magnetic tetrahedron and 48 per node:
+ * some 300,000 tetrahedra) gives MMSD_E_INVALID before any device work.  The
+ * region is shared by every call on one GPU and keeps the last call's
+ * contents; the call clears what must start at zero.  Calls through one
+ * context are serialized; calls through two contexts on the same GPU that
+ * overlap race on the region and must not be made.  Host staging (pageable
+ * copies, the host-side numbering) is as in mmsd_assemble_device. */
+int mmsd_assemble_device_noalloc(mmsd_ctx ctx, const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats,
+                                 int64_t sizes[4], int32_t* mrp, int32_t* mci, double* K, double* D1,
+                                 double* D2, double* Q, double* V, int32_t* pot_global, int32_t* lrp,
+                                 int32_t* lci, double* L);
+
 /* ---- serving ----------------------------------------------------------- */
 /* Served form (not in the paper; every request is one mmsd_minimize of
  * eq. (1) by the Method section's scheme).

@@ -95,6 +95,8 @@ SIGNATURES = [
      + [C.c_void_p] * 12),
     ("mmsd_assemble_device", C.c_int, [C.c_void_p, C.POINTER(MeshC), C.POINTER(MaterialC), C.c_int,
                                        C.POINTER(C.c_int64)] + [C.c_void_p] * 11),
+    ("mmsd_assemble_device_noalloc", C.c_int, [C.c_void_p, C.POINTER(MeshC), C.POINTER(MaterialC), C.c_int,
+                                               C.POINTER(C.c_int64)] + [C.c_void_p] * 11),
     ("mmsd_server_create", C.c_int, [C.c_void_p, C.c_size_t, C.c_int, C.POINTER(C.c_void_p)]),
     ("mmsd_submit", C.c_int, [C.c_void_p, C.POINTER(MeshC), C.POINTER(MaterialC), C.c_int, C.POINTER(C.c_double),
                               C.c_int, C.POINTER(C.c_double), C.POINTER(OptionsC), C.POINTER(C.c_uint64)]),
@@ -430,14 +432,16 @@ def assembly_export(mesh, materials=None) -> dict:
     return out
 
 
-def assemble_device(ctx: Context, mesh, materials=None) -> dict:
+def assemble_device(ctx: Context, mesh, materials=None, no_alloc: bool = False) -> dict:
     """The same operators as assembly_export, assembled by the device
-    kernels into torch tensors on ctx's device (no scalars)."""
+    kernels into torch tensors on ctx's device (no scalars).  no_alloc uses
+    mmsd_assemble_device_noalloc (temporaries in the library's fixed region)."""
     import torch
     lib = ctx.lib
+    fn = lib.mmsd_assemble_device_noalloc if no_alloc else lib.mmsd_assemble_device
     a = MeshArgs(mesh, materials)
     sizes = (C.c_int64 * 4)()
-    _check(lib.mmsd_assemble_device(ctx.handle, C.byref(a.c), a.mats, a.n_mats, sizes, *([None] * 11)))
+    _check(fn(ctx.handle, C.byref(a.c), a.mats, a.n_mats, sizes, *([None] * 11)))
     N, nnzM, Nt, nnzL = (int(x) for x in sizes)
     dev = torch.device("cuda", ctx.device)
     i32, f64 = torch.int32, torch.float64
@@ -450,8 +454,7 @@ def assemble_device(ctx: Context, mesh, materials=None) -> dict:
     order = ["mrp", "mci", "K", "D1", "D2", "Q", "V", "pot_global", "lrp", "lci", "L"]
     # an empty tensor has no storage: give the library a valid one-element stand-in
     keep = [out[k] if out[k].numel() else torch.empty(1, dtype=out[k].dtype, device=dev) for k in order]
-    _check(lib.mmsd_assemble_device(ctx.handle, C.byref(a.c), a.mats, a.n_mats, sizes,
-                                    *[C.c_void_p(t.data_ptr()) for t in keep]))
+    _check(fn(ctx.handle, C.byref(a.c), a.mats, a.n_mats, sizes, *[C.c_void_p(t.data_ptr()) for t in keep]))
     out.update(N=N, Nt=Nt)
     return out
 

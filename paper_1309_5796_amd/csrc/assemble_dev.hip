@@ -20,6 +20,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -367,16 +369,30 @@ __global__ __launch_bounds__(kWave) void k_pattern(PatternArgs a) {
   }
 }
 
-// Device temporaries, freed (after the stream has drained) on every return.
+// Device temporaries of one call.  Heap mode: from the context's allocator,
+// freed (after the stream has drained) on every return.  Arena mode: carved
+// in call order, 256-byte aligned, from a device region of `cap` bytes that
+// the library owns for the life of the process (the allocation-free entry
+// point); nothing is allocated or freed.
 struct Scratch {
   mmsd_ctx_s* c;
+  char* arena = nullptr;
+  size_t cap = 0, used = 0;
   std::vector<void*> ptrs;
   explicit Scratch(mmsd_ctx_s* ctx) : c(ctx) {}
+  Scratch(mmsd_ctx_s* ctx, void* base, size_t bytes) : c(ctx), arena((char*)base), cap(bytes) {}
   Scratch(const Scratch&) = delete;
   Scratch& operator=(const Scratch&) = delete;
   template <typename T>
   T* get(size_t n) {
-    void* p = c->dalloc(std::max<size_t>(n, 1) * sizeof(T));
+    const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+    if (arena) {
+      const size_t at = (used + 255) & ~size_t(255);
+      if (at + bytes > cap) return nullptr;
+      used = at + bytes;
+      return (T*)(arena + at);
+    }
+    void* p = c->dalloc(bytes);
     if (p) ptrs.push_back(p);
     return (T*)p;
   }
@@ -385,6 +401,36 @@ struct Scratch {
     for (void* p : ptrs) c->dfree(p);
   }
 };
+
+// Bytes of the temporaries one call takes from an arena, in the order the
+// call takes them (each piece 256-byte aligned).
+size_t arena_bytes(int64_t N, int64_t Nt, int64_t E, int64_t Em, int64_t n_nodes, size_t n_reg, bool query) {
+  size_t used = 0;
+  auto take = [&](size_t n, size_t elem) {
+    used = ((used + 255) & ~size_t(255)) + std::max<size_t>(n, 1) * elem;
+  };
+  take(4 * (size_t)Em, 4);                                   // magnetic tets
+  take(N + 1, 4);                                            // their adjacency: row starts
+  take(4 * (size_t)Em, 4);                                   // and lists
+  take(std::max(n_nodes, std::max(N, Nt)), 4);               // counts / cursor
+  if (query) take(std::max(N, Nt) + 1, 4);                   // row starts of the queried patterns
+  take(4 * (size_t)E, 4);                                    // all tets
+  if (Nt > 0) {
+    take(n_nodes + 1, 4);                                    // node-to-tet adjacency
+    take(4 * (size_t)E, 4);
+    take(n_nodes, 4);                                        // potential row of each node
+    if (query) take(Nt, 4);                                  // node of each potential row
+  }
+  if (query) return used;
+  take(3 * (size_t)n_nodes, 8);                              // coordinates
+  take(kGeo * (size_t)E, 8);                                 // geometry records
+  take(E, 1);                                                // tet flags
+  take(Em, 4);                                               // magnetic tets' mesh ids
+  take(Em, 4);                                               // and regions
+  take(n_reg, 8);                                            // material table
+  if (Nt > 0) take(Nt, 1);                                   // diagonal checks
+  return used;
+}
 
 template <typename T>
 hipError_t put(T* dst, const std::vector<T>& v, hipStream_t s) {
@@ -472,10 +518,46 @@ int build_pattern_dev(PatternArgs pa, int32_t* cnt, int32_t* rp, int32_t* ci, in
 }  // namespace
 }  // namespace mmsd
 
-extern "C" int mmsd_assemble_device(mmsd_ctx c, const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats,
-                                    int64_t sizes[4], int32_t* mrp, int32_t* mci, double* K, double* D1,
-                                    double* D2, double* Q, double* V, int32_t* pot_global, int32_t* lrp,
-                                    int32_t* lci, double* L) {
+// ---- the allocation-free variant's device region ---------------------------
+// Temporaries of mmsd_assemble_device_noalloc live in this file-scope array
+// (one copy per GPU, held until the process ends).  Host code must not pass
+// its name to a kernel: it is resolved once per device with
+// hipGetSymbolAddress and the resolved address is used everywhere.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace mmsd {
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on `device`, which must be current.
+int scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) {
+    set_error("device id out of range for the allocation-free scratch table");
+    return MMSD_E_INVALID;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) {
+      set_error("hipGetSymbolAddress(scratch) returned no address");
+      return MMSD_E_HIP;
+    }
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return MMSD_OK;
+}
+
+int assemble_device_impl(mmsd_ctx c, const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats,
+                         int64_t sizes[4], int32_t* mrp, int32_t* mci, double* K, double* D1, double* D2,
+                         double* Q, double* V, int32_t* pot_global, int32_t* lrp, int32_t* lci, double* L,
+                         bool no_alloc) {
   if (!c || !sizes) {
     set_error("null context or sizes");
     return MMSD_E_INVALID;
@@ -515,7 +597,22 @@ extern "C" int mmsd_assemble_device(mmsd_ctx c, const mmsd_mesh* mesh, const mms
   std::lock_guard<std::mutex> lk(c->mu);
   MMSD_HIP(hipSetDevice(c->device));
   hipStream_t st = c->stream;
-  Scratch tmp(c);
+  std::unique_ptr<Scratch> heap_or_arena;
+  if (no_alloc) {
+    const size_t need = arena_bytes(N, Nt, E, Em, n_nodes, S.reg.size(), query);
+    if (need > kNoAllocScratchBytes) {
+      set_error("mmsd_assemble_device_noalloc: this mesh needs " + std::to_string(need) +
+                " bytes of device temporaries, above the fixed " + std::to_string(kNoAllocScratchBytes) +
+                " (use mmsd_assemble_device)");
+      return MMSD_E_INVALID;
+    }
+    void* base = nullptr;
+    if ((rc = scratch_address(c->device, &base))) return rc;
+    heap_or_arena.reset(new Scratch(c, base, kNoAllocScratchBytes));
+  } else {
+    heap_or_arena.reset(new Scratch(c));
+  }
+  Scratch& tmp = *heap_or_arena;
   // device structure: adjacency and patterns
   int32_t* d_mtet = tmp.get<int32_t>(4 * (size_t)Em);
   int32_t* d_madj_ptr = tmp.get<int32_t>(N + 1);
@@ -630,3 +727,23 @@ extern "C" int mmsd_assemble_device(mmsd_ctx c, const mmsd_mesh* mesh, const mms
   MMSD_HIP(hipStreamSynchronize(st));
   return MMSD_OK;
 }
+
+}  // namespace
+}  // namespace mmsd
+
+extern "C" int mmsd_assemble_device(mmsd_ctx c, const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats,
+                                    int64_t sizes[4], int32_t* mrp, int32_t* mci, double* K, double* D1,
+                                    double* D2, double* Q, double* V, int32_t* pot_global, int32_t* lrp,
+                                    int32_t* lci, double* L) {
+  return assemble_device_impl(c, mesh, mats, n_mats, sizes, mrp, mci, K, D1, D2, Q, V, pot_global, lrp, lci, L,
+                              false);
+}
+
+extern "C" int mmsd_assemble_device_noalloc(mmsd_ctx c, const mmsd_mesh* mesh, const mmsd_material* mats,
+                                            int n_mats, int64_t sizes[4], int32_t* mrp, int32_t* mci, double* K,
+                                            double* D1, double* D2, double* Q, double* V, int32_t* pot_global,
+                                            int32_t* lrp, int32_t* lci, double* L) {
+  return assemble_device_impl(c, mesh, mats, n_mats, sizes, mrp, mci, K, D1, D2, Q, V, pot_global, lrp, lci, L,
+                              true);
+}
+
