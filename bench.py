@@ -377,11 +377,12 @@ def run_sphere(args):
     print(f"[bench] sphere setup {time.perf_counter() - t0:.1f} s: {p.N} magnet / {p.Nt} potential nodes",
           file=sys.stderr, flush=True)
     fields = cfg["fields"]
+    stop = binding.STOP_SUM_SQ if args.stop == "sumsq" else binding.STOP_MAX_TORQUE
     res, bsw = [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k0 in range(0, len(fields), args.chunk * 5):
-        r_chunk, b_chunk = p.hysteresis(fields[k0:k0 + args.chunk * 5], refine_tol_T=1e-4)
+        r_chunk, b_chunk = p.hysteresis(fields[k0:k0 + args.chunk * 5], refine_tol_T=1e-4, stop_rule=stop)
         res.extend(r_chunk)
         bsw.extend(float(b) for b in b_chunk)
         print(f"[bench] sphere field points {len(res)}/{len(fields)}: {time.perf_counter() - t0:.1f} s",
@@ -397,7 +398,9 @@ def run_sphere(args):
     hc = bsw[0] if bsw else ((flips[0] - 0.5) * 0.01 if flips else None)
     line = base_line(p.N * evals / wall, len(fields), 0, wall, "f64",
                      {"workload": "20 nm sphere (85k-tet Kuhn ball), FP64, 0 -> -6 T in 0.01 T at 45 deg",
-                      "magnet_nodes": p.N, "potential_nodes": p.Nt})
+                      "magnet_nodes": p.N, "potential_nodes": p.Nt,
+                      "stopping_test": "sum of squared torques < 1e-12 (the paper's)" if args.stop == "sumsq"
+                      else "max torque < 1e-6"})
     line["roofline"] = None
     line["detail"] = {"evals": evals, "iterations": sum(r.iterations for r in res),
                       "pcg_iters": sum(r.pcg_iters for r in res), "wall_s": wall,
@@ -408,6 +411,49 @@ def run_sphere(args):
     p.close()
     ctx.close()
     print(json.dumps(line), flush=True)
+
+
+def run_ablation(args):
+    """Step-length rules (eq. (10) and the adaptive switch the paper adopts):
+    energy-gradient evaluations per rule on config 1 (one minimization) and
+    on the whole FP64 loop of the 80 nm cube (321 points)."""
+    import numpy as np
+    import torch
+    from paper_1309_5796_amd import binding, meshgen
+    rules = [("adaptive", binding.STEP_ADAPTIVE), ("alternate", binding.STEP_ALTERNATE),
+             ("bb1", binding.STEP_BB1), ("bb2", binding.STEP_BB2)]
+    ctx = binding.Context(0)
+    c1 = meshgen.config1()
+    c2 = meshgen.config2()
+    out = {}
+    p1 = binding.Problem(ctx, c1["mesh"])
+    p2 = binding.Problem(ctx, c2["mesh"])
+    s2 = p2.get_state()
+    npts = min(args.ablation_points, len(c2["fields"]))
+    for name, rule in rules:
+        p1.set_m(c1["m0"])
+        p1.set_field(c1["b_ext"])
+        r1 = p1.minimize(step_rule=rule)
+        p2.set_state(s2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res, bsw = p2.hysteresis(c2["fields"][:npts], step_rule=rule)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        proj = [float(np.dot(r.m_avg, meshgen.U_H_1DEG)) for r in res]
+        bu = c2["fields"][:npts] @ meshgen.U_H_1DEG
+        sw = [0.5 * (bu[k - 1] + bu[k]) for k in range(1, npts) if np.sign(proj[k]) != np.sign(proj[k - 1])]
+        out[name] = {"config1_evals": r1.evals, "config1_iterations": r1.iterations, "config1_status": r1.status,
+                     "sweep_evals": sum(r.evals for r in res), "sweep_iterations": sum(r.iterations for r in res),
+                     "sweep_pcg_iters": sum(r.pcg_iters for r in res), "sweep_wall_s": wall,
+                     "sweep_statuses": sorted(set(r.status for r in res)), "switching_fields_T": sw}
+        print(f"[bench] rule {name}: config1 {r1.evals} evals; sweep {out[name]['sweep_evals']} evals "
+              f"{wall:.1f} s", file=sys.stderr, flush=True)
+    p1.close()
+    p2.close()
+    ctx.close()
+    print(json.dumps({"workload": f"step-rule ablation: config 1 minimization and the first {npts} points of "
+                                  f"the 80 nm cube's FP64 loop", "detail": out}), flush=True)
 
 
 def run_assemble(args):
@@ -560,7 +606,10 @@ def main():
     ap.add_argument("--blocks", type=int, default=0, help="blocks per problem (multiple of 8; 0 = library default)")
     ap.add_argument("--chunk", type=int, default=20, help="field points per library call (sphere)")
     ap.add_argument("--workload", default="sweep80",
-                    choices=["sweep80", "poly", "grains", "serve", "sphere", "copy", "assemble"])
+                    choices=["sweep80", "poly", "grains", "serve", "sphere", "copy", "assemble", "ablation"])
+    ap.add_argument("--stop", default="max", choices=["max", "sumsq"],
+                    help="stopping test of --workload sphere: max torque < 1e-6 or the paper's sum of squares")
+    ap.add_argument("--ablation-points", type=int, default=321)
     ap.add_argument("--assemble-request", type=int, default=38,
                     help="request of the served stream whose mesh --workload assemble times")
     ap.add_argument("--max-evals", type=int, default=100000)
@@ -582,7 +631,7 @@ def main():
         sys.exit(2)
     if args.workload != "sweep80":
         {"poly": run_poly, "grains": run_grains, "serve": run_serve, "sphere": run_sphere,
-         "copy": run_copy, "assemble": run_assemble}[args.workload](args)
+         "copy": run_copy, "assemble": run_assemble, "ablation": run_ablation}[args.workload](args)
         return
 
     value, K, wall, config, roof, detail = run_sweep(args)

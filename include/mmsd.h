@@ -72,6 +72,11 @@ extern "C" {
 #define MMSD_PRECOND_JACOBI 1 /* Jacobi, single-reduction CG: one launch per iteration */
 #define MMSD_PRECOND_AMG 2    /* smoothed-aggregation multigrid V(1,1) cycle, PCG */
 
+/* stopping tests (tol = mmsd_options.tol_torque) */
+#define MMSD_STOP_MAX_TORQUE 0 /* max_i |m_i x h_i| < tol */
+#define MMSD_STOP_SUM_SQ 1     /* sum_i |m_i x h_i|^2 < tol^2: the paper's test on the squared
+                                  projected gradient (Results, comparison with the LLG solver) */
+
 /* step-length rules (eq. (10)); ADAPTIVE is the rule the paper uses */
 #define MMSD_STEP_ADAPTIVE 0  /* adaptive tau1/tau2 switching with a min-window */
 #define MMSD_STEP_ALTERNATE 1 /* plain alternation of tau1 and tau2 */
@@ -177,7 +182,7 @@ typedef struct {
   int step_rule;        /* MMSD_STEP_*; default adaptive */
   double refine_tol_T;  /* hysteresis: > 0 bisects each switching field to this width (T) */
   int precond;          /* MMSD_PRECOND_*; default AUTO */
-  int pad0;
+  int stop_rule;        /* MMSD_STOP_*; default MMSD_STOP_MAX_TORQUE */
 } mmsd_options;
 
 /* Defaults: every field zero selects its default. */

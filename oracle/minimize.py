@@ -60,6 +60,8 @@ class Options:
     tau_floor: float = 1e-14
     theta0: float = 0.1
     step_rule: str = "adaptive"  # "adaptive" (the paper's choice), "alternate", "bb1", "bb2"
+    stop: str = "max"          # "max": max_i |m_i x h_i| < tol; "sumsq": sum_i |m_i x h_i|^2 < tol^2,
+                               # the paper's test on the squared projected gradient (Results)
     record: bool = False       # keep per-step diagnostics
 
 
@@ -118,6 +120,12 @@ def minimize(sys, m0: np.ndarray, b_ext, opts: Optional[Options] = None) -> Resu
     H = cross(m, h)
     Tn = np.linalg.norm(H, axis=1)
     T = float(Tn.max())
+
+    def converged(H_):
+        if o.stop == "sumsq":
+            return float(np.sum(H_ * H_)) < o.tol * o.tol
+        return float(np.linalg.norm(H_, axis=1).max()) < o.tol
+
     hist = [e]
     drift = 0.0
     # with record=True: every trial (tau, its energy, the reference it was
@@ -133,7 +141,7 @@ def minimize(sys, m0: np.ndarray, b_ext, opts: Optional[Options] = None) -> Resu
                       energies=list(hist) if o.record else [], norm_drift=drift,
                       trials=trials, steps=steps)
 
-    if T < o.tol:
+    if converged(H):
         return result(OK, 0)
     tau = o.theta0 / T
     kappa = o.kappa0
@@ -175,7 +183,7 @@ def minimize(sys, m0: np.ndarray, b_ext, opts: Optional[Options] = None) -> Resu
         hist.append(e)
         iters += 1
         T = float(np.linalg.norm(H, axis=1).max())
-        if T < o.tol:
+        if converged(H):
             return result(OK, iters)
         if evals >= o.max_evals:
             return result(MAXEVALS, iters)

@@ -25,6 +25,7 @@ E_INVALID, E_MESH, E_NOMEM, E_HIP, E_NONFINITE, E_BUSY, E_CANCELLED = -1, -2, -3
 FP64, MIXED = 0, 1
 EXCH, ANIS, ZEEM, DEMAG, ALL = 1, 2, 4, 8, 15
 STEP_ADAPTIVE, STEP_ALTERNATE, STEP_BB1, STEP_BB2 = 0, 1, 2, 3
+STOP_MAX_TORQUE, STOP_SUM_SQ = 0, 1
 PRECOND_AUTO, PRECOND_JACOBI, PRECOND_AMG = 0, 1, 2
 VC_FUSE_REST, VC_FOLD_SOLVE, VC_SLICE_ALL = 1, 2, 4
 
@@ -48,7 +49,7 @@ class OptionsC(C.Structure):
     _fields_ = [("tol_torque", C.c_double), ("max_evals", C.c_int64), ("terms", C.c_int),
                 ("nonmono_M", C.c_int), ("pcg_rtol", C.c_double), ("pcg_maxit", C.c_int),
                 ("step_rule", C.c_int), ("refine_tol_T", C.c_double), ("precond", C.c_int),
-                ("pad0", C.c_int)]
+                ("stop_rule", C.c_int)]
 
 
 class ResultC(C.Structure):
@@ -175,9 +176,10 @@ class Result:
 
 def make_options(tol: float = 0.0, max_evals: int = 0, terms: int = 0, nonmono_M: int = 0,
                  pcg_rtol: float = 0.0, pcg_maxit: int = 0, step_rule: int = 0,
-                 refine_tol_T: float = 0.0, precond: int = 0) -> OptionsC:
+                 refine_tol_T: float = 0.0, precond: int = 0, stop_rule: int = 0) -> OptionsC:
     """Options struct; zero fields select the library defaults."""
-    return OptionsC(tol, max_evals, terms, nonmono_M, pcg_rtol, pcg_maxit, step_rule, refine_tol_T, precond, 0)
+    return OptionsC(tol, max_evals, terms, nonmono_M, pcg_rtol, pcg_maxit, step_rule, refine_tol_T, precond,
+                    stop_rule)
 
 
 class _TorchAllocator:

@@ -816,6 +816,8 @@ int resolve(mmsd_problem p, const mmsd_options* o, Resolved* r) {
     if (o->refine_tol_T > 0) d.refine_tol_T = o->refine_tol_T;
     if (o->precond > 0) d.precond = o->precond;
     if (o->precond < 0 || o->precond > MMSD_PRECOND_AMG) return invalid("unknown preconditioner");
+    if (o->stop_rule < 0 || o->stop_rule > MMSD_STOP_SUM_SQ) return invalid("unknown stopping test");
+    d.stop_rule = o->stop_rule;
     if (o->terms < 0 || o->terms > MMSD_ALL || o->nonmono_M > kMaxHist || o->step_rule < 0 ||
         o->step_rule > MMSD_STEP_BB2)
       return invalid("options out of range");
@@ -831,6 +833,7 @@ int resolve(mmsd_problem p, const mmsd_options* o, Resolved* r) {
   r->rule = d.step_rule;
   r->maxit = d.pcg_maxit;
   r->refine = d.refine_tol_T;
+  r->stop = d.stop_rule;
   if (d.precond == MMSD_PRECOND_AMG && !p->has_amg)
     return invalid("multigrid preconditioner requested but not available for this mesh");
   r->precond = (d.precond == MMSD_PRECOND_JACOBI || !p->has_amg) ? PC_JACOBI : PC_AMG;
@@ -858,7 +861,7 @@ int arm(mmsd_problem p, const Resolved& r, int stage, int store_h) {
                          mixed ? std::ldexp(1.0, -20) : 0.0};
   MMSD_HIP(launch_ctrl_init(p->dctrl, kArmSlot, stage, r.terms, r.M, r.rule, r.maxit, store_h,
                             (r.terms & MMSD_DEMAG) ? 1 : 0, p->acc, r.precond, mixed ? 1 : 0,
-                            mixed ? kMixedHalvings : 0, (long long)r.max_evals, dp, p->ctx->stream));
+                            mixed ? kMixedHalvings : 0, r.stop, (long long)r.max_evals, dp, p->ctx->stream));
   return MMSD_OK;
 }
 
@@ -1168,7 +1171,7 @@ void mmsd_options_default(mmsd_options* o) {
   o->step_rule = MMSD_STEP_ADAPTIVE;
   o->refine_tol_T = 0;
   o->precond = MMSD_PRECOND_AUTO;
-  o->pad0 = 0;
+  o->stop_rule = MMSD_STOP_MAX_TORQUE;
 }
 
 int mmsd_ctx_create(int device, void* hip_stream, mmsd_alloc_fn alloc, mmsd_free_fn free_fn, void* user,

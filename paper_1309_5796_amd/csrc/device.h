@@ -71,7 +71,7 @@ struct Ctrl {
   int first, backtrack, status, pcg_it;
   int hist_n, hist_pos, win_n, win_pos;
   int terms, nonmono_M, step_rule, alt;
-  int pcg_maxit, store_h, demag, pad0;
+  int pcg_maxit, store_h, demag, stop_sum2;   // stop_sum2: test sum |H|^2 < tol^2, else max |H| < tol
   long long evals, iters, pcg_total, max_evals;
   long long launches_done;       // phases executed
   long long nphase[4];           // executed PREP, CG0 / MG, CG / PCG_A + PCG_B, FIELD phases

@@ -114,16 +114,24 @@ __device__ __forceinline__ void st(DevPtr<Rec<real>> p, int i, const Rec<real>& 
   reinterpret_cast<DevPtr<vec4<real>>>(p)[i] = vec4<real>{x.r, x.s, x.w, x.d};
 }
 
-// Rows [r0, r1) of block `blk` (of G, a multiple of 8) for R rows.  The rows
-// are cut into chunks of ceil(R / G) rounded up to `align` (64 for the
-// sliced layout, whose wavefronts each own one slice), and to whole block
-// passes of `rpp` rows when a chunk takes more than one, so a small level
+// Rows of block `blk` (of G, a multiple of 8) for R rows, as passes of
+// `rpp` rows starting at r0, r0 + rs, ... below r1 (row i of a pass is valid
+// when i < r1).  The rows are cut into chunks of ceil(R / G) rounded up to
+// `align` (64 for the sliced layout, whose wavefronts each own one slice),
+// and to whole passes when a chunk takes more than one, so a small level
 // spreads over up to G blocks.  The chunks are dealt to the 8 XCDs (block b
 // runs on XCD b % 8) as 8 contiguous runs of almost equal length: each XCD
 // sweeps neighbouring rows, which keeps their gathers in its own L2, and all
-// 8 XCDs share the work also when there are fewer chunks than blocks.
-__device__ __forceinline__ void chunk_rows(int R, int G, int blk, int rpp, int align, int& r0, int& r1) {
+// 8 XCDs share the work also when there are fewer chunks than blocks.  When
+// a chunk takes several passes, the blocks of an XCD take the passes of the
+// XCD's run in turn (block k the passes k, k + n, k + 2n, ... of its n
+// blocks) instead of one contiguous chunk each: the XCD then sweeps its run
+// as one front of n passes, so a row's neighbours a grid plane away (tens
+// of thousands of rows on the largest meshes) were just loaded by the front
+// and are still in the L2 when they are gathered.
+__device__ __forceinline__ void chunk_rows(int R, int G, int blk, int rpp, int align, int& r0, int& r1, int& rs) {
   r0 = r1 = R;
+  rs = rpp;
   if (R <= 0) return;
   long long c = ((long long)R + G - 1) / G;
   c = (c + align - 1) / align * align;
@@ -132,9 +140,16 @@ __device__ __forceinline__ void chunk_rows(int R, int G, int blk, int rpp, int a
   const int x = blk & 7, k = blk >> 3;
   const int s = x * nch / 8, e = (x + 1) * nch / 8;
   if (k >= e - s) return;
-  const long long a = (long long)(s + k) * c;
-  r0 = (int)a;
-  r1 = (int)(a + c < R ? a + c : R);
+  if (c <= rpp) {   // one pass: the block's own chunk
+    const long long a = (long long)(s + k) * c;
+    r0 = (int)a;
+    r1 = (int)(a + c < R ? a + c : R);
+    return;
+  }
+  const long long a = (long long)s * c, b = (long long)e * c;
+  r0 = (int)(a + (long long)k * rpp);
+  r1 = (int)(b < R ? b : R);
+  rs = (e - s) * rpp;
 }
 
 // Rows of the potential matrix are swept one per thread from its 64-row
@@ -227,8 +242,8 @@ __device__ void phase_prep(const ProbDev<real>& P, const Ctrl* C, int blk, doubl
   const bool demag = C->demag != 0;
   const bool amg = C->precond == PC_AMG;
   const int R = demag ? P.Nt : P.N;
-  int r0, r1;
-  chunk_rows(R, P.G, blk, kBlock, 64, r0, r1);
+  int r0, r1, rs;
+  chunk_rows(R, P.G, blk, kBlock, 64, r0, r1, rs);
   const int a = C->acc, tr = 1 - a;
   const real ht = real(0.5 * C->tau);
   DevPtr<const real> __restrict__ max_ = P.m[a][0];
@@ -240,7 +255,8 @@ __device__ void phase_prep(const ProbDev<real>& P, const Ctrl* C, int blk, doubl
   DevPtr<real> __restrict__ r2 = P.r2[C->rcur];
   DevPtr<Rec<real>> __restrict__ rec = P.rec[C->pcur];
   const int m1 = r1 < P.N ? r1 : P.N;
-  for (int base = r0; base < m1; base += RPP) {
+  for (int pass = r0; pass < m1; pass += rs)
+  for (int base = pass; base < pass + kBlock && base < m1; base += RPP) {
     const int i = base + slot;
     const bool valid = i < m1;
     real bi = 0;
@@ -273,7 +289,7 @@ __device__ void phase_prep(const ProbDev<real>& P, const Ctrl* C, int blk, doubl
   if (!demag) return;
   __syncthreads();
   DevPtr<const real> __restrict__ u = P.u;
-  for (int base = r0; base < r1; base += kBlock) {
+  for (int base = r0; base < r1; base += rs) {
     const int i = base + threadIdx.x;
     if (i >= r1) continue;
     const real bi = i < P.N ? (amg ? r2[i] : rec[i].r) : real(0);
@@ -300,10 +316,10 @@ __device__ void phase_prep(const ProbDev<real>& P, const Ctrl* C, int blk, doubl
 template <typename real, int LPR>
 __device__ void phase_cg0(const ProbDev<real>& P, const Ctrl* C, int blk, double* acc) {
   constexpr int RPP = kBlock;
-  int r0, r1;
-  chunk_rows(P.Nt, P.G, blk, RPP, 64, r0, r1);
+  int r0, r1, rs;
+  chunk_rows(P.Nt, P.G, blk, RPP, 64, r0, r1, rs);
   DevPtr<Rec<real>> __restrict__ rec = P.rec[C->pcur];
-  for (int base = r0; base < r1; base += RPP) {
+  for (int base = r0; base < r1; base += rs) {
     const int i = base + threadIdx.x;
     if (i >= r1) continue;
     const Rec<real> own = ld<real>(rec, i);
@@ -326,13 +342,13 @@ __device__ void phase_cg0(const ProbDev<real>& P, const Ctrl* C, int blk, double
 template <typename real, int LPR>
 __device__ void phase_cg(const ProbDev<real>& P, const Ctrl* C, int blk, double* acc) {
   constexpr int RPP = kBlock;
-  int r0, r1;
-  chunk_rows(P.Nt, P.G, blk, RPP, 64, r0, r1);
+  int r0, r1, rs;
+  chunk_rows(P.Nt, P.G, blk, RPP, 64, r0, r1, rs);
   const int c = C->pcur;
   const real alpha = real(C->alpha), beta = real(C->beta);
   DevPtr<const Rec<real>> __restrict__ ro = P.rec[c];
   DevPtr<Rec<real>> __restrict__ rn = P.rec[1 - c];
-  for (int base = r0; base < r1; base += RPP) {
+  for (int base = r0; base < r1; base += rs) {
     const int i = base + threadIdx.x;
     if (i >= r1) continue;
     const Rec<real> own = ld<real>(ro, i);
@@ -477,15 +493,15 @@ __device__ void mg_rows(const ProbDev<real>& P, const Ctrl* C, DevRef<const MgLe
   DevPtr<const real> __restrict__ wd = L.wd;
   DevPtr<const real> __restrict__ wb = L.wb;
   const bool last = l + 1 == P.n_lev;
-  int r0, r1;
+  int r0, r1, rs;
   if (op == MG_REST || op == MG_RESTM) {
     DevPtr<real> __restrict__ bn = last ? P.bc : P.lev[l + 1].b;
     DevPtr<real> __restrict__ wbn = last ? nullptr : P.lev[l + 1].wb;
     DevPtr<const real> __restrict__ wdn = last ? nullptr : P.lev[l + 1].wd;
     DevPtr<const real> __restrict__ res = L.res;
     const bool m = op == MG_RESTM;   // b_{l+1} = M b, else R res
-    chunk_rows(L.n_next, G, blk, RPP, W == 1 ? 64 : 1, r0, r1);
-    for (int base = r0; base < r1; base += RPP) {
+    chunk_rows(L.n_next, G, blk, RPP, W == 1 ? 64 : 1, r0, r1, rs);
+    for (int base = r0; base < r1; base += rs) {
       const int i = base + slot;
       const bool valid = i < r1;
       const real wi = (valid && lane == 0 && !last) ? wdn[i] : real(0);
@@ -501,9 +517,9 @@ __device__ void mg_rows(const ProbDev<real>& P, const Ctrl* C, DevRef<const MgLe
     }
     return;
   }
-  chunk_rows(L.n, G, blk, RPP, W == 1 ? 64 : 1, r0, r1);
+  chunk_rows(L.n, G, blk, RPP, W == 1 ? 64 : 1, r0, r1, rs);
   if (op == MG_DOWN) {
-    for (int base = r0; base < r1; base += RPP) {
+    for (int base = r0; base < r1; base += rs) {
       const int i = base + slot;
       const bool valid = i < r1;
       const real bi = (valid && lane == 0) ? b[i] : real(0);
@@ -515,7 +531,7 @@ __device__ void mg_rows(const ProbDev<real>& P, const Ctrl* C, DevRef<const MgLe
   } else {   // MG_POST
     DevPtr<const real> __restrict__ xn = last ? P.xc : P.lev[l + 1].xb;
     DevPtr<const real> __restrict__ res = L.res;
-    for (int base = r0; base < r1; base += RPP) {
+    for (int base = r0; base < r1; base += rs) {
       const int i = base + slot;
       const bool valid = i < r1;
       real bi = 0, wi = 0, ri = 0, pold = 0;
@@ -647,14 +663,14 @@ __device__ void phase_mg(const ProbDev<real>& P, const Ctrl* C, int blk, double*
 template <typename real, int LPR>
 __device__ void phase_pcg_a(const ProbDev<real>& P, const Ctrl* C, int blk, double* acc) {
   constexpr int RPP = kBlock;
-  int r0, r1;
-  chunk_rows(P.Nt, P.G, blk, RPP, 64, r0, r1);
+  int r0, r1, rs;
+  chunk_rows(P.Nt, P.G, blk, RPP, 64, r0, r1, rs);
   const real beta = real(C->beta);
   const bool first = C->beta == 0.0;
   DevPtr<const Pair<real>> __restrict__ zp = P.zp;
   DevPtr<const real> __restrict__ r = P.r2[C->rcur];
   DevPtr<const real> __restrict__ wd = P.lev[0].wd;
-  for (int base = r0; base < r1; base += RPP) {
+  for (int base = r0; base < r1; base += rs) {
     const int i = base + threadIdx.x;
     if (i >= r1) continue;
     const Pair<real> own = ld<real>(zp, i);
@@ -679,8 +695,8 @@ __device__ void phase_pcg_a(const ProbDev<real>& P, const Ctrl* C, int blk, doub
 template <typename real, int LPR>
 __device__ void phase_pcg_b(const ProbDev<real>& P, const Ctrl* C, int blk, double* acc) {
   constexpr int RPP = kBlock;
-  int r0, r1;
-  chunk_rows(P.Nt, P.G, blk, RPP, 64, r0, r1);
+  int r0, r1, rs;
+  chunk_rows(P.Nt, P.G, blk, RPP, 64, r0, r1, rs);
   const real alpha = real(C->alpha), beta = real(C->beta);
   const bool first = C->beta == 0.0;
   DevPtr<Pair<real>> __restrict__ zp = P.zp;
@@ -688,7 +704,7 @@ __device__ void phase_pcg_b(const ProbDev<real>& P, const Ctrl* C, int blk, doub
   DevPtr<real> __restrict__ rn = P.r2[1 - C->rcur];
   DevPtr<const real> __restrict__ q = P.q;
   DevPtr<const Pair<real>> __restrict__ rq = P.rq;
-  for (int base = r0; base < r1; base += RPP) {
+  for (int base = r0; base < r1; base += rs) {
     const int i = base + threadIdx.x;
     if (i >= r1) continue;
     const real roi = ro[i], qi = q[i], uo = P.u[i];
@@ -721,8 +737,8 @@ __device__ void phase_field(const ProbDev<real>& P, const Ctrl* C, int blk, doub
   // node, sum_j K_ij (m_j - m_i) and sum_j D2_ij (u_j - u_i): the large
   // diagonal no longer cancels against its neighbours in single precision.
   constexpr bool kDiff = std::is_same<real, float>::value;
-  int r0, r1;
-  chunk_rows(P.N, P.G, blk, RPP, RPP, r0, r1);
+  int r0, r1, rs;
+  chunk_rows(P.N, P.G, blk, RPP, RPP, r0, r1, rs);
   const int a = C->acc, tr = 1 - a;
   const int terms = C->terms;
   const bool exch = terms & MMSD_EXCH, anis = terms & MMSD_ANIS, zeem = terms & MMSD_ZEEM;
@@ -739,7 +755,7 @@ __device__ void phase_field(const ProbDev<real>& P, const Ctrl* C, int blk, doub
   double* fa = s_facc[slot];
   if (lane == 0)
     for (int k = 0; k < kNPart; ++k) fa[k] = 0.0;
-  for (int base = r0; base < r1; base += RPP) {
+  for (int base = r0; base < r1; base += rs) {
     const int i = base + slot;
     const bool valid = i < r1;
     real kx = 0, ky = 0, kz = 0, dx = 0, dy = 0, dz = 0;
@@ -922,6 +938,13 @@ __device__ void accept_trial(Ctrl* C, const double* v, double e_t, const double*
 
 constexpr int kStall = 50;   // accepted steps without progress that end a mixed run
 
+// Stopping test on the accepted state: the largest torque (default), or the
+// sum of the squared torques against tol^2 (the paper's test on the squared
+// projected gradient, Results section).
+__device__ __forceinline__ bool converged(const Ctrl* C) {
+  return C->stop_sum2 ? C->h2_acc < C->tol * C->tol : C->T_acc < C->tol;
+}
+
 __device__ void finish_done(Ctrl* C, int status) {
   C->status = status;
   C->phase = PH_DONE;
@@ -959,7 +982,7 @@ __device__ void step_logic(Ctrl* C, const double* v) {
   }
   if (C->stage == ST_INIT) {
     accept_trial(C, v, e_t, eterm);
-    if (C->T_acc < C->tol) {
+    if (converged(C)) {
       finish_done(C, MMSD_OK);
       return;
     }
@@ -1001,7 +1024,7 @@ __device__ void step_logic(Ctrl* C, const double* v) {
   const double ss = v[FP_SS], sy = v[FP_SY], yy = v[FP_YY];
   accept_trial(C, v, e_t, eterm);
   C->iters++;
-  if (C->T_acc < C->tol) {
+  if (converged(C)) {
     finish_done(C, MMSD_OK);
     return;
   }
@@ -1343,7 +1366,7 @@ __global__ void __launch_bounds__(kBlock, 4) k_step(const ProbDev<real>* __restr
 // slot `slot` (the one the next step launch reads), with a sequence number
 // above both slots' so the host always picks the newest.
 struct CtrlInit {
-  int stage, terms, nonmono_M, step_rule, pcg_maxit, store_h, demag, acc, precond, chain, max_halvings, pad;
+  int stage, terms, nonmono_M, step_rule, pcg_maxit, store_h, demag, acc, precond, chain, max_halvings, stop_sum2;
   long long max_evals;
   double tol, pcg_rtol2, c1, rho, kappa0, theta0, tau_min, tau_max, tau_floor, e_res;
   double bz[3], c_an, vol;
@@ -1373,6 +1396,7 @@ __global__ void k_ctrl_init(Ctrl* ctrl, int slot, CtrlInit a) {
   C->pcg_maxit = a.pcg_maxit;
   C->store_h = a.store_h;
   C->demag = a.demag;
+  C->stop_sum2 = a.stop_sum2;
   C->evals = 0;
   C->iters = 0;
   C->pcg_total = 0;
@@ -1448,12 +1472,13 @@ template hipError_t launch_step<float>(int, const Prob<float>*, int, const int*,
 
 hipError_t launch_ctrl_init(Ctrl* ctrl, int slot, int stage, int terms, int nonmono_M, int step_rule,
                             int pcg_maxit, int store_h, int demag, int acc, int precond, int chain,
-                            int max_halvings, long long max_evals, const double* dparams, hipStream_t s) {
+                            int max_halvings, int stop_sum2, long long max_evals, const double* dparams,
+                            hipStream_t s) {
   CtrlInit a;
   a.precond = precond;
   a.chain = chain;
   a.max_halvings = max_halvings;
-  a.pad = 0;
+  a.stop_sum2 = stop_sum2;
   a.stage = stage;
   a.terms = terms;
   a.nonmono_M = nonmono_M;

@@ -31,7 +31,8 @@ hipError_t launch_step(int lpr, const Prob<real>* probs, int nprob, const int* b
                        hipStream_t s);
 hipError_t launch_ctrl_init(Ctrl* ctrl, int slot, int stage, int terms, int nonmono_M, int step_rule,
                             int pcg_maxit, int store_h, int demag, int acc, int precond, int chain,
-                            int max_halvings, long long max_evals, const double* dparams, hipStream_t s);
+                            int max_halvings, int stop_sum2, long long max_evals, const double* dparams,
+                            hipStream_t s);
 
 hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream_t s);
 
@@ -45,7 +46,7 @@ inline const Ctrl& latest(const Ctrl* two) { return two[1].seq > two[0].seq ? tw
 struct Resolved {
   double tol, rtol;
   int64_t max_evals;
-  int terms, M, rule, maxit, precond;
+  int terms, M, rule, maxit, precond, stop;
   double refine;
 };
 

@@ -393,3 +393,20 @@ def test_vcycle_forms_match_oracle(cfg1, cfg1_system, flags, blocks):
         p.close()
     finally:
         c.close()
+
+
+def test_sum_of_squares_stopping_matches_oracle(ctx, cfg1, cfg1_system):
+    """The paper's stopping test (sum of the squared torques below tol^2):
+    the library stops where the oracle does, at its minimum."""
+    from paper_1309_5796_amd import binding
+    say("minimize config1, sum-of-squares stopping test")
+    s = cfg1_system
+    ro = oracle.minimize(s, cfg1["m0"], cfg1["b_ext"], Options(stop="sumsq"))
+    p = binding.Problem(ctx, cfg1["mesh"])
+    p.set_m(cfg1["m0"])
+    p.set_field(cfg1["b_ext"])
+    r = p.minimize(stop_rule=binding.STOP_SUM_SQ)
+    assert r.status == 0 and r.sum_torque2 < 1e-12 and ro.status == 0
+    assert rel_energy_err(r.energy_J, s.evaluate(ro.m, cfg1["b_ext"])) < 1e-10
+    assert abs(r.evals - ro.evals) <= 3, (r.evals, ro.evals)
+    p.close()

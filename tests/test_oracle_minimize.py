@@ -352,3 +352,14 @@ def test_acceptance_replays_against_the_last_M_accepted_energies(cfg1, cfg1_syst
         assert raises == 0                    # memory 1 is a monotone line search
     else:
         assert raises >= 1                    # the nonmonotone rule accepts energy increases
+
+
+def test_sum_of_squares_stopping_test(cfg1, cfg1_system):
+    """The paper's stopping test (Results: the squared projected gradient
+    summed over the nodes below 1e-12) ends a run only when every node's
+    torque is below 1e-6 too, and later than the max-torque test."""
+    r_max = minimize(cfg1_system, cfg1["m0"], cfg1["b_ext"], Options())
+    r_sum = minimize(cfg1_system, cfg1["m0"], cfg1["b_ext"], Options(stop="sumsq"))
+    H = np.cross(r_sum.m, r_sum.h)
+    assert r_sum.status == 0 and float(np.sum(H * H)) < 1e-12
+    assert r_sum.max_torque < 1e-6 and r_sum.evals >= r_max.evals
