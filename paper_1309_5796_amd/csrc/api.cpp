@@ -38,7 +38,7 @@ size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 // Layout of one problem's device arena.
 struct Layout {
   size_t mrp, mci, K, D1[3], D2[3], Q[6], V, m[2][3], H[2][3], h[3], mh[2];
-  size_t lso, lsc, lsv, lsum, u, p, rec[2];
+  size_t lso, lsc, lsv, lsum, u[3], p, rec[2];
   size_t part, ctrl, prob, blk, btab;
   size_t snap[2][2];
   size_t total;
@@ -76,7 +76,7 @@ Layout make_layout(int64_t N, int64_t nnzM, int64_t Nt, int64_t nnzLs, size_t s)
   L.lsc = take(4 * nnzLs);
   L.lsv = take(s * nnzLs);
   L.lsum = take(s * Nt);
-  L.u = take(s * Nt);
+  for (int k = 0; k < 3; ++k) L.u[k] = take(s * Nt);
   L.p = take(s * Nt);
   for (int k = 0; k < 2; ++k) L.rec[k] = take(4 * s * Nt);
   L.part = take(8 * 2 * (size_t)kMaxBlocks * kNPart);   // G may change between runs
@@ -399,7 +399,8 @@ void bytes_model(mmsd_problem p) {
   const double spmvL = 4 * (Nt + 1) + 4 * zL + s * zL;
   double* b = p->btab;
   for (int k = 0; k < kByteSlots; ++k) b[k] = 0;
-  b[PH_PREP] = 4 * (N + 1) + 4 * zM + 3 * s * zM + 9 * s * N + spmvL + 2 * s * Nt;   // trial m, b = D1 m, r = b - L u
+  b[PH_PREP] = 4 * (N + 1) + 4 * zM + 3 * s * zM + 9 * s * N + spmvL + 3 * s * Nt;   // trial m, b = D1 m, r = b - L u
+                                                                                       // (and the working u written)
   if (p->precision == MMSD_MIXED) b[PH_PREP] += s * Nt;   // row sums of L
   b[PH_CG0] = spmvL + 5 * s * Nt;                                                       // w = L D^-1 r
   b[PH_CG] = spmvL + 12 * s * Nt;                                                       // one CG iteration
@@ -760,7 +761,7 @@ int build_device(mmsd_problem p) {
   P.lsc = (const int*)(base + L.lsc);
   P.lsv = (const real*)(base + L.lsv);
   P.lsum = (const real*)(base + L.lsum);
-  P.u = (real*)(base + L.u);
+  for (int k = 0; k < 3; ++k) P.u3[k] = (real*)(base + L.u[k]);
   P.p = (real*)(base + L.p);
   for (int k = 0; k < 2; ++k) P.rec[k] = (Rec<real>*)(base + L.rec[k]);
   P.ndone = nullptr;
@@ -861,7 +862,8 @@ int arm(mmsd_problem p, const Resolved& r, int stage, int store_h) {
                          mixed ? std::ldexp(1.0, -20) : 0.0};
   MMSD_HIP(launch_ctrl_init(p->dctrl, kArmSlot, stage, r.terms, r.M, r.rule, r.maxit, store_h,
                             (r.terms & MMSD_DEMAG) ? 1 : 0, p->acc, r.precond, mixed ? 1 : 0,
-                            mixed ? kMixedHalvings : 0, r.stop, (long long)r.max_evals, dp, p->ctx->stream));
+                            mixed ? kMixedHalvings : 0, r.stop, p->ucur, (long long)r.max_evals, dp,
+                            p->ctx->stream));
   return MMSD_OK;
 }
 
@@ -1055,6 +1057,7 @@ int run_single(mmsd_problem p, const Resolved& r, int stage, int store_h, mmsd_r
     c->timing.bytes += run_bytes(p, C);
   }
   p->acc = C.acc;
+  p->ucur = C.ucur;
   p->h_valid = store_h != 0 && C.status == MMSD_OK;
   p->last_launches = launched;
   double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1112,8 +1115,8 @@ int snapshot(mmsd_problem p, int k, bool save) {
     else MMSD_HIP(hipMemcpyAsync(live, sm + c * N, sizeof(real) * N, hipMemcpyDeviceToDevice, st));
   }
   if (Nt) {
-    if (save) MMSD_HIP(hipMemcpyAsync(p->snap[k][1], P.u, sizeof(real) * Nt, hipMemcpyDeviceToDevice, st));
-    else MMSD_HIP(hipMemcpyAsync(P.u, p->snap[k][1], sizeof(real) * Nt, hipMemcpyDeviceToDevice, st));
+    if (save) MMSD_HIP(hipMemcpyAsync(p->snap[k][1], P.u3[p->ucur], sizeof(real) * Nt, hipMemcpyDeviceToDevice, st));
+    else MMSD_HIP(hipMemcpyAsync(P.u3[p->ucur], p->snap[k][1], sizeof(real) * Nt, hipMemcpyDeviceToDevice, st));
   }
   return MMSD_OK;
 }
@@ -1442,11 +1445,11 @@ int mmsd_get_potential(mmsd_problem p, double* u_out) {
   std::vector<double> u(A.Nt);
   if (p->precision == MMSD_MIXED) {
     std::vector<float> f(A.Nt);
-    MMSD_HIP(hipMemcpyAsync(f.data(), desc_of<float>(p).u, 4 * (size_t)A.Nt, hipMemcpyDeviceToHost, st));
+    MMSD_HIP(hipMemcpyAsync(f.data(), desc_of<float>(p).u3[p->ucur], 4 * (size_t)A.Nt, hipMemcpyDeviceToHost, st));
     MMSD_HIP(hipStreamSynchronize(st));
     for (int i = 0; i < A.Nt; ++i) u[i] = f[i];
   } else {
-    MMSD_HIP(hipMemcpyAsync(u.data(), desc_of<double>(p).u, 8 * (size_t)A.Nt, hipMemcpyDeviceToHost, st));
+    MMSD_HIP(hipMemcpyAsync(u.data(), desc_of<double>(p).u3[p->ucur], 8 * (size_t)A.Nt, hipMemcpyDeviceToHost, st));
     MMSD_HIP(hipStreamSynchronize(st));
   }
   const double scale = A.Ms * 1e-9;   // internal unit of the potential: Ms nm
@@ -1679,6 +1682,7 @@ int mmsd_minimize_batch(mmsd_problem* probs, int n, const mmsd_options* o, mmsd_
     }
     const Ctrl& C = latest(&p->hctrl[0]);
     p->acc = C.acc;
+    p->ucur = C.ucur;
     p->h_valid = false;
     if (c->timing.stride > 0) c->timing.bytes += run_bytes(p, C);
     fill_result(p, C, &out[i], secs, C.launches_done);
@@ -1889,11 +1893,11 @@ int mmsd_get_state(mmsd_problem p, void* buf, size_t* bytes) {
     hipStream_t st = p->ctx->stream;
     if (p->precision == MMSD_MIXED) {
       std::vector<float> f(Nt);
-      MMSD_HIP(hipMemcpyAsync(f.data(), desc_of<float>(p).u, 4 * Nt, hipMemcpyDeviceToHost, st));
+      MMSD_HIP(hipMemcpyAsync(f.data(), desc_of<float>(p).u3[p->ucur], 4 * Nt, hipMemcpyDeviceToHost, st));
       MMSD_HIP(hipStreamSynchronize(st));
       for (size_t i = 0; i < Nt; ++i) u[i] = f[i];
     } else {
-      MMSD_HIP(hipMemcpyAsync(u, desc_of<double>(p).u, 8 * Nt, hipMemcpyDeviceToHost, st));
+      MMSD_HIP(hipMemcpyAsync(u, desc_of<double>(p).u3[p->ucur], 8 * Nt, hipMemcpyDeviceToHost, st));
       MMSD_HIP(hipStreamSynchronize(st));
     }
   }
@@ -1926,10 +1930,10 @@ int mmsd_set_state(mmsd_problem p, const void* buf, size_t bytes) {
     const double* u = (const double*)(b + 64 + 24 * N);
     if (p->precision == MMSD_MIXED) {
       std::vector<float> f(u, u + Nt);
-      MMSD_HIP(hipMemcpyAsync(desc_of<float>(p).u, f.data(), 4 * Nt, hipMemcpyHostToDevice, st));
+      MMSD_HIP(hipMemcpyAsync(desc_of<float>(p).u3[p->ucur], f.data(), 4 * Nt, hipMemcpyHostToDevice, st));
       MMSD_HIP(hipStreamSynchronize(st));
     } else {
-      MMSD_HIP(hipMemcpyAsync(desc_of<double>(p).u, u, 8 * Nt, hipMemcpyHostToDevice, st));
+      MMSD_HIP(hipMemcpyAsync(desc_of<double>(p).u3[p->ucur], u, 8 * Nt, hipMemcpyHostToDevice, st));
       MMSD_HIP(hipStreamSynchronize(st));
     }
   }

@@ -86,6 +86,10 @@ struct Ctrl {
   // progress, FP32 resolution of the energy, accepted steps since
   double prog_e, prog_T, e_res;
   int stall, pad3;
+  // potential buffers (indices into u3): the working one, the accepted
+  // state's, and the two a PREP starts from (u_src2 < 0: u_src alone; else
+  // the interpolation u_src + rho (u_src2 - u_src) after a rejected trial)
+  int ucur, uacc, u_src, u_src2;
   double bz[3];                  // applied field / Js
   double c_an;                   // sum_e V_e K1_e / (mu0 Ms^2)
   double vol;                    // sum_i V_i
@@ -200,7 +204,8 @@ struct ProbT {
   Ptr<const real> lsum;       // row sums of the potential matrix (zero but on rows next to the
                               // Dirichlet boundary); the FP32 form takes L u as
                               // sum_j L_ij (u_j - u_i) + lsum_i u_i
-  Ptr<real> u;                // potential (the CG iterate), warm start across solves
+  Ptr<real> u3[3];            // potential buffers: the CG iterate (Ctrl::ucur) and the accepted
+                              // state's potential (Ctrl::uacc), the warm starts across solves
   Ptr<real> p;                // search direction (row-local)
   Ptr<Rec<real>> rec[2];      // CG state by buffer parity (pcur)
   // multigrid-preconditioned CG (absent when n_lev == 0)

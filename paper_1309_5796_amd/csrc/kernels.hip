@@ -288,21 +288,32 @@ __device__ void phase_prep(const ProbDev<real>& P, const Ctrl* C, int blk, doubl
   }
   if (!demag) return;
   __syncthreads();
-  DevPtr<const real> __restrict__ u = P.u;
+  // warm start of the solve: the accepted state's potential, or after a
+  // rejected trial (tau halved) the interpolation between the accepted and
+  // the rejected trial's potentials at the halved step, which leaves only the
+  // curvature of the Cayley curve in the starting residual.  It is written to
+  // the solve's working buffer while L u is formed from it.
+  DevPtr<const real> __restrict__ ua = P.u3[C->u_src];
+  DevPtr<const real> __restrict__ ub = C->u_src2 >= 0 ? P.u3[C->u_src2] : ua;
+  DevPtr<real> __restrict__ uw = P.u3[C->ucur];
+  const bool interp = C->u_src2 >= 0;
+  const real wr = real(C->rho);
+  auto u_at = [&](int j) -> real { return interp ? ua[j] + wr * (ub[j] - ua[j]) : ua[j]; };
   for (int base = r0; base < r1; base += rs) {
     const int i = base + threadIdx.x;
     if (i >= r1) continue;
     const real bi = i < P.N ? (amg ? r2[i] : rec[i].r) : real(0);
-    const real ui = u[i];
+    const real ui = u_at(i);
+    uw[i] = ui;
     // FP32: the potential is large and smooth next to its residual, and the
     // rounding of the matrix values times u would swamp b - L u; L's rows sum
     // to zero away from the Dirichlet boundary, so the sum is taken over
     // differences u_j - u_i plus the (exactly assembled) row sum times u_i
     real lu;
     if constexpr (std::is_same<real, float>::value)
-      lu = sell_sum(P, i, [&](int j) { return u[j] - ui; }) + P.lsum[i] * ui;
+      lu = sell_sum(P, i, [&](int j) { return u_at(j) - ui; }) + P.lsum[i] * ui;
     else
-      lu = sell_sum(P, i, [&](int j) { return u[j]; });
+      lu = sell_sum(P, i, [&](int j) { return u_at(j); });
     const real ri = bi - lu;
     if (amg) r2[i] = ri;
     else rec[i].r = ri;
@@ -353,7 +364,7 @@ __device__ void phase_cg(const ProbDev<real>& P, const Ctrl* C, int blk, double*
     if (i >= r1) continue;
     const Rec<real> own = ld<real>(ro, i);
     real pi = P.p[i];
-    real ui = P.u[i];
+    real ui = P.u3[C->ucur][i];
     const real sw = sell_sum(P, i, [&](int j) {
       const Rec<real> nb = ld<real>(ro, j);
       return nb.d * (nb.r - alpha * (nb.w + beta * nb.s));
@@ -364,7 +375,7 @@ __device__ void phase_cg(const ProbDev<real>& P, const Ctrl* C, int blk, double*
     const real ri = own.r - alpha * si;
     const real zi = own.d * ri;
     P.p[i] = pi;
-    P.u[i] = ui;
+    P.u3[C->ucur][i] = ui;
     Rec<real> out;
     out.r = ri;
     out.s = si;
@@ -704,10 +715,11 @@ __device__ void phase_pcg_b(const ProbDev<real>& P, const Ctrl* C, int blk, doub
   DevPtr<real> __restrict__ rn = P.r2[1 - C->rcur];
   DevPtr<const real> __restrict__ q = P.q;
   DevPtr<const Pair<real>> __restrict__ rq = P.rq;
+  DevPtr<real> __restrict__ U = P.u3[C->ucur];
   for (int base = r0; base < r1; base += rs) {
     const int i = base + threadIdx.x;
     if (i >= r1) continue;
-    const real roi = ro[i], qi = q[i], uo = P.u[i];
+    const real roi = ro[i], qi = q[i], uo = U[i];
     const Pair<real> own = ld<real>(zp, i);
     const real sum = sell_sum(P, i, [&](int j) {
       const Pair<real> e = ld<real>(rq, j);
@@ -718,7 +730,7 @@ __device__ void phase_pcg_b(const ProbDev<real>& P, const Ctrl* C, int blk, doub
     const real ri = roi - alpha * qi;
     const real ui = uo + alpha * pi;
     rn[i] = ri;
-    P.u[i] = ui;
+    U[i] = ui;
     P.lev[0].res[i] = ri - sum;
     acc[0] += (double)ri * (double)ri;
     acc[1] += (double)ri * (double)ui;
@@ -764,7 +776,7 @@ __device__ void phase_field(const ProbDev<real>& P, const Ctrl* C, int blk, doub
       oi0 = mx[i];
       oi1 = my[i];
       oi2 = mz[i];
-      if (demag) oiu = P.u[i];
+      if (demag) oiu = P.u3[C->ucur][i];
     }
     if (valid) {
       const int ke = P.mrp[i + 1];
@@ -803,7 +815,7 @@ __device__ void phase_field(const ProbDev<real>& P, const Ctrl* C, int blk, doub
             ex[u] = f * P.D2[0][k];
             ey[u] = f * P.D2[1][k];
             ez[u] = f * P.D2[2][k];
-            uj[u] = P.u[j[u]] - oiu;
+            uj[u] = P.u3[C->ucur][j[u]] - oiu;
           }
 #pragma unroll
           for (int u = 0; u < kU; ++u) {
@@ -1090,9 +1102,28 @@ __device__ void step_logic(Ctrl* C, const double* v) {
 }
 
 
+// Potential buffers of the solve a PREP starts: after an accepted state
+// (or at the start) the working buffer holds its potential, which becomes
+// the accepted one and is copied into the next working buffer; after a
+// rejected trial the start is interpolated between the accepted and the
+// rejected trial's potentials into the third buffer.
+__device__ void enter_prep(Ctrl* C) {
+  if (!C->demag) return;
+  if (C->backtrack) {
+    C->u_src = C->uacc;
+    C->u_src2 = C->ucur;
+    C->ucur = 3 - C->uacc - C->ucur;
+  } else {
+    C->u_src = C->ucur;
+    C->u_src2 = -1;
+    C->uacc = C->ucur;
+    C->ucur = (C->ucur + 1) % 3;
+  }
+}
+
 // Advance the state by the outcome of the phase it records (v: the finished
 // reductions of that phase's partials).
-__device__ void transition(Ctrl* C, const double* v, const double* btab, int n_lev, int fused, bool folded) {
+__device__ void transition_phase(Ctrl* C, const double* v, const double* btab, int n_lev, int fused, bool folded) {
   C->seq++;
   const int phase = C->phase;
   if (phase == PH_IDLE || phase == PH_DONE) return;
@@ -1206,6 +1237,11 @@ __device__ void transition(Ctrl* C, const double* v, const double* btab, int n_l
       step_logic(C, v);
       return;
   }
+}
+
+__device__ void transition(Ctrl* C, const double* v, const double* btab, int n_lev, int fused, bool folded) {
+  transition_phase(C, v, btab, n_lev, fused, folded);
+  if (C->phase == PH_PREP) enter_prep(C);
 }
 
 // out[k] = sum (max for the torque slot) over the G block partials of slot k.
@@ -1367,6 +1403,7 @@ __global__ void __launch_bounds__(kBlock, 4) k_step(const ProbDev<real>* __restr
 // above both slots' so the host always picks the newest.
 struct CtrlInit {
   int stage, terms, nonmono_M, step_rule, pcg_maxit, store_h, demag, acc, precond, chain, max_halvings, stop_sum2;
+  int ucur, pad;
   long long max_evals;
   double tol, pcg_rtol2, c1, rho, kappa0, theta0, tau_min, tau_max, tau_floor, e_res;
   double bz[3], c_an, vol;
@@ -1397,6 +1434,8 @@ __global__ void k_ctrl_init(Ctrl* ctrl, int slot, CtrlInit a) {
   C->store_h = a.store_h;
   C->demag = a.demag;
   C->stop_sum2 = a.stop_sum2;
+  C->ucur = C->uacc = C->u_src = a.ucur;
+  C->u_src2 = -1;
   C->evals = 0;
   C->iters = 0;
   C->pcg_total = 0;
@@ -1472,9 +1511,11 @@ template hipError_t launch_step<float>(int, const Prob<float>*, int, const int*,
 
 hipError_t launch_ctrl_init(Ctrl* ctrl, int slot, int stage, int terms, int nonmono_M, int step_rule,
                             int pcg_maxit, int store_h, int demag, int acc, int precond, int chain,
-                            int max_halvings, int stop_sum2, long long max_evals, const double* dparams,
-                            hipStream_t s) {
+                            int max_halvings, int stop_sum2, int ucur, long long max_evals,
+                            const double* dparams, hipStream_t s) {
   CtrlInit a;
+  a.ucur = ucur;
+  a.pad = 0;
   a.precond = precond;
   a.chain = chain;
   a.max_halvings = max_halvings;

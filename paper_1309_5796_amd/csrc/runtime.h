@@ -31,8 +31,8 @@ hipError_t launch_step(int lpr, const Prob<real>* probs, int nprob, const int* b
                        hipStream_t s);
 hipError_t launch_ctrl_init(Ctrl* ctrl, int slot, int stage, int terms, int nonmono_M, int step_rule,
                             int pcg_maxit, int store_h, int demag, int acc, int precond, int chain,
-                            int max_halvings, int stop_sum2, long long max_evals, const double* dparams,
-                            hipStream_t s);
+                            int max_halvings, int stop_sum2, int ucur, long long max_evals,
+                            const double* dparams, hipStream_t s);
 
 hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream_t s);
 
@@ -115,6 +115,7 @@ struct mmsd_problem_s {
   void* snap[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [set][m | u]
   int G = 0, lpr = 4;
   int acc = 0;
+  int ucur = 0;                           // potential buffer holding the current potential
   bool h_valid = false;
   double b_ext[3] = {0, 0, 0};
   double btab[mmsd::kByteSlots] = {};     // algorithmic bytes per executed phase (also on the device)

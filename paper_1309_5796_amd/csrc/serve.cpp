@@ -369,6 +369,7 @@ void mmsd_server_s::device_loop() {
       }
       const Ctrl& C = latest(two);
       p->acc = C.acc;
+      p->ucur = C.ucur;
       fill_result(p, C, &r->result, 0.0, C.launches_done);
       r->m_final.resize(3 * (size_t)p->A.N);
       if (mmsd_get_m(p, r->m_final.data()) != MMSD_OK) {
