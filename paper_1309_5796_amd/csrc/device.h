@@ -51,7 +51,7 @@ constexpr int kMaxLevels = 12;
 enum Stage : int { ST_INIT = 0, ST_RUN = 1, ST_EVAL = 2 };
 
 constexpr int kBlock = 512;        // threads per block (8 wavefronts of 64)
-constexpr int kNPart = 14;         // partial sums per block (FIELD needs 14)
+constexpr int kNPart = 15;         // partial sums per block (FIELD needs 15)
 constexpr int kMaxHist = 64;       // nonmonotone memory capacity
 constexpr int kMaxBlocks = 2048;   // per problem (every block reads all partials)
 
@@ -59,7 +59,8 @@ constexpr int kMaxBlocks = 2048;   // per problem (every block reads all partial
 enum FieldPart : int {
   FP_EEX = 0, FP_EAN = 1, FP_EZ = 2, FP_ED = 3, FP_TMAX = 4, FP_D = 5,
   FP_SS = 6, FP_SY = 7, FP_YY = 8, FP_MX = 9, FP_MY = 10, FP_MZ = 11, FP_H2 = 12,
-  FP_DE = 13   // mixed form: energy change from the accepted state, -1/2 sum V s.(h_t + h)
+  FP_DE = 13,  // mixed form: energy change from the accepted state, -1/2 sum V s.(h_t + h)
+  FP_SD = 14   // sum V s.(H_t x m_t): the step against the next descent direction
 };
 
 // Control state of one problem (two slots, one per launch parity).  `phase`
@@ -90,6 +91,8 @@ struct Ctrl {
   // state's, and the two a PREP starts from (u_src2 < 0: u_src alone; else
   // the interpolation u_src + rho (u_src2 - u_src) after a rejected trial)
   int ucur, uacc, u_src, u_src2;
+  double u_w;                    // weight of u_src2 - u_src in the start of the solve
+  double step_proj;              // projection of the next step on the last one (s_new.s / s.s, first order)
   double bz[3];                  // applied field / Js
   double c_an;                   // sum_e V_e K1_e / (mu0 Ms^2)
   double vol;                    // sum_i V_i

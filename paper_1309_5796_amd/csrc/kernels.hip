@@ -297,7 +297,7 @@ __device__ void phase_prep(const ProbDev<real>& P, const Ctrl* C, int blk, doubl
   DevPtr<const real> __restrict__ ub = C->u_src2 >= 0 ? P.u3[C->u_src2] : ua;
   DevPtr<real> __restrict__ uw = P.u3[C->ucur];
   const bool interp = C->u_src2 >= 0;
-  const real wr = real(C->rho);
+  const real wr = real(C->u_w);
   auto u_at = [&](int j) -> real { return interp ? ua[j] + wr * (ub[j] - ua[j]) : ua[j]; };
   for (int base = r0; base < r1; base += rs) {
     const int i = base + threadIdx.x;
@@ -882,6 +882,9 @@ __device__ void phase_field(const ProbDev<real>& P, const Ctrl* C, int blk, doub
       const double y1 = (double)(m2 * Hx - m0 * Hz) - (double)(n2 * G0 - n0 * G2);
       const double y2 = (double)(m0 * Hy - m1 * Hx) - (double)(n0 * G1 - n1 * G0);
       fa[FP_SS] += V * (s0 * s0 + s1 * s1 + s2 * s2);
+      // the next step goes along H_t x m_t (first order): its overlap with this one
+      fa[FP_SD] += V * (s0 * ((double)Hy * m2 - (double)Hz * m1) + s1 * ((double)Hz * m0 - (double)Hx * m2) +
+                        s2 * ((double)Hx * m1 - (double)Hy * m0));
       fa[FP_SY] += V * (s0 * y0 + s1 * y1 + s2 * y2);
       fa[FP_YY] += V * (y0 * y0 + y1 * y1 + y2 * y2);
       fa[FP_MX] += V * (double)m0;
@@ -1098,6 +1101,8 @@ __device__ void step_logic(Ctrl* C, const double* v) {
     }
   }
   C->tau = fmin(fmax(tau, C->tau_min), C->tau_max);
+  // first-order overlap of the next step (tau (H x m) at the new state) with the last
+  C->step_proj = ss > 0.0 ? C->tau * v[FP_SD] / ss : 0.0;
   C->phase = PH_PREP;
 }
 
@@ -1112,10 +1117,21 @@ __device__ void enter_prep(Ctrl* C) {
   if (C->backtrack) {
     C->u_src = C->uacc;
     C->u_src2 = C->ucur;
+    C->u_w = C->rho;
     C->ucur = 3 - C->uacc - C->ucur;
+  } else if (C->iters > 0 && C->ucur != C->uacc) {
+    // after an accepted step s: the next step's potential change is about
+    // (s_new.s / s.s) times this step's, u_acc - u_prev
+    C->u_src = C->ucur;
+    C->u_src2 = C->uacc;
+    C->u_w = -C->step_proj;
+    const int w = 3 - C->uacc - C->ucur;
+    C->uacc = C->ucur;
+    C->ucur = w;
   } else {
     C->u_src = C->ucur;
     C->u_src2 = -1;
+    C->u_w = 0.0;
     C->uacc = C->ucur;
     C->ucur = (C->ucur + 1) % 3;
   }
@@ -1436,6 +1452,8 @@ __global__ void k_ctrl_init(Ctrl* ctrl, int slot, CtrlInit a) {
   C->stop_sum2 = a.stop_sum2;
   C->ucur = C->uacc = C->u_src = a.ucur;
   C->u_src2 = -1;
+  C->u_w = 0.0;
+  C->step_proj = 0.0;
   C->evals = 0;
   C->iters = 0;
   C->pcg_total = 0;
