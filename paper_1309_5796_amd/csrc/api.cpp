@@ -685,6 +685,8 @@ int build_amg(mmsd_problem p) {
   return MMSD_OK;
 }
 
+constexpr double kStreamBytes = 128.0 * (1 << 20);
+
 template <typename real>
 int build_device(mmsd_problem p) {
   mmsd_ctx c = p->ctx;
@@ -741,6 +743,9 @@ int build_device(mmsd_problem p) {
   P.N = (int)N;
   P.Nt = (int)Nt;
   P.G = G;
+  // stream the sliced matrices past the caches when the potential matrix
+  // alone exceeds half of the 256 MB Infinity Cache
+  P.stream = (double)nnzLs * (4 + sizeof(real)) > kStreamBytes ? 1 : 0;
   P.blk0 = 0;
   P.mrp = (const int*)(base + L.mrp);
   P.mci = (const int*)(base + L.mci);

@@ -186,6 +186,7 @@ __host__ __device__ inline int byte_slot(int phase, int op, int lev) {
 template <typename real, template <typename> class Ptr>
 struct ProbT {
   int N, Nt, G, blk0;
+  int stream, pad_s;          // 1: sliced matrices too large for the Infinity Cache are read non-temporally
   // magnet rows: CSR pattern shared by K, D1 (b = D1 m) and D2 (h_d = -D2 u)
   Ptr<const int> mrp;
   Ptr<const int> mci;

@@ -152,6 +152,17 @@ __device__ __forceinline__ void chunk_rows(int R, int G, int blk, int rpp, int a
   rs = (e - s) * rpp;
 }
 
+// Matrix entries of the sliced sweeps are read once per sweep.  On problems
+// whose potential matrix exceeds the Infinity Cache they are streamed with the
+// non-temporal hint (nt), so that they do not push the gathered vectors and
+// the coarse levels' data out of the L2 (polycrystal: -6% per launch); on
+// smaller ones, which the Infinity Cache holds, the plain loads are faster.
+template <bool NT, typename T>
+__device__ __forceinline__ T stream_ld(DevPtr<const T> p, int i) {
+  if constexpr (NT) return __builtin_nontemporal_load(p + i);
+  else return p[i];
+}
+
 // Rows of the potential matrix are swept one per thread from its 64-row
 // sliced layout: a wavefront owns one slice, so every index and value load
 // is one contiguous 64-wide access, and a whole block-pass covers 512 rows.
@@ -160,9 +171,9 @@ constexpr int kSellU = 4;   // entries per thread loaded before their gathers
 // sum_k v[k] * g(column k) over row i of a matrix in the sliced layout
 // (slice offsets so, columns sc, values sv).  The calling wavefront's active
 // lanes all lie in one slice.
-template <typename real, typename G>
-__device__ __forceinline__ real sell_row(DevPtr<const int> so, DevPtr<const int> sc, DevPtr<const real> sv, int i,
-                                         G&& g) {
+template <typename real, bool NT, typename G>
+__device__ __forceinline__ real sell_row_t(DevPtr<const int> so, DevPtr<const int> sc, DevPtr<const real> sv, int i,
+                                           G&& g) {
   const int sl = __builtin_amdgcn_readfirstlane(i >> 6);
   const int o0 = so[sl];
   const int w = (so[sl + 1] - o0) >> 6;
@@ -175,8 +186,8 @@ __device__ __forceinline__ real sell_row(DevPtr<const int> so, DevPtr<const int>
     for (int u = 0; u < kSellU; ++u) {
       const bool ok = k0 + u < w;
       const int q = o + 64 * (ok ? k0 + u : 0);
-      j[u] = sc[q];
-      v[u] = ok ? sv[q] : real(0);
+      j[u] = stream_ld<NT>(sc, q);
+      v[u] = ok ? stream_ld<NT>(sv, q) : real(0);
     }
     real x[kSellU];
 #pragma unroll
@@ -190,9 +201,9 @@ __device__ __forceinline__ real sell_row(DevPtr<const int> so, DevPtr<const int>
 // Row i of the sliced fused matrix Q: {sum (A P)_ik g(k), sum P_ik g(k)}
 // from one gather per entry; P's values cover the first wp entries of the
 // row (sliced with offsets po), the (A P) values all of them.
-template <typename real, typename G>
-__device__ __forceinline__ Pair<real> sell_row_q(DevPtr<const int> so, DevPtr<const int> sc, DevPtr<const real> sv,
-                                                 DevPtr<const int> po, DevPtr<const real> pv, int i, G&& g) {
+template <typename real, bool NT, typename G>
+__device__ __forceinline__ Pair<real> sell_row_q_t(DevPtr<const int> so, DevPtr<const int> sc, DevPtr<const real> sv,
+                                                   DevPtr<const int> po, DevPtr<const real> pv, int i, G&& g) {
   const int sl = __builtin_amdgcn_readfirstlane(i >> 6);
   const int o0 = so[sl], p0 = po[sl];
   const int w = (so[sl + 1] - o0) >> 6, wp = (po[sl + 1] - p0) >> 6;
@@ -206,9 +217,9 @@ __device__ __forceinline__ Pair<real> sell_row_q(DevPtr<const int> so, DevPtr<co
       const int k = k0 + u;
       const bool ok = k < w;
       const int q = o + 64 * (ok ? k : 0);
-      j[u] = sc[q];
-      va[u] = ok ? sv[q] : real(0);
-      vb[u] = k < wp ? pv[op + 64 * k] : real(0);
+      j[u] = stream_ld<NT>(sc, q);
+      va[u] = ok ? stream_ld<NT>(sv, q) : real(0);
+      vb[u] = k < wp ? stream_ld<NT>(pv, op + 64 * k) : real(0);
     }
     real x[kSellU];
 #pragma unroll
@@ -222,10 +233,24 @@ __device__ __forceinline__ Pair<real> sell_row_q(DevPtr<const int> so, DevPtr<co
   return Pair<real>{sa, sb};
 }
 
+// The sliced sweeps with the problem's load form (a uniform branch: both
+// loops are compiled, one runs).
+template <typename real, typename G>
+__device__ __forceinline__ real sell_row(DevPtr<const int> so, DevPtr<const int> sc, DevPtr<const real> sv, int i,
+                                         bool nt, G&& g) {
+  return nt ? sell_row_t<real, true>(so, sc, sv, i, g) : sell_row_t<real, false>(so, sc, sv, i, g);
+}
+template <typename real, typename G>
+__device__ __forceinline__ Pair<real> sell_row_q(DevPtr<const int> so, DevPtr<const int> sc, DevPtr<const real> sv,
+                                                 DevPtr<const int> po, DevPtr<const real> pv, int i, bool nt,
+                                                 G&& g) {
+  return nt ? sell_row_q_t<real, true>(so, sc, sv, po, pv, i, g) : sell_row_q_t<real, false>(so, sc, sv, po, pv, i, g);
+}
+
 // ... over row i of the potential matrix
 template <typename real, typename G>
 __device__ __forceinline__ real sell_sum(const ProbDev<real>& P, int i, G&& g) {
-  return sell_row<real>(P.lso, P.lsc, P.lsv, i, g);
+  return sell_row<real>(P.lso, P.lsc, P.lsv, i, P.stream != 0, g);
 }
 
 // ---- PREP: trial magnetization, Poisson right-hand side, initial residual ----
@@ -472,18 +497,18 @@ template <int W>
 constexpr int kRowU = W >= 8 ? 8 : kUnroll;
 
 template <typename real, int W, typename G>
-__device__ __forceinline__ real a_row(DevRef<const MgLevelDev<real>> L, int i, int lane, G&& g) {
-  if constexpr (W == 1) return sell_row<real>(L.aso, L.asc, L.asv, i, g);
+__device__ __forceinline__ real a_row(DevRef<const MgLevelDev<real>> L, int i, int lane, bool nt, G&& g) {
+  if constexpr (W == 1) return sell_row<real>(L.aso, L.asc, L.asv, i, nt, g);
   else return row_sum<real, W, kRowU<W>>(L.arp, L.aci, L.av, i, lane, g);
 }
 template <typename real, int W, typename G>
-__device__ __forceinline__ Pair<real> q_row(DevRef<const MgLevelDev<real>> L, int i, int lane, G&& g) {
-  if constexpr (W == 1) return sell_row_q<real>(L.qso, L.qsc, L.qsv, L.qpo, L.qpv, i, g);
+__device__ __forceinline__ Pair<real> q_row(DevRef<const MgLevelDev<real>> L, int i, int lane, bool nt, G&& g) {
+  if constexpr (W == 1) return sell_row_q<real>(L.qso, L.qsc, L.qsv, L.qpo, L.qpv, i, nt, g);
   else return row_sum2<real, W, kUnroll>(L.qrp, L.qci, L.qv, i, lane, g);   // two values: half the batch
 }
 template <typename real, int W, typename G>
-__device__ __forceinline__ real r_row(DevRef<const MgLevelDev<real>> L, int i, int lane, G&& g) {
-  if constexpr (W == 1) return sell_row<real>(L.rso, L.rsc, L.rsv, i, g);
+__device__ __forceinline__ real r_row(DevRef<const MgLevelDev<real>> L, int i, int lane, bool nt, G&& g) {
+  if constexpr (W == 1) return sell_row<real>(L.rso, L.rsc, L.rsv, i, nt, g);
   else return row_sum<real, W, kRowU<W>>(L.rrp, L.rci, L.rv, i, lane, g);
 }
 
@@ -504,6 +529,7 @@ __device__ void mg_rows(const ProbDev<real>& P, const Ctrl* C, DevRef<const MgLe
   DevPtr<const real> __restrict__ wd = L.wd;
   DevPtr<const real> __restrict__ wb = L.wb;
   const bool last = l + 1 == P.n_lev;
+  const bool nt = P.stream != 0;
   int r0, r1, rs;
   if (op == MG_REST || op == MG_RESTM) {
     DevPtr<real> __restrict__ bn = last ? P.bc : P.lev[l + 1].b;
@@ -519,7 +545,7 @@ __device__ void mg_rows(const ProbDev<real>& P, const Ctrl* C, DevRef<const MgLe
       real sum = 0;
       if (valid)
         sum = m ? m_row<real, W>(L, i, lane, [&](int j) { return b[j]; })
-                : r_row<real, W>(L, i, lane, [&](int j) { return res[j]; });
+                : r_row<real, W>(L, i, lane, nt, [&](int j) { return res[j]; });
       sum = group_sum<real, W>(sum);
       if (valid && lane == 0) {
         bn[i] = sum;
@@ -534,7 +560,7 @@ __device__ void mg_rows(const ProbDev<real>& P, const Ctrl* C, DevRef<const MgLe
       const int i = base + slot;
       const bool valid = i < r1;
       const real bi = (valid && lane == 0) ? b[i] : real(0);
-      real sum = valid ? a_row<real, W>(L, i, lane, [&](int j) { return l == 0 ? wd[j] * b[j] : wb[j]; })
+      real sum = valid ? a_row<real, W>(L, i, lane, nt, [&](int j) { return l == 0 ? wd[j] * b[j] : wb[j]; })
                        : real(0);
       sum = group_sum<real, W>(sum);
       if (valid && lane == 0) L.res[i] = bi - sum;
@@ -552,7 +578,7 @@ __device__ void mg_rows(const ProbDev<real>& P, const Ctrl* C, DevRef<const MgLe
         ri = res[i];
         if (l == 0) pold = P.zp[i].b;
       }
-      Pair<real> sum = valid ? q_row<real, W>(L, i, lane, [&](int j) { return xn[j]; }) : Pair<real>{0, 0};
+      Pair<real> sum = valid ? q_row<real, W>(L, i, lane, nt, [&](int j) { return xn[j]; }) : Pair<real>{0, 0};
       sum.a = group_sum<real, W>(sum.a);
       sum.b = group_sum<real, W>(sum.b);
       if (valid && lane == 0) {
