@@ -281,14 +281,14 @@ def run_grains(args):
     print(json.dumps(line), flush=True)
 
 
-def serve_stream(n_requests, hbm_gb, slots, timeout_s, log_every=15.0):
+def serve_stream(n_requests, hbm_gb, slots, timeout_s, log_every=15.0, rate_hz=200.0):
     """Submit the first n_requests of the seeded 200 req/s Poisson stream at
     their arrival times to a server with an HBM budget; latency from each
     request's arrival time (its place in the stream) and from the return of
     its submit call (which only copies the request)."""
     import numpy as np
     from paper_1309_5796_amd import binding, meshgen
-    reqs = meshgen.config5_requests()[:n_requests]
+    reqs = meshgen.config5_requests(rate_hz=rate_hz)[:n_requests]
     t0 = time.perf_counter()
     built = [meshgen.request_mesh(r) for r in reqs]
     print(f"[bench] {len(built)} request meshes {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
@@ -339,7 +339,7 @@ def serve_stream(n_requests, hbm_gb, slots, timeout_s, log_every=15.0):
             "p50_from_submit_s": pct(lat_sub, 50), "p99_from_submit_s": pct(lat_sub, 99),
             "statuses": sorted(set(statuses)), "device_launches": st["launches"],
             "setup_seconds_summed": st["setup_seconds"], "device_loop_busy_s": st["loop_seconds"],
-            "offered_rate_req_s": 200.0, "served_rate_req_s": len(lat) / wall,
+            "offered_rate_req_s": rate_hz, "served_rate_req_s": len(lat) / wall,
             "hbm_budget_GB": hbm_gb, "slots": slots}
 
 
@@ -348,9 +348,9 @@ def run_serve(args):
     submitted at their arrival times to a server with an HBM budget; reports
     arrival-to-result latency percentiles (and from the submit call's
     return) and node-iterations/s."""
-    d = serve_stream(args.requests, args.hbm_gb, args.slots, args.serve_timeout)
+    d = serve_stream(args.requests, args.hbm_gb, args.slots, args.serve_timeout, rate_hz=args.rate)
     line = base_line(d["node_iterations_per_s"], d["completed"], 0, d["wall_s"], "mixed f64/f32 per request",
-                     {"workload": f"served minimizations: first {d['requests']} requests of the seeded 200 req/s "
+                     {"workload": f"served minimizations: first {d['requests']} requests of the seeded {args.rate:g} req/s "
                                   f"Poisson stream, 2:2:1 boxes 1.2k-520k nodes, 64-grain density, "
                                   f"B ~ U(-4,4) T, FP64/mixed coin", "hbm_budget_GB": args.hbm_gb,
                       "slots": args.slots})
@@ -618,6 +618,7 @@ def main():
     ap.add_argument("--hbm-gb", type=float, default=64.0)
     ap.add_argument("--slots", type=int, default=32)
     ap.add_argument("--serve-timeout", type=float, default=900.0)
+    ap.add_argument("--rate", type=float, default=200.0, help="arrival rate of the served stream (req/s)")
     ap.add_argument("--poly-prec", default="both", choices=["both", "mixed", "fp64"])
     ap.add_argument("--precond", default="auto", choices=["auto", "jacobi", "amg"],
                     help="preconditioner of the potential solve")
