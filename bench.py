@@ -281,7 +281,7 @@ def run_grains(args):
     print(json.dumps(line), flush=True)
 
 
-def serve_stream(n_requests, hbm_gb, slots, timeout_s, log_every=15.0, rate_hz=200.0):
+def serve_stream(n_requests, hbm_gb, slots, timeout_s, log_every=15.0, rate_hz=200.0, assembly="host"):
     """Submit the first n_requests of the seeded 200 req/s Poisson stream at
     their arrival times to a server with an HBM budget; latency from each
     request's arrival time (its place in the stream) and from the return of
@@ -293,6 +293,8 @@ def serve_stream(n_requests, hbm_gb, slots, timeout_s, log_every=15.0, rate_hz=2
     built = [meshgen.request_mesh(r) for r in reqs]
     print(f"[bench] {len(built)} request meshes {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     ctx = binding.Context(0)
+    if assembly == "device":
+        ctx.set_assembly(binding.ASSEMBLE_DEVICE)
     srv = binding.Server(ctx, hbm_budget=int(hbm_gb * (1 << 30)), max_slots=slots)
     t_start = time.perf_counter()
     t_last = t_start
@@ -339,7 +341,7 @@ def serve_stream(n_requests, hbm_gb, slots, timeout_s, log_every=15.0, rate_hz=2
             "p50_from_submit_s": pct(lat_sub, 50), "p99_from_submit_s": pct(lat_sub, 99),
             "statuses": sorted(set(statuses)), "device_launches": st["launches"],
             "setup_seconds_summed": st["setup_seconds"], "device_loop_busy_s": st["loop_seconds"],
-            "offered_rate_req_s": rate_hz, "served_rate_req_s": len(lat) / wall,
+            "offered_rate_req_s": rate_hz, "served_rate_req_s": len(lat) / wall, "assembly": assembly,
             "hbm_budget_GB": hbm_gb, "slots": slots}
 
 
@@ -348,7 +350,8 @@ def run_serve(args):
     submitted at their arrival times to a server with an HBM budget; reports
     arrival-to-result latency percentiles (and from the submit call's
     return) and node-iterations/s."""
-    d = serve_stream(args.requests, args.hbm_gb, args.slots, args.serve_timeout, rate_hz=args.rate)
+    d = serve_stream(args.requests, args.hbm_gb, args.slots, args.serve_timeout, rate_hz=args.rate,
+                     assembly=args.assembly)
     line = base_line(d["node_iterations_per_s"], d["completed"], 0, d["wall_s"], "mixed f64/f32 per request",
                      {"workload": f"served minimizations: first {d['requests']} requests of the seeded {args.rate:g} req/s "
                                   f"Poisson stream, 2:2:1 boxes 1.2k-520k nodes, 64-grain density, "
@@ -496,9 +499,28 @@ def run_assemble(args):
             times_d.append(time.perf_counter() - t0)
         print(f"[bench] assemble {name}: host {min(times_h):.3f} s, device {min(times_d):.3f} s",
               file=sys.stderr, flush=True)
-        out.append({"mesh": name, "magnet_nodes": N, "potential_nodes": Nt, "tets": int(mesh.tets.shape[0]),
-                    "host_s": min(times_h), "device_s": min(times_d)})
+        row = {"mesh": name, "magnet_nodes": N, "potential_nodes": Nt, "tets": int(mesh.tets.shape[0]),
+               "host_s": min(times_h), "device_s": min(times_d)}
         del outs, host
+        # whole problem creation (assembly, multigrid setup, device build),
+        # FP64, with the operators from each assembly; best of two
+        for where, flag in (("host", binding.ASSEMBLE_HOST), ("device", binding.ASSEMBLE_DEVICE)):
+            ctx.set_assembly(flag)
+            best = None
+            for rep in range(2):
+                t0 = time.perf_counter()
+                p = binding.Problem(ctx, mesh)
+                wall = time.perf_counter() - t0
+                t = p.setup_times()
+                t["wall"] = wall
+                p.close()
+                if best is None or t["total"] < best["total"]:
+                    best = t
+            row[f"create_{where}_assembly"] = best
+            print(f"[bench] create {name} with {where} assembly: " +
+                  ", ".join(f"{k} {v:.3f}" for k, v in best.items()), file=sys.stderr, flush=True)
+        ctx.set_assembly(binding.ASSEMBLE_HOST)
+        out.append(row)
     ctx.close()
     print(json.dumps({"workload": "operator assembly, host vs device", "host_threads":
                       min(16, os.cpu_count() or 1), "detail": out}), flush=True)
@@ -619,6 +641,8 @@ def main():
     ap.add_argument("--slots", type=int, default=32)
     ap.add_argument("--serve-timeout", type=float, default=900.0)
     ap.add_argument("--rate", type=float, default=200.0, help="arrival rate of the served stream (req/s)")
+    ap.add_argument("--assembly", default="host", choices=["host", "device"],
+                    help="where served requests assemble their operators")
     ap.add_argument("--poly-prec", default="both", choices=["both", "mixed", "fp64"])
     ap.add_argument("--precond", default="auto", choices=["auto", "jacobi", "amg"],
                     help="preconditioner of the potential solve")

@@ -145,6 +145,11 @@ int mmsd_footprint(const mmsd_mesh* mesh, int precision, size_t* bytes_out);
 int mmsd_problem_create(mmsd_ctx ctx, const mmsd_mesh* mesh, const mmsd_material* mats,
                         int n_mats, int precision, mmsd_problem* out);
 int mmsd_problem_destroy(mmsd_problem p);
+/* Wall seconds of the problem's creation: t[4] = {assembly (host, or device
+ * with the copies the host keeps), multigrid setup (host), device build
+ * (arena, conversions, uploads, the hierarchy's layout; includes waiting for
+ * the context's lock), total}. */
+int mmsd_problem_setup_times(mmsd_problem p, double t[4]);
 
 int mmsd_n_magnetic(mmsd_problem p, int64_t* n);   /* N: magnetic nodes */
 int mmsd_n_potential(mmsd_problem p, int64_t* n);  /* free (non-Dirichlet) nodes, 0 if none */
@@ -293,6 +298,24 @@ int mmsd_set_launch_config(mmsd_ctx ctx, int lanes_per_row, int max_blocks);
 #define MMSD_VC_FOLD_SOLVE 2
 #define MMSD_VC_SLICE_ALL 4
 int mmsd_set_vcycle(mmsd_ctx ctx, int flags);
+
+/* Where problems created through this context (and the requests of a server
+ * created on it) assemble their operators (Abstract: linear tetrahedral
+ * elements; Results, comparison section: the transformed open-boundary
+ * Laplacian).  MMSD_ASSEMBLE_HOST (default): the host assembly, uploaded.
+ * MMSD_ASSEMBLE_DEVICE: mmsd_assemble_device's kernels build the operators
+ * on the device and the problem's sliced potential matrix, row sums and
+ * Jacobi factors are formed there too; the host keeps only what later calls
+ * need (numbering, the magnet pattern, lumped volumes, the magnetic tets'
+ * geometry for mmsd_set_material, and a copy of the potential matrix for the
+ * multigrid setup).  The two give the same operators up to the rounding of
+ * fused multiply-adds (relative 1e-15); errors are those of
+ * mmsd_assemble_device (a node in more than 512 tets is MMSD_E_INVALID).
+ * Device temporaries of up to ~190 bytes per tet are held during creation.
+ * MMSD_E_INVALID for any other value. */
+#define MMSD_ASSEMBLE_HOST 0
+#define MMSD_ASSEMBLE_DEVICE 1
+int mmsd_set_assembly(mmsd_ctx ctx, int where);
 
 /* Measurement aid: `reps` launches of a plain device-to-device copy kernel
  * (k_copy_probe) of `bytes` bytes each; *ms_out (nullable) gets the mean

@@ -28,6 +28,7 @@ STEP_ADAPTIVE, STEP_ALTERNATE, STEP_BB1, STEP_BB2 = 0, 1, 2, 3
 STOP_MAX_TORQUE, STOP_SUM_SQ = 0, 1
 PRECOND_AUTO, PRECOND_JACOBI, PRECOND_AMG = 0, 1, 2
 VC_FUSE_REST, VC_FOLD_SOLVE, VC_SLICE_ALL = 1, 2, 4
+ASSEMBLE_HOST, ASSEMBLE_DEVICE = 0, 1
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -66,9 +67,11 @@ SIGNATURES = [
     ("mmsd_ctx_destroy", C.c_int, [C.c_void_p]),
     ("mmsd_footprint", C.c_int, [C.POINTER(MeshC), C.c_int, C.POINTER(C.c_size_t)]),
     ("mmsd_set_vcycle", C.c_int, [C.c_void_p, C.c_int]),
+    ("mmsd_set_assembly", C.c_int, [C.c_void_p, C.c_int]),
     ("mmsd_problem_create", C.c_int, [C.c_void_p, C.POINTER(MeshC), C.POINTER(MaterialC), C.c_int, C.c_int,
                                       C.POINTER(C.c_void_p)]),
     ("mmsd_problem_destroy", C.c_int, [C.c_void_p]),
+    ("mmsd_problem_setup_times", C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     ("mmsd_n_magnetic", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     ("mmsd_n_potential", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     ("mmsd_problem_sizes", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
@@ -244,6 +247,10 @@ class Context:
         """V-cycle forms for problems created afterwards (VC_FUSE_REST, VC_FOLD_SOLVE, VC_SLICE_ALL)."""
         _check(self.lib.mmsd_set_vcycle(self.handle, flags))
 
+    def set_assembly(self, where: int):
+        """Where problems created afterwards assemble their operators (ASSEMBLE_HOST, ASSEMBLE_DEVICE)."""
+        _check(self.lib.mmsd_set_assembly(self.handle, where))
+
     def timing(self, on: bool):
         _check(self.lib.mmsd_timing_enable(self.handle, 1 if on else 0))
 
@@ -323,6 +330,12 @@ class Problem:
         self.N = int(n.value)
         _check(self.lib.mmsd_n_potential(h, C.byref(n)))
         self.Nt = int(n.value)
+
+    def setup_times(self) -> dict:
+        """Seconds of this problem's creation by stage."""
+        t = (C.c_double * 4)()
+        _check(self.lib.mmsd_problem_setup_times(self.handle, t))
+        return dict(assembly=t[0], multigrid=t[1], device_build=t[2], total=t[3])
 
     def sizes(self) -> dict:
         """N, magnet-pattern entries, N_t and potential-matrix entries."""

@@ -222,19 +222,27 @@ struct Sliced {
   std::vector<int> so, sc;
   std::vector<double> sv;
 };
-Sliced make_sliced(const std::vector<int>& rp, const std::vector<int>& ci, const std::vector<double>& v,
-                   int ncols, int stride = 1, int off = 0) {
+// Offsets of the 64-row slices of a CSR pattern: slice s starts at so[s]
+// and holds 64 x (its longest row) entries.
+std::vector<int> slice_offsets(const std::vector<int>& rp) {
   const int64_t n = (int64_t)rp.size() - 1, ns = (n + 63) / 64;
-  Sliced S;
-  S.so.assign(ns + 1, 0);
+  std::vector<int> so(ns + 1, 0);
   parallel_for(ns, [&](int64_t a, int64_t b) {
     for (int64_t sl = a; sl < b; ++sl) {
       int w = 0;
       for (int64_t i = 64 * sl; i < std::min<int64_t>(n, 64 * sl + 64); ++i) w = std::max(w, rp[i + 1] - rp[i]);
-      S.so[sl + 1] = 64 * w;
+      so[sl + 1] = 64 * w;
     }
   });
-  for (int64_t sl = 0; sl < ns; ++sl) S.so[sl + 1] += S.so[sl];
+  for (int64_t sl = 0; sl < ns; ++sl) so[sl + 1] += so[sl];
+  return so;
+}
+
+Sliced make_sliced(const std::vector<int>& rp, const std::vector<int>& ci, const std::vector<double>& v,
+                   int ncols, int stride = 1, int off = 0) {
+  const int64_t n = (int64_t)rp.size() - 1, ns = (n + 63) / 64;
+  Sliced S;
+  S.so = slice_offsets(rp);
   S.sc.assign(S.so[ns], 0);
   S.sv.assign(S.so[ns], 0.0);
   parallel_for(ns, [&](int64_t a, int64_t b) {
@@ -687,8 +695,11 @@ int build_amg(mmsd_problem p) {
 
 constexpr double kStreamBytes = 128.0 * (1 << 20);
 
+// The problem's device arena: operators, node state, control.  With D the
+// operators come from the device assembly's buffers (converted on the
+// device); otherwise they are uploaded from the host assembly.
 template <typename real>
-int build_device(mmsd_problem p) {
+int build_device(mmsd_problem p, const DeviceAssembly* D = nullptr) {
   mmsd_ctx c = p->ctx;
   const Assembly& A = p->A;
   const int64_t N = A.N, Nt = A.Nt, nnzM = (int64_t)A.mci.size();
@@ -708,15 +719,35 @@ int build_device(mmsd_problem p) {
   char* base = p->arena;
   MMSD_HIP(hipMemsetAsync(base, 0, L.total, st));
   int rc;
-  if ((rc = upload_int(st, base + L.mrp, A.mrp)) || (rc = upload_int(st, base + L.mci, A.mci)) ||
-      (rc = upload_vec<real>(st, base + L.K, A.K)) || (rc = upload_vec<real>(st, base + L.V, A.V)))
-    return rc;
-  for (int k = 0; k < 3; ++k)
-    if ((rc = upload_vec<real>(st, base + L.D1[k], A.D1[k])) || (rc = upload_vec<real>(st, base + L.D2[k], A.D2[k])))
+  if (D) {
+    MMSD_HIP(hipMemcpyAsync(base + L.mrp, D->mrp, 4 * (N + 1), hipMemcpyDeviceToDevice, st));
+    MMSD_HIP(hipMemcpyAsync(base + L.mci, D->mci, 4 * nnzM, hipMemcpyDeviceToDevice, st));
+    MMSD_HIP(launch_to_real<real>(D->K, (real*)(base + L.K), nnzM, st));
+    MMSD_HIP(launch_to_real<real>(D->V, (real*)(base + L.V), N, st));
+    for (int k = 0; k < 3; ++k) {
+      MMSD_HIP(launch_to_real<real>(D->D1 + k * nnzM, (real*)(base + L.D1[k]), nnzM, st));
+      MMSD_HIP(launch_to_real<real>(D->D2 + k * nnzM, (real*)(base + L.D2[k]), nnzM, st));
+    }
+    for (int k = 0; k < 6; ++k) MMSD_HIP(launch_to_real<real>(D->Q + k * N, (real*)(base + L.Q[k]), N, st));
+  } else {
+    if ((rc = upload_int(st, base + L.mrp, A.mrp)) || (rc = upload_int(st, base + L.mci, A.mci)) ||
+        (rc = upload_vec<real>(st, base + L.K, A.K)) || (rc = upload_vec<real>(st, base + L.V, A.V)))
       return rc;
-  for (int k = 0; k < 6; ++k)
-    if ((rc = upload_vec<real>(st, base + L.Q[k], A.Q[k]))) return rc;
-  if (Nt > 0) {
+    for (int k = 0; k < 3; ++k)
+      if ((rc = upload_vec<real>(st, base + L.D1[k], A.D1[k])) ||
+          (rc = upload_vec<real>(st, base + L.D2[k], A.D2[k])))
+        return rc;
+    for (int k = 0; k < 6; ++k)
+      if ((rc = upload_vec<real>(st, base + L.Q[k], A.Q[k]))) return rc;
+  }
+  if (Nt > 0 && D) {
+    // sliced on the device from the assembled CSR; only the slice offsets
+    // come from the host (the copy of the row starts it keeps)
+    if ((rc = upload_int(st, base + L.lso, slice_offsets(A.lrp)))) return rc;
+    MMSD_HIP(launch_slice_rows<real>(D->lrp, D->lci, D->L, (const int32_t*)(base + L.lso), Nt,
+                                     (int32_t*)(base + L.lsc), (real*)(base + L.lsv), (real*)(base + L.lsum),
+                                     (real*)(base + L.rec[0]), (real*)(base + L.rec[1]), st));
+  } else if (Nt > 0) {
     // the potential matrix lives on the device only in its sliced layout
     const Sliced S = make_sliced(A.lrp, A.lci, A.L, (int)Nt);
     if ((rc = upload_int(st, base + L.lso, S.so)) || (rc = upload_int(st, base + L.lsc, S.sc)) ||
@@ -1164,6 +1195,42 @@ void mmsd_ctx_s::dfree(void* p) {
 }
 
 // ============================ C ABI =======================================
+// Operators assembled on the device (into D) and the host side the problem
+// keeps: the magnet pattern and lumped volumes (sizes, material changes) and
+// the potential matrix (multigrid setup) come back; the coupling, exchange
+// and anisotropy values stay on the device.
+int assemble_on_device(mmsd_problem p, const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats,
+                       DeviceAssembly* D) {
+  mmsd_ctx c = p->ctx;
+  AssemblyStructure S;
+  int rc = assemble_device_owned(c, mesh, mats, n_mats, D, &S);
+  if (rc) return rc;
+  Assembly& A = p->A;
+  std::vector<double> V(D->N);
+  A.mrp.resize(D->N + 1);
+  A.mci.resize(D->nnzM);
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    MMSD_HIP(hipSetDevice(c->device));
+    hipStream_t st = c->stream;
+    MMSD_HIP(hipMemcpyAsync(V.data(), D->V, 8 * D->N, hipMemcpyDeviceToHost, st));
+    MMSD_HIP(hipMemcpyAsync(A.mrp.data(), D->mrp, 4 * (D->N + 1), hipMemcpyDeviceToHost, st));
+    MMSD_HIP(hipMemcpyAsync(A.mci.data(), D->mci, 4 * D->nnzM, hipMemcpyDeviceToHost, st));
+    if (D->Nt > 0) {
+      A.lrp.resize(D->Nt + 1);
+      A.lci.resize(D->nnzL);
+      A.L.resize(D->nnzL);
+      MMSD_HIP(hipMemcpyAsync(A.lrp.data(), D->lrp, 4 * (D->Nt + 1), hipMemcpyDeviceToHost, st));
+      MMSD_HIP(hipMemcpyAsync(A.lci.data(), D->lci, 4 * D->nnzL, hipMemcpyDeviceToHost, st));
+      MMSD_HIP(hipMemcpyAsync(A.L.data(), D->L, 8 * D->nnzL, hipMemcpyDeviceToHost, st));
+    }
+    MMSD_HIP(hipStreamSynchronize(st));
+  }
+  std::string err;
+  if ((rc = assemble_host_side(mesh, mats, n_mats, &S, std::move(V), &A, &err))) set_error(err);
+  return rc;
+}
+
 extern "C" {
 
 const char* mmsd_last_error(void) { return mmsd::g_err.c_str(); }
@@ -1238,6 +1305,20 @@ int mmsd_set_vcycle(mmsd_ctx c, int flags) {
   return MMSD_OK;
 }
 
+int mmsd_set_assembly(mmsd_ctx c, int where) {
+  if (!c) return invalid("null context");
+  if (where != MMSD_ASSEMBLE_HOST && where != MMSD_ASSEMBLE_DEVICE)
+    return invalid("assembly must be MMSD_ASSEMBLE_HOST or MMSD_ASSEMBLE_DEVICE");
+  c->assembly = where;
+  return MMSD_OK;
+}
+
+int mmsd_problem_setup_times(mmsd_problem p, double t[4]) {
+  if (!p || !t) return invalid("null argument");
+  for (int k = 0; k < 4; ++k) t[k] = p->setup_t[k];
+  return MMSD_OK;
+}
+
 int mmsd_timing_enable(mmsd_ctx c, int stride) {
   if (!c || stride < 0) return invalid("bad timing request");
   c->timing.stride = stride;
@@ -1277,16 +1358,25 @@ int mmsd_problem_create(mmsd_ctx c, const mmsd_mesh* mesh, const mmsd_material* 
   if (!c || !out) return invalid("null handle");
   if (precision != MMSD_FP64 && precision != MMSD_MIXED) return invalid("precision must be MMSD_FP64 or MMSD_MIXED");
   if (n_mats < 0 || (n_mats > 0 && !mats)) return invalid("bad material table");
+  using Clock = std::chrono::steady_clock;
+  const auto t0 = Clock::now();
   auto* p = new mmsd_problem_s;
   p->ctx = c;
   p->precision = precision;
   std::string err;
-  int rc = assemble(mesh, mats, n_mats, &p->A, &err);
-  if (rc) {
-    delete p;
+  DeviceAssembly D;
+  int rc = MMSD_OK;
+  if (c->assembly == MMSD_ASSEMBLE_DEVICE) {
+    rc = assemble_on_device(p, mesh, mats, n_mats, &D);
+  } else if ((rc = assemble(mesh, mats, n_mats, &p->A, &err))) {
     set_error(err);
+  }
+  if (rc) {
+    D.release(c);
+    delete p;
     return rc;
   }
+  const auto t1 = Clock::now();
   if (p->A.Nt > 0) {
     Csr L0;
     L0.nrows = L0.ncols = p->A.Nt;
@@ -1296,15 +1386,30 @@ int mmsd_problem_create(mmsd_ctx c, const mmsd_mesh* mesh, const mmsd_material* 
     p->has_amg = amg_setup(std::move(L0), AmgParams{}, &p->amg) && (int)p->amg.lv.size() <= kMaxLevels;
     // the level operators are kept only for sizes and byte counts
   }
-  std::lock_guard<std::mutex> lk(c->mu);
-  (void)hipSetDevice(c->device);
-  rc = precision == MMSD_MIXED ? build_device<float>(p) : build_device<double>(p);
+  const auto t2 = Clock::now();
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    (void)hipSetDevice(c->device);
+    const DeviceAssembly* dp = c->assembly == MMSD_ASSEMBLE_DEVICE ? &D : nullptr;
+    rc = precision == MMSD_MIXED ? build_device<float>(p, dp) : build_device<double>(p, dp);
+    if (!rc && dp) {
+      const hipError_t e = hipStreamSynchronize(c->stream);
+      if (e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize");
+    }
+  }
+  D.release(c);
   if (rc) {
     if (p->arena) c->dfree(p->arena);
     if (p->amg_arena) c->dfree(p->amg_arena);
     delete p;
     return rc;
   }
+  const auto t3 = Clock::now();
+  auto secs = [](Clock::time_point a, Clock::time_point b) { return std::chrono::duration<double>(b - a).count(); };
+  p->setup_t[0] = secs(t0, t1);
+  p->setup_t[1] = secs(t1, t2);
+  p->setup_t[2] = secs(t2, t3);
+  p->setup_t[3] = secs(t0, t3);
   *out = p;
   return MMSD_OK;
 }
@@ -1349,6 +1454,7 @@ int mmsd_set_material(mmsd_problem p, const mmsd_material* m) {
   double un = std::sqrt(dot3(m->easy_axis, m->easy_axis));
   if (m->region < 1 || !(un > 0) || !(m->Js_T > 0) || !(m->A_Jm >= 0) || !std::isfinite(m->K1_Jm3))
     return invalid("invalid material");
+  ensure_magnet_adjacency(&p->A);
   auto saved = p->A.mats;
   p->A.mats[m->region] = MatLine{m->Js_T, m->K1_Jm3, m->A_Jm, {m->easy_axis[0], m->easy_axis[1], m->easy_axis[2]}};
   std::string err;

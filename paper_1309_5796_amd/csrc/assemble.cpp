@@ -12,6 +12,7 @@
 #include "amg.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <functional>
@@ -269,7 +270,7 @@ int64_t sliced_entries(const std::vector<int>& rp) {
   return total;
 }
 
-int assemble_material_values(Assembly* A, std::string* err) {
+int assemble_material_values(Assembly* A, std::string* err, bool operators) {
   const int N = A->N;
   const int64_t Em = (int64_t)A->mregion.size();
   // every region used needs a material with a common Js; the regions'
@@ -320,6 +321,7 @@ int assemble_material_values(Assembly* A, std::string* err) {
     c_an.add(Ve * M.K1 / mu0Ms2);
   }
   A->c_an = c_an.value();
+  if (!operators) return MMSD_OK;
   A->K.assign(A->mci.size(), 0.0);
   for (int k = 0; k < 6; ++k) A->Q[k].assign(N, 0.0);
   parallel_for(N, [&](int64_t a, int64_t b) {
@@ -510,6 +512,55 @@ int assemble(const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats, Assem
     }
   }
   return MMSD_OK;
+}
+
+int assemble_host_side(const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats, AssemblyStructure* S,
+                       std::vector<double>&& V, Assembly* A, std::string* err) {
+  A->n_nodes = mesh->n_nodes;
+  A->N = S->N;
+  A->Nt = S->Nt;
+  A->mag_global = std::move(S->mag_global);
+  A->pot_global = std::move(S->pot_global);
+  A->mats.clear();
+  for (int k = 0; k < n_mats; ++k) {
+    const mmsd_material& m = mats[k];
+    A->mats[m.region] = MatLine{m.Js_T, m.K1_Jm3, m.A_Jm, {m.easy_axis[0], m.easy_axis[1], m.easy_axis[2]}};
+  }
+  A->mtet = std::move(S->mtet);
+  A->mregion = std::move(S->mregion);
+  const int64_t Em = (int64_t)A->mregion.size();
+  A->mgeo.resize(13 * Em);
+  std::atomic<int> bad{0};
+  parallel_for(Em, [&](int64_t k0, int64_t k1) {
+    for (int64_t k = k0; k < k1; ++k) {
+      double g[4][3], Ve;
+      if (!tet_geo(mesh->xyz, mesh->tets + 4 * (int64_t)S->mtet_mesh[k], &Ve, g)) {
+        bad.store(1);
+        continue;
+      }
+      A->mgeo[13 * k] = Ve;
+      for (int a = 0; a < 4; ++a)
+        for (int c = 0; c < 3; ++c) A->mgeo[13 * k + 1 + 3 * a + c] = g[a][c];
+    }
+  });
+  if (bad) {
+    *err = "mesh: degenerate tetrahedron";
+    return MMSD_E_MESH;
+  }
+  A->V = std::move(V);
+  CompensatedSum vol;
+  for (int i = 0; i < A->N; ++i) vol.add(A->V[i]);
+  A->vol = vol.value();
+  A->mnode_tets_ptr.clear();
+  A->mnode_tets.clear();
+  return assemble_material_values(A, err, /*operators=*/false);
+}
+
+void ensure_magnet_adjacency(Assembly* A) {
+  if (!A->mnode_tets_ptr.empty()) return;
+  const int64_t Em = (int64_t)A->mregion.size();
+  std::vector<char> all(Em, 1);
+  node_tets(A->N, A->mtet.data(), Em, all, A->mnode_tets_ptr, A->mnode_tets);
 }
 
 int assemble_structure(const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats, AssemblyStructure* S,

@@ -59,8 +59,9 @@ int pattern_sizes(const mmsd_mesh* mesh, PatternSizes* out, std::string* err);
 int assemble(const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats, Assembly* out,
              std::string* err);
 
-// Recompute K, Q and c_an from a.mats (after a material change).
-int assemble_material_values(Assembly* a, std::string* err);
+// Recompute K, Q and c_an from a.mats (after a material change); with
+// operators false only Js, Ms, mu0 Ms^2 and c_an.
+int assemble_material_values(Assembly* a, std::string* err, bool operators = true);
 
 // The combinatorial half of the assembly, for the device-side assembly of
 // the values: numbering, the magnetic tets with their node adjacency, both
@@ -92,5 +93,17 @@ struct AssemblyStructure {
 // Returns an MMSD_* status.
 int assemble_structure(const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats, AssemblyStructure* out,
                        std::string* err, bool with_patterns = true);
+
+// The host side of a problem whose operators were assembled on the device:
+// numbering, materials, the magnetic tets with their geometry (for later
+// material changes), the lumped volumes V (the device's, copied back), their
+// total and the anisotropy constant.  Consumes S's numbering and tet lists.
+// The operator arrays (K, D1, D2, Q, L, invd) stay empty.
+int assemble_host_side(const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats, AssemblyStructure* S,
+                       std::vector<double>&& V, Assembly* A, std::string* err);
+
+// The magnetic node -> (magnetic tet, vertex) lists that a material change
+// re-assembles from, built if absent (problems assembled on the device).
+void ensure_magnet_adjacency(Assembly* A);
 
 }  // namespace mmsd

@@ -494,20 +494,17 @@ int build_adjacency(const int32_t* d_tets, int64_t E, int64_t n, int32_t* ptr, i
   return MMSD_OK;
 }
 
-// Pattern of R rows: counts, row starts into rp[R + 1], and (when ci is
-// set) the columns; returns the entry count.  Before writing columns the
-// count must equal `capacity`, the caller's buffer size.
-int build_pattern_dev(PatternArgs pa, int32_t* cnt, int32_t* rp, int32_t* ci, int64_t capacity, hipStream_t st,
-                      int64_t* nnz) {
+// Pattern of R rows, first pass: counts and row starts into rp[R + 1];
+// returns the entry count.
+int pattern_count(PatternArgs pa, int32_t* cnt, int32_t* rp, hipStream_t st, int64_t* nnz) {
   pa.cnt = cnt;
   k_pattern<false><<<(unsigned)pa.R, kWave, 0, st>>>(pa);
   MMSD_HIP(hipGetLastError());
-  int rc = scan_counts(cnt, pa.R, rp, st, nnz, nullptr);
-  if (rc || !ci) return rc;
-  if (*nnz != capacity) {
-    set_error("device assembly: sizes[] does not hold this mesh's sizes (query them first)");
-    return MMSD_E_INVALID;
-  }
+  return scan_counts(cnt, pa.R, rp, st, nnz, nullptr);
+}
+
+// Second pass: the columns, ascending per row, into ci[rp[R]].
+int pattern_write(PatternArgs pa, const int32_t* rp, int32_t* ci, hipStream_t st) {
   pa.rp = rp;
   pa.ci = ci;
   k_pattern<true><<<(unsigned)pa.R, kWave, 0, st>>>(pa);
@@ -554,10 +551,15 @@ int scratch_address(int device, void** out) {
   return MMSD_OK;
 }
 
-int assemble_device_impl(mmsd_ctx c, const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats,
-                         int64_t sizes[4], int32_t* mrp, int32_t* mci, double* K, double* D1, double* D2,
-                         double* Q, double* V, int32_t* pot_global, int32_t* lrp, int32_t* lci, double* L,
-                         bool no_alloc) {
+enum class Outputs { QUERY, CALLER, OWNED };
+
+// The device assembly.  QUERY: sizes only.  CALLER: into the eleven device
+// arrays of `o`, sized by sizes[].  OWNED: `o`'s arrays are allocated here,
+// from the context's allocator, as their sizes become known (the caller
+// releases them).  S_keep, when set, receives the host structure.
+int assemble_device_run(mmsd_ctx c, const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats,
+                        int64_t sizes[4], DeviceAssembly* o, Outputs mode, bool no_alloc,
+                        AssemblyStructure* S_keep) {
   if (!c || !sizes) {
     set_error("null context or sizes");
     return MMSD_E_INVALID;
@@ -566,13 +568,7 @@ int assemble_device_impl(mmsd_ctx c, const mmsd_mesh* mesh, const mmsd_material*
     set_error("bad material table");
     return MMSD_E_INVALID;
   }
-  const void* outs[11] = {mrp, mci, K, D1, D2, Q, V, pot_global, lrp, lci, L};
-  const int given = (int)std::count_if(outs, outs + 11, [](const void* p) { return p != nullptr; });
-  if (given != 0 && given != 11) {
-    set_error("output pointers must be all null (size query) or all set");
-    return MMSD_E_INVALID;
-  }
-  const bool query = given == 0;
+  const bool query = mode == Outputs::QUERY;
   // host: validation, numbering, magnetic tets, material table
   AssemblyStructure S;
   std::string err;
@@ -584,7 +580,7 @@ int assemble_device_impl(mmsd_ctx c, const mmsd_mesh* mesh, const mmsd_material*
   const int64_t N = S.N, Nt = S.Nt, E = S.E, Em = (int64_t)S.mregion.size(), n_nodes = mesh->n_nodes;
   // the assemble call gets the query's sizes back: the output buffers' sizes
   const int64_t cap[4] = {sizes[0], sizes[1], sizes[2], sizes[3]};
-  if (!query && (cap[0] != N || cap[2] != Nt)) {
+  if (mode == Outputs::CALLER && (cap[0] != N || cap[2] != Nt)) {
     set_error("device assembly: sizes[] does not hold this mesh's sizes (query them first)");
     return MMSD_E_INVALID;
   }
@@ -613,49 +609,72 @@ int assemble_device_impl(mmsd_ctx c, const mmsd_mesh* mesh, const mmsd_material*
     heap_or_arena.reset(new Scratch(c));
   }
   Scratch& tmp = *heap_or_arena;
+  // an output array of n elements (OWNED mode)
+  auto own = [&](auto*& slot, size_t n) {
+    using T = std::remove_reference_t<decltype(*slot)>;
+    void* q = c->dalloc(std::max<size_t>(n, 1) * sizeof(T));
+    if (q) o->owned.push_back(q);
+    slot = (T*)q;
+    return q != nullptr;
+  };
+  auto nomem = [] {
+    set_error("device allocation failed (assembly)");
+    return MMSD_E_NOMEM;
+  };
+  auto mismatch = [] {
+    set_error("device assembly: sizes[] does not hold this mesh's sizes (query them first)");
+    return MMSD_E_INVALID;
+  };
   // device structure: adjacency and patterns
   int32_t* d_mtet = tmp.get<int32_t>(4 * (size_t)Em);
   int32_t* d_madj_ptr = tmp.get<int32_t>(N + 1);
   int32_t* d_madj = tmp.get<int32_t>(4 * (size_t)Em);
   int32_t* d_cur = tmp.get<int32_t>(std::max(n_nodes, std::max(N, Nt)));
   int32_t* d_rp = query ? tmp.get<int32_t>(std::max(N, Nt) + 1) : nullptr;
-  if (!d_mtet || !d_madj_ptr || !d_madj || !d_cur || (query && !d_rp)) {
-    set_error("device allocation failed (assembly temporaries)");
-    return MMSD_E_NOMEM;
-  }
+  if (!d_mtet || !d_madj_ptr || !d_madj || !d_cur || (query && !d_rp)) return nomem();
+  if (mode == Outputs::OWNED && (!own(o->mrp, N + 1) || !own(o->lrp, Nt + 1))) return nomem();
   MMSD_HIP(put(d_mtet, S.mtet, st));
   if ((rc = build_adjacency(d_mtet, Em, N, d_madj_ptr, d_madj, d_cur, st))) return rc;
   int64_t nnzM = 0, nnzL = 0;
   PatternArgs pm{(int)N, nullptr, d_madj_ptr, d_madj, d_mtet, nullptr, nullptr, nullptr, nullptr};
-  if ((rc = build_pattern_dev(pm, d_cur, query ? d_rp : mrp, query ? nullptr : mci, cap[1], st, &nnzM))) return rc;
+  if ((rc = pattern_count(pm, d_cur, query ? d_rp : o->mrp, st, &nnzM))) return rc;
+  if (mode == Outputs::CALLER && nnzM != cap[1]) return mismatch();
+  if (mode == Outputs::OWNED && !own(o->mci, nnzM)) return nomem();
+  if (!query && (rc = pattern_write(pm, o->mrp, o->mci, st))) return rc;
   int32_t *d_tets = nullptr, *d_tptr = nullptr, *d_tlst = nullptr, *d_pot_of = nullptr, *d_pot_global = nullptr;
   d_tets = tmp.get<int32_t>(4 * (size_t)E);
-  if (!d_tets) {
-    set_error("device allocation failed (assembly temporaries)");
-    return MMSD_E_NOMEM;
-  }
+  if (!d_tets) return nomem();
   MMSD_HIP(hipMemcpyAsync(d_tets, mesh->tets, 4 * E * sizeof(int32_t), hipMemcpyHostToDevice, st));
   if (Nt > 0) {
     d_tptr = tmp.get<int32_t>(n_nodes + 1);
     d_tlst = tmp.get<int32_t>(4 * (size_t)E);
     d_pot_of = tmp.get<int32_t>(n_nodes);
-    d_pot_global = query ? tmp.get<int32_t>(Nt) : pot_global;
-    if (!d_tptr || !d_tlst || !d_pot_of || !d_pot_global) {
-      set_error("device allocation failed (assembly temporaries)");
-      return MMSD_E_NOMEM;
-    }
+    if (mode == Outputs::OWNED && !own(o->pot_global, Nt)) return nomem();
+    d_pot_global = query ? tmp.get<int32_t>(Nt) : o->pot_global;
+    if (!d_tptr || !d_tlst || !d_pot_of || !d_pot_global) return nomem();
     MMSD_HIP(put(d_pot_of, S.pot_of, st));
     MMSD_HIP(put(d_pot_global, S.pot_global, st));
     if ((rc = build_adjacency(d_tets, E, n_nodes, d_tptr, d_tlst, d_cur, st))) return rc;
     PatternArgs pp{(int)Nt, d_pot_global, d_tptr, d_tlst, d_tets, d_pot_of, nullptr, nullptr, nullptr};
-    if ((rc = build_pattern_dev(pp, d_cur, query ? d_rp : lrp, query ? nullptr : lci, cap[3], st, &nnzL)))
-      return rc;
+    if ((rc = pattern_count(pp, d_cur, query ? d_rp : o->lrp, st, &nnzL))) return rc;
+    if (mode == Outputs::CALLER && nnzL != cap[3]) return mismatch();
+    if (mode == Outputs::OWNED && !own(o->lci, nnzL)) return nomem();
+    if (!query && (rc = pattern_write(pp, o->lrp, o->lci, st))) return rc;
   }
   sizes[0] = N;
   sizes[1] = nnzM;
   sizes[2] = Nt;
   sizes[3] = nnzL;
   if (query) return MMSD_OK;
+  if (mode == Outputs::OWNED) {
+    o->N = N;
+    o->nnzM = nnzM;
+    o->Nt = Nt;
+    o->nnzL = nnzL;
+    if (!own(o->K, nnzM) || !own(o->D1, 3 * (size_t)nnzM) || !own(o->D2, 3 * (size_t)nnzM) ||
+        !own(o->Q, 6 * (size_t)N) || !own(o->V, N) || !own(o->L, nnzL))
+      return nomem();
+  }
 
   // geometry, shell metric and validity of every tet
   double* d_xyz = tmp.get<double>(3 * (size_t)n_nodes);
@@ -664,10 +683,7 @@ int assemble_device_impl(mmsd_ctx c, const mmsd_mesh* mesh, const mmsd_material*
   int32_t* d_mtet_mesh = tmp.get<int32_t>(Em);
   int32_t* d_mregion = tmp.get<int32_t>(Em);
   double* d_reg = tmp.get<double>(S.reg.size());
-  if (!d_xyz || !d_geo || !d_flag || !d_mtet_mesh || !d_mregion || !d_reg) {
-    set_error("device allocation failed (assembly temporaries)");
-    return MMSD_E_NOMEM;
-  }
+  if (!d_xyz || !d_geo || !d_flag || !d_mtet_mesh || !d_mregion || !d_reg) return nomem();
   MMSD_HIP(hipMemcpyAsync(d_xyz, mesh->xyz, 3 * n_nodes * sizeof(double), hipMemcpyHostToDevice, st));
   ShellDev sh{};
   sh.on = mesh->shell != nullptr;
@@ -698,17 +714,14 @@ int assemble_device_impl(mmsd_ctx c, const mmsd_mesh* mesh, const mmsd_material*
   MMSD_HIP(put(d_mtet_mesh, S.mtet_mesh, st));
   MMSD_HIP(put(d_mregion, S.mregion, st));
   MMSD_HIP(put(d_reg, S.reg, st));
-  MagnetArgs ma{(int)N, nnzM, mrp, mci, d_madj_ptr, d_madj, d_mtet, d_mtet_mesh, d_mregion, d_reg, d_geo,
-                S.mu0Ms2, K, D1, D2, Q, V};
+  MagnetArgs ma{(int)N, nnzM, o->mrp, o->mci, d_madj_ptr, d_madj, d_mtet, d_mtet_mesh, d_mregion, d_reg, d_geo,
+                S.mu0Ms2, o->K, o->D1, o->D2, o->Q, o->V};
   k_asm_magnet<<<(unsigned)N, kWave, 0, st>>>(ma);
   MMSD_HIP(hipGetLastError());
   if (Nt > 0) {
     unsigned char* d_bad = tmp.get<unsigned char>(Nt);
-    if (!d_bad) {
-      set_error("device allocation failed (assembly temporaries)");
-      return MMSD_E_NOMEM;
-    }
-    PotentialArgs pa{(int)Nt, lrp, lci, pot_global, d_pot_of, d_tptr, d_tlst, d_tets, d_geo, L, d_bad};
+    if (!d_bad) return nomem();
+    PotentialArgs pa{(int)Nt, o->lrp, o->lci, o->pot_global, d_pot_of, d_tptr, d_tlst, d_tets, d_geo, o->L, d_bad};
     k_asm_potential<<<(unsigned)Nt, kWave, 0, st>>>(pa);
     MMSD_HIP(hipGetLastError());
     std::vector<unsigned char> bad(Nt);
@@ -722,13 +735,140 @@ int assemble_device_impl(mmsd_ctx c, const mmsd_mesh* mesh, const mmsd_material*
   } else {
     // no potential problem: lrp still holds its single zero
     static const int32_t zero = 0;
-    MMSD_HIP(hipMemcpyAsync(lrp, &zero, sizeof(int32_t), hipMemcpyHostToDevice, st));
+    MMSD_HIP(hipMemcpyAsync(o->lrp, &zero, sizeof(int32_t), hipMemcpyHostToDevice, st));
   }
   MMSD_HIP(hipStreamSynchronize(st));
+  if (S_keep) *S_keep = std::move(S);
   return MMSD_OK;
 }
 
+int assemble_device_impl(mmsd_ctx c, const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats,
+                         int64_t sizes[4], int32_t* mrp, int32_t* mci, double* K, double* D1, double* D2,
+                         double* Q, double* V, int32_t* pot_global, int32_t* lrp, int32_t* lci, double* L,
+                         bool no_alloc) {
+  const void* outs[11] = {mrp, mci, K, D1, D2, Q, V, pot_global, lrp, lci, L};
+  const int given = (int)std::count_if(outs, outs + 11, [](const void* p) { return p != nullptr; });
+  if (given != 0 && given != 11) {
+    set_error("output pointers must be all null (size query) or all set");
+    return MMSD_E_INVALID;
+  }
+  DeviceAssembly o;
+  o.mrp = mrp;
+  o.mci = mci;
+  o.K = K;
+  o.D1 = D1;
+  o.D2 = D2;
+  o.Q = Q;
+  o.V = V;
+  o.pot_global = pot_global;
+  o.lrp = lrp;
+  o.lci = lci;
+  o.L = L;
+  return assemble_device_run(c, mesh, mats, n_mats, sizes, &o, given == 0 ? Outputs::QUERY : Outputs::CALLER,
+                             no_alloc, nullptr);
+}
+
 }  // namespace
+}  // namespace mmsd
+
+// ---- device-assembled operators into a problem's arena ----------------------
+
+namespace mmsd {
+namespace {
+
+template <typename real>
+__global__ __launch_bounds__(kAsmBlock) void k_to_real(const double* __restrict__ src, real* __restrict__ dst,
+                                                        int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kAsmBlock + threadIdx.x;
+  if (i < n) dst[i] = (real)src[i];
+}
+
+// The potential matrix into the 64-row sliced layout: one thread per row of
+// the padded slices.  Slice s holds w_s = (so[s+1] - so[s]) / 64 columns
+// per row, column k of its row r at so[s] + 64 k + r; a row's entries past
+// its length (and the rows past the last) get column min(row, n - 1) and
+// value 0.  Each real row also gets its FP64 row sum and the reciprocal of
+// its diagonal, written into the d field of both CG record buffers.
+template <typename real>
+__global__ __launch_bounds__(kAsmBlock) void k_slice_rows(const int32_t* __restrict__ rp,
+                                                           const int32_t* __restrict__ ci,
+                                                           const double* __restrict__ v,
+                                                           const int32_t* __restrict__ so, int64_t n,
+                                                           int32_t* __restrict__ sc, real* __restrict__ sv,
+                                                           real* __restrict__ lsum, real* __restrict__ rec0,
+                                                           real* __restrict__ rec1) {
+  const int64_t i = (int64_t)blockIdx.x * kAsmBlock + threadIdx.x;
+  const int64_t sl = i >> 6;
+  if (sl >= (n + 63) / 64) return;
+  const int r = (int)(i & 63);
+  const int w = (so[sl + 1] - so[sl]) / 64;
+  const int a = i < n ? rp[i] : 0, len = i < n ? rp[i + 1] - a : 0;
+  const int pad = (int)(i < n - 1 ? i : n - 1);
+  double sum = 0, dinv = 0;
+  for (int k = 0; k < w; ++k) {
+    const int64_t q = so[sl] + 64LL * k + r;
+    if (k < len) {
+      const int c = ci[a + k];
+      const double x = v[a + k];
+      sc[q] = c;
+      sv[q] = (real)x;
+      sum += x;
+      if (c == i) dinv = 1.0 / x;
+    } else {
+      sc[q] = pad;
+      sv[q] = (real)0;
+    }
+  }
+  if (i < n) {
+    lsum[i] = (real)sum;
+    rec0[4 * i + 3] = (real)dinv;
+    rec1[4 * i + 3] = (real)dinv;
+  }
+}
+
+}  // namespace
+
+template <typename real>
+hipError_t launch_to_real(const double* src, real* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_to_real<real><<<grid_of(n), kAsmBlock, 0, s>>>(src, dst, n);
+  return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_slice_rows(const int32_t* rp, const int32_t* ci, const double* v, const int32_t* so, int64_t n,
+                             int32_t* sc, real* sv, real* lsum, real* rec0, real* rec1, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_slice_rows<real><<<grid_of(64 * ((n + 63) / 64)), kAsmBlock, 0, s>>>(rp, ci, v, so, n, sc, sv, lsum, rec0, rec1);
+  return hipGetLastError();
+}
+
+template hipError_t launch_to_real<float>(const double*, float*, int64_t, hipStream_t);
+template hipError_t launch_to_real<double>(const double*, double*, int64_t, hipStream_t);
+template hipError_t launch_slice_rows<float>(const int32_t*, const int32_t*, const double*, const int32_t*, int64_t,
+                                             int32_t*, float*, float*, float*, float*, hipStream_t);
+template hipError_t launch_slice_rows<double>(const int32_t*, const int32_t*, const double*, const int32_t*,
+                                              int64_t, int32_t*, double*, double*, double*, double*, hipStream_t);
+
+}  // namespace mmsd
+
+namespace mmsd {
+
+void DeviceAssembly::release(mmsd_ctx_s* c) {
+  if (!owned.empty()) (void)hipStreamSynchronize(c->stream);
+  for (void* q : owned) c->dfree(q);
+  owned.clear();
+  *this = DeviceAssembly();
+}
+
+int assemble_device_owned(mmsd_ctx_s* c, const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats,
+                          DeviceAssembly* out, AssemblyStructure* S) {
+  int64_t sizes[4] = {0, 0, 0, 0};
+  const int rc = assemble_device_run(c, mesh, mats, n_mats, sizes, out, Outputs::OWNED, false, S);
+  if (rc) out->release(c);
+  return rc;
+}
+
 }  // namespace mmsd
 
 extern "C" int mmsd_assemble_device(mmsd_ctx c, const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats,

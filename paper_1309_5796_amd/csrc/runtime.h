@@ -15,6 +15,8 @@
 #include "device.h"
 #include "mmsd.h"
 
+struct mmsd_ctx_s;
+
 namespace mmsd {
 
 void set_error(const std::string& msg);
@@ -35,6 +37,31 @@ hipError_t launch_ctrl_init(Ctrl* ctrl, int slot, int stage, int terms, int nonm
                             const double* dparams, hipStream_t s);
 
 hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream_t s);
+
+// Operators assembled on the device into buffers the library allocated from
+// a context's allocator (FP64 values; the layouts of mmsd_assembly_export).
+struct DeviceAssembly {
+  int64_t N = 0, nnzM = 0, Nt = 0, nnzL = 0;
+  int32_t *mrp = nullptr, *mci = nullptr, *pot_global = nullptr, *lrp = nullptr, *lci = nullptr;
+  double *K = nullptr, *D1 = nullptr, *D2 = nullptr, *Q = nullptr, *V = nullptr, *L = nullptr;
+  std::vector<void*> owned;
+  void release(mmsd_ctx_s* c);   // waits for the context's stream, frees every owned buffer
+};
+// Validate, number and assemble on the device (mmsd_assemble_device's
+// kernels) into owned buffers; S receives the host structure.  Takes the
+// context's lock.  On failure nothing stays allocated.
+int assemble_device_owned(mmsd_ctx_s* c, const mmsd_mesh* mesh, const mmsd_material* mats, int n_mats,
+                          DeviceAssembly* out, AssemblyStructure* S);
+// FP64 -> real copy of n values (device to device).
+template <typename real>
+hipError_t launch_to_real(const double* src, real* dst, int64_t n, hipStream_t s);
+// CSR (rp, ci, v) of n rows into the 64-row sliced layout with the slice
+// offsets so[(n + 63) / 64 + 1] (every slice as wide as its longest row),
+// plus the FP64 row sums (lsum) and the diagonal's reciprocal in the d field
+// of the two CG record buffers (rec0, rec1: 4 reals per row).
+template <typename real>
+hipError_t launch_slice_rows(const int32_t* rp, const int32_t* ci, const double* v, const int32_t* so, int64_t n,
+                             int32_t* sc, real* sv, real* lsum, real* rec0, real* rec1, hipStream_t s);
 
 // Every batch of step launches starts with parity 0 and has an even length,
 // so the state a run is armed with goes into slot 1.
@@ -92,6 +119,7 @@ struct mmsd_ctx_s {
   int lpr = 4;
   int max_blocks = 512;
   int vcycle = MMSD_VC_FUSE_REST | MMSD_VC_FOLD_SOLVE;   // V-cycle forms for new problems
+  int assembly = MMSD_ASSEMBLE_HOST;                     // where new problems' operators are assembled
   bool use_graph = true;
   mmsd::TimingState timing;
   std::map<int64_t, std::pair<int, int>> tuned;   // autotuner results by problem class
@@ -133,4 +161,5 @@ struct mmsd_problem_s {
   mmsd::Ctrl* hctrl = nullptr;            // pinned mirrors [2 polls][2 slots]
   std::map<int, hipGraphExec_t> graphs;   // batch size -> instantiated graph
   int64_t last_launches = 0;
+  double setup_t[4] = {0, 0, 0, 0};       // creation: assembly, multigrid setup, device build, total (s)
 };

@@ -415,6 +415,7 @@ int mmsd_server_create(mmsd_ctx ctx, size_t hbm_budget, int max_slots, mmsd_serv
   if (!rc) {
     s->upload_ctx->lpr = s->loop_ctx->lpr = ctx->lpr;
     s->upload_ctx->max_blocks = s->loop_ctx->max_blocks = ctx->max_blocks;
+    s->upload_ctx->assembly = ctx->assembly;
     if (hipHostMalloc((void**)&s->hdone, sizeof(unsigned) * (2 + max_slots), hipHostMallocDefault) != hipSuccess)
       rc = MMSD_E_NOMEM;
   }
