@@ -21,6 +21,9 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     # packed FP32 instructions are disabled on purpose
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # kernel arguments arrive in SGPRs: the step kernel's first loads (its
+    # problem descriptor, control block and partials) need not wait for them
+    "-mllvm", "-amdgpu-kernarg-preload-count=8",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
     "-Wall", "-Wno-unused-result",
 ]

@@ -231,7 +231,7 @@ struct ProbT {
   Ptr<unsigned> ndone;        // nullable: incremented once when the problem finishes
   Ptr<int> done_list;         // nullable: receives `slot` at position ndone - 1
   int slot;
-  Ptr<double> part;           // [2][G][kNPart] per-block partials, by launch parity
+  Ptr<double> part;           // [2][kNPart][G] per-block partials (slot-major), by launch parity
   Ptr<Ctrl> ctrl;             // [2] control state, by launch parity
 };
 

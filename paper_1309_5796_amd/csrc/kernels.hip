@@ -28,24 +28,79 @@
 namespace mmsd {
 namespace {
 
+// Sums (and the max) over groups of W consecutive lanes of a wavefront,
+// the result in every lane of the group: a butterfly whose steps are VALU
+// cross-lane moves (CDNA4) instead of LDS permutes: quad permutations for
+// lane distances 1 and 2, the half-row and row mirrors for 4 and 8 (after
+// the earlier steps every lane of a quad, then of a half-row, holds the same
+// partial, so a mirror partner holds what the xor partner would), and the
+// 16- and 32-lane permlane swaps.  Each step adds two partials, so every
+// lane of the group ends with the same value.
+namespace xl {
+constexpr int kXor1 = 0xB1;        // quad_perm [1, 0, 3, 2]
+constexpr int kXor2 = 0x4E;        // quad_perm [2, 3, 0, 1]
+constexpr int kHalfMirror = 0x141; // row_half_mirror
+constexpr int kMirror = 0x140;     // row_mirror
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+// {lower, upper}: the values of lane l and of lane l ^ 16 (S = 16) or
+// l ^ 32 (S = 32), the one of the lower row (half) first
+template <int S>
+__device__ __forceinline__ void swap_pair(float x, float& a, float& b) {
+  const int v = __float_as_int(x);
+  const auto r = S == 16 ? __builtin_amdgcn_permlane16_swap(v, v, false, false)
+                         : __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  a = __int_as_float(r[0]);
+  b = __int_as_float(r[1]);
+}
+template <int S>
+__device__ __forceinline__ void swap_pair(double x, double& a, double& b) {
+  const int lo = __double2loint(x), hi = __double2hiint(x);
+  const auto rl = S == 16 ? __builtin_amdgcn_permlane16_swap(lo, lo, false, false)
+                          : __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto rh = S == 16 ? __builtin_amdgcn_permlane16_swap(hi, hi, false, false)
+                          : __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  a = __hiloint2double(rh[0], rl[0]);
+  b = __hiloint2double(rh[1], rl[1]);
+}
+template <typename T, int W, bool MAX>
+__device__ __forceinline__ T reduce(T v) {
+  auto op = [](T p, T q) { return MAX ? fmax(p, q) : p + q; };
+  if constexpr (W >= 2) v = op(v, dpp<kXor1>(v));
+  if constexpr (W >= 4) v = op(v, dpp<kXor2>(v));
+  if constexpr (W >= 8) v = op(v, dpp<kHalfMirror>(v));
+  if constexpr (W >= 16) v = op(v, dpp<kMirror>(v));
+  if constexpr (W >= 32) {
+    T a, b;
+    swap_pair<16>(v, a, b);
+    v = op(a, b);
+  }
+  if constexpr (W >= 64) {
+    T a, b;
+    swap_pair<32>(v, a, b);
+    v = op(a, b);
+  }
+  return v;
+}
+}  // namespace xl
+
 template <typename T, int W>
 __device__ __forceinline__ T group_sum(T v) {
-#pragma unroll
-  for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
-  return v;
+  return xl::reduce<T, W, false>(v);
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
+__device__ __forceinline__ double wave_sum(double v) { return xl::reduce<double, 64, false>(v); }
 
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
+__device__ __forceinline__ double wave_max(double v) { return xl::reduce<double, 64, true>(v); }
 
 // Explicit solution of the curvilinear step m+ = m - tau (m + m+)/2 x H
 // (eq. (8)): with a = (tau/2) H and c = a x m, m+ = m + 2 (c + a x c) / (1 + a.a).
@@ -414,6 +469,16 @@ __device__ void phase_cg(const ProbDev<real>& P, const Ctrl* C, int blk, double*
   }
 }
 
+// The level descriptors, copied to LDS by every block in the prologue
+// (their loads then travel with the control block's instead of after it).
+__shared__ __align__(16) unsigned char s_lev_raw[kMaxLevels * sizeof(MgLevelDev<double>)];
+static_assert(sizeof(MgLevelDev<double>) == sizeof(MgLevelDev<float>) && sizeof(MgLevelDev<double>) % 8 == 0,
+              "level descriptors are copied as 8-byte words");
+template <typename real>
+__device__ __forceinline__ const MgLevelDev<real>& lev_of(int l) {
+  return reinterpret_cast<const MgLevelDev<real>*>(s_lev_raw)[l];
+}
+
 // ---- multigrid-preconditioned CG ----
 // Lane-partial sum over row i of a CSR matrix of v[k] * g(column): column
 // indices and values first, then all the gathers, then the products.
@@ -497,30 +562,30 @@ template <int W>
 constexpr int kRowU = W >= 8 ? 8 : kUnroll;
 
 template <typename real, int W, typename G>
-__device__ __forceinline__ real a_row(DevRef<const MgLevelDev<real>> L, int i, int lane, bool nt, G&& g) {
+__device__ __forceinline__ real a_row(const MgLevelDev<real>& L, int i, int lane, bool nt, G&& g) {
   if constexpr (W == 1) return sell_row<real>(L.aso, L.asc, L.asv, i, nt, g);
   else return row_sum<real, W, kRowU<W>>(L.arp, L.aci, L.av, i, lane, g);
 }
 template <typename real, int W, typename G>
-__device__ __forceinline__ Pair<real> q_row(DevRef<const MgLevelDev<real>> L, int i, int lane, bool nt, G&& g) {
+__device__ __forceinline__ Pair<real> q_row(const MgLevelDev<real>& L, int i, int lane, bool nt, G&& g) {
   if constexpr (W == 1) return sell_row_q<real>(L.qso, L.qsc, L.qsv, L.qpo, L.qpv, i, nt, g);
   else return row_sum2<real, W, kUnroll>(L.qrp, L.qci, L.qv, i, lane, g);   // two values: half the batch
 }
 template <typename real, int W, typename G>
-__device__ __forceinline__ real r_row(DevRef<const MgLevelDev<real>> L, int i, int lane, bool nt, G&& g) {
+__device__ __forceinline__ real r_row(const MgLevelDev<real>& L, int i, int lane, bool nt, G&& g) {
   if constexpr (W == 1) return sell_row<real>(L.rso, L.rsc, L.rsv, i, nt, g);
   else return row_sum<real, W, kRowU<W>>(L.rrp, L.rci, L.rv, i, lane, g);
 }
 
 template <typename real, int W, typename G>
-__device__ __forceinline__ real m_row(DevRef<const MgLevelDev<real>> L, int i, int lane, G&& g) {
+__device__ __forceinline__ real m_row(const MgLevelDev<real>& L, int i, int lane, G&& g) {
   return row_sum<real, W, kRowU<W>>(L.mrp, L.mci, L.mv, i, lane, g);
 }
 
 // Rows of operation `op` on level l, block blk of the G blocks that share
 // them.
 template <typename real, int W>
-__device__ void mg_rows(const ProbDev<real>& P, const Ctrl* C, DevRef<const MgLevelDev<real>> L, int op, int l, int blk,
+__device__ void mg_rows(const ProbDev<real>& P, const Ctrl* C, const MgLevelDev<real>& L, int op, int l, int blk,
                         int G, double* acc) {
   constexpr int RPP = kBlock / W;
   const int lane = threadIdx.x & (W - 1);
@@ -532,9 +597,9 @@ __device__ void mg_rows(const ProbDev<real>& P, const Ctrl* C, DevRef<const MgLe
   const bool nt = P.stream != 0;
   int r0, r1, rs;
   if (op == MG_REST || op == MG_RESTM) {
-    DevPtr<real> __restrict__ bn = last ? P.bc : P.lev[l + 1].b;
-    DevPtr<real> __restrict__ wbn = last ? nullptr : P.lev[l + 1].wb;
-    DevPtr<const real> __restrict__ wdn = last ? nullptr : P.lev[l + 1].wd;
+    DevPtr<real> __restrict__ bn = last ? P.bc : lev_of<real>(l + 1).b;
+    DevPtr<real> __restrict__ wbn = last ? nullptr : lev_of<real>(l + 1).wb;
+    DevPtr<const real> __restrict__ wdn = last ? nullptr : lev_of<real>(l + 1).wd;
     DevPtr<const real> __restrict__ res = L.res;
     const bool m = op == MG_RESTM;   // b_{l+1} = M b, else R res
     chunk_rows(L.n_next, G, blk, RPP, W == 1 ? 64 : 1, r0, r1, rs);
@@ -566,7 +631,7 @@ __device__ void mg_rows(const ProbDev<real>& P, const Ctrl* C, DevRef<const MgLe
       if (valid && lane == 0) L.res[i] = bi - sum;
     }
   } else {   // MG_POST
-    DevPtr<const real> __restrict__ xn = last ? P.xc : P.lev[l + 1].xb;
+    DevPtr<const real> __restrict__ xn = last ? P.xc : lev_of<real>(l + 1).xb;
     DevPtr<const real> __restrict__ res = L.res;
     for (int base = r0; base < r1; base += rs) {
       const int i = base + slot;
@@ -597,7 +662,7 @@ __device__ void mg_rows(const ProbDev<real>& P, const Ctrl* C, DevRef<const MgLe
 
 // The row layout of an operation's matrix picks the kernel variant.
 template <typename real>
-__device__ __forceinline__ void mg_dispatch(const ProbDev<real>& P, const Ctrl* C, DevRef<const MgLevelDev<real>> L, int op, int l,
+__device__ __forceinline__ void mg_dispatch(const ProbDev<real>& P, const Ctrl* C, const MgLevelDev<real>& L, int op, int l,
                             int blk, int G, double* acc) {
   const int lanes = op == MG_REST    ? L.lanes_r
                     : op == MG_RESTM ? L.lanes_m
@@ -623,7 +688,7 @@ __device__ __forceinline__ void mg_dispatch(const ProbDev<real>& P, const Ctrl* 
 // streamed coalesced by the whole block, wavefront sums, then the waves in
 // order.
 template <typename real>
-__device__ void coarse_rows(const ProbDev<real>& P, DevRef<const MgLevelDev<real>> L, int blk, int G) {
+__device__ void coarse_rows(const ProbDev<real>& P, const MgLevelDev<real>& L, int blk, int G) {
   __shared__ double s_row[kBlock / 64];
   const int nc = P.nc, n = L.n;
   DevPtr<const real> __restrict__ b = L.b;
@@ -665,7 +730,7 @@ __device__ void phase_mg(const ProbDev<real>& P, const Ctrl* C, int blk, double*
     }
     return;
   }
-  DevRef<const MgLevelDev<real>> L = P.lev[l];
+  const MgLevelDev<real>& L = lev_of<real>(l);
   int o = op, b = blk, g = P.G, passes = 1;
   if (op == MG_DOWN && L.m_blocks > 0) {
     // fused restriction: the last gm blocks sweep M, the others A; with
@@ -706,7 +771,7 @@ __device__ void phase_pcg_a(const ProbDev<real>& P, const Ctrl* C, int blk, doub
   const bool first = C->beta == 0.0;
   DevPtr<const Pair<real>> __restrict__ zp = P.zp;
   DevPtr<const real> __restrict__ r = P.r2[C->rcur];
-  DevPtr<const real> __restrict__ wd = P.lev[0].wd;
+  DevPtr<const real> __restrict__ wd = lev_of<real>(0).wd;
   for (int base = r0; base < r1; base += rs) {
     const int i = base + threadIdx.x;
     if (i >= r1) continue;
@@ -757,7 +822,7 @@ __device__ void phase_pcg_b(const ProbDev<real>& P, const Ctrl* C, int blk, doub
     const real ui = uo + alpha * pi;
     rn[i] = ri;
     U[i] = ui;
-    P.lev[0].res[i] = ri - sum;
+    lev_of<real>(0).res[i] = ri - sum;
     acc[0] += (double)ri * (double)ri;
     acc[1] += (double)ri * (double)ui;
   }
@@ -1164,7 +1229,8 @@ __device__ void enter_prep(Ctrl* C) {
 }
 
 // Advance the state by the outcome of the phase it records (v: the finished
-// reductions of that phase's partials).
+// reductions of that phase's partials); the phases of the potential solve's
+// iterations are advanced by transition_fast() below.
 __device__ void transition_phase(Ctrl* C, const double* v, const double* btab, int n_lev, int fused, bool folded) {
   C->seq++;
   const int phase = C->phase;
@@ -1198,60 +1264,6 @@ __device__ void transition_phase(Ctrl* C, const double* v, const double* btab, i
         C->phase = PH_CG0;
       }
       return;
-    case PH_MG:
-      switch (C->mg_op) {
-        case MG_DOWN:
-          if (!((fused >> C->mg_lev) & 1)) {
-            C->mg_op = MG_REST;
-            return;
-          }
-          [[fallthrough]];   // this DOWN also restricted
-        case MG_REST:
-          if (C->mg_lev + 1 < n_lev) {
-            C->mg_lev++;
-            C->mg_op = MG_DOWN;
-          } else if (folded) {   // the last DOWN also solved the coarsest level
-            C->mg_op = MG_POST;
-          } else {
-            C->mg_op = MG_SOLVE;
-            C->mg_lev = 0;
-          }
-          return;
-        case MG_SOLVE:
-          C->mg_lev = n_lev - 1;
-          C->mg_op = MG_POST;
-          return;
-        default:   // MG_POST
-          if (C->mg_lev > 0) {
-            C->mg_lev--;
-            return;
-          }
-          // z = M r is complete: next search direction
-          C->beta = C->mg_first ? 0.0 : v[0] / C->gam;
-          C->gam = v[0];
-          C->mg_first = 0;
-          C->phase = PH_PCG_A;
-          return;
-      }
-    case PH_PCG_A:
-      C->alpha = C->gam / v[0];
-      C->pcur ^= 1;
-      C->phase = PH_PCG_B;
-      return;
-    case PH_PCG_B:
-      C->rr = v[0];
-      C->ru = v[1];
-      C->rcur ^= 1;
-      C->pcg_it++;
-      C->pcg_total++;
-      if (C->rr <= C->pcg_rtol2 * C->bb || C->pcg_it >= C->pcg_maxit) {
-        C->phase = PH_FIELD;
-      } else {   // the finest pre-smoothing residual is already done
-        C->phase = PH_MG;
-        C->mg_op = MG_REST;
-        C->mg_lev = 0;
-      }
-      return;
     case PH_CG0:
       C->gam = v[0];
       C->dlt = v[1];
@@ -1281,12 +1293,76 @@ __device__ void transition_phase(Ctrl* C, const double* v, const double* btab, i
   }
 }
 
+// The transitions inside the potential solve (after a V-cycle operation or
+// one of the two PCG phases: every launch of a PCG iteration), in a short
+// inline path of their own: the general transition is long, and each launch
+// starts with a cold instruction cache.  Returns false for every other
+// phase.
+__device__ __forceinline__ bool transition_fast(Ctrl* C, const double* v, const double* btab, int n_lev, int fused,
+                                                bool folded) {
+  const int phase = C->phase;
+  if (phase != PH_MG && phase != PH_PCG_A && phase != PH_PCG_B) return false;
+  C->seq++;
+  C->launches_done++;
+  if (btab) C->alg_bytes += btab[byte_slot(phase, C->mg_op, C->mg_lev)];
+  if (phase == PH_MG) {
+    C->nphase[1]++;
+    const int op = C->mg_op, lev = C->mg_lev;
+    if (op == MG_DOWN && !((fused >> lev) & 1)) {
+      C->mg_op = MG_REST;
+    } else if (op == MG_DOWN || op == MG_REST) {
+      if (lev + 1 < n_lev) {
+        C->mg_lev = lev + 1;
+        C->mg_op = MG_DOWN;
+      } else if (folded) {
+        C->mg_op = MG_POST;
+      } else {
+        C->mg_op = MG_SOLVE;
+        C->mg_lev = 0;
+      }
+    } else if (op == MG_SOLVE) {
+      C->mg_lev = n_lev - 1;
+      C->mg_op = MG_POST;
+    } else if (lev > 0) {
+      C->mg_lev = lev - 1;
+    } else {
+      C->beta = C->mg_first ? 0.0 : v[0] / C->gam;
+      C->gam = v[0];
+      C->mg_first = 0;
+      C->phase = PH_PCG_A;
+    }
+    return true;
+  }
+  C->nphase[2]++;
+  if (phase == PH_PCG_A) {
+    C->alpha = C->gam / v[0];
+    C->pcur ^= 1;
+    C->phase = PH_PCG_B;
+    return true;
+  }
+  C->rr = v[0];
+  C->ru = v[1];
+  C->rcur ^= 1;
+  C->pcg_it++;
+  C->pcg_total++;
+  if (C->rr <= C->pcg_rtol2 * C->bb || C->pcg_it >= C->pcg_maxit) {
+    C->phase = PH_FIELD;
+  } else {
+    C->phase = PH_MG;
+    C->mg_op = MG_REST;
+    C->mg_lev = 0;
+  }
+  return true;
+}
+
+// Every other transition (PREP, the Jacobi-CG phases, FIELD's step logic).
 __device__ void transition(Ctrl* C, const double* v, const double* btab, int n_lev, int fused, bool folded) {
   transition_phase(C, v, btab, n_lev, fused, folded);
   if (C->phase == PH_PREP) enter_prep(C);
 }
 
-// out[k] = sum (max for the torque slot) over the G block partials of slot k.
+// out[k] = sum (max for the torque slot) over the G block partials of slot k
+// (stored slot-major: the G partials of one slot are contiguous).
 // Wavefront w takes slots w, w + 8, ...; lanes stride over the blocks, then a
 // butterfly combines them: the same fixed order in every block.  Slots 0 and
 // 1 were already fetched (`pre`, by waves 0 and 1) together with the control
@@ -1305,7 +1381,7 @@ __device__ void reduce_partials(DevPtr<const double> src, int G, int np, int pha
       }
     } else {
       for (int q = lid; q < G; q += 64) {
-        const double x = src[(size_t)q * kNPart + k];
+        const double x = src[(size_t)k * G + q];
         v = mx ? fmax(v, x) : v + x;
       }
     }
@@ -1349,7 +1425,7 @@ __device__ __forceinline__ void run_phase(const ProbDev<real>& P, const Ctrl* C,
     const bool mx = (PHASE == PH_FIELD && k == FP_TMAX);
     double v = s_red[0][k];
     for (int w = 1; w < kBlock / 64; ++w) v = mx ? fmax(v, s_red[w][k]) : v + s_red[w][k];
-    P.part[((size_t)parity * P.G + lb) * kNPart + k] = v;
+    P.part[((size_t)parity * kNPart + k) * P.G + lb] = v;
   }
 }
 
@@ -1388,13 +1464,17 @@ __global__ void __launch_bounds__(kBlock, 4) k_step(const ProbDev<real>* __restr
 #pragma unroll
     for (int u = 0; u < kPreParts; ++u) {
       const int q = lid + 64 * u;
-      pre[u] = (wid < 2 && q < P.G) ? part_prev[(size_t)q * kNPart + wid] : 0.0;
+      pre[u] = (wid < 2 && q < P.G) ? part_prev[(size_t)wid * P.G + q] : 0.0;
     }
     DevPtr<const long long> src = reinterpret_cast<DevPtr<const long long>>(P.ctrl + prev);
     long long* dst = reinterpret_cast<long long*>(&s_c);
     for (int w = threadIdx.x; w < (int)(sizeof(Ctrl) / 8); w += kBlock) dst[w] = src[w];
     if (lb == 0)
       for (int w = threadIdx.x; w < kByteSlots; w += kBlock) s_btab[w] = P.btab[w];
+    DevPtr<const long long> ls = reinterpret_cast<DevPtr<const long long>>(P.lev);
+    long long* ldst = reinterpret_cast<long long*>(s_lev_raw);
+    const int lwords = P.n_lev * (int)(sizeof(MgLevelDev<real>) / 8);
+    for (int w = threadIdx.x; w < lwords; w += kBlock) ldst[w] = ls[w];
   }
   __syncthreads();
   const int ran = s_c.phase;
@@ -1402,7 +1482,8 @@ __global__ void __launch_bounds__(kBlock, 4) k_step(const ProbDev<real>* __restr
   if (np_prev > 0) reduce_partials(part_prev, P.G, np_prev, ran, pre, s_tot);
   __syncthreads();
   if (threadIdx.x == 0) {
-    transition(&s_c, s_tot, lb == 0 ? s_btab : nullptr, P.n_lev, P.mg_fused, P.AinvM != nullptr);
+    if (!transition_fast(&s_c, s_tot, lb == 0 ? s_btab : nullptr, P.n_lev, P.mg_fused, P.AinvM != nullptr))
+      transition(&s_c, s_tot, lb == 0 ? s_btab : nullptr, P.n_lev, P.mg_fused, P.AinvM != nullptr);
     s_newly_done = (ran != PH_DONE && s_c.phase == PH_DONE);
   }
   __syncthreads();
