@@ -201,6 +201,27 @@ static void fused_shape(int64_t nA, double avgA, int wa, int64_t nR, double avgR
   if (best >= separate) m_blocks = 0;
 }
 
+// Shape of the last DOWN when it also forms the coarsest solution (Ainv M
+// folded in): the dense rows of Ainv M take one block each per pass (the
+// whole block streams a row), so the split of the 512 blocks and A's lanes
+// per row are chosen together for the fewest round trips of the slower
+// part (on ties: the most blocks for the dense rows).  On the 80 nm cube
+// this gives each of the 384 dense rows a block of its own, A at 16 lanes.
+static void folded_shape(int64_t nA, double avgA, int64_t nc, int& wa, int& m_blocks) {
+  int64_t best = INT64_MAX;
+  for (int64_t gd = 8; gd <= 504; gd += 8) {
+    const int64_t gm = 512 - gd, cm = 2 * ((nc + gm - 1) / gm);
+    for (int W : {4, 8, 16, 32}) {
+      const int64_t c = std::max(sweep_cost(nA, avgA, gd, W), cm);
+      if (c < best || (c == best && gm > m_blocks)) {
+        best = c;
+        wa = W;
+        m_blocks = (int)gm;
+      }
+    }
+  }
+}
+
 // Largest dense Ainv M (coarsest size x last level's rows) folded into the
 // last DOWN.
 constexpr double kMaxFoldedBytes = 64.0 * (1 << 20);
@@ -517,6 +538,7 @@ int build_amg(mmsd_problem p) {
   // and the dense product Ainv M is small: x_c = (Ainv M) b
   std::vector<double> ainv_m;
   p->amg_folded = false;
+  int wa_last = 0;   // A's lanes on the last level when the solve is folded (0: the default)
   if ((c->vcycle & MMSD_VC_FOLD_SOLVE) && nl >= 2 && mblk[nl - 1] > 0 &&
       (double)H.nc * H.lv[nl - 1].A.nrows * s <= kMaxFoldedBytes) {
     const Csr& Ml = M[nl - 1];
@@ -532,6 +554,9 @@ int build_amg(mmsd_problem p) {
       }
     });
     p->amg_folded = true;
+    const AmgLevel& Ll = H.lv[nl - 1];
+    if (sl[nl - 1][0].so.empty())
+      folded_shape(Ll.A.nrows, (double)Ll.A.ci.size() / Ll.A.nrows, H.nc, wa_last, mblk[nl - 1]);
   }
   for (int l = 1; l < nl; ++l) {
     if (mblk[l] > 0 && !(p->amg_folded && l == nl - 1)) p->amg_m_nnz[l] = (int64_t)M[l].ci.size();
@@ -648,7 +673,7 @@ int build_amg(mmsd_problem p) {
     d.rsv = sv[2];
     d.n = L.A.nrows;
     d.n_next = L.P.ncols;
-    d.lanes_a = model_lanes(L.A);
+    d.lanes_a = (l == nl - 1 && wa_last) ? wa_last : model_lanes(L.A);
     d.lanes_q = model_lanes(Q[l]);
     d.lanes_r = model_lanes(L.R);
     d.lanes_m = wm[l];

@@ -557,7 +557,9 @@ __device__ __forceinline__ Pair<real> row_sum2(DevPtr<const int> __restrict__ rp
 // (one thread per row) reads the operation's matrix in the sliced layout,
 // in which matrices with many short rows are held (the level-0 operator is
 // the potential matrix).  A lane loads 8 entries per batch with 8 or more lanes (matrices
-// with long rows), kUnroll with 4.
+// with long rows), kUnroll with 4 (8 for Q's value pairs: the 39k-row level-1
+// post-smoothing of the 80 nm cube then takes one batch per row, 0.5 us
+// faster; R and A at 4 lanes measured no faster with 8).
 template <int W>
 constexpr int kRowU = W >= 8 ? 8 : kUnroll;
 
@@ -569,7 +571,7 @@ __device__ __forceinline__ real a_row(const MgLevelDev<real>& L, int i, int lane
 template <typename real, int W, typename G>
 __device__ __forceinline__ Pair<real> q_row(const MgLevelDev<real>& L, int i, int lane, bool nt, G&& g) {
   if constexpr (W == 1) return sell_row_q<real>(L.qso, L.qsc, L.qsv, L.qpo, L.qpv, i, nt, g);
-  else return row_sum2<real, W, kUnroll>(L.qrp, L.qci, L.qv, i, lane, g);   // two values: half the batch
+  else return row_sum2<real, W, W == 4 ? 8 : kUnroll>(L.qrp, L.qci, L.qv, i, lane, g);   // two values per entry
 }
 template <typename real, int W, typename G>
 __device__ __forceinline__ real r_row(const MgLevelDev<real>& L, int i, int lane, bool nt, G&& g) {
@@ -708,8 +710,7 @@ __device__ void coarse_rows(const ProbDev<real>& P, const MgLevelDev<real>& L, i
 }
 
 template <typename real, int LPR>
-__device__ void phase_mg(const ProbDev<real>& P, const Ctrl* C, int blk, double* acc) {
-  const int op = C->mg_op, l = C->mg_lev;
+__device__ void phase_mg(const ProbDev<real>& P, const Ctrl* C, int op, int l, int blk, double* acc) {
   if (op == MG_SOLVE) {
     // dense coarsest solve: one row per block at a time, the whole block
     // streams the row coalesced, then wavefront sums and the waves in order
@@ -1293,6 +1294,39 @@ __device__ void transition_phase(Ctrl* C, const double* v, const double* btab, i
   }
 }
 
+// The V-cycle operation after (op, lev), in (nop, nlev); false after the
+// post-smoothing of level 0, which completes z = M r.
+__device__ __forceinline__ bool mg_next(int op, int lev, int n_lev, int fused, bool folded, int& nop, int& nlev) {
+  nop = op;
+  nlev = lev;
+  if (op == MG_DOWN && !((fused >> lev) & 1)) {
+    nop = MG_REST;
+    return true;
+  }
+  if (op == MG_DOWN || op == MG_REST) {   // a fused DOWN also restricted
+    if (lev + 1 < n_lev) {
+      nlev = lev + 1;
+      nop = MG_DOWN;
+    } else if (folded) {   // the last DOWN also solved the coarsest level
+      nop = MG_POST;
+    } else {
+      nop = MG_SOLVE;
+      nlev = 0;
+    }
+    return true;
+  }
+  if (op == MG_SOLVE) {
+    nlev = n_lev - 1;
+    nop = MG_POST;
+    return true;
+  }
+  if (lev > 0) {
+    nlev = lev - 1;
+    return true;
+  }
+  return false;
+}
+
 // The transitions inside the potential solve (after a V-cycle operation or
 // one of the two PCG phases: every launch of a PCG iteration), in a short
 // inline path of their own: the general transition is long, and each launch
@@ -1307,25 +1341,11 @@ __device__ __forceinline__ bool transition_fast(Ctrl* C, const double* v, const 
   if (btab) C->alg_bytes += btab[byte_slot(phase, C->mg_op, C->mg_lev)];
   if (phase == PH_MG) {
     C->nphase[1]++;
-    const int op = C->mg_op, lev = C->mg_lev;
-    if (op == MG_DOWN && !((fused >> lev) & 1)) {
-      C->mg_op = MG_REST;
-    } else if (op == MG_DOWN || op == MG_REST) {
-      if (lev + 1 < n_lev) {
-        C->mg_lev = lev + 1;
-        C->mg_op = MG_DOWN;
-      } else if (folded) {
-        C->mg_op = MG_POST;
-      } else {
-        C->mg_op = MG_SOLVE;
-        C->mg_lev = 0;
-      }
-    } else if (op == MG_SOLVE) {
-      C->mg_lev = n_lev - 1;
-      C->mg_op = MG_POST;
-    } else if (lev > 0) {
-      C->mg_lev = lev - 1;
-    } else {
+    int nop, nlev;
+    if (mg_next(C->mg_op, C->mg_lev, n_lev, fused, folded, nop, nlev)) {
+      C->mg_op = nop;
+      C->mg_lev = nlev;
+    } else {   // z = M r is complete: next search direction
       C->beta = C->mg_first ? 0.0 : v[0] / C->gam;
       C->gam = v[0];
       C->mg_first = 0;
@@ -1396,7 +1416,7 @@ __device__ void reduce_partials(DevPtr<const double> src, int G, int np, int pha
 // each phase is register-allocated on its own.
 template <typename real, int LPR, int PHASE>
 __device__ __forceinline__ void run_phase(const ProbDev<real>& P, const Ctrl* C, int lb, int parity,
-                                          double (*s_red)[kNPart]) {
+                                          double (*s_red)[kNPart], int mop = 0, int mlev = 0) {
   constexpr int NA = PHASE == PH_FIELD ? kNPart : PHASE == PH_PREP ? 3 : PHASE == PH_MG ? 1 : 4;
   double acc[NA];
 #pragma unroll
@@ -1405,11 +1425,11 @@ __device__ __forceinline__ void run_phase(const ProbDev<real>& P, const Ctrl* C,
   else if constexpr (PHASE == PH_CG0) phase_cg0<real, LPR>(P, C, lb, acc);
   else if constexpr (PHASE == PH_CG) phase_cg<real, LPR>(P, C, lb, acc);
   else if constexpr (PHASE == PH_FIELD) phase_field<real, LPR>(P, C, lb, acc);
-  else if constexpr (PHASE == PH_MG) phase_mg<real, LPR>(P, C, lb, acc);
+  else if constexpr (PHASE == PH_MG) phase_mg<real, LPR>(P, C, mop, mlev, lb, acc);
   else if constexpr (PHASE == PH_PCG_A) phase_pcg_a<real, LPR>(P, C, lb, acc);
   else phase_pcg_b<real, LPR>(P, C, lb, acc);
 
-  const int np = n_parts(PHASE, C->mg_op, C->mg_lev);
+  const int np = n_parts(PHASE, mop, mlev);
   if (np == 0) return;
   const int wid = threadIdx.x >> 6, lid = threadIdx.x & 63;
 #pragma unroll
@@ -1478,23 +1498,40 @@ __global__ void __launch_bounds__(kBlock, 4) k_step(const ProbDev<real>* __restr
   }
   __syncthreads();
   const int ran = s_c.phase;
-  const int np_prev = n_parts(ran, s_c.mg_op, s_c.mg_lev);
-  if (np_prev > 0) reduce_partials(part_prev, P.G, np_prev, ran, pre, s_tot);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    if (!transition_fast(&s_c, s_tot, lb == 0 ? s_btab : nullptr, P.n_lev, P.mg_fused, P.AinvM != nullptr))
-      transition(&s_c, s_tot, lb == 0 ? s_btab : nullptr, P.n_lev, P.mg_fused, P.AinvM != nullptr);
-    s_newly_done = (ran != PH_DONE && s_c.phase == PH_DONE);
-  }
-  __syncthreads();
-  if (lb == 0) {
+  auto publish = [&] {   // block 0: the new control state into slot `parity`
     const long long* src = reinterpret_cast<const long long*>(&s_c);
     DevPtr<long long> dst = reinterpret_cast<DevPtr<long long>>(P.ctrl + parity);
     for (int w = threadIdx.x; w < (int)(sizeof(Ctrl) / 8); w += kBlock) dst[w] = src[w];
-    if (threadIdx.x == 0 && s_newly_done) signal_done<real>(P, &s_c);
+  };
+  // From one V-cycle operation to the next nothing is reduced and only the
+  // cycle position changes: every thread knows the next operation at once,
+  // thread 0 records the transition and block 0 publishes it at the end.
+  int mop = 0, mlev = 0;
+  const bool in_cycle =
+      ran == PH_MG && mg_next(s_c.mg_op, s_c.mg_lev, P.n_lev, P.mg_fused, P.AinvM != nullptr, mop, mlev);
+  int phase = PH_MG;
+  if (in_cycle) {
+    if (threadIdx.x == 0)
+      transition_fast(&s_c, s_tot, lb == 0 ? s_btab : nullptr, P.n_lev, P.mg_fused, P.AinvM != nullptr);
+  } else {
+    const int np_prev = n_parts(ran, s_c.mg_op, s_c.mg_lev);
+    if (np_prev > 0) reduce_partials(part_prev, P.G, np_prev, ran, pre, s_tot);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      if (!transition_fast(&s_c, s_tot, lb == 0 ? s_btab : nullptr, P.n_lev, P.mg_fused, P.AinvM != nullptr))
+        transition(&s_c, s_tot, lb == 0 ? s_btab : nullptr, P.n_lev, P.mg_fused, P.AinvM != nullptr);
+      s_newly_done = (ran != PH_DONE && s_c.phase == PH_DONE);
+    }
+    __syncthreads();
+    if (lb == 0) {
+      publish();
+      if (threadIdx.x == 0 && s_newly_done) signal_done<real>(P, &s_c);
+    }
+    phase = s_c.phase;
+    mop = s_c.mg_op;
+    mlev = s_c.mg_lev;
+    if (!is_work(phase)) return;
   }
-  const int phase = s_c.phase;
-  if (!is_work(phase)) return;
 
   switch (phase) {
     case PH_PREP:
@@ -1510,7 +1547,7 @@ __global__ void __launch_bounds__(kBlock, 4) k_step(const ProbDev<real>* __restr
       run_phase<real, LPR, PH_FIELD>(P, &s_c, lb, parity, s_red);
       break;
     case PH_MG:
-      run_phase<real, LPR, PH_MG>(P, &s_c, lb, parity, s_red);
+      run_phase<real, LPR, PH_MG>(P, &s_c, lb, parity, s_red, mop, mlev);
       break;
     case PH_PCG_A:
       run_phase<real, LPR, PH_PCG_A>(P, &s_c, lb, parity, s_red);
@@ -1518,6 +1555,10 @@ __global__ void __launch_bounds__(kBlock, 4) k_step(const ProbDev<real>* __restr
     case PH_PCG_B:
       run_phase<real, LPR, PH_PCG_B>(P, &s_c, lb, parity, s_red);
       break;
+  }
+  if (in_cycle && lb == 0) {
+    __syncthreads();   // thread 0's record of the transition
+    publish();
   }
 }
 
