@@ -325,6 +325,36 @@ def test_polycrystal_full_size_local_terms_match_oracle(ctx):
         p.close()
 
 
+def test_polycrystal_mixed_minimum_matches_fp64(ctx):
+    """The mixed form's minimum of the full-size polycrystal with all four
+    terms (stray field included) against the FP64 path's: the FP32 storage
+    with the difference forms of the exchange, coupling and potential sums
+    must reach the FP64 minimum's energy within 1e-6 of the term magnitudes
+    (the accuracy gate of the mixed form) at a torque floor of about 1e-4.
+    Parity unpinned beyond the FP64 path, which the cube's full-size test and
+    the polycrystal's local-term test tie to the oracle."""
+    from paper_1309_5796_amd import binding
+    say("polycrystal mixed vs FP64: mesh")
+    cfg = meshgen.config3()
+    out = {}
+    for prec in (binding.FP64, binding.MIXED):
+        say(f"polycrystal mixed vs FP64: minimize, precision {prec}")
+        p = binding.Problem(ctx, cfg["mesh"], precision=prec)
+        p.set_m(cfg["m0"])
+        p.set_field(cfg["b_ext"])
+        out[prec] = p.minimize()
+        p.close()
+    rf, rm = out[binding.FP64], out[binding.MIXED]
+    say(f"FP64 status {rf.status} E {rf.energy_J:.12e} torque {rf.max_torque:.2e}; "
+        f"mixed status {rm.status} E {rm.energy_J:.12e} torque {rm.max_torque:.2e}")
+    assert rf.status == binding.OK and rf.max_torque < 1e-6
+    assert rm.status in (binding.OK, binding.W_FLOOR)
+    assert rm.max_torque < 3e-4
+    scale = abs(rf.e_exch_J) + abs(rf.e_anis_J) + abs(rf.e_zeem_J) + abs(rf.e_demag_J)
+    assert abs(rm.energy_J - rf.energy_J) <= 1e-6 * scale, (rm.energy_J - rf.energy_J) / scale
+    assert np.abs(rm.m_avg - rf.m_avg).max() <= 1e-3
+
+
 def test_degenerate_sizes_and_states(ctx):
     """Edge cases: the smallest mesh (one Kuhn cell, 6 tets, 8 nodes, no air:
     fewer rows than one wavefront), a start already at the minimum (zero
