@@ -162,6 +162,12 @@ struct MgLevelT {
   Ptr<const int> rso;
   Ptr<const int> rsc;
   Ptr<const real> rsv;
+  // sliced rows are held in a windowed order (rows sorted by length inside
+  // windows of 512, which cuts the slices' padding): the row at each
+  // position of A's, Q's and R's sliced copies (null: position = row)
+  Ptr<const int> aord;
+  Ptr<const int> qord;
+  Ptr<const int> rord;
   Ptr<real> b;                 // right-hand side (level 0 uses the CG residual)
   Ptr<real> wb;                // wd b (levels >= 1), written with b
   Ptr<real> res;               // residual after pre-smoothing

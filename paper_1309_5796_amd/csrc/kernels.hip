@@ -604,58 +604,74 @@ __device__ void mg_rows(const ProbDev<real>& P, const Ctrl* C, const MgLevelDev<
     DevPtr<const real> __restrict__ wdn = last ? nullptr : lev_of<real>(l + 1).wd;
     DevPtr<const real> __restrict__ res = L.res;
     const bool m = op == MG_RESTM;   // b_{l+1} = M b, else R res
+    // a sliced R holds its rows in a windowed order: position i is row ri
+    DevPtr<const int> __restrict__ ord = W == 1 ? L.rord : nullptr;
     chunk_rows(L.n_next, G, blk, RPP, W == 1 ? 64 : 1, r0, r1, rs);
     for (int base = r0; base < r1; base += rs) {
       const int i = base + slot;
       const bool valid = i < r1;
-      const real wi = (valid && lane == 0 && !last) ? wdn[i] : real(0);
+      const int ri = (valid && ord) ? ord[i] : i;
+      // the row's own values: before the sweep when rows are in place, after
+      // it when their index comes from the row order (so that its load does
+      // not hold up the sweep's)
+      real wi = (valid && lane == 0 && !last && !ord) ? wdn[i] : real(0);
       real sum = 0;
       if (valid)
         sum = m ? m_row<real, W>(L, i, lane, [&](int j) { return b[j]; })
                 : r_row<real, W>(L, i, lane, nt, [&](int j) { return res[j]; });
       sum = group_sum<real, W>(sum);
       if (valid && lane == 0) {
-        bn[i] = sum;
-        if (!last) wbn[i] = wi * sum;
+        if (ord && !last) wi = wdn[ri];
+        bn[ri] = sum;
+        if (!last) wbn[ri] = wi * sum;
       }
     }
     return;
   }
   chunk_rows(L.n, G, blk, RPP, W == 1 ? 64 : 1, r0, r1, rs);
   if (op == MG_DOWN) {
+    DevPtr<const int> __restrict__ ord = W == 1 ? L.aord : nullptr;   // windowed row order of a sliced A
     for (int base = r0; base < r1; base += rs) {
       const int i = base + slot;
       const bool valid = i < r1;
-      const real bi = (valid && lane == 0) ? b[i] : real(0);
+      const int ri = (valid && ord) ? ord[i] : i;
+      real bi = (valid && lane == 0 && !ord) ? b[i] : real(0);   // (as in REST)
       real sum = valid ? a_row<real, W>(L, i, lane, nt, [&](int j) { return l == 0 ? wd[j] * b[j] : wb[j]; })
                        : real(0);
       sum = group_sum<real, W>(sum);
-      if (valid && lane == 0) L.res[i] = bi - sum;
+      if (valid && lane == 0) {
+        if (ord) bi = b[ri];
+        L.res[ri] = bi - sum;
+      }
     }
   } else {   // MG_POST
     DevPtr<const real> __restrict__ xn = last ? P.xc : lev_of<real>(l + 1).xb;
     DevPtr<const real> __restrict__ res = L.res;
+    DevPtr<const int> __restrict__ ord = W == 1 ? L.qord : nullptr;   // windowed row order of a sliced Q
     for (int base = r0; base < r1; base += rs) {
       const int i = base + slot;
       const bool valid = i < r1;
-      real bi = 0, wi = 0, ri = 0, pold = 0;
-      if (valid && lane == 0) {
-        bi = b[i];
-        wi = wd[i];
-        ri = res[i];
-        if (l == 0) pold = P.zp[i].b;
-      }
+      const int ri = (valid && ord) ? ord[i] : i;
+      real bi = 0, wi = 0, rr = 0, pold = 0;
+      auto own = [&](int r) {   // (as in REST)
+        bi = b[r];
+        wi = wd[r];
+        rr = res[r];
+        if (l == 0) pold = P.zp[r].b;
+      };
+      if (valid && lane == 0 && !ord) own(i);
       Pair<real> sum = valid ? q_row<real, W>(L, i, lane, nt, [&](int j) { return xn[j]; }) : Pair<real>{0, 0};
       sum.a = group_sum<real, W>(sum.a);
       sum.b = group_sum<real, W>(sum.b);
       if (valid && lane == 0) {
+        if (ord) own(ri);
         const real xai = wi * bi + sum.b;
-        const real zi = xai + wi * (ri - sum.a);
+        const real zi = xai + wi * (rr - sum.a);
         if (l == 0) {
-          st<real>(P.zp, i, Pair<real>{zi, pold});
+          st<real>(P.zp, ri, Pair<real>{zi, pold});
           acc[0] += (double)bi * (double)zi;
         } else {
-          L.xb[i] = zi;
+          L.xb[ri] = zi;
         }
       }
     }
