@@ -75,13 +75,17 @@ print(json.dumps(dict(evals=r.evals, seconds=dt, N=s.N)))
 def kernel_source_hash() -> str:
     """Hash of the step kernel's source and of the host code that lays out its
     operands (layouts, lanes per row, block splits, the multigrid hierarchy):
-    a change to any of them changes the traffic the counters measured."""
+    a change to any of them changes the traffic the counters measured.
+    Comments and blank lines are left out (they change no code)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in ("paper_1309_5796_amd/csrc/kernels.hip", "paper_1309_5796_amd/csrc/device.h",
               "paper_1309_5796_amd/csrc/api.cpp", "paper_1309_5796_amd/csrc/amg.cpp"):
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f), encoding="utf-8") as fh:
+            text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        lines = (re.sub(r"//.*$", "", ln).rstrip() for ln in text.splitlines())
+        h.update("\n".join(ln for ln in lines if ln).encode())
     return h.hexdigest()
 
 

@@ -249,8 +249,8 @@ struct Sliced {
 // (8 slices): a slice is as wide as its longest row, and the multigrid's
 // matrices mix row lengths (aggregates of 5-47 fine nodes, rows of A P next
 // to aggregate boundaries), so that sorting cuts the padding (polycrystal:
-// R_0 1.34x -> 1.0Nx the entries, A P 1.16x, P's fronts 1.53x) while rows
-// stay inside their neighbourhood for the gathers and the XCD chunks.
+// R_0 1.34x -> 1.06x its entries, A P 1.16x -> 1.03x) while rows stay
+// inside their neighbourhood for the gathers and the XCD chunks.
 constexpr int kOrderWindow = 512;
 std::vector<int> window_order(const std::vector<int>& len) {
   const int64_t n = (int64_t)len.size();
