@@ -1404,7 +1404,7 @@ __device__ void transition(Ctrl* C, const double* v, const double* btab, int n_l
 // 1 were already fetched (`pre`, by waves 0 and 1) together with the control
 // block.
 constexpr int kPreParts = 8;   // partials per lane fetched early: G <= 64 * kPreParts
-__device__ void reduce_partials(DevPtr<const double> src, int G, int np, int phase, const double* pre, double* out) {
+__device__ __forceinline__ void reduce_partials(DevPtr<const double> src, int G, int np, int phase, const double* pre, double* out) {
   const int wid = threadIdx.x >> 6, lid = threadIdx.x & 63;
   for (int k = wid; k < np; k += kBlock / 64) {
     const bool mx = (phase == PH_FIELD && k == FP_TMAX);
@@ -1494,23 +1494,32 @@ __global__ void __launch_bounds__(kBlock, 4) k_step(const ProbDev<real>* __restr
   // The control block, block 0's byte table and partial slots 0 and 1 are
   // fetched in one round trip; the phase decides later what is used.
   DevPtr<const double> part_prev = P.part + (size_t)prev * P.G * kNPart;
+  // The control block, the level descriptors and block 0's byte table (one
+  // word per thread each) are loaded before the partials and stored to LDS
+  // after them: loads complete in order, so the stores, and the barrier,
+  // wait only for those words, and the partials stay in flight through the
+  // transition of the V-cycle launches, which do not use them.
+  static_assert(sizeof(Ctrl) / 8 <= kBlock && kByteSlots <= kBlock &&
+                    kMaxLevels * sizeof(MgLevelDev<double>) / 8 <= kBlock,
+                "one word per thread");
   double pre[kPreParts];
   {
-    const int wid = threadIdx.x >> 6, lid = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6, lid = threadIdx.x & 63, t = threadIdx.x;
+    const int cwords = (int)(sizeof(Ctrl) / 8);
+    const int lwords = P.n_lev * (int)(sizeof(MgLevelDev<real>) / 8);
+    DevPtr<const long long> csrc = reinterpret_cast<DevPtr<const long long>>(P.ctrl + prev);
+    DevPtr<const long long> lsrc = reinterpret_cast<DevPtr<const long long>>(P.lev);
+    const long long cw = t < cwords ? csrc[t] : 0;
+    const long long lw = t < lwords ? lsrc[t] : 0;
+    const double bw = (lb == 0 && t < kByteSlots) ? P.btab[t] : 0.0;
 #pragma unroll
     for (int u = 0; u < kPreParts; ++u) {
       const int q = lid + 64 * u;
       pre[u] = (wid < 2 && q < P.G) ? part_prev[(size_t)wid * P.G + q] : 0.0;
     }
-    DevPtr<const long long> src = reinterpret_cast<DevPtr<const long long>>(P.ctrl + prev);
-    long long* dst = reinterpret_cast<long long*>(&s_c);
-    for (int w = threadIdx.x; w < (int)(sizeof(Ctrl) / 8); w += kBlock) dst[w] = src[w];
-    if (lb == 0)
-      for (int w = threadIdx.x; w < kByteSlots; w += kBlock) s_btab[w] = P.btab[w];
-    DevPtr<const long long> ls = reinterpret_cast<DevPtr<const long long>>(P.lev);
-    long long* ldst = reinterpret_cast<long long*>(s_lev_raw);
-    const int lwords = P.n_lev * (int)(sizeof(MgLevelDev<real>) / 8);
-    for (int w = threadIdx.x; w < lwords; w += kBlock) ldst[w] = ls[w];
+    if (t < cwords) reinterpret_cast<long long*>(&s_c)[t] = cw;
+    if (t < lwords) reinterpret_cast<long long*>(s_lev_raw)[t] = lw;
+    if (lb == 0 && t < kByteSlots) s_btab[t] = bw;
   }
   __syncthreads();
   const int ran = s_c.phase;
