@@ -1459,10 +1459,10 @@ int mmsd_problem_create(mmsd_ctx c, const mmsd_mesh* mesh, const mmsd_material* 
     (void)hipSetDevice(c->device);
     const DeviceAssembly* dp = c->assembly == MMSD_ASSEMBLE_DEVICE ? &D : nullptr;
     rc = precision == MMSD_MIXED ? build_device<float>(p, dp) : build_device<double>(p, dp);
-    if (!rc && dp) {
-      const hipError_t e = hipStreamSynchronize(c->stream);
-      if (e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize");
-    }
+    // the build's copies and kernels read D and write the arena: both are
+    // released below only once they are done, on failure too
+    const hipError_t e = hipStreamSynchronize(c->stream);
+    if (!rc && e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize");
   }
   D.release(c);
   if (rc) {
