@@ -334,6 +334,23 @@ int mmsd_set_problem_launch(mmsd_problem p, int lanes_per_row, int max_blocks);
  * potential) is unchanged.  Outputs are nullable. */
 int mmsd_autotune(mmsd_problem p, int* lanes_out, int* blocks_out, double* us_out);
 
+/* The autotuner's per-context cache as plain records, so that a caller can
+ * keep it across processes (a file, a service) and hand it to a new context
+ * instead of timing again.  A record is 5 int32: {precision (MMSD_FP64 or
+ * MMSD_MIXED), floor(log2(N + 1)), floor(log2(N_t + 1)), lanes per row,
+ * block cap}, the class key and the shape mmsd_autotune keeps.
+ * mmsd_autotune_cache_get writes min(cap, count) records to rec (host
+ * memory the caller owns, 5 * cap int32; NULL with cap 0 for the count
+ * only) in ascending key order and the cache's record count to *n.
+ * mmsd_autotune_cache_put adds n records (a class already cached takes the
+ * new shape); it checks every record first and adds none if one is invalid
+ * (unknown precision, a log2 outside [0, 62], lanes not 4, 8 or 16, blocks
+ * not a multiple of 8 in [8, 2048]): MMSD_E_INVALID.  Cached shapes apply
+ * to the problems autotuned afterwards, not to existing ones.  Both are
+ * host-only and take the context's lock. */
+int mmsd_autotune_cache_get(mmsd_ctx ctx, int32_t* rec, int cap, int* n);
+int mmsd_autotune_cache_put(mmsd_ctx ctx, const int32_t* rec, int n);
+
 /* Host-side assembly only (no device): sizes[4] = {N, nnz of the magnet
  * pattern, N_t, nnz of the potential matrix}; every array pointer may be
  * NULL (query sizes first).  Values are in the library's internal units

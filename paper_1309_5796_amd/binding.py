@@ -95,6 +95,8 @@ SIGNATURES = [
     ("mmsd_copy_probe", C.c_int, [C.c_void_p, C.c_size_t, C.c_int, C.POINTER(C.c_double)]),
     ("mmsd_set_problem_launch", C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     ("mmsd_autotune", C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double)]),
+    ("mmsd_autotune_cache_get", C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.POINTER(C.c_int)]),
+    ("mmsd_autotune_cache_put", C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     ("mmsd_assembly_export", C.c_int, [C.POINTER(MeshC), C.POINTER(MaterialC), C.c_int, C.POINTER(C.c_int64)]
      + [C.c_void_p] * 12),
     ("mmsd_assemble_device", C.c_int, [C.c_void_p, C.POINTER(MeshC), C.POINTER(MaterialC), C.c_int,
@@ -250,6 +252,21 @@ class Context:
     def set_assembly(self, where: int):
         """Where problems created afterwards assemble their operators (ASSEMBLE_HOST, ASSEMBLE_DEVICE)."""
         _check(self.lib.mmsd_set_assembly(self.handle, where))
+
+    def autotune_cache(self) -> np.ndarray:
+        """The autotuner's cache as an (n, 5) int32 array of records
+        {precision, log2(N + 1), log2(N_t + 1), lanes, blocks}."""
+        n = C.c_int()
+        _check(self.lib.mmsd_autotune_cache_get(self.handle, None, 0, C.byref(n)))
+        rec = np.zeros((n.value, 5), np.int32)
+        if n.value:
+            _check(self.lib.mmsd_autotune_cache_get(self.handle, rec.ctypes.data, n.value, C.byref(n)))
+        return rec
+
+    def put_autotune_cache(self, records):
+        """Add records (as returned by autotune_cache) to this context's cache."""
+        rec = np.ascontiguousarray(np.asarray(records, np.int32).reshape(-1, 5))
+        _check(self.lib.mmsd_autotune_cache_put(self.handle, rec.ctypes.data if len(rec) else None, len(rec)))
 
     def timing(self, on: bool):
         _check(self.lib.mmsd_timing_enable(self.handle, 1 if on else 0))

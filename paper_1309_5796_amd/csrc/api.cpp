@@ -1261,6 +1261,12 @@ void mmsd_ctx_s::dfree(void* p) {
   else (void)hipFree(p);
 }
 
+// Key of the autotuner's cache: a problem class (precision, floor(log2(N + 1)),
+// floor(log2(N_t + 1))).
+static int64_t tune_key(int precision, int log2_n, int log2_nt) {
+  return ((int64_t)precision << 40) | ((int64_t)log2_n << 20) | (int64_t)log2_nt;
+}
+
 // ============================ C ABI =======================================
 // Operators assembled on the device (into D) and the host side the problem
 // keeps: the magnet pattern and lumped volumes (sizes, material changes) and
@@ -1924,8 +1930,8 @@ int mmsd_autotune(mmsd_problem p, int* lanes_out, int* blocks_out, double* us_ou
   if (!p) return invalid("null problem");
   mmsd_ctx c = p->ctx;
   // cache: (precision, log2 N, log2 Nt) -> best shape, per context
-  const int64_t key = ((int64_t)p->precision << 40) | ((int64_t)std::ilogb((double)p->A.N + 1) << 20) |
-                      (int64_t)std::ilogb((double)p->A.Nt + 1);
+  const int64_t key =
+      tune_key(p->precision, std::ilogb((double)p->A.N + 1), std::ilogb((double)p->A.Nt + 1));
   {
     std::lock_guard<std::mutex> lk(c->mu);
     auto it = c->tuned.find(key);
@@ -2000,6 +2006,41 @@ int mmsd_autotune(mmsd_problem p, int* lanes_out, int* blocks_out, double* us_ou
   if (lanes_out) *lanes_out = best_l;
   if (blocks_out) *blocks_out = best_b;
   if (us_out) *us_out = best;
+  return MMSD_OK;
+}
+
+int mmsd_autotune_cache_get(mmsd_ctx c, int32_t* rec, int cap, int* n) {
+  if (!c || !n || cap < 0 || (cap > 0 && !rec)) return invalid("bad autotune cache request");
+  std::lock_guard<std::mutex> lk(c->mu);
+  int k = 0;
+  for (const auto& kv : c->tuned) {   // std::map: ascending keys
+    if (k < cap) {
+      int32_t* r = rec + 5 * (size_t)k;
+      r[0] = (int32_t)(kv.first >> 40);
+      r[1] = (int32_t)((kv.first >> 20) & 0xFFFFF);
+      r[2] = (int32_t)(kv.first & 0xFFFFF);
+      r[3] = kv.second.first;
+      r[4] = kv.second.second;
+    }
+    ++k;
+  }
+  *n = k;
+  return MMSD_OK;
+}
+
+int mmsd_autotune_cache_put(mmsd_ctx c, const int32_t* rec, int n) {
+  if (!c || n < 0 || (n > 0 && !rec)) return invalid("bad autotune cache request");
+  for (int k = 0; k < n; ++k) {
+    const int32_t* r = rec + 5 * (size_t)k;
+    if ((r[0] != MMSD_FP64 && r[0] != MMSD_MIXED) || r[1] < 0 || r[1] > 62 || r[2] < 0 || r[2] > 62 ||
+        (r[3] != 4 && r[3] != 8 && r[3] != 16) || r[4] < 8 || r[4] > kMaxBlocks || r[4] % 8)
+      return invalid("autotune cache record " + std::to_string(k) + " is not valid");
+  }
+  std::lock_guard<std::mutex> lk(c->mu);
+  for (int k = 0; k < n; ++k) {
+    const int32_t* r = rec + 5 * (size_t)k;
+    c->tuned[tune_key(r[0], r[1], r[2])] = {r[3], r[4]};
+  }
   return MMSD_OK;
 }
 

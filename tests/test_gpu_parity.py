@@ -201,6 +201,38 @@ def test_autotune_keeps_state_and_result(ctx, cfg1):
     q.close()
 
 
+def test_autotune_cache_carries_over_to_a_new_context(ctx, cfg1):
+    """The cache read out of one context and put into a fresh one (as a
+    process would keep it in a file) gives the same shape without timing;
+    invalid records are refused whole."""
+    from paper_1309_5796_amd import binding
+    say("autotune cache transfer")
+    p = binding.Problem(ctx, cfg1["mesh"])
+    lanes, blocks, _ = p.autotune()
+    rec = ctx.autotune_cache()
+    n_log = int(np.floor(np.log2(p.N + 1)))
+    nt_log = int(np.floor(np.log2(p.Nt + 1)))
+    assert [binding.FP64, n_log, nt_log, lanes, blocks] in rec.tolist()
+    p.close()
+    fresh = binding.Context(0)
+    try:
+        assert len(fresh.autotune_cache()) == 0
+        bad = rec.copy()
+        bad[0, 3] = 5   # lanes must be 4, 8 or 16
+        with pytest.raises(binding.MMSDError) as e:
+            fresh.put_autotune_cache(np.concatenate([rec, bad]))
+        assert e.value.code == binding.E_INVALID
+        assert len(fresh.autotune_cache()) == 0     # nothing added
+        fresh.put_autotune_cache(rec)
+        assert np.array_equal(fresh.autotune_cache(), rec)
+        q = binding.Problem(fresh, cfg1["mesh"])
+        l2, b2, us = q.autotune()
+        assert (l2, b2, us) == (lanes, blocks, -1.0)   # applied from the cache, not timed
+        q.close()
+    finally:
+        fresh.close()
+
+
 @pytest.mark.parametrize("precond", [1, 2])
 def test_evaluate_config1_each_preconditioner(ctx, cfg1, cfg1_system, precond):
     from paper_1309_5796_amd import binding
