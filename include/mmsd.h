@@ -310,7 +310,7 @@ int mmsd_set_vcycle(mmsd_ctx ctx, int flags);
  * geometry for mmsd_set_material, and a copy of the potential matrix for the
  * multigrid setup).  The two give the same operators up to the rounding of
  * fused multiply-adds (relative 1e-15); errors are those of
- * mmsd_assemble_device (a node in more than 512 tets is MMSD_E_INVALID).
+ * mmsd_assemble_device (a node in more than 3,276 tets is MMSD_E_INVALID).
  * Device temporaries of up to ~190 bytes per tet are held during creation.
  * MMSD_E_INVALID for any other value. */
 #define MMSD_ASSEMBLE_HOST 0
@@ -373,8 +373,9 @@ int mmsd_assembly_export(const mmsd_mesh* mesh, const mmsd_material* mats, int n
  * eleven NULL = size query (writes sizes[4]; runs the pattern kernels), all
  * eleven set = assemble, with sizes[4] holding what the query returned (the
  * buffers' sizes; a mismatch is MMSD_E_INVALID before anything is written);
- * a mix of NULL and set is MMSD_E_INVALID.  A node in more than 512 tets is
- * MMSD_E_INVALID (the host assembly has no such limit).
+ * a mix of NULL and set is MMSD_E_INVALID.  A node in more than 3,276 tets
+ * is MMSD_E_INVALID (a row's candidate columns are held in 64 KB of LDS; the
+ * host assembly has no such limit).
  * With N_t = 0, lrp[1] = {0} and lci, L, pot_global are untouched.
  * Temporaries (up to ~190 B per tet: a 128-B geometry record, vertex ids,
  * the node-to-tet adjacencies) come from ctx's allocator and are freed before

@@ -267,7 +267,9 @@ __global__ __launch_bounds__(kWave) void k_asm_potential(PotentialArgs a) {
 
 // ---- structure: node-to-tet adjacency and sparsity patterns ----------
 
-constexpr int kMaxCand = 2048;   // candidate columns of one row: 4 per incident tet
+// Candidate columns of one row (4 per incident tet) held in LDS by the
+// pattern kernel, 5 bytes each: at most 64 KB.
+constexpr int kMaxCand = 13104;
 
 __global__ __launch_bounds__(kAsmBlock) void k_asm_zero(int32_t* __restrict__ p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * kAsmBlock + threadIdx.x;
@@ -323,22 +325,25 @@ struct PatternArgs {
   int32_t* cnt;              // [R] distinct columns (count pass)
   const int32_t* rp;         // row starts (write pass)
   int32_t* ci;               // columns, ascending per row (write pass)
+  int cand;                  // 4 x the longest adjacency list: the LDS candidate slots
 };
 
 // The columns of row r are the distinct columns of the vertices of the
 // tets around its node.  One 64-lane block per row: the lanes stage the
 // 4 x (incident tets) candidates in LDS and mark first occurrences; the
 // count pass sums the marks, the write pass puts each distinct column at
-// its rank among them, so every row comes out sorted and unique.
+// its rank among them, so every row comes out sorted and unique.  The
+// candidate list takes a.cand ints and a.cand bytes of dynamic LDS.
 template <bool WRITE>
 __global__ __launch_bounds__(kWave) void k_pattern(PatternArgs a) {
-  __shared__ int s_c[kMaxCand];
-  __shared__ unsigned char s_first[kMaxCand];
+  extern __shared__ int s_dyn[];
+  int* s_c = s_dyn;
+  unsigned char* s_first = reinterpret_cast<unsigned char*>(s_dyn + a.cand);
   const int lane = threadIdx.x;
   const int r = blockIdx.x;
   const int g = a.row_node ? a.row_node[r] : r;
   const int k0 = a.adj_ptr[g];
-  const int m = 4 * (a.adj_ptr[g + 1] - k0);   // at most kMaxCand (checked on the host)
+  const int m = 4 * (a.adj_ptr[g + 1] - k0);   // at most a.cand <= kMaxCand (set and checked on the host)
   for (int j = lane; j < m; j += kWave) {
     const int e = a.adj[k0 + j / 4] >> 2;
     const int x = a.tets4[4 * (int64_t)e + (j & 3)];
@@ -473,9 +478,10 @@ int scan_counts(const int32_t* d_cnt, int64_t n, int32_t* d_ptr, hipStream_t st,
 }
 
 // Node-to-(tet, vertex) adjacency of n nodes over E tets, into ptr[n + 1]
-// and lst[4 E] (device); cur is an n-int temporary.
+// and lst[4 E] (device); cur is an n-int temporary; *longest gets the
+// longest list's length.
 int build_adjacency(const int32_t* d_tets, int64_t E, int64_t n, int32_t* ptr, int32_t* lst, int32_t* cur,
-                    hipStream_t st) {
+                    hipStream_t st, int* longest) {
   k_asm_zero<<<grid_of(n), kAsmBlock, 0, st>>>(cur, n);
   k_adj_count<<<grid_of(E), kAsmBlock, 0, st>>>(d_tets, E, cur);
   MMSD_HIP(hipGetLastError());
@@ -483,10 +489,11 @@ int build_adjacency(const int32_t* d_tets, int64_t E, int64_t n, int32_t* ptr, i
   int largest = 0;
   int rc = scan_counts(cur, n, ptr, st, &total, &largest);
   if (rc) return rc;
-  if (4 * largest > kMaxCand) {
+  if (4 * (int64_t)largest > kMaxCand) {
     set_error("device assembly: a node lies in more than " + std::to_string(kMaxCand / 4) + " tets");
     return MMSD_E_INVALID;
   }
+  *longest = largest;
   k_asm_zero<<<grid_of(n), kAsmBlock, 0, st>>>(cur, n);
   k_adj_fill<<<grid_of(E), kAsmBlock, 0, st>>>(d_tets, E, ptr, cur, lst);
   k_adj_sort<<<grid_of(n), kAsmBlock, 0, st>>>(ptr, n, lst);
@@ -494,11 +501,15 @@ int build_adjacency(const int32_t* d_tets, int64_t E, int64_t n, int32_t* ptr, i
   return MMSD_OK;
 }
 
+// Dynamic LDS bytes of a pattern launch: the candidate columns and their
+// first-occurrence marks.
+size_t pattern_lds(const PatternArgs& pa) { return (size_t)std::max(pa.cand, 4) * (sizeof(int) + 1); }
+
 // Pattern of R rows, first pass: counts and row starts into rp[R + 1];
 // returns the entry count.
 int pattern_count(PatternArgs pa, int32_t* cnt, int32_t* rp, hipStream_t st, int64_t* nnz) {
   pa.cnt = cnt;
-  k_pattern<false><<<(unsigned)pa.R, kWave, 0, st>>>(pa);
+  k_pattern<false><<<(unsigned)pa.R, kWave, pattern_lds(pa), st>>>(pa);
   MMSD_HIP(hipGetLastError());
   return scan_counts(cnt, pa.R, rp, st, nnz, nullptr);
 }
@@ -507,7 +518,7 @@ int pattern_count(PatternArgs pa, int32_t* cnt, int32_t* rp, hipStream_t st, int
 int pattern_write(PatternArgs pa, const int32_t* rp, int32_t* ci, hipStream_t st) {
   pa.rp = rp;
   pa.ci = ci;
-  k_pattern<true><<<(unsigned)pa.R, kWave, 0, st>>>(pa);
+  k_pattern<true><<<(unsigned)pa.R, kWave, pattern_lds(pa), st>>>(pa);
   MMSD_HIP(hipGetLastError());
   return MMSD_OK;
 }
@@ -634,9 +645,10 @@ int assemble_device_run(mmsd_ctx c, const mmsd_mesh* mesh, const mmsd_material* 
   if (!d_mtet || !d_madj_ptr || !d_madj || !d_cur || (query && !d_rp)) return nomem();
   if (mode == Outputs::OWNED && (!own(o->mrp, N + 1) || !own(o->lrp, Nt + 1))) return nomem();
   MMSD_HIP(put(d_mtet, S.mtet, st));
-  if ((rc = build_adjacency(d_mtet, Em, N, d_madj_ptr, d_madj, d_cur, st))) return rc;
+  int longest = 0;
+  if ((rc = build_adjacency(d_mtet, Em, N, d_madj_ptr, d_madj, d_cur, st, &longest))) return rc;
   int64_t nnzM = 0, nnzL = 0;
-  PatternArgs pm{(int)N, nullptr, d_madj_ptr, d_madj, d_mtet, nullptr, nullptr, nullptr, nullptr};
+  PatternArgs pm{(int)N, nullptr, d_madj_ptr, d_madj, d_mtet, nullptr, nullptr, nullptr, nullptr, 4 * longest};
   if ((rc = pattern_count(pm, d_cur, query ? d_rp : o->mrp, st, &nnzM))) return rc;
   if (mode == Outputs::CALLER && nnzM != cap[1]) return mismatch();
   if (mode == Outputs::OWNED && !own(o->mci, nnzM)) return nomem();
@@ -654,8 +666,8 @@ int assemble_device_run(mmsd_ctx c, const mmsd_mesh* mesh, const mmsd_material* 
     if (!d_tptr || !d_tlst || !d_pot_of || !d_pot_global) return nomem();
     MMSD_HIP(put(d_pot_of, S.pot_of, st));
     MMSD_HIP(put(d_pot_global, S.pot_global, st));
-    if ((rc = build_adjacency(d_tets, E, n_nodes, d_tptr, d_tlst, d_cur, st))) return rc;
-    PatternArgs pp{(int)Nt, d_pot_global, d_tptr, d_tlst, d_tets, d_pot_of, nullptr, nullptr, nullptr};
+    if ((rc = build_adjacency(d_tets, E, n_nodes, d_tptr, d_tlst, d_cur, st, &longest))) return rc;
+    PatternArgs pp{(int)Nt, d_pot_global, d_tptr, d_tlst, d_tets, d_pot_of, nullptr, nullptr, nullptr, 4 * longest};
     if ((rc = pattern_count(pp, d_cur, query ? d_rp : o->lrp, st, &nnzL))) return rc;
     if (mode == Outputs::CALLER && nnzL != cap[3]) return mismatch();
     if (mode == Outputs::OWNED && !own(o->lci, nnzL)) return nomem();

@@ -89,6 +89,8 @@ def star_ball(r_in=5e-9, r_out=10e-9, subdivisions=2):
 
 MESHES = {
     "star_valence_320": star_ball,    # multi-pass rows in both row kernels
+    # a node in 1,280 tets (5,120 candidate columns in the pattern kernel's LDS)
+    "star_valence_1280": lambda: star_ball(subdivisions=3),
     "kuhn_two_regions": two_region_config1,
     "delaunay": lambda: meshgen.delaunay_box(5),     # irregular rows of 4 to ~25 entries
     "sphere_staircase": lambda: meshgen.kuhn_ball(cells=8),
@@ -124,13 +126,18 @@ def test_patterns_equal_the_host_patterns(assembled):
 
 def test_values_equal_the_host_values(assembled):
     """Same terms in the same order: equal up to the rounding of fused
-    multiply-adds (a few ulps of each array's largest entry)."""
-    _, _, d, h = assembled
+    multiply-adds.  An entry sums one term per incident tet, each of which
+    may differ by an ulp or so, so the bound grows linearly with the number
+    of terms (the error bound of a recursive sum): 1e-14 of each array's
+    largest entry up to 100 tets per node, in proportion beyond."""
+    _, mesh, d, h = assembled
+    valence = np.bincount(np.asarray(mesh.tets).ravel()).max()
+    tol = 1e-14 * max(1.0, valence / 100)
     keys = ["K", "D1", "D2", "Q", "V"] + (["L"] if h["Nt"] else [])
     for k in keys:
         scale = np.abs(h[k]).max()
         err = np.abs(d[k] - h[k]).max()
-        assert err <= 1e-14 * scale, (k, err / scale)
+        assert err <= tol * scale, (k, err / scale)
 
 
 def test_values_match_the_oracle(assembled):
