@@ -91,6 +91,23 @@ double spectral_radius(const Csr& A, const std::vector<double>& dinv) {
   return lam;
 }
 
+// Upper bound of rho(D^-1 A) (a_ii > 0): the smaller of the Gershgorin
+// bounds of D^-1 A, max_i sum_j |a_ij| / a_ii, and of the similar matrix
+// D^-1/2 A D^-1/2, max_i sum_j |a_ij| / sqrt(a_ii a_jj).
+double gershgorin(const Csr& A, const std::vector<double>& dinv) {
+  double g1 = 0, g2 = 0;
+  for (int i = 0; i < A.nrows; ++i) {
+    double s1 = 0, s2 = 0;
+    for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+      s1 += std::fabs(A.v[k]);
+      s2 += std::fabs(A.v[k]) * std::sqrt(dinv[A.ci[k]]);
+    }
+    g1 = std::max(g1, s1 * dinv[i]);
+    g2 = std::max(g2, s2 * std::sqrt(dinv[i]));
+  }
+  return std::min(g1, g2);
+}
+
 int aggregate(const Csr& A, const std::vector<double>& d, double theta, std::vector<int>& agg) {
   const int n = A.nrows;
   // strength graph
@@ -271,7 +288,7 @@ Csr residual_restriction(const AmgLevel& L) {
       const int c = std::min(ca, cb);
       double x = 0;
       if (cb == c) x += R.v[b++];
-      if (ca == c) x -= T.v[a++] * L.omega * L.dinv[c];
+      if (ca == c) x -= T.v[a++] * L.wsmooth * L.dinv[c];
       if (ci) {
         ci[o] = c;
         v[o] = x;
@@ -304,6 +321,7 @@ bool amg_setup(Csr A0, const AmgParams& prm, AmgHierarchy* h) {
     for (int i = 0; i < A.nrows; ++i) L.dinv[i] = 1.0 / d[i];
     const double rho = spectral_radius(A, L.dinv);
     L.omega = 4.0 / (3.0 * rho);
+    L.wsmooth = std::min(prm.smooth_scale * L.omega, 1.9 / gershgorin(A, L.dinv));
     std::vector<int> agg;
     const int na = aggregate(A, d, prm.theta, agg);
     if (na >= (int)(0.8 * A.nrows) || na < 1) break;   // no useful coarsening

@@ -659,7 +659,7 @@ int build_amg(mmsd_problem p) {
   for (int l = 0; l < nl; ++l) {
     const AmgLevel& L = H.lv[l];
     std::vector<double> wd(L.dinv.size());
-    for (size_t i = 0; i < wd.size(); ++i) wd[i] = L.omega * L.dinv[i];
+    for (size_t i = 0; i < wd.size(); ++i) wd[i] = L.wsmooth * L.dinv[i];
     const bool csr[3] = {l > 0 && sl[l][0].so.empty(), sl[l][1].so.empty(), sl[l][2].so.empty()};
     if (csr[0] && ((rc = upload_int(st, base + lo[l].arp, L.A.rp)) || (rc = upload_int(st, base + lo[l].aci, L.A.ci)) ||
                    (rc = upload_vec<real>(st, base + lo[l].av, L.A.v))))

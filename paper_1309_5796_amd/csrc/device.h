@@ -110,7 +110,7 @@ struct Ctrl {
 static_assert(sizeof(Ctrl) % 8 == 0, "Ctrl is copied as 8-byte words");
 
 // One level of the multigrid hierarchy (level 0 is the potential matrix).
-// wd = omega / diag: damped-Jacobi smoothing factor.
+// wd = w / diag, w the V-cycle smoother's damped-Jacobi weight.
 // Two node values gathered together: one 16-byte (8-byte in FP32) load per
 // neighbour instead of two.
 template <typename real>

@@ -2,7 +2,7 @@
 // the device's rearranged V(1,1) cycle rests.  Reads a CSR matrix (int32 n,
 // int32 nnz, rp, ci, values) from argv[1], builds the hierarchy and prints
 // one line per level with the largest relative deviations:
-//   rest  |R (b - A W b) - M b|, M = residual_restriction (W = omega D^-1)
+//   rest  |R (b - A W b) - M b|, M = residual_restriction (W = wsmooth D^-1)
 //   post  |xa + W (b - A xa) - (xa + W (res - (A P) x))|, xa = W b + P x,
 //         res = b - A W b (the fused post-smoothing)
 //   rap   |R A P - A_next| (Galerkin product against the stored next level)
@@ -59,7 +59,7 @@ int main(int argc, char** argv) {
     std::vector<double> b(nl), x(nn), wb(nl), res(nl), xa(nl);
     for (auto& v : b) v = N01(g);
     for (auto& v : x) v = N01(g);
-    for (int i = 0; i < nl; ++i) wb[i] = L.omega * L.dinv[i] * b[i];
+    for (int i = 0; i < nl; ++i) wb[i] = L.wsmooth * L.dinv[i] * b[i];
     const std::vector<double> Awb = spmv(L.A, wb);
     for (int i = 0; i < nl; ++i) res[i] = b[i] - Awb[i];
     // restriction of the pre-smoothed residual
@@ -70,7 +70,7 @@ int main(int argc, char** argv) {
     const std::vector<double> Axa = spmv(L.A, xa);
     std::vector<double> z1(nl), z2(nl);
     for (int i = 0; i < nl; ++i) {
-      const double w = L.omega * L.dinv[i];
+      const double w = L.wsmooth * L.dinv[i];
       z1[i] = xa[i] + w * (b[i] - Axa[i]);
       z2[i] = xa[i] + w * (res[i] - APx[i]);
     }
