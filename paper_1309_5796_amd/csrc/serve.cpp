@@ -84,13 +84,7 @@ struct Request {
 
 struct mmsd_server_s {
   mmsd_ctx user_ctx = nullptr;
-  // The setups' device work (assembly kernels, uploads, arming) and the step
-  // launches share the loop context's stream: what a setup writes is read by
-  // later launches in the same queue.  With a stream of its own, requests
-  // set up by the device assembly while others were resident failed (a
-  // potential solve stalled at its iteration cap, 1-5 of 120 requests),
-  // with or without an event ordering the two streams; on one stream, none.
-  mmsd_ctx upload_ctx = nullptr;   // hipMalloc; the loop context's stream
+  mmsd_ctx upload_ctx = nullptr;   // own stream, hipMalloc
   mmsd_ctx loop_ctx = nullptr;     // own stream for the step launches
   size_t budget = 0;
   int max_slots = 0;
@@ -416,8 +410,8 @@ int mmsd_server_create(mmsd_ctx ctx, size_t hbm_budget, int max_slots, mmsd_serv
   s->user_ctx = ctx;
   s->budget = hbm_budget;
   s->max_slots = max_slots;
-  int rc = mmsd_ctx_create(ctx->device, nullptr, nullptr, nullptr, nullptr, &s->loop_ctx);
-  if (!rc) rc = mmsd_ctx_create(ctx->device, (void*)s->loop_ctx->stream, nullptr, nullptr, nullptr, &s->upload_ctx);
+  int rc = mmsd_ctx_create(ctx->device, nullptr, nullptr, nullptr, nullptr, &s->upload_ctx);
+  if (!rc) rc = mmsd_ctx_create(ctx->device, nullptr, nullptr, nullptr, nullptr, &s->loop_ctx);
   if (!rc) {
     s->upload_ctx->lpr = s->loop_ctx->lpr = ctx->lpr;
     s->upload_ctx->max_blocks = s->loop_ctx->max_blocks = ctx->max_blocks;

@@ -171,33 +171,3 @@ def test_server_with_device_assembly_matches_direct_minimization(ctxs):
         assert np.abs(r.m_avg - ref.m_avg).max() <= 1e-6
     finally:
         srv.close()
-
-
-def test_served_stream_with_device_assembly_completes():
-    """The first 40 requests of the seeded stream (1.2k-520k nodes, FP64 and
-    mixed), set up by the device assembly while earlier ones are resident:
-    every one converges or stops at the mixed form's floor.  (With the
-    setups' device work on a stream of its own, 1-5 of 120 such requests
-    stalled in a potential solve.)"""
-    from paper_1309_5796_amd import binding
-    reqs = meshgen.config5_requests(rate_hz=200.0)[:40]
-    built = [meshgen.request_mesh(r) for r in reqs]
-    say(f"served stream, device assembly: {len(built)} requests")
-    ctx = binding.Context(0)
-    ctx.set_assembly(binding.ASSEMBLE_DEVICE)
-    srv = binding.Server(ctx, hbm_budget=64 << 30, max_slots=32)
-    try:
-        tick = {srv.submit(b["mesh"], b["b_ext"], precision=q.precision): k for k, (b, q) in enumerate(zip(built, reqs))}
-        statuses = {}
-        t0 = time.time()
-        while tick and time.time() - t0 < 150:
-            for t in list(tick):
-                out = srv.poll(t)
-                if out is not None:
-                    statuses[tick.pop(t)] = out[0].status
-            time.sleep(0.005)
-        assert not tick, f"{len(tick)} requests unfinished"
-        assert set(statuses.values()) <= {binding.OK, binding.W_FLOOR}, statuses
-    finally:
-        srv.close()
-        ctx.close()
