@@ -303,7 +303,7 @@ def serve_stream(n_requests, hbm_gb, slots, timeout_s, log_every=15.0, rate_hz=2
     t_start = time.perf_counter()
     t_last = t_start
     pending = {}
-    lat, lat_sub, node_evals, statuses, nodes = [], [], 0.0, [], 0
+    lat, lat_sub, node_evals, statuses, nodes, failed = [], [], 0.0, [], 0, []
     k = 0
     while k < len(reqs) or pending:
         now = time.perf_counter() - t_start
@@ -313,7 +313,12 @@ def serve_stream(n_requests, hbm_gb, slots, timeout_s, log_every=15.0, rate_hz=2
             pending[t] = (t_start + reqs[k].arrival_s, time.perf_counter(), meshgen.n_magnetic(b["mesh"]))
             k += 1
         for t in list(pending):
-            got = srv.poll(t)
+            try:
+                got = srv.poll(t)
+            except binding.MMSDError as e:   # a failed request: counted, not timed
+                pending.pop(t)
+                failed.append(e.code)
+                continue
             if got is not None:
                 r, _ = got
                 t_arr, t_sub, n = pending.pop(t)
@@ -343,7 +348,8 @@ def serve_stream(n_requests, hbm_gb, slots, timeout_s, log_every=15.0, rate_hz=2
             "node_iterations_per_s": node_evals / wall, "magnet_nodes_completed": nodes,
             "p50_s": pct(lat, 50), "p99_s": pct(lat, 99),
             "p50_from_submit_s": pct(lat_sub, 50), "p99_from_submit_s": pct(lat_sub, 99),
-            "statuses": sorted(set(statuses)), "device_launches": st["launches"],
+            "statuses": sorted(set(statuses)), "failed": len(failed), "failed_codes": sorted(set(failed)),
+            "device_launches": st["launches"],
             "setup_seconds_summed": st["setup_seconds"], "device_loop_busy_s": st["loop_seconds"],
             "offered_rate_req_s": rate_hz, "served_rate_req_s": len(lat) / wall, "assembly": assembly,
             "hbm_budget_GB": hbm_gb, "slots": slots}
