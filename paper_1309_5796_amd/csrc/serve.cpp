@@ -289,11 +289,17 @@ void mmsd_server_s::device_loop() {
       int* dlist = (int*)(dtab + 256);
       size_t off = 256 + align_up_bytes(4 * (size_t)(resident.size() + 2));
       if (!rc && hipMemsetAsync(dtab, 0, 256, st) != hipSuccess) rc = MMSD_E_HIP;
+      // the host sources of the table copies live until the stream is
+      // synchronized below: an asynchronous copy may read them after the call
+      std::vector<unsigned char> hq[2];
+      std::vector<int> bq[2];
       for (int q = 0; q < 2 && !rc; ++q) {
         if (idx[q].empty()) continue;
         const size_t ps = q ? sizeof(Prob<float>) : sizeof(Prob<double>);
-        std::vector<unsigned char> h(ps * idx[q].size());
-        std::vector<int> blk(idx[q].size() + 1, 0);
+        std::vector<unsigned char>& h = hq[q];
+        std::vector<int>& blk = bq[q];
+        h.assign(ps * idx[q].size(), 0);
+        blk.assign(idx[q].size() + 1, 0);
         int lpr = resident[idx[q][0]]->prob->lpr;
         for (size_t k = 0; k < idx[q].size(); ++k) {
           Request* r = resident[idx[q][k]];
