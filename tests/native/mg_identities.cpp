@@ -6,7 +6,12 @@
 //   post  |xa + W (b - A xa) - (xa + W (res - (A P) x))|, xa = W b + P x,
 //         res = b - A W b (the fused post-smoothing)
 //   rap   |R A P - A_next| (Galerkin product against the stored next level)
-// for seeded random b and x.
+// for seeded random b and x, and the smoother's damping on that level:
+//   wg    w g, g the Gershgorin bound of D^-1 A or of D^-1/2 A D^-1/2,
+//         whichever is smaller, recomputed here from A's own diagonal
+//   wlam  w lambda_max(D^-1 A), lambda from 300 power iterations on the
+//         symmetric scaling D^-1/2 A D^-1/2 (its Rayleigh quotient)
+// with w = wsmooth; damped Jacobi on an SPD matrix converges iff w lambda < 2.
 #include <cmath>
 #include <cstdio>
 #include <random>
@@ -21,6 +26,55 @@ static std::vector<double> spmv(const Csr& A, const std::vector<double>& x) {
   for (int i = 0; i < A.nrows; ++i)
     for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) y[i] += A.v[k] * x[A.ci[k]];
   return y;
+}
+
+// Largest eigenvalue of D^-1 A for SPD A, by power iteration on the
+// similar symmetric matrix D^-1/2 A D^-1/2.
+static double lambda_max(const Csr& A, std::mt19937_64& g) {
+  const int n = A.nrows;
+  std::vector<double> s(n, 0.0), x(n), y(n);
+  for (int i = 0; i < n; ++i)
+    for (int k = A.rp[i]; k < A.rp[i + 1]; ++k)
+      if (A.ci[k] == i) s[i] = 1.0 / std::sqrt(A.v[k]);
+  std::normal_distribution<double> N01;
+  for (auto& v : x) v = N01(g);
+  double lam = 0;
+  for (int it = 0; it < 300; ++it) {
+    double nx = 0;
+    for (double v : x) nx += v * v;
+    nx = std::sqrt(nx);
+    for (auto& v : x) v /= nx;
+    for (int i = 0; i < n; ++i) {
+      double acc = 0;
+      for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) acc += A.v[k] * s[A.ci[k]] * x[A.ci[k]];
+      y[i] = s[i] * acc;
+    }
+    lam = 0;
+    for (int i = 0; i < n; ++i) lam += x[i] * y[i];
+    x.swap(y);
+  }
+  return lam;
+}
+
+// Smaller of the Gershgorin bounds of D^-1 A (row sums of |a_ij| / a_ii) and
+// of D^-1/2 A D^-1/2 (row sums of |a_ij| / sqrt(a_ii a_jj)).
+static double gershgorin_bound(const Csr& A) {
+  const int n = A.nrows;
+  std::vector<double> d(n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int k = A.rp[i]; k < A.rp[i + 1]; ++k)
+      if (A.ci[k] == i) d[i] = A.v[k];
+  double g1 = 0, g2 = 0;
+  for (int i = 0; i < n; ++i) {
+    double r1 = 0, r2 = 0;
+    for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+      r1 += std::fabs(A.v[k]) / d[i];
+      r2 += std::fabs(A.v[k]) / std::sqrt(d[i] * d[A.ci[k]]);
+    }
+    g1 = std::fmax(g1, r1);
+    g2 = std::fmax(g2, r2);
+  }
+  return std::fmin(g1, g2);
 }
 
 static double rel(const std::vector<double>& a, const std::vector<double>& b) {
@@ -83,7 +137,9 @@ int main(int argc, char** argv) {
       for (auto& v : y) v = N01(g);
       e_rap = rel(spmv(L.R, spmv(L.A, spmv(L.P, y))), spmv(An, y));
     }
-    std::printf("level %zu rows %d rest %.3e post %.3e rap %.3e\n", l, nl, e_rest, e_post, e_rap);
+    const double wg = L.wsmooth * gershgorin_bound(L.A), wlam = L.wsmooth * lambda_max(L.A, g);
+    std::printf("level %zu rows %d rest %.3e post %.3e rap %.3e wg %.6f wlam %.6f\n", l, nl, e_rest, e_post, e_rap,
+                wg, wlam);
   }
   return 0;
 }

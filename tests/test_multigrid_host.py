@@ -30,12 +30,18 @@ def test_vcycle_rearrangements_are_identities(tmp_path):
         a["lci"].astype(np.int32).tofile(f)
         a["L"].astype(np.float64).tofile(f)
     out = subprocess.run([exe, path], check=True, capture_output=True, text=True).stdout
-    rows = re.findall(r"level (\d+) rows (\d+) rest (\S+) post (\S+) rap (\S+)", out)
+    rows = re.findall(r"level (\d+) rows (\d+) rest (\S+) post (\S+) rap (\S+) wg (\S+) wlam (\S+)", out)
     assert len(rows) >= 2, out   # at least two levels: a coarse level to restrict to and solve
-    for lev, n, e_rest, e_post, e_rap in rows:
+    for lev, n, e_rest, e_post, e_rap, wg, wlam in rows:
         assert float(e_rest) < 1e-12, out
         assert float(e_post) < 1e-12, out
         assert float(e_rap) < 1e-12, out
+        # Damped Jacobi with weight w on SPD A converges iff w lambda_max(D^-1 A) < 2.
+        # w g <= 1.9 bounds it from above (lambda_max <= g, both Gershgorin forms);
+        # the power-iteration estimate, a lower bound on w lambda_max, shows the
+        # weight is not so small that the smoother stops damping high modes.
+        assert float(wg) <= 1.9 + 1e-12, out
+        assert 1.0 < float(wlam) < 2.0, out
 
 
 def write_mesh(path, mesh):
