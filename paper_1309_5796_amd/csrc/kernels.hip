@@ -1529,16 +1529,17 @@ __global__ void __launch_bounds__(kBlock, 4) k_step(const ProbDev<real>* __restr
     for (int w = threadIdx.x; w < (int)(sizeof(Ctrl) / 8); w += kBlock) dst[w] = src[w];
   };
   // From one V-cycle operation to the next nothing is reduced and only the
-  // cycle position changes: every thread knows the next operation at once,
-  // thread 0 records the transition and block 0 publishes it at the end.
+  // cycle position changes: every thread derives the next operation from the
+  // position it read after the barrier above, and only block 0 records the
+  // transition, at the end, once every wavefront of the block has passed a
+  // second barrier.  Recording it here would race with wavefronts that have
+  // not yet read the position: a late one would run the operation after the
+  // next (or take the other branch, with its own barriers).
   int mop = 0, mlev = 0;
   const bool in_cycle =
       ran == PH_MG && mg_next(s_c.mg_op, s_c.mg_lev, P.n_lev, P.mg_fused, P.AinvM != nullptr, mop, mlev);
   int phase = PH_MG;
-  if (in_cycle) {
-    if (threadIdx.x == 0)
-      transition_fast(&s_c, s_tot, lb == 0 ? s_btab : nullptr, P.n_lev, P.mg_fused, P.AinvM != nullptr);
-  } else {
+  if (!in_cycle) {
     const int np_prev = n_parts(ran, s_c.mg_op, s_c.mg_lev);
     if (np_prev > 0) reduce_partials(part_prev, P.G, np_prev, ran, pre, s_tot);
     __syncthreads();
@@ -1582,6 +1583,8 @@ __global__ void __launch_bounds__(kBlock, 4) k_step(const ProbDev<real>* __restr
       break;
   }
   if (in_cycle && lb == 0) {
+    __syncthreads();   // every wavefront has read the cycle position
+    if (threadIdx.x == 0) transition_fast(&s_c, s_tot, s_btab, P.n_lev, P.mg_fused, P.AinvM != nullptr);
     __syncthreads();   // thread 0's record of the transition
     publish();
   }
