@@ -254,6 +254,45 @@ def test_server_results_equal_alone_and_in_the_mix(ctx):
     srv.close()
 
 
+def test_served_stream_under_load_finishes_every_request():
+    """The first 48 requests of the seeded 200 req/s stream (grain boxes of
+    1.2k-520k nodes, FP64/mixed), submitted at once to a 32-slot server with
+    the device assembly: many problems share each launch while setup kernels
+    run beside the step loop.  Every request must finish with a finite
+    result.  Under this load a missing barrier in the V-cycle launches (a
+    wavefront reading the cycle position after thread 0 had advanced it)
+    once ended a few percent of requests non-finite."""
+    from paper_1309_5796_amd import binding
+    say("served stream under load: 48 requests, 32 slots, device assembly")
+    reqs = meshgen.config5_requests(n_requests=48, rate_hz=200.0)
+    built = [meshgen.request_mesh(r) for r in reqs]
+    c = binding.Context(0)
+    c.set_assembly(binding.ASSEMBLE_DEVICE)
+    srv = binding.Server(c, hbm_budget=64 << 30, max_slots=32)
+    tickets = {srv.submit(b["mesh"], b["b_ext"], precision=r.precision): k for k, (r, b) in enumerate(zip(reqs, built))}
+    done, failed = {}, {}
+    t0 = time.time()
+    while len(done) + len(failed) < len(tickets) and time.time() - t0 < 240:
+        for t, k in tickets.items():
+            if k in done or k in failed:
+                continue
+            try:
+                out = srv.poll(t)
+            except binding.MMSDError as e:
+                failed[k] = e.code
+                continue
+            if out is not None:
+                done[k] = out[0]
+        time.sleep(0.005)
+    say(f"served {len(done)} failed {len(failed)} in {time.time() - t0:.1f} s")
+    srv.close()
+    c.close()
+    assert not failed, failed
+    assert len(done) == len(reqs)
+    for k, r in done.items():
+        assert r.status >= 0 and math.isfinite(r.energy_J) and math.isfinite(r.max_torque), (k, r.status)
+
+
 def test_sphere_short_sweep_matches_oracle(ctx):
     """Coarse staircase ball (the paper's sphere experiment at 8 cells per
     diameter): field points 0, -1.5, -3 T at 45 degrees, warm-started, against
