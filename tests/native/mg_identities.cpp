@@ -12,6 +12,13 @@
 //   wlam  w lambda_max(D^-1 A), lambda from 300 power iterations on the
 //         symmetric scaling D^-1/2 A D^-1/2 (its Rayleigh quotient)
 // with w = wsmooth; damped Jacobi on an SPD matrix converges iff w lambda < 2.
+// Then one line for the whole cycle, V(1,1) from zero written out plainly
+// (damped Jacobi before and after, Galerkin coarse correction, the dense
+// inverse on the coarsest level), which the CG needs symmetric positive
+// definite:
+//   coarse  |Ainv (R A P) y - y| / |y| on the last level
+//   sym     largest |y.V x - x.V y| / |y| |V x| over seeded pairs
+//   pd      smallest x.V x / x.x over seeded x (must be > 0)
 #include <cmath>
 #include <cstdio>
 #include <random>
@@ -77,6 +84,36 @@ static double gershgorin_bound(const Csr& A) {
   return std::fmin(g1, g2);
 }
 
+// One V(1,1) cycle from zero on level l.
+static std::vector<double> vcycle(const AmgHierarchy& h, size_t l, const std::vector<double>& b) {
+  const AmgLevel& L = h.lv[l];
+  const int n = L.A.nrows;
+  std::vector<double> x(n), r(n);
+  for (int i = 0; i < n; ++i) x[i] = L.wsmooth * L.dinv[i] * b[i];
+  std::vector<double> Ax = spmv(L.A, x);
+  for (int i = 0; i < n; ++i) r[i] = b[i] - Ax[i];
+  const std::vector<double> bc = spmv(L.R, r);
+  std::vector<double> xc;
+  if (l + 1 < h.lv.size()) {
+    xc = vcycle(h, l + 1, bc);
+  } else {
+    xc.assign(h.nc, 0.0);
+    for (int I = 0; I < h.nc; ++I)
+      for (int K = 0; K < h.nc; ++K) xc[I] += h.Ainv[(size_t)I * h.nc + K] * bc[K];
+  }
+  const std::vector<double> Pxc = spmv(L.P, xc);
+  for (int i = 0; i < n; ++i) x[i] += Pxc[i];
+  Ax = spmv(L.A, x);
+  for (int i = 0; i < n; ++i) x[i] += L.wsmooth * L.dinv[i] * (b[i] - Ax[i]);
+  return x;
+}
+
+static double dot(const std::vector<double>& a, const std::vector<double>& b) {
+  double s = 0;
+  for (size_t i = 0; i < a.size(); ++i) s += a[i] * b[i];
+  return s;
+}
+
 static double rel(const std::vector<double>& a, const std::vector<double>& b) {
   double d = 0, m = 0;
   for (size_t i = 0; i < a.size(); ++i) {
@@ -140,6 +177,28 @@ int main(int argc, char** argv) {
     const double wg = L.wsmooth * gershgorin_bound(L.A), wlam = L.wsmooth * lambda_max(L.A, g);
     std::printf("level %zu rows %d rest %.3e post %.3e rap %.3e wg %.6f wlam %.6f\n", l, nl, e_rest, e_post, e_rap,
                 wg, wlam);
+  }
+  {
+    // the dense inverse against the coarsest Galerkin operator
+    const AmgLevel& Ll = h.lv.back();
+    std::vector<double> y(h.nc), z(h.nc, 0.0);
+    for (auto& v : y) v = N01(g);
+    const std::vector<double> Ay = spmv(Ll.R, spmv(Ll.A, spmv(Ll.P, y)));
+    for (int I = 0; I < h.nc; ++I)
+      for (int K = 0; K < h.nc; ++K) z[I] += h.Ainv[(size_t)I * h.nc + K] * Ay[K];
+    const double e_coarse = rel(z, y);
+    // the whole cycle: symmetric, positive definite
+    const int n0 = h.lv[0].A.nrows;
+    double asym = 0, pd = 1e300;
+    for (int t = 0; t < 4; ++t) {
+      std::vector<double> x(n0), y0(n0);
+      for (auto& v : x) v = N01(g);
+      for (auto& v : y0) v = N01(g);
+      const std::vector<double> Vx = vcycle(h, 0, x), Vy = vcycle(h, 0, y0);
+      asym = std::fmax(asym, std::fabs(dot(y0, Vx) - dot(x, Vy)) / std::sqrt(dot(y0, y0) * dot(Vx, Vx)));
+      pd = std::fmin(pd, dot(x, Vx) / dot(x, x));
+    }
+    std::printf("cycle coarse %.3e sym %.3e pd %.6e\n", e_coarse, asym, pd);
   }
   return 0;
 }

@@ -1,7 +1,9 @@
 """Host-side multigrid identities behind the device's rearranged V-cycle
 (prolongation inside post-smoothing, restriction inside the down-sweep,
-Galerkin coarse operators), checked on the hierarchy of config 1's
-potential matrix with the library's own host setup code (CPU only)."""
+Galerkin coarse operators), the smoother's convergence on every level, and
+the plain V(1,1) cycle being symmetric positive definite, checked on the
+hierarchy of config 1's potential matrix with the library's own host setup
+code (CPU only)."""
 import os
 import re
 import shutil
@@ -42,6 +44,16 @@ def test_vcycle_rearrangements_are_identities(tmp_path):
         # weight is not so small that the smoother stops damping high modes.
         assert float(wg) <= 1.9 + 1e-12, out
         assert 1.0 < float(wlam) < 2.0, out
+    # The plain V(1,1) cycle is what the CG preconditions with: symmetric and
+    # positive definite (W (2 W^-1 - A) W > 0 needs w lambda_max < 2; the
+    # coarse correction needs R = P^T and a symmetric dense inverse that does
+    # invert the coarsest Galerkin operator).
+    cyc = re.findall(r"cycle coarse (\S+) sym (\S+) pd (\S+)", out)
+    assert len(cyc) == 1, out
+    e_coarse, asym, pd = map(float, cyc[0])
+    assert e_coarse < 1e-12, out
+    assert asym < 1e-12, out
+    assert pd > 0, out
 
 
 def write_mesh(path, mesh):
