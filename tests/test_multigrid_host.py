@@ -2,8 +2,8 @@
 (prolongation inside post-smoothing, restriction inside the down-sweep,
 Galerkin coarse operators), the smoother's convergence on every level, and
 the plain V(1,1) cycle being symmetric positive definite, checked on the
-hierarchy of config 1's potential matrix with the library's own host setup
-code (CPU only)."""
+hierarchies of config 1's and of the 80 nm cube's potential matrices with
+the library's own host setup code (CPU only)."""
 import os
 import re
 import shutil
@@ -18,13 +18,19 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1309_5796_amd", "csrc")
 
 
-def test_vcycle_rearrangements_are_identities(tmp_path):
+# config 1 (two levels) and the 80 nm cube (three levels; the smoother's
+# Gershgorin cap binds on its coarsest)
+MESHES = {"config1": lambda: meshgen.config1()["mesh"], "cube80": lambda: meshgen.config2()["mesh"]}
+
+
+@pytest.mark.parametrize("name", sorted(MESHES))
+def test_vcycle_rearrangements_are_identities(tmp_path, name):
     if shutil.which("g++") is None:
         pytest.skip("g++ not available")
     exe = str(tmp_path / "mg_identities")
     subprocess.run(["g++", "-O2", "-std=c++17", "-I", CSRC, os.path.join(ROOT, "tests", "native", "mg_identities.cpp"),
                     os.path.join(CSRC, "amg.cpp"), "-o", exe, "-lpthread"], check=True)
-    a = binding.assembly_export(meshgen.config1()["mesh"])
+    a = binding.assembly_export(MESHES[name]())
     path = str(tmp_path / "L.bin")
     with open(path, "wb") as f:
         np.array([a["Nt"], len(a["lci"])], np.int32).tofile(f)
