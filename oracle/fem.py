@@ -64,7 +64,8 @@ def shell_metric(centroids: np.ndarray, shell) -> np.ndarray:
     J = diag(f'_x, f'_y, f'_z) the transformed Laplacian has the metric
     |det J| J^{-1} J^{-T} = diag(f'_y f'_z / f'_x, f'_x f'_z / f'_y,
     f'_x f'_y / f'_z), evaluated at the centroid.  Returns (E, 3) diagonals.
-    parity unpinned as a formula; pinned through the demagnetizing factors.
+    Pinned against its definition (the map's Jacobian by central differences,
+    the metric by generic 3x3 algebra) and through the demagnetizing factors.
     """
     E = centroids.shape[0]
     if shell is None:

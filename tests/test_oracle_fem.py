@@ -195,3 +195,51 @@ def test_elementwise_terms_equal_the_assembled_ones():
     for k in ("E_ex", "E_an", "E_Z"):
         assert abs(lt[k] - ev[k]) <= 1e-13 * abs(ev[k])
     assert np.abs(lt["h"] - ev["h"][smp]).max() <= 1e-13 * np.abs(ev["h"]).max()
+
+
+def test_shell_metric_is_the_transformed_laplacians_metric():
+    """The shell metric against its definition: per axis the open-boundary
+    transformation maps the distance s = |t - c| to itself inside the inner
+    box and to a (b - a) / (b - s) in the shell a <= s < b.  Its Jacobian J
+    is taken here by central differences of that map and the metric
+    |det J| J^-1 J^-T by generic 3x3 linear algebra; the oracle's closed
+    form (derivative and diagonal simplification) must agree, off-diagonal
+    entries included."""
+    c = np.array([1.0, -2.0, 0.5])
+    a = np.array([3.0, 2.0, 4.0])
+    b = np.array([5.0, 4.5, 5.5])
+
+    def F(x):
+        d = x - c
+        s = np.abs(d)
+        g = np.where(s <= a, s, a * (b - a) / (b - np.minimum(s, b - 1e-300)))
+        return c + np.sign(d) * g
+
+    rng = np.random.default_rng(11)
+    pts = []
+    while len(pts) < 60:
+        # per axis: inside, or in the shell, away from the kink at s = a
+        x = np.empty(3)
+        for k in range(3):
+            if rng.random() < 0.5:
+                s = rng.uniform(0.0, 0.95 * a[k])
+            else:
+                s = rng.uniform(a[k] + 0.02 * (b[k] - a[k]), b[k] - 0.05 * (b[k] - a[k]))
+            x[k] = c[k] + (1 if rng.random() < 0.5 else -1) * s
+        pts.append(x)
+    pts = np.array(pts)
+    shell = np.concatenate([c, a, b])
+    got = oracle.fem.shell_metric(pts, shell)
+    h = 1e-6
+    for x, gdiag in zip(pts, got):
+        J = np.empty((3, 3))
+        for j in range(3):
+            e = np.zeros(3)
+            e[j] = h
+            J[:, j] = (F(x + e) - F(x - e)) / (2 * h)
+        Ji = np.linalg.inv(J)
+        G = abs(np.linalg.det(J)) * Ji @ Ji.T
+        np.testing.assert_allclose(np.diag(G), gdiag, rtol=1e-6)
+        assert np.max(np.abs(G - np.diag(np.diag(G)))) <= 1e-12 * np.max(np.abs(G))
+    # no shell: the identity metric
+    np.testing.assert_array_equal(oracle.fem.shell_metric(pts, None), np.ones((len(pts), 3)))
