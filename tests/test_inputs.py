@@ -1,7 +1,9 @@
-"""The seeded request stream of the served form (CPU only): Poisson
-arrivals, log-uniform problem sizes, 2:2:1 boxes, the FP64/mixed coin, the
-field range and the grain density, checked statistically on the 2,000
-requests, and the prefix property the bounded runs rely on."""
+"""The seeded input generators (CPU only).  The request stream of the served
+form: Poisson arrivals, log-uniform problem sizes, 2:2:1 boxes, the
+FP64/mixed coin, the field range and the grain density, checked
+statistically on the 2,000 requests, and the prefix property the bounded
+runs rely on.  The easy axes, uniform on the 15 degree cap; the grains and
+their boundary phase; the grain cubes' cell rule."""
 import math
 
 import numpy as np
@@ -49,3 +51,46 @@ def test_request_stream_is_seeded_and_prefix_stable():
         np.testing.assert_array_equal(x.b_ext, y.b_ext)
     c = meshgen.config5_requests(n_requests=2000)
     assert [r.seed for r in a] == [r.seed for r in c]
+
+
+def test_easy_axes_uniform_on_the_15_degree_cap():
+    rng = np.random.default_rng(3)
+    ax = np.array([meshgen.cap_axis(rng) for _ in range(4000)])
+    np.testing.assert_allclose(np.linalg.norm(ax, axis=1), 1.0, atol=1e-15)
+    c15 = math.cos(math.radians(15.0))
+    assert ax[:, 2].min() >= c15 - 1e-15
+    # uniform on the cap: cos(theta) uniform on [cos 15 deg, 1], azimuth uniform
+    assert abs(ax[:, 2].mean() - (1 + c15) / 2) < 6 * (1 - c15) / math.sqrt(12 * len(ax))   # 6 standard errors
+    phi = np.arctan2(ax[:, 1], ax[:, 0])
+    assert abs(np.cos(phi).mean()) < 0.05 and abs(np.sin(phi).mean()) < 0.05
+
+
+def test_grains_and_their_boundary_phase():
+    mesh = meshgen.kuhn_box((20e-9, 20e-9, 10e-9), (20, 20, 10), air=True)
+    meshgen.assign_grains(mesh, 8, np.random.default_rng(4))
+    mag = mesh.region > 0
+    regs = set(np.unique(mesh.region[mag]).tolist())
+    assert regs <= set(range(1, 10)) and 9 in regs and len(regs) >= 6
+    # grain boundaries: no anisotropy, reduced exchange; grains: the bulk
+    # constants with easy axes on the 15 degree cap
+    mats = {m.region: m for m in mesh.materials}
+    assert mats[9].K1 == 0.0 and mats[9].A == meshgen.A_GB_JM == 2e-12
+    c15 = math.cos(math.radians(15.0))
+    for g in range(1, 9):
+        assert mats[g].K1 == meshgen.K1_JM3 and mats[g].A == meshgen.A_JM
+        assert float(mats[g].axis[2]) >= c15 - 1e-15
+    # a thin layer: some, but a minority, of the magnet tets
+    frac = np.mean(mesh.region[mag] == 9)
+    assert 0.0 < frac < 0.5
+    # air keeps region 0
+    assert np.all(mesh.region[~mag] == 0)
+
+
+def test_grain_cube_cells_rule():
+    # n(L) = round(9 (L / 10 nm)^(ln 4 / ln 6)): 9 cells at 10 nm and, six
+    # times the edge giving four times the cells, 36 at 60 nm
+    assert meshgen.config4_cells(10e-9) == 9
+    assert meshgen.config4_cells(60e-9) == 36
+    Ls = np.exp(np.linspace(np.log(10e-9), np.log(60e-9), 50))
+    n = [meshgen.config4_cells(L) for L in Ls]
+    assert all(b >= a for a, b in zip(n, n[1:]))
